@@ -1,0 +1,103 @@
+"""CPU oracle: exact triangle counts and clustering coefficients.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package. The product path never does, and it
+shares no code with the GPU path: the arithmetic lives in the plain C file
+``tricc_oracle.c`` (node iterator over sorted adjacency lists, FP64 clustering
+coefficients), built by ``build.py`` into ``liboracle.so``.
+
+The definitions it follows are stated at the top of ``tricc_oracle.c``: the
+paper names node clustering coefficient and triangle counting among SNAP's
+triadic-closure methods (Section 4, table of analytics methods) and keeps
+sorted adjacency vectors per node (Section 5.1), without giving formulas.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.oracle_count.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        L.oracle_count.restype = ctypes.c_int
+        L.oracle_induced.argtypes = [i64, i64, P, P, i64, P, ctypes.c_int, P, P, P, P, P]
+        L.oracle_induced.restype = ctypes.c_int
+        L.oracle_sampled.argtypes = [i64, i64, P, P, i64, P, P, P]
+        L.oracle_sampled.restype = ctypes.c_int
+        L.oracle_wtime.argtypes = []
+        L.oracle_wtime.restype = ctypes.c_double
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def count(n, src, dst, order=0, threads=0):
+    """Whole-graph result: dict with T (uint64[n]), cc (float64[n]),
+    deg (int64[n]), total (int), avg (float), m (undirected simple edges).
+    ``order`` 0 ranks nodes by id, 1 by (degree, id)."""
+    src, dst = _i32(src), _i32(dst)
+    assert src.shape == dst.shape
+    T = np.zeros(n, np.uint64)
+    cc = np.zeros(n, np.float64)
+    deg = np.zeros(n, np.int64)
+    total = ctypes.c_uint64()
+    avg = ctypes.c_double()
+    m = ctypes.c_int64()
+    rc = lib().oracle_count(n, src.size, _ptr(src), _ptr(dst), order, threads, _ptr(T), _ptr(cc),
+                            _ptr(deg), ctypes.byref(total), ctypes.byref(avg), ctypes.byref(m))
+    if rc:
+        raise OracleError(f"oracle_count failed ({rc})")
+    return dict(T=T, cc=cc, deg=deg, total=int(total.value), avg=float(avg.value), m=int(m.value))
+
+
+def induced(n, src, dst, nodes, threads=0):
+    """Result on the induced subgraph G[S], indexed by position in ``nodes``."""
+    src, dst, S = _i32(src), _i32(dst), _i32(nodes)
+    k = S.size
+    T = np.zeros(k, np.uint64)
+    cc = np.zeros(k, np.float64)
+    total = ctypes.c_uint64()
+    avg = ctypes.c_double()
+    m = ctypes.c_int64()
+    rc = lib().oracle_induced(n, src.size, _ptr(src), _ptr(dst), k, _ptr(S), threads, _ptr(T), _ptr(cc),
+                              ctypes.byref(total), ctypes.byref(avg), ctypes.byref(m))
+    if rc:
+        raise OracleError(f"oracle_induced failed ({rc})")
+    return dict(T=T, cc=cc, total=int(total.value), avg=float(avg.value), m=int(m.value))
+
+
+def sampled(n, src, dst, samples):
+    """T(s) and d(s) for distinct sampled nodes, from the raw edge list."""
+    src, dst, S = _i32(src), _i32(dst), _i32(samples)
+    T = np.zeros(S.size, np.uint64)
+    deg = np.zeros(S.size, np.int64)
+    rc = lib().oracle_sampled(n, src.size, _ptr(src), _ptr(dst), S.size, _ptr(S), _ptr(T), _ptr(deg))
+    if rc:
+        raise OracleError(f"oracle_sampled failed ({rc})")
+    return dict(T=T, deg=deg)
+
+
+def wtime():
+    return lib().oracle_wtime()

@@ -1,0 +1,343 @@
+/*
+ * CPU oracle for exact triangle counting and clustering coefficients.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do. It shares no code, header or constant with the GPU path.
+ *
+ * What it computes (the paper lists "node clustering coefficient" and
+ * "triangle counting" among SNAP's triadic-closure methods, in the table of
+ * graph manipulation and analytics methods of Section 4; it states no
+ * formula, so the plain graph-theoretic definitions are written out):
+ *
+ *   E     = { {u,v} : (u,v) or (v,u) is an input pair, u != v }   (undirected
+ *           simple graph, Section 3.1: undirected edges, no explicit ids)
+ *   N(v)  = sorted neighbours of v, d(v) = |N(v)|   (Section 5.1: every node
+ *           keeps a sorted vector of adjacent nodes)
+ *   T(v)  = number of pairs {u,w} in N(v) with {u,w} in E
+ *   T     = number of node triples that are pairwise adjacent = sum T(v) / 3
+ *   CC(v) = 2 T(v) / (d(v)(d(v)-1)) for d(v) >= 2, else 0      (FP64)
+ *   avg   = (1/n) * sum over all n ids of CC(v)                 (FP64)
+ *
+ * Counting is the plain node iterator: every triangle is met once at its
+ * lowest-ranked vertex v, through a neighbour u ranked above v and a
+ * neighbour w of u ranked above u that is marked as a neighbour of v.
+ * The rank is either the node id (order_mode 0) or the pair (d(v), v)
+ * (order_mode 1); both must give identical results.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC tricc_oracle.c -o liboracle.so
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+static int cmp_u64(const void* a, const void* b) {
+  const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+  const int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Undirected simple graph as sorted adjacency lists. */
+typedef struct {
+  int64_t n, m;
+  int64_t* off;  /* [n+1] */
+  int32_t* adj;  /* [2m], each row sorted ascending */
+} og_graph;
+
+static void og_free(og_graph* g) {
+  free(g->off);
+  free(g->adj);
+  g->off = NULL;
+  g->adj = NULL;
+}
+
+/* Symmetrise, drop self loops and duplicate pairs. Returns 0, -1 on an id
+ * outside [0,n), -2 on allocation failure. */
+static int og_build(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, og_graph* g) {
+  memset(g, 0, sizeof(*g));
+  g->n = n;
+  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m_raw > 0 ? m_raw : 1));
+  if (!key) return -2;
+  int64_t k = 0;
+  for (int64_t e = 0; e < m_raw; ++e) {
+    int64_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) { free(key); return -1; }
+    if (u == v) continue;
+    int64_t a = u < v ? u : v, b = u < v ? v : u;
+    key[k++] = ((uint64_t)a << 32) | (uint64_t)b;
+  }
+  qsort(key, (size_t)k, sizeof(uint64_t), cmp_u64);
+  int64_t m = 0;
+  for (int64_t i = 0; i < k; ++i)
+    if (i == 0 || key[i] != key[i - 1]) key[m++] = key[i];
+  g->m = m;
+  g->off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  g->adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m > 0 ? 2 * m : 1));
+  if (!g->off || !g->adj) { free(key); og_free(g); return -2; }
+  for (int64_t i = 0; i < m; ++i) {
+    g->off[(key[i] >> 32) + 1]++;
+    g->off[(key[i] & 0xffffffffu) + 1]++;
+  }
+  for (int64_t v = 0; v < n; ++v) g->off[v + 1] += g->off[v];
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!cur) { free(key); og_free(g); return -2; }
+  memcpy(cur, g->off, sizeof(int64_t) * (size_t)n);
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t a = (int64_t)(key[i] >> 32), b = (int64_t)(key[i] & 0xffffffffu);
+    g->adj[cur[a]++] = (int32_t)b;
+    g->adj[cur[b]++] = (int32_t)a;
+  }
+  free(cur);
+  free(key);
+  for (int64_t v = 0; v < n; ++v)
+    qsort(g->adj + g->off[v], (size_t)(g->off[v + 1] - g->off[v]), sizeof(int32_t), cmp_i32);
+  return 0;
+}
+
+/* rank(a) < rank(b) */
+static inline int og_below(const og_graph* g, int order_mode, int64_t a, int64_t b) {
+  if (order_mode == 0) return a < b;
+  int64_t da = g->off[a + 1] - g->off[a], db = g->off[b + 1] - g->off[b];
+  return da < db || (da == db && a < b);
+}
+
+/* Node-iterator count over the whole graph; T must be zeroed. */
+static uint64_t og_count(const og_graph* g, int order_mode, int nthreads, uint64_t* T) {
+  const int64_t n = g->n;
+  uint64_t total = 0;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(+ : total)
+  {
+    int64_t* mark = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t v = 0; v < n; ++v) {
+      for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) mark[g->adj[p]] = v + 1;
+      for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) {
+        const int64_t u = g->adj[p];
+        if (!og_below(g, order_mode, v, u)) continue;
+        for (int64_t q = g->off[u]; q < g->off[u + 1]; ++q) {
+          const int64_t w = g->adj[q];
+          if (!og_below(g, order_mode, u, w)) continue;
+          if (mark[w] != v + 1) continue;
+          /* triangle {v, u, w}, met only here */
+#pragma omp atomic
+          T[v] += 1;
+#pragma omp atomic
+          T[u] += 1;
+#pragma omp atomic
+          T[w] += 1;
+          total += 1;
+        }
+      }
+    }
+    free(mark);
+  }
+  return total;
+}
+
+static void og_cc(const og_graph* g, const uint64_t* T, double* cc, double* avg) {
+  double sum = 0.0;
+  for (int64_t v = 0; v < g->n; ++v) {
+    const int64_t d = g->off[v + 1] - g->off[v];
+    const double c = d >= 2 ? 2.0 * (double)T[v] / ((double)d * (double)(d - 1)) : 0.0;
+    if (cc) cc[v] = c;
+    sum += c;
+  }
+  *avg = g->n > 0 ? sum / (double)g->n : 0.0;
+}
+
+/*
+ * Per-node triangle counts T[n], per-node clustering coefficients cc[n]
+ * (FP64), degrees deg[n], the total triangle count, the average clustering
+ * coefficient over all n ids, and the number of undirected simple edges.
+ * Any output pointer except total/avg/m_out may be NULL.
+ * Returns 0; -1 if an id is outside [0,n); -2 on allocation failure.
+ */
+int oracle_count(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst,
+                 int order_mode, int nthreads, uint64_t* T, double* cc, int64_t* deg,
+                 uint64_t* total, double* avg, int64_t* m_out) {
+  og_graph g;
+  int rc = og_build(n, m_raw, src, dst, &g);
+  if (rc) return rc;
+  uint64_t* t = T ? T : (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  if (!t) { og_free(&g); return -2; }
+  memset(t, 0, sizeof(uint64_t) * (size_t)n);
+  *total = og_count(&g, order_mode, nthreads, t);
+  og_cc(&g, t, cc, avg);
+  if (deg)
+    for (int64_t v = 0; v < n; ++v) deg[v] = g.off[v + 1] - g.off[v];
+  if (m_out) *m_out = g.m;
+  if (!T) free(t);
+  og_free(&g);
+  return 0;
+}
+
+/*
+ * Induced subgraph G[S] (subgraph extraction, Table of analytics methods;
+ * node ids are kept, Section 3.1): the edges of G with both ends in S.
+ * Results are indexed by position in S: T[k], cc[k]; the average is over
+ * the k = |S| nodes. Returns -3 if S holds a repeated or invalid id.
+ */
+int oracle_induced(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst,
+                   int64_t k, const int32_t* S, int nthreads, uint64_t* T, double* cc,
+                   uint64_t* total, double* avg, int64_t* m_out) {
+  int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!pos) return -2;
+  for (int64_t v = 0; v < n; ++v) pos[v] = -1;
+  for (int64_t i = 0; i < k; ++i) {
+    if (S[i] < 0 || S[i] >= n || pos[S[i]] >= 0) { free(pos); return -3; }
+    pos[S[i]] = i;
+  }
+  int64_t cnt = 0;
+  for (int64_t e = 0; e < m_raw; ++e) {
+    if (src[e] < 0 || dst[e] < 0 || src[e] >= n || dst[e] >= n) { free(pos); return -1; }
+    if (pos[src[e]] >= 0 && pos[dst[e]] >= 0) ++cnt;
+  }
+  int32_t* s2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cnt > 0 ? cnt : 1));
+  int32_t* d2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cnt > 0 ? cnt : 1));
+  if (!s2 || !d2) { free(pos); free(s2); free(d2); return -2; }
+  cnt = 0;
+  for (int64_t e = 0; e < m_raw; ++e)
+    if (pos[src[e]] >= 0 && pos[dst[e]] >= 0) {
+      s2[cnt] = (int32_t)pos[src[e]];
+      d2[cnt] = (int32_t)pos[dst[e]];
+      ++cnt;
+    }
+  free(pos);
+  int rc = oracle_count(k, cnt, s2, d2, 0, nthreads, T, cc, NULL, total, avg, m_out);
+  free(s2);
+  free(d2);
+  return rc;
+}
+
+/*
+ * T(s) and d(s) for a few sampled nodes, straight from the definition and
+ * the raw edge list, without building the graph: N(s) is collected from the
+ * pairs that touch s, and T(s) is the number of distinct undirected pairs
+ * {a,b}, a != b, among the input edges with both a and b in N(s).
+ * Samples must be distinct ids in [0,n). Single-threaded.
+ */
+int oracle_sampled(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst,
+                   int64_t ns, const int32_t* samples, uint64_t* T, int64_t* deg) {
+  int rc = 0;
+  int64_t* sid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* noff = (int64_t*)calloc((size_t)ns + 1, sizeof(int64_t));
+  int64_t* inv_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t* nb = NULL;
+  int32_t* inv = NULL;
+  int64_t* poff = NULL;
+  uint64_t* pairs = NULL;
+  if (!sid || !noff || !inv_off) { rc = -2; goto done; }
+  for (int64_t v = 0; v < n; ++v) sid[v] = -1;
+  for (int64_t i = 0; i < ns; ++i) {
+    if (samples[i] < 0 || samples[i] >= n || sid[samples[i]] >= 0) { rc = -3; goto done; }
+    sid[samples[i]] = i;
+  }
+  /* N(s): raw neighbour occurrences, then sort + unique */
+  for (int64_t e = 0; e < m_raw; ++e) {
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) { rc = -1; goto done; }
+    if (u == v) continue;
+    if (sid[u] >= 0) noff[sid[u] + 1]++;
+    if (sid[v] >= 0) noff[sid[v] + 1]++;
+  }
+  for (int64_t i = 0; i < ns; ++i) noff[i + 1] += noff[i];
+  nb = (int32_t*)malloc(sizeof(int32_t) * (size_t)(noff[ns] > 0 ? noff[ns] : 1));
+  if (!nb) { rc = -2; goto done; }
+  {
+    int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    if (!cur) { rc = -2; goto done; }
+    memcpy(cur, noff, sizeof(int64_t) * (size_t)ns);
+    for (int64_t e = 0; e < m_raw; ++e) {
+      const int32_t u = src[e], v = dst[e];
+      if (u == v) continue;
+      if (sid[u] >= 0) nb[cur[sid[u]]++] = v;
+      if (sid[v] >= 0) nb[cur[sid[v]]++] = u;
+    }
+    free(cur);
+  }
+  for (int64_t i = 0; i < ns; ++i) {
+    int32_t* row = nb + noff[i];
+    int64_t len = noff[i + 1] - noff[i], d = 0;
+    qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+    for (int64_t j = 0; j < len; ++j)
+      if (j == 0 || row[j] != row[j - 1]) row[d++] = row[j];
+    deg[i] = d;
+  }
+  /* inverse lists: for node x, the samples whose neighbourhood holds x */
+  for (int64_t i = 0; i < ns; ++i)
+    for (int64_t j = 0; j < deg[i]; ++j) inv_off[nb[noff[i] + j] + 1]++;
+  for (int64_t v = 0; v < n; ++v) inv_off[v + 1] += inv_off[v];
+  inv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(inv_off[n] > 0 ? inv_off[n] : 1));
+  if (!inv) { rc = -2; goto done; }
+  {
+    int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!cur) { rc = -2; goto done; }
+    memcpy(cur, inv_off, sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < ns; ++i)
+      for (int64_t j = 0; j < deg[i]; ++j) {
+        const int32_t x = nb[noff[i] + j];
+        inv[cur[x]++] = (int32_t)i; /* ascending sample index */
+      }
+    free(cur);
+  }
+  /* edges {a,b} with both ends in N(s): count, fill, then sort + unique */
+  poff = (int64_t*)calloc((size_t)ns + 1, sizeof(int64_t));
+  if (!poff) { rc = -2; goto done; }
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t* cur = NULL;
+    if (pass == 1) {
+      for (int64_t i = 0; i < ns; ++i) poff[i + 1] += poff[i];
+      pairs = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(poff[ns] > 0 ? poff[ns] : 1));
+      cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+      if (!pairs || !cur) { free(cur); rc = -2; goto done; }
+      memcpy(cur, poff, sizeof(int64_t) * (size_t)ns);
+    }
+    for (int64_t e = 0; e < m_raw; ++e) {
+      const int64_t a = src[e], b = dst[e];
+      if (a == b) continue;
+      int64_t i = inv_off[a], j = inv_off[b];
+      const int64_t ie = inv_off[a + 1], je = inv_off[b + 1];
+      while (i < ie && j < je) {
+        if (inv[i] < inv[j]) ++i;
+        else if (inv[i] > inv[j]) ++j;
+        else {
+          if (pass == 0) poff[inv[i] + 1]++;
+          else {
+            const uint64_t lo = (uint64_t)(a < b ? a : b), hi = (uint64_t)(a < b ? b : a);
+            pairs[cur[inv[i]]++] = (lo << 32) | hi;
+          }
+          ++i;
+          ++j;
+        }
+      }
+    }
+    free(cur);
+  }
+  for (int64_t i = 0; i < ns; ++i) {
+    uint64_t* row = pairs + poff[i];
+    const int64_t len = poff[i + 1] - poff[i];
+    qsort(row, (size_t)len, sizeof(uint64_t), cmp_u64);
+    uint64_t t = 0;
+    for (int64_t j = 0; j < len; ++j)
+      if (j == 0 || row[j] != row[j - 1]) ++t;
+    T[i] = t;
+  }
+done:
+  free(sid);
+  free(noff);
+  free(inv_off);
+  free(nb);
+  free(inv);
+  free(poff);
+  free(pairs);
+  return rc;
+}
+
+/* Wall-clock seconds (monotonic), for timing the oracle in the benchmark. */
+double oracle_wtime(void) { return omp_get_wtime(); }
