@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-graph path on one MI355X.
+
+One step is one pass of the whole path over the resident edge list: CSR
+build (validate, symmetrise, drop loops, sort, dedup), degree-order
+orientation, binning (a1..a5), the intersection kernels and the clustering
+epilogue (a6..a7). The edge list is generated on the host, copied to HBM
+before the timed region, and stays there.
+
+Prints one JSON line. ``value`` is m / step time, with m the number of
+undirected simple edges (edges/s). ``roofline`` describes the dominant
+intersection kernel (the bin whose kernel takes longest), timed with HIP
+events on the stream it runs on; ``cpu_baseline`` is the CPU oracle timed on
+a bounded sample on this host.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+METRIC = "triangle-count edges/s vs HBM roofline; batched graphs/s; p50/p99 query latency"
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    # name: (scale, edge_factor, seed)
+    "rmat24": (24, 16, 24),
+    "rmat22": (22, 16, 22),
+    "rmat20": (20, 16, 20),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS) + ["er"])
+    ap.add_argument("--cpu-sample-scale", type=int, default=19,
+                    help="R-MAT scale of the CPU oracle's sample (same generator and parameters)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default=None, help="JSON file with bin_limit / bin_variant")
+    ap.add_argument("--out", default=None, help="also append the JSON line to this file")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_1606_07550_amd import inputs as I
+    if name == "er":
+        s, d = I.er(10_000, 100_000, 1)
+        return {"workload": "er", "n": 10_000, "m_raw": 100_000, "seed": 1}, 10_000, s, d
+    scale, ef, seed = WORKLOADS[name]
+    n, s, d = I.rmat(scale, ef, seed=seed)
+    cfg = {"workload": f"rmat{scale}", "scale": scale, "edge_factor": ef, "n": n, "m_raw": int(s.size),
+           "abcd": list(I.RMAT_ABCD), "noise": 0.1, "permuted": True, "seed": seed}
+    return cfg, n, s, d
+
+
+def probe_bandwidth(torch, N, nbytes=2 << 30, reps=5):
+    """Achievable HBM bandwidth (read + write) of a streaming copy."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    N.check(N.lib().tricc_probe_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), nbytes, sp),
+            "probe")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        N.check(N.lib().tricc_probe_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), nbytes,
+                                         sp), "probe")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(scale):
+    import oracle
+    from paper_1606_07550_amd import inputs as I
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    n, s, d = I.rmat(scale, 16, seed=scale)
+    t0 = time.perf_counter()
+    r = oracle.count(n, s, d, order=1, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r["m"] / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"R-MAT scale {scale}, edge factor 16, same generator parameters (n={n}, "
+                      f"m={r['m']}, {r['total']} triangles); whole oracle run (build + count) "
+                      f"{dt:.2f} s on {threads} threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (this path runs on a "
+              "single device; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1606_07550_amd as P
+    from paper_1606_07550_amd import _native as N
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    cfg, n, s, d = make_workload(args.workload)
+    log(f"generated {cfg['workload']} n={n} m_raw={s.size} in {time.perf_counter() - t0:.1f}s")
+    src = torch.from_numpy(s).to(dev)
+    dst = torch.from_numpy(d).to(dev)
+    del s, d
+    tuning = None
+    if args.tuning:
+        with open(args.tuning) as f:
+            tuning = N.Tuning.from_dict(json.load(f))
+    ws = torch.empty(P.workspace_size(n, src.numel()), dtype=torch.uint8, device=dev)
+    T = torch.empty(n, dtype=torch.int64, device=dev)
+    cc = torch.empty(n, dtype=torch.float32, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    avg = torch.empty(1, dtype=torch.float64, device=dev)
+    L = N.lib()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    nb = N.NUM_BINS
+    bin_ms = [0.0] * nb
+    bin_launches = [0] * nb
+
+    def step(timed):
+        tb0 = time.perf_counter()
+        g = P.Graph(n, src, dst, tuning=tuning, workspace=ws)
+        tb1 = time.perf_counter()
+        h = g._h
+        N.check(L.tricc_count_begin(h, ptr(T), sp), "begin")
+        evs = []
+        for b in range(nb):
+            if g.info["bin_count"][b] == 0:
+                continue
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            N.check(L.tricc_count_bin(h, b, ptr(T), sp), "bin")
+            e1.record(stream)
+            evs.append((b, e0, e1))
+        N.check(L.tricc_count_finish(h, ptr(T), ptr(cc), ptr(total), ptr(avg), sp), "finish")
+        if timed:
+            torch.cuda.synchronize()
+            for b, e0, e1 in evs:
+                bin_ms[b] += e0.elapsed_time(e1)
+                bin_launches[b] += 1
+        return g, tb1 - tb0
+
+    for i in range(args.warmup):
+        g, _ = step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    info = g.info
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    build_s = 0.0
+    for i in range(args.steps):
+        g, bs = step(True)
+        build_s += bs
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * t_total / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+
+    # count-only timing (a6..a7) with events
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps)
+    e0.record(stream)
+    for _ in range(reps):
+        g.count(out={"T": T, "cc": cc, "total": total, "avg": avg})
+    e1.record(stream)
+    torch.cuda.synchronize()
+    count_ms = e0.elapsed_time(e1) / reps
+
+    m = info["m"]
+    tri = int(total.cpu().item())
+    # dominant intersection kernel
+    avg_bin_ms = [bin_ms[b] / bin_launches[b] if bin_launches[b] else 0.0 for b in range(nb)]
+    dom = max(range(nb), key=lambda b: avg_bin_ms[b])
+    dom_bytes = 4 * info["bin_list_elems"][dom] + 4 * info["bin_edges"][dom]
+    achieved = dom_bytes / (avg_bin_ms[dom] * 1e-3) / 1e9 if avg_bin_ms[dom] > 0 else 0.0
+    stage_bytes = 4 * info["list_elems"] + 4 * m + 8 * (n + 1) + 12 * n
+    a6_ms = sum(avg_bin_ms)
+    tuning_used = (tuning or P.default_tuning()).as_dict()
+    variant = tuning_used["bin_variant"][dom]
+    bw, _ = probe_bandwidth(torch, N)
+    line = {
+        "metric": METRIC,
+        "value": m / (ms_per_step * 1e-3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": dict(cfg, m=m, triangles=tri, max_deg=info["max_deg"], max_outdeg=info["max_outdeg"],
+                       tuning=tuning_used),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "kernel": f"intersection bin {dom} (variant {variant})",
+            "kernel_ms": avg_bin_ms[dom],
+            "alg_bytes_per_launch": dom_bytes,
+        },
+        "stage_a6": {"ms": a6_ms, "alg_bytes": stage_bytes,
+                     "achieved_GBps": stage_bytes / (a6_ms * 1e-3) / 1e9 if a6_ms else 0.0,
+                     "frac": stage_bytes / (a6_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if a6_ms else 0.0,
+                     "bin_ms": avg_bin_ms, "bin_count": info["bin_count"]},
+        "count_only": {"ms": count_ms, "edges_per_s": m / (count_ms * 1e-3)},
+        "build_ms": 1e3 * build_s / args.steps,
+        "probe_copy_GBps": bw,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on its sample ...")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)
+    else:
+        line["cpu_baseline"] = None
+    text = json.dumps(line)
+    print(text, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(text + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * tricc — exact triangle counting and clustering coefficients on MI355X
+ * (gfx950), C ABI.
+ *
+ * The operation (paper: SNAP, Leskovec and Sosic, ACM TIST 2016; Section 4,
+ * table of graph analytics methods, "triadic closure": node clustering
+ * coefficient and triangle counting). The paper names the methods without
+ * formulas; this library computes the plain definitions:
+ *
+ *   E     = { {u,v} : (u,v) or (v,u) in the input edge list, u != v }
+ *           (undirected simple graph: Section 3.1 — undirected graphs, edges
+ *           as node pairs without ids; duplicates and self loops are dropped)
+ *   N(v)  = neighbours of v, d(v) = |N(v)|  (Section 5.1: a sorted vector of
+ *           adjacent nodes per node)
+ *   T(v)  = number of triangles that contain v
+ *   T     = number of triangles = sum_v T(v) / 3
+ *   CC(v) = 2 T(v) / (d(v) (d(v) - 1)) if d(v) >= 2, else 0   (FP32)
+ *   avg   = (1/n) sum over all n node ids of CC(v)             (FP64)
+ *
+ * Nodes are the dense ids 0..n-1 (Section 3.1 allows any non-negative id;
+ * relabel to a dense range first). Isolated ids are nodes with CC 0 and
+ * count in the average.
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device pointers (HIP device memory, e.g. the
+ *     data of a torch CUDA tensor); h_* are host pointers.
+ *   - The caller owns every buffer it passes and must keep the workspace
+ *     alive while a handle built on it is in use. Handles are owned by the
+ *     library and released with the matching *_free call.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Calls documented
+ *     as asynchronous only enqueue work on it.
+ *   - Return value: a TRICC_* status. No C++ exception crosses the ABI. The
+ *     text of the last error of the calling thread is tricc_last_error().
+ *   - Node ids are int32 in [0, n), n < 2^31 - 1. Counts are uint64.
+ */
+#ifndef TRICC_H_
+#define TRICC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRICC_OK 0
+#define TRICC_EINVAL 1    /* bad argument */
+#define TRICC_ERANGE 2    /* a node id outside [0, n) */
+#define TRICC_ENOMEM 3    /* workspace or memory budget too small */
+#define TRICC_EHIP 4      /* HIP runtime error, see tricc_last_error() */
+#define TRICC_EBUSY 5     /* admission refused: retry later */
+#define TRICC_EOVERFLOW 6 /* a size exceeds what the library supports */
+
+#define TRICC_NUM_BINS 6
+
+/* Degree-binned scheduling of the intersection kernels. A node u with
+ * out-degree d+(u) >= 2 in the degree-ordered DAG goes to the first bin b
+ * with d+(u) <= bin_limit[b] (bins 0..4), else to bin 5; bin b runs the
+ * kernel variant bin_variant[b]. A variant's capacity (the largest d+ it
+ * accepts, tricc_variant_capacity) must cover the largest d+ of its bin. */
+typedef struct tricc_tuning {
+  int32_t bin_limit[TRICC_NUM_BINS - 1];
+  int32_t bin_variant[TRICC_NUM_BINS];
+} tricc_tuning;
+
+typedef struct tricc_graph_info {
+  int32_t n;
+  int64_t m_raw;               /* input pairs */
+  int64_t m;                   /* undirected simple edges (= DAG edges) */
+  int64_t max_deg;             /* max d(v) */
+  int64_t max_outdeg;          /* max d+(v) */
+  int64_t bin_count[TRICC_NUM_BINS];
+  uint64_t list_elems;         /* sum over DAG edges u->w of d+(u) + d+(w) */
+  int64_t large_rows;          /* rows sorted by the chunk + merge path */
+  uint64_t bin_list_elems[TRICC_NUM_BINS]; /* list_elems of the nodes of each bin */
+  int64_t bin_edges[TRICC_NUM_BINS];       /* sum of d+(u) over the nodes of each bin */
+} tricc_graph_info;
+
+typedef struct tricc_graph tricc_graph;
+
+const char* tricc_status_str(int status);
+/* Last error text of the calling thread ("" if none). */
+const char* tricc_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int tricc_version(void);
+
+/* Default tuning (no device access). */
+int tricc_default_tuning(tricc_tuning* out);
+/* Largest d+ a kernel variant accepts; -1 if the variant does not exist. */
+int tricc_variant_capacity(int variant);
+/* Number of kernel variants (valid ids are 0 .. count-1). */
+int tricc_variant_count(void);
+
+/* Bytes of device workspace tricc_graph_build needs for (n, m_raw). */
+int tricc_graph_workspace_size(int32_t n, int64_t m_raw, size_t* bytes);
+
+/*
+ * Steps a1..a5 of the path: validate, symmetrise, drop self loops, sort each
+ * row and drop duplicates (CSR of the simple graph), orient every edge from
+ * the lower to the higher (degree, id) rank (a DAG whose out-degrees are at
+ * most sqrt(2m)), and bin the DAG's nodes for the intersection kernels.
+ *   n        number of nodes (0 <= n < 2^31 - 1)
+ *   m_raw    number of input pairs (0 <= m_raw <= 2^30)
+ *   d_src, d_dst  device int32[m_raw]: pair e is (d_src[e], d_dst[e]);
+ *                 any order, duplicates and self loops allowed
+ *   d_ws, ws_bytes  device workspace of at least tricc_graph_workspace_size
+ *   tuning   NULL for the default
+ * Synchronises `stream` (sizes of later launches are read back).
+ * Errors: TRICC_ERANGE if any id is outside [0, n) (no handle is made),
+ * TRICC_ENOMEM if ws_bytes is too small, TRICC_EINVAL on bad sizes or tuning.
+ */
+int tricc_graph_build(int32_t n, int64_t m_raw, const int32_t* d_src, const int32_t* d_dst,
+                      void* d_ws, size_t ws_bytes, const tricc_tuning* tuning, void* stream,
+                      tricc_graph** out);
+
+int tricc_graph_info_get(const tricc_graph* g, tricc_graph_info* out);
+
+/* Re-bins the graph's nodes with another tuning. Synchronises `stream`. */
+int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream);
+
+/*
+ * Steps a6..a7: per-node triangle counts, clustering coefficients, the total
+ * and the average. Asynchronous on `stream`.
+ *   d_node_tri  device uint64[n] (overwritten)
+ *   d_node_cc   device float[n]
+ *   d_total     device uint64[1]
+ *   d_avg_cc    device double[1]; the FP64 sum is taken in a fixed order,
+ *               so repeated calls give bit-identical results.
+ */
+int tricc_count(tricc_graph* g, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
+                double* d_avg_cc, void* stream);
+
+/*
+ * The three parts of tricc_count, for callers that time or overlap them:
+ * begin zeroes d_node_tri; bin b (0 <= b < TRICC_NUM_BINS) runs the
+ * intersection kernel of one bin (no-op for an empty bin); finish runs the
+ * epilogue (CC, total, average). Issued in that order on one stream they
+ * equal tricc_count. Asynchronous.
+ */
+int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream);
+int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream);
+int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
+                       double* d_avg_cc, void* stream);
+
+/* Streaming copy of `bytes` (a multiple of 16, both pointers 16-byte
+ * aligned) from d_src to d_dst: the reference kernel for achievable HBM
+ * bandwidth and for calibrating memory-traffic counters. Asynchronous. */
+int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
+
+/* Device views of the graph held in the workspace, for inspection:
+ * row v of the simple graph is d_adj[d_off[v] .. d_off[v] + d_deg[v]) in
+ * ascending id order; the DAG out-list of v is d_dcol[d_doff[v] ..
+ * d_doff[v+1]) in ascending id order. Any pointer may be NULL. */
+int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_t** d_deg,
+                       const int32_t** d_adj, const int64_t** d_doff, const int32_t** d_dcol);
+
+void tricc_graph_free(tricc_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRICC_H_ */

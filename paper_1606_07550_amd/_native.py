@@ -1,0 +1,112 @@
+"""ctypes binding of ``libtricc.so`` (the C ABI in ``include/tricc.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library. There is no fallback; if the library is missing the
+import of :func:`lib` raises.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtricc.so")
+
+TRICC_OK = 0
+TRICC_EINVAL = 1
+TRICC_ERANGE = 2
+TRICC_ENOMEM = 3
+TRICC_EHIP = 4
+TRICC_EBUSY = 5
+TRICC_EOVERFLOW = 6
+NUM_BINS = 6
+
+
+class TriccError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status}): {last_error()}")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("bin_limit", ctypes.c_int32 * (NUM_BINS - 1)),
+                ("bin_variant", ctypes.c_int32 * NUM_BINS)]
+
+    def as_dict(self):
+        return {"bin_limit": list(self.bin_limit), "bin_variant": list(self.bin_variant)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for i, v in enumerate(d["bin_limit"]):
+            t.bin_limit[i] = int(v)
+        for i, v in enumerate(d["bin_variant"]):
+            t.bin_variant[i] = int(v)
+        return t
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m_raw", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("max_deg", ctypes.c_int64), ("max_outdeg", ctypes.c_int64),
+                ("bin_count", ctypes.c_int64 * NUM_BINS), ("list_elems", ctypes.c_uint64),
+                ("large_rows", ctypes.c_int64), ("bin_list_elems", ctypes.c_uint64 * NUM_BINS),
+                ("bin_edges", ctypes.c_int64 * NUM_BINS)]
+
+    def as_dict(self):
+        return {"n": self.n, "m_raw": self.m_raw, "m": self.m, "max_deg": self.max_deg,
+                "max_outdeg": self.max_outdeg, "bin_count": list(self.bin_count),
+                "list_elems": int(self.list_elems), "large_rows": self.large_rows,
+                "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges)}
+
+
+_LIB = None
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "tricc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "tricc_last_error": (ctypes.c_char_p, []),
+    "tricc_version": (ctypes.c_int, []),
+    "tricc_default_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+    "tricc_variant_capacity": (ctypes.c_int, [ctypes.c_int]),
+    "tricc_variant_count": (ctypes.c_int, []),
+    "tricc_graph_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "tricc_graph_build": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
+                                         ctypes.POINTER(Tuning), _P, ctypes.POINTER(_P)]),
+    "tricc_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(GraphInfo)]),
+    "tricc_graph_retune": (ctypes.c_int, [_P, ctypes.POINTER(Tuning), _P]),
+    "tricc_count": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_count_begin": (ctypes.c_int, [_P, _P, _P]),
+    "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "tricc_count_finish": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_probe_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "tricc_graph_arrays": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                          ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "tricc_graph_free": (None, [_P]),
+}
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                              "or python -m paper_1606_07550_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def status_str(status):
+    return lib().tricc_status_str(status).decode()
+
+
+def last_error():
+    return lib().tricc_last_error().decode()
+
+
+def check(status, what):
+    if status != TRICC_OK:
+        raise TriccError(status, what)

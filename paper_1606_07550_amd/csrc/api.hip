@@ -1,0 +1,483 @@
+// C ABI of the library: workspace layout, the graph build sequence (steps
+// a1..a5), the count sequence (a6..a7) and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tricc.h"
+#include "kernels.h"
+
+using namespace tricc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(TRICC_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                  __FILE__, __LINE__);                                                     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Header words (int32 unless stated).
+enum : int {
+  kHdrErr = 0,
+  kHdrStats = 4,      // [0] max d, [1] max d+
+  kHdrRowCnt = 8,     // [kNumRowClasses]
+  kHdrBinCnt = 16,    // [kNumBins]
+  kHdrLimits = 24,    // [kNumBins - 1]
+  kHdrListElems = 32, // u64 at byte 128
+  kHdrClsOff = 64,    // int64[kNumRowClasses + 1] at byte 256
+  kHdrBinOff = 96,    // int64[kNumBins + 1] at byte 384
+  kHdrBinElems = 128, // u64[kNumBins] at byte 512
+  kHdrBinEdges = 140, // u64[kNumBins] at byte 560, right after the elems
+};
+constexpr size_t kHdrBytes = 1024;
+
+struct Layout {
+  size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
+      part_T, meta, total;
+  int64_t max_jobs;
+};
+
+Layout make_layout(int64_t n, int64_t m_raw) {
+  Layout L{};
+  size_t p = 0;
+  auto take = [&](size_t bytes) { size_t at = p; p = align_up(p + std::max<size_t>(bytes, 1)); return at; };
+  L.max_jobs = 4 * m_raw / kLargeChunk + 16;
+  L.hdr = take(kHdrBytes);
+  L.raw_off = take(sizeof(int64_t) * (n + 1));
+  L.len = take(sizeof(int32_t) * n);
+  L.deg = take(sizeof(int32_t) * n);
+  L.dplus = take(sizeof(int32_t) * n);
+  L.doff = take(sizeof(int64_t) * (n + 1));
+  L.scan_tmp = take(sizeof(int64_t) * scan_tmp_elems(n + 1));
+  L.rowlist = take(sizeof(int32_t) * n);
+  L.binlist = take(sizeof(int32_t) * n);
+  L.adj = take(sizeof(int32_t) * 2 * m_raw);
+  L.tmp = take(sizeof(int32_t) * 2 * m_raw);
+  L.dcol = take(sizeof(int32_t) * m_raw);
+  L.part_cc = take(sizeof(double) * epilogue_blocks(n));
+  L.part_T = take(sizeof(unsigned long long) * epilogue_blocks(n));
+  L.meta = take(64 * (size_t)L.max_jobs + 4096);
+  L.total = p;
+  return L;
+}
+
+}  // namespace
+
+struct tricc_graph {
+  int32_t n;
+  int64_t m_raw;
+  char* ws;
+  Layout L;
+  hipStream_t stream;
+  tricc_tuning tuning;
+  tricc_graph_info info;
+  int64_t bin_off[kNumBins + 1];
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  int32_t* hdr32() const { return at<int32_t>(L.hdr); }
+};
+
+namespace {
+
+int sync_copy(void* h, const void* d, size_t bytes, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return TRICC_OK;
+}
+
+int upload(void* d, const void* h, size_t bytes, hipStream_t s) {
+  if (!bytes) return TRICC_OK;
+  HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return TRICC_OK;
+}
+
+int check_tuning(const tricc_tuning* t) {
+  for (int b = 0; b < kNumBins; ++b)
+    if (!count_variant_valid(t->bin_variant[b]))
+      return fail(TRICC_EINVAL, "tuning: bin %d has unknown variant %d", b, t->bin_variant[b]);
+  for (int b = 0; b < kNumBins - 1; ++b)
+    if (t->bin_limit[b] < 0) return fail(TRICC_EINVAL, "tuning: negative bin limit");
+  return TRICC_OK;
+}
+
+// Large rows (> kLargeChunk entries): sort chunks in LDS, merge runs pairwise
+// between adj and tmp, then dedup into adj.
+int sort_large_rows(tricc_graph* g, int32_t nl, const int32_t* rows_dev) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  char* meta = g->ws + L.meta;
+  int64_t* d_off = reinterpret_cast<int64_t*>(meta);
+  int32_t* d_len = reinterpret_cast<int32_t*>(meta + align_up(sizeof(int64_t) * nl));
+  HIPCHK(launch_gather_rows(rows_dev, nl, g->at<int64_t>(L.raw_off), g->at<int32_t>(L.len), d_off, d_len, s));
+  std::vector<int64_t> h_off(nl), tmp_beg(nl);
+  std::vector<int32_t> h_len(nl);
+  int rc = sync_copy(h_off.data(), d_off, sizeof(int64_t) * nl, s);
+  if (rc) return rc;
+  if ((rc = sync_copy(h_len.data(), d_len, sizeof(int32_t) * nl, s))) return rc;
+  int64_t acc = 0;
+  int32_t maxL = 0;
+  for (int i = 0; i < nl; ++i) { tmp_beg[i] = acc; acc += h_len[i]; maxL = std::max(maxL, h_len[i]); }
+  int32_t* adj = g->at<int32_t>(L.adj);
+  int32_t* tmp = g->at<int32_t>(L.tmp);
+
+  std::vector<int64_t> cbeg;
+  std::vector<int32_t> clen;
+  for (int i = 0; i < nl; ++i)
+    for (int64_t c = 0; c < h_len[i]; c += kLargeChunk) {
+      cbeg.push_back(h_off[i] + c);
+      clen.push_back((int32_t)std::min<int64_t>(kLargeChunk, h_len[i] - c));
+    }
+  const int64_t nj_max = (int64_t)cbeg.size();
+  if (nj_max > L.max_jobs) return fail(TRICC_EOVERFLOW, "too many large-row chunks");
+  // meta layout for the passes
+  size_t p = 0;
+  auto carve = [&](size_t bytes) { char* at = meta + p; p = align_up(p + bytes); return at; };
+  int64_t* m_a = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * nj_max));
+  int32_t* m_la = reinterpret_cast<int32_t*>(carve(sizeof(int32_t) * nj_max));
+  int32_t* m_lb = reinterpret_cast<int32_t*>(carve(sizeof(int32_t) * nj_max));
+  int64_t* m_o = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * nj_max));
+  int64_t* m_t = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (nj_max + 1)));
+  if ((rc = upload(m_a, cbeg.data(), sizeof(int64_t) * nj_max, s))) return rc;
+  if ((rc = upload(m_la, clen.data(), sizeof(int32_t) * nj_max, s))) return rc;
+  HIPCHK(launch_sort_chunks(m_a, m_la, (int32_t)nj_max, adj, s));
+
+  bool in_adj = true;
+  for (int64_t R = kLargeChunk; R < maxL; R *= 2) {
+    std::vector<int64_t> a, o, t;
+    std::vector<int32_t> la, lb;
+    int64_t tiles = 0;
+    for (int i = 0; i < nl; ++i) {
+      const int64_t Li = h_len[i];
+      const int64_t bin = in_adj ? h_off[i] : tmp_beg[i];
+      const int64_t bout = in_adj ? tmp_beg[i] : h_off[i];
+      for (int64_t k = 0; k < Li; k += 2 * R) {
+        const int64_t A = std::min(R, Li - k);
+        const int64_t B = std::max<int64_t>(0, std::min(R, Li - k - R));
+        a.push_back(bin + k);
+        o.push_back(bout + k);
+        la.push_back((int32_t)A);
+        lb.push_back((int32_t)B);
+        t.push_back(tiles);
+        tiles += (A + B + kMergeTile - 1) / kMergeTile;
+      }
+    }
+    t.push_back(tiles);
+    const int32_t nj = (int32_t)a.size();
+    if ((rc = upload(m_a, a.data(), sizeof(int64_t) * nj, s))) return rc;
+    if ((rc = upload(m_la, la.data(), sizeof(int32_t) * nj, s))) return rc;
+    if ((rc = upload(m_lb, lb.data(), sizeof(int32_t) * nj, s))) return rc;
+    if ((rc = upload(m_o, o.data(), sizeof(int64_t) * nj, s))) return rc;
+    if ((rc = upload(m_t, t.data(), sizeof(int64_t) * (nj + 1), s))) return rc;
+    HIPCHK(launch_merge_pass(m_a, m_la, m_lb, m_o, m_t, nj, tiles, in_adj ? adj : tmp, in_adj ? tmp : adj, s));
+    HIPCHK(hipStreamSynchronize(s));
+    in_adj = !in_adj;
+  }
+  std::vector<int64_t> seg(nl);
+  for (int i = 0; i < nl; ++i) seg[i] = in_adj ? h_off[i] : tmp_beg[i];
+  if ((rc = upload(m_a, seg.data(), sizeof(int64_t) * nl, s))) return rc;
+  HIPCHK(launch_dedup_rows(rows_dev, m_a, nl, g->at<int32_t>(L.len), in_adj ? adj : tmp,
+                           g->at<int64_t>(L.raw_off), adj, g->at<int32_t>(L.deg), s));
+  HIPCHK(hipStreamSynchronize(s));
+  g->info.large_rows = nl;
+  return TRICC_OK;
+}
+
+int bin_nodes(tricc_graph* g) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  int32_t* hdr = g->hdr32();
+  const int32_t n = g->n;
+  int rc = upload(hdr + kHdrLimits, g->tuning.bin_limit, sizeof(int32_t) * (kNumBins - 1), s);
+  if (rc) return rc;
+  HIPCHK(hipMemsetAsync(hdr + kHdrBinCnt, 0, sizeof(int32_t) * kNumBins, s));
+  int64_t* d_bin_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrBinOff * 4);
+  HIPCHK(launch_bin_nodes(0, n, g->at<int32_t>(L.dplus), hdr + kHdrLimits, hdr + kHdrBinCnt, d_bin_off,
+                          g->at<int32_t>(L.binlist), s));
+  int32_t cnt[kNumBins];
+  if ((rc = sync_copy(cnt, hdr + kHdrBinCnt, sizeof(cnt), s))) return rc;
+  g->bin_off[0] = 0;
+  for (int b = 0; b < kNumBins; ++b) g->bin_off[b + 1] = g->bin_off[b] + cnt[b];
+  if ((rc = upload(d_bin_off, g->bin_off, sizeof(g->bin_off), s))) return rc;
+  HIPCHK(hipMemsetAsync(hdr + kHdrBinCnt, 0, sizeof(int32_t) * kNumBins, s));
+  HIPCHK(launch_bin_nodes(1, n, g->at<int32_t>(L.dplus), hdr + kHdrLimits, hdr + kHdrBinCnt, d_bin_off,
+                          g->at<int32_t>(L.binlist), s));
+  unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinElems * 4);
+  unsigned long long* d_edges = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinEdges * 4);
+  HIPCHK(hipMemsetAsync(d_elems, 0, sizeof(unsigned long long) * 2 * kNumBins, s));
+  HIPCHK(launch_bin_elems(g->at<int32_t>(L.binlist), d_bin_off, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
+                          d_elems, d_edges, g->bin_off[kNumBins], s));
+  unsigned long long be[2 * kNumBins];
+  if ((rc = sync_copy(be, d_elems, sizeof(be), s))) return rc;
+  for (int b = 0; b < kNumBins; ++b) {
+    g->info.bin_list_elems[b] = be[b];
+    g->info.bin_edges[b] = (int64_t)be[kNumBins + b];
+  }
+  for (int b = 0; b < kNumBins; ++b) {
+    g->info.bin_count[b] = cnt[b];
+    if (!cnt[b]) continue;
+    int64_t bound = g->info.max_outdeg;
+    if (b < kNumBins - 1) bound = std::min<int64_t>(bound, g->tuning.bin_limit[b]);
+    const int cap = count_variant_capacity(g->tuning.bin_variant[b]);
+    if (cap < bound)
+      return fail(TRICC_EINVAL, "tuning: bin %d holds out-degrees up to %lld but variant %d accepts %d", b,
+                  (long long)bound, g->tuning.bin_variant[b], cap);
+  }
+  return TRICC_OK;
+}
+
+int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  const int32_t n = g->n;
+  const int64_t m_raw = g->m_raw;
+  int32_t* hdr = g->hdr32();
+  int32_t* len = g->at<int32_t>(L.len);
+  int32_t* deg = g->at<int32_t>(L.deg);
+  int64_t* raw_off = g->at<int64_t>(L.raw_off);
+  int64_t* scan_tmp = g->at<int64_t>(L.scan_tmp);
+  int32_t* adj = g->at<int32_t>(L.adj);
+  int rc;
+
+  HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
+  HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
+  // a1: validate + raw degrees
+  HIPCHK(launch_degree_raw(src, dst, m_raw, n, len, hdr + kHdrErr, s));
+  int32_t err = 0;
+  if ((rc = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return rc;
+  if (err) return fail(TRICC_ERANGE, "edge list holds a node id outside [0, %d)", n);
+  // a2: row offsets
+  HIPCHK(launch_scan_i32(len, n, raw_off, scan_tmp, s));
+  HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
+  // a3: scatter (len ends equal to the raw row lengths again), sort, dedup
+  HIPCHK(launch_scatter(src, dst, m_raw, raw_off, len, adj, s));
+  int32_t* rowlist = g->at<int32_t>(L.rowlist);
+  int64_t* d_cls_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrClsOff * 4);
+  HIPCHK(launch_row_classes(0, n, len, deg, hdr + kHdrRowCnt, d_cls_off, rowlist, s));
+  int32_t cnt[kNumRowClasses];
+  if ((rc = sync_copy(cnt, hdr + kHdrRowCnt, sizeof(cnt), s))) return rc;
+  int64_t cls_off[kNumRowClasses + 1];
+  cls_off[0] = 0;
+  for (int c = 0; c < kNumRowClasses; ++c) cls_off[c + 1] = cls_off[c] + cnt[c];
+  if ((rc = upload(d_cls_off, cls_off, sizeof(cls_off), s))) return rc;
+  HIPCHK(hipMemsetAsync(hdr + kHdrRowCnt, 0, sizeof(int32_t) * kNumRowClasses, s));
+  HIPCHK(launch_row_classes(1, n, len, deg, hdr + kHdrRowCnt, d_cls_off, rowlist, s));
+  for (int c = kRow8; c <= kRowLds32k; ++c)
+    HIPCHK(launch_sort_rows(c, rowlist + cls_off[c], cnt[c], raw_off, len, adj, deg, s));
+  g->info.large_rows = 0;
+  if (cnt[kRowLarge] > 0)
+    if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
+  // a4: orientation
+  int32_t* dplus = g->at<int32_t>(L.dplus);
+  int64_t* doff = g->at<int64_t>(L.doff);
+  HIPCHK(launch_outdeg(n, raw_off, deg, adj, dplus, hdr + kHdrStats, s));
+  HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
+  HIPCHK(launch_dag_fill(n, raw_off, deg, adj, doff, g->at<int32_t>(L.dcol), s));
+  unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrListElems * 4);
+  HIPCHK(launch_list_elems(n, doff, g->at<int32_t>(L.dcol), d_elems, s));
+  int32_t stats[2];
+  if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
+  int64_t m = 0;
+  if ((rc = sync_copy(&m, doff + n, sizeof(m), s))) return rc;
+  unsigned long long elems = 0;
+  if ((rc = sync_copy(&elems, d_elems, sizeof(elems), s))) return rc;
+  g->info.n = n;
+  g->info.m_raw = m_raw;
+  g->info.m = m;
+  g->info.max_deg = stats[0];
+  g->info.max_outdeg = stats[1];
+  g->info.list_elems = elems;
+  // a5: binning
+  return bin_nodes(g);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tricc_status_str(int status) {
+  switch (status) {
+    case TRICC_OK: return "ok";
+    case TRICC_EINVAL: return "invalid argument";
+    case TRICC_ERANGE: return "node id out of range";
+    case TRICC_ENOMEM: return "workspace or memory budget too small";
+    case TRICC_EHIP: return "HIP runtime error";
+    case TRICC_EBUSY: return "busy: admission refused";
+    case TRICC_EOVERFLOW: return "size not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* tricc_last_error(void) { return g_err; }
+
+int tricc_version(void) { return 100; }
+
+int tricc_default_tuning(tricc_tuning* out) {
+  if (!out) return fail(TRICC_EINVAL, "null tuning");
+  static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
+  static const int32_t var[kNumBins] = {0, 3, 6, 9, 11, 14};
+  std::memcpy(out->bin_limit, lim, sizeof(lim));
+  std::memcpy(out->bin_variant, var, sizeof(var));
+  return TRICC_OK;
+}
+
+int tricc_variant_capacity(int variant) { return count_variant_capacity(variant); }
+
+int tricc_variant_count(void) {
+  int v = 0;
+  while (count_variant_valid(v)) ++v;
+  return v;
+}
+
+int tricc_graph_workspace_size(int32_t n, int64_t m_raw, size_t* bytes) {
+  if (!bytes) return fail(TRICC_EINVAL, "null bytes");
+  if (n < 0 || n >= 0x7fffffff) return fail(TRICC_EINVAL, "n out of range");
+  if (m_raw < 0) return fail(TRICC_EINVAL, "m_raw negative");
+  if (m_raw > (int64_t(1) << 30)) return fail(TRICC_EOVERFLOW, "m_raw above 2^30");
+  *bytes = make_layout(n, m_raw).total;
+  return TRICC_OK;
+}
+
+int tricc_graph_build(int32_t n, int64_t m_raw, const int32_t* d_src, const int32_t* d_dst, void* d_ws,
+                      size_t ws_bytes, const tricc_tuning* tuning, void* stream, tricc_graph** out) {
+  g_err[0] = 0;
+  if (!out) return fail(TRICC_EINVAL, "null out");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = tricc_graph_workspace_size(n, m_raw, &need);
+  if (rc) return rc;
+  if (m_raw > 0 && (!d_src || !d_dst)) return fail(TRICC_EINVAL, "null edge arrays");
+  if (!d_ws) return fail(TRICC_EINVAL, "null workspace");
+  if (ws_bytes < need) return fail(TRICC_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(TRICC_EINVAL, "workspace not 256-byte aligned");
+  tricc_tuning t;
+  if (tuning) t = *tuning; else tricc_default_tuning(&t);
+  if ((rc = check_tuning(&t))) return rc;
+  tricc_graph* g = new (std::nothrow) tricc_graph();
+  if (!g) return fail(TRICC_ENOMEM, "host allocation failed");
+  g->n = n;
+  g->m_raw = m_raw;
+  g->ws = static_cast<char*>(d_ws);
+  g->L = make_layout(n, m_raw);
+  g->stream = static_cast<hipStream_t>(stream);
+  g->tuning = t;
+  std::memset(&g->info, 0, sizeof(g->info));
+  rc = build_impl(g, d_src, d_dst);
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return TRICC_OK;
+}
+
+int tricc_graph_info_get(const tricc_graph* g, tricc_graph_info* out) {
+  if (!g || !out) return fail(TRICC_EINVAL, "null argument");
+  *out = g->info;
+  return TRICC_OK;
+}
+
+int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream) {
+  if (!g || !tuning) return fail(TRICC_EINVAL, "null argument");
+  int rc = check_tuning(tuning);
+  if (rc) return rc;
+  const tricc_tuning old = g->tuning;
+  g->tuning = *tuning;
+  g->stream = static_cast<hipStream_t>(stream);
+  rc = bin_nodes(g);
+  if (rc) {
+    g->tuning = old;
+    int rc2 = bin_nodes(g);
+    (void)rc2;
+  }
+  return rc;
+}
+
+int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (g->n > 0 && !d_node_tri) return fail(TRICC_EINVAL, "null output");
+  HIPCHK(launch_zero_u64(reinterpret_cast<unsigned long long*>(d_node_tri), g->n, static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
+int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (bin < 0 || bin >= kNumBins) return fail(TRICC_EINVAL, "bin %d out of range", bin);
+  const int32_t count = (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin]);
+  if (count == 0) return TRICC_OK;
+  if (!d_node_tri) return fail(TRICC_EINVAL, "null output");
+  const Layout& L = g->L;
+  BinLaunch bl{g->tuning.bin_variant[bin], g->at<int32_t>(L.binlist) + g->bin_off[bin], count};
+  HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
+                          reinterpret_cast<unsigned long long*>(d_node_tri), static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
+int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
+                       double* d_avg_cc, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if ((g->n > 0 && (!d_node_tri || !d_node_cc)) || !d_total || !d_avg_cc) return fail(TRICC_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = g->L;
+  double* part_cc = g->at<double>(L.part_cc);
+  unsigned long long* part_T = g->at<unsigned long long>(L.part_T);
+  const unsigned long long* T = reinterpret_cast<const unsigned long long*>(d_node_tri);
+  HIPCHK(launch_epilogue(g->n, T, g->at<int32_t>(L.deg), d_node_cc, part_cc, part_T, s));
+  HIPCHK(launch_finish(epilogue_blocks(g->n), g->n, part_cc, part_T,
+                       reinterpret_cast<unsigned long long*>(d_total), d_avg_cc, s));
+  return TRICC_OK;
+}
+
+int tricc_count(tricc_graph* g, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total, double* d_avg_cc,
+                void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if ((g->n > 0 && (!d_node_tri || !d_node_cc)) || !d_total || !d_avg_cc)
+    return fail(TRICC_EINVAL, "null output");
+  int rc = tricc_count_begin(g, d_node_tri, stream);
+  for (int b = 0; b < kNumBins && !rc; ++b) rc = tricc_count_bin(g, b, d_node_tri, stream);
+  if (!rc) rc = tricc_count_finish(g, d_node_tri, d_node_cc, d_total, d_avg_cc, stream);
+  return rc;
+}
+
+int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream) {
+  if (bytes % 16 || reinterpret_cast<uintptr_t>(d_dst) % 16 || reinterpret_cast<uintptr_t>(d_src) % 16)
+    return fail(TRICC_EINVAL, "probe copy needs 16-byte multiples and alignment");
+  if (bytes && (!d_dst || !d_src)) return fail(TRICC_EINVAL, "null pointer");
+  HIPCHK(launch_probe_copy(d_dst, d_src, bytes, static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
+int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_t** d_deg, const int32_t** d_adj,
+                       const int64_t** d_doff, const int32_t** d_dcol) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (d_off) *d_off = g->at<int64_t>(g->L.raw_off);
+  if (d_deg) *d_deg = g->at<int32_t>(g->L.deg);
+  if (d_adj) *d_adj = g->at<int32_t>(g->L.adj);
+  if (d_doff) *d_doff = g->at<int64_t>(g->L.doff);
+  if (d_dcol) *d_dcol = g->at<int32_t>(g->L.dcol);
+  return TRICC_OK;
+}
+
+void tricc_graph_free(tricc_graph* g) { delete g; }
+
+}  // extern "C"

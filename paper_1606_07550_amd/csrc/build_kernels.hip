@@ -1,0 +1,615 @@
+// CSR builder for gfx950: validate + symmetrise + drop self loops (degree
+// count, prefix sum, scatter), a segmented row sort binned by row length
+// with in-place dedup, and the degree-order orientation into a DAG.
+//
+// The paper keeps, per node, a vector of adjacent nodes held in sorted order
+// (Section 5.1); an undirected edge is stored in both endpoints' vectors.
+// Here all vectors live in one array: row v occupies adj[off[v], off[v+1])
+// of which the first deg[v] entries are the sorted, duplicate-free
+// neighbours once the build is done.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace tricc {
+
+namespace {
+
+inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (int64_t)cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// a1: validation and raw degree count (both directions, loops dropped)
+__global__ __launch_bounds__(256) void k_degree_raw(const int32_t* __restrict__ src,
+                                                    const int32_t* __restrict__ dst, int64_t m_raw,
+                                                    int32_t n, int32_t* __restrict__ cnt,
+                                                    int32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_raw; e += stride) {
+    const int32_t u = src[e], v = dst[e];
+    if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) { bad = true; continue; }
+    if (u == v) continue;
+    atomicAdd(&cnt[u], 1);
+    atomicAdd(&cnt[v], 1);
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1);
+}
+
+hipError_t launch_degree_raw(const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t n,
+                             int32_t* cnt, int32_t* err, hipStream_t s) {
+  if (m_raw == 0) return hipSuccess;
+  k_degree_raw<<<grid_for(m_raw, 256 * 8, 1u << 16), 256, 0, s>>>(src, dst, m_raw, n, cnt, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum (reduce, scan of block sums, apply).
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int64_t kScanTile = kScanThreads * kScanItems;
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
+
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Tin* __restrict__ in, int64_t n,
+                                                              int64_t* __restrict__ bsum) {
+  __shared__ int64_t lds[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+    if (i < n) acc += (int64_t)in[i];
+  }
+  const int64_t t = block_sum<int64_t, kScanThreads>(acc, lds);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+// Single block: exclusive scan of nb block sums in place; bsum[nb] = total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int64_t lds[1024 / kWave + 1];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t x = i < nb ? bsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, 1024>(x, lds, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const Tin* __restrict__ in, int64_t n,
+                                                             const int64_t* __restrict__ bsum,
+                                                             int64_t* __restrict__ out, int64_t nb) {
+  __shared__ int64_t lds[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // blocked arrangement: thread t owns kScanItems consecutive elements
+  int64_t v[kScanItems];
+  int64_t acc = 0;
+  const int64_t tb = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = tb + k;
+    v[k] = i < n ? (int64_t)in[i] : 0;
+    acc += v[k];
+  }
+  int64_t tot;
+  int64_t run = bsum[blockIdx.x] + block_excl_scan<int64_t, kScanThreads>(acc, lds, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = tb + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
+}
+
+template <typename Tin>
+static hipError_t scan_impl(const Tin* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) {
+    return hipMemsetAsync(out, 0, sizeof(int64_t), s);
+  }
+  k_scan_reduce<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
+  k_scan_blocks<<<1, 1024, 0, s>>>(tmp, nb);
+  k_scan_apply<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp, out, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_i32(const int32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+  return scan_impl<int32_t>(in, n, out, tmp, s);
+}
+hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+  return scan_impl<int64_t>(in, n, out, tmp, s);
+}
+
+// ---------------------------------------------------------------------------
+// a1/a3: scatter both directions into the row segments (unsorted).
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ src,
+                                                 const int32_t* __restrict__ dst, int64_t m_raw,
+                                                 const int64_t* __restrict__ off,
+                                                 int32_t* __restrict__ cur, int32_t* __restrict__ adj) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_raw; e += stride) {
+    const int32_t u = src[e], v = dst[e];
+    if (u == v) continue;
+    adj[off[u] + atomicAdd(&cur[u], 1)] = v;
+    adj[off[v] + atomicAdd(&cur[v], 1)] = u;
+  }
+}
+
+hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw, const int64_t* off,
+                          int32_t* cur, int32_t* adj, hipStream_t s) {
+  if (m_raw == 0) return hipSuccess;
+  k_scatter<<<grid_for(m_raw, 256 * 8, 1u << 16), 256, 0, s>>>(src, dst, m_raw, off, cur, adj);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row classes by raw length (wave-aggregated appends).
+__device__ __forceinline__ int row_class(int32_t len) {
+  if (len <= 1) return kRowTrivial;
+  if (len <= 8) return kRow8;
+  if (len <= 16) return kRow16;
+  if (len <= 32) return kRow32;
+  if (len <= 64) return kRow64;
+  if (len <= 4096) return kRowLds4k;
+  if (len <= kLargeChunk) return kRowLds32k;
+  return kRowLarge;
+}
+
+// Appends `item` to class `cls` for every active lane; one atomic per class per wave.
+template <int NC>
+__device__ __forceinline__ void wave_append(bool active, int cls, int32_t item, int pass, int32_t* cnt,
+                                            const int64_t* cls_off, int32_t* list) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const uint64_t mask = __ballot(active && cls == c);
+    if (!mask) continue;
+    const int leader = __builtin_ctzll(mask);
+    int32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&cnt[c], (int32_t)__popcll(mask));
+    base = __shfl(base, leader, kWave);
+    if (pass == 1 && active && cls == c) list[cls_off[c] + base + mask_below(mask)] = item;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_classes(int pass, int32_t n, const int32_t* __restrict__ len,
+                                                     int32_t* __restrict__ deg, int32_t* __restrict__ cnt,
+                                                     const int64_t* __restrict__ cls_off,
+                                                     int32_t* __restrict__ list) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    const bool in = v < n;
+    const int32_t L = in ? len[v] : 0;
+    const int c = row_class(L);
+    if (pass == 0 && in && c == kRowTrivial) deg[v] = L;
+    // trivial rows are not listed
+    wave_append<kNumRowClasses>(in && c != kRowTrivial, c, (int32_t)v, pass, cnt, cls_off, list);
+  }
+}
+
+hipError_t launch_row_classes(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* cnt,
+                              const int64_t* cls_off, int32_t* list, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_row_classes<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(pass, n, len, deg, cnt, cls_off, list);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ constexpr uint64_t group_bits() {
+  return G >= 64 ? ~0ull : ((1ull << (G & 63)) - 1);
+}
+
+// Rows of up to G entries: a group of G lanes sorts one row in registers with
+// a bitonic network over __shfl_xor, then compacts the unique values.
+template <int G>
+__global__ __launch_bounds__(256) void k_sort_small(const int32_t* __restrict__ rows, int32_t nrows,
+                                                    const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ len,
+                                                    int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  const int gi = (blockIdx.x * 256 + threadIdx.x) / G;
+  const int g = threadIdx.x % G;
+  const bool active = gi < nrows;
+  int32_t v = 0, L = 0;
+  int64_t beg = 0;
+  int32_t x = kPad;
+  if (active) {
+    v = rows[gi];
+    beg = off[v];
+    L = len[v];
+    if (g < L) x = adj[beg + g];
+  }
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int32_t y = __shfl_xor(x, j, G);
+      const bool up = (g & k) == 0;
+      const bool low = (g & j) == 0;
+      x = (low == up) ? min(x, y) : max(x, y);
+    }
+  }
+  const int32_t prev = __shfl_up(x, 1, G);
+  const bool uniq = active && x != kPad && (g == 0 || x != prev);
+  const uint64_t mask = __ballot(uniq);
+  const int shift = lane_id() & ~(G - 1);
+  const uint64_t gm = (mask >> shift) & group_bits<G>();
+  if (uniq) adj[beg + __popcll(gm & ((1ull << g) - 1))] = x;
+  if (active && g == 0) deg[v] = (int32_t)__popcll(gm);
+}
+
+// Rows of up to CAP entries: one block sorts one row (or one chunk) in LDS
+// with a bitonic network. DEDUP: compact the unique values in place and write
+// deg; otherwise write the sorted chunk back as is.
+template <int CAP, int NT, bool DEDUP>
+__global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ rows,
+                                                 const int64_t* __restrict__ seg_beg,
+                                                 const int32_t* __restrict__ seg_len,
+                                                 const int64_t* __restrict__ off,
+                                                 const int32_t* __restrict__ len,
+                                                 int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  __shared__ int32_t s[CAP];
+  __shared__ int32_t lds_scan[NT / kWave + 1];
+  int32_t v = -1;
+  int64_t beg;
+  int32_t L;
+  if (DEDUP) {
+    v = rows[blockIdx.x];
+    beg = off[v];
+    L = len[v];
+  } else {
+    beg = seg_beg[blockIdx.x];
+    L = seg_len[blockIdx.x];
+  }
+  int P = 2;
+  while (P < L) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += NT) s[i] = i < L ? adj[beg + i] : kPad;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < (P >> 1); i += NT) {
+        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const int hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const int32_t a = s[lo], b = s[hi];
+        if ((a > b) == up) { s[lo] = b; s[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  if (!DEDUP) {
+    for (int i = threadIdx.x; i < L; i += NT) adj[beg + i] = s[i];
+    return;
+  }
+  int32_t carry = 0;
+  for (int base = 0; base < L; base += NT) {
+    const int i = base + threadIdx.x;
+    const int32_t x = i < L ? s[i] : kPad;
+    const bool u = i < L && (i == 0 || x != s[i - 1]);
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, NT>(u ? 1 : 0, lds_scan, &tot);
+    if (u) adj[beg + carry + ex] = x;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) deg[v] = carry;
+}
+
+hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const int64_t* off,
+                            const int32_t* len, int32_t* adj, int32_t* deg, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  switch (cls) {
+    case kRow8: k_sort_small<8><<<grid_for((int64_t)nrows * 8, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow16: k_sort_small<16><<<grid_for((int64_t)nrows * 16, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow32: k_sort_small<32><<<grid_for((int64_t)nrows * 32, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow64: k_sort_small<64><<<grid_for((int64_t)nrows * 64, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRowLds4k: k_sort_lds<4096, 256, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds32k: k_sort_lds<kLargeChunk, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_chunks(const int64_t* chunk_beg, const int32_t* chunk_len, int32_t nchunks,
+                              int32_t* buf, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  k_sort_lds<kLargeChunk, 512, false><<<nchunks, 512, 0, s>>>(nullptr, chunk_beg, chunk_len, nullptr, nullptr, buf, nullptr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Merge pass for large rows (merge path partition, A first on ties).
+constexpr int kMergeItems = 8;
+static_assert(kMergeTile == 256 * kMergeItems, "tile");
+
+__global__ __launch_bounds__(256) void k_merge(const int64_t* __restrict__ a_beg, const int32_t* __restrict__ la_,
+                                               const int32_t* __restrict__ lb_, const int64_t* __restrict__ out_beg,
+                                               const int64_t* __restrict__ tile_off, int32_t njobs,
+                                               const int32_t* __restrict__ in, int32_t* __restrict__ out) {
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = njobs - 1;  // job = last k with tile_off[k] <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_off[mid] <= tile) lo = mid; else hi = mid - 1;
+  }
+  const int job = lo;
+  const int32_t la = la_[job], lb = lb_[job];
+  const int32_t* A = in + a_beg[job];
+  const int32_t* B = A + la;
+  int32_t* O = out + out_beg[job];
+  const int64_t k0l = (tile - tile_off[job]) * (int64_t)kMergeTile + (int64_t)threadIdx.x * kMergeItems;
+  if (k0l >= (int64_t)la + lb) return;
+  const int32_t k0 = (int32_t)k0l;
+  int32_t b0 = max(0, k0 - lb), e0 = min(k0, la);
+  while (b0 < e0) {
+    const int32_t mid = (b0 + e0) >> 1;
+    if (A[mid] <= B[k0 - 1 - mid]) b0 = mid + 1; else e0 = mid;
+  }
+  int32_t i = b0, j = k0 - b0;
+#pragma unroll
+  for (int t = 0; t < kMergeItems; ++t) {
+    if (k0 + t >= la + lb) break;
+    const bool takeA = j >= lb || (i < la && A[i] <= B[j]);
+    O[k0 + t] = takeA ? A[i] : B[j];
+    if (takeA) ++i; else ++j;
+  }
+}
+
+hipError_t launch_merge_pass(const int64_t* a_beg, const int32_t* la, const int32_t* lb,
+                             const int64_t* out_beg, const int64_t* tile_off, int32_t njobs,
+                             int64_t ntiles, const int32_t* buf_in, int32_t* buf_out, hipStream_t s) {
+  if (njobs == 0 || ntiles == 0) return hipSuccess;
+  k_merge<<<(unsigned)ntiles, 256, 0, s>>>(a_beg, la, lb, out_beg, tile_off, njobs, buf_in, buf_out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_dedup_rows(const int32_t* __restrict__ rows,
+                                                    const int64_t* __restrict__ seg_beg,
+                                                    const int32_t* __restrict__ len,
+                                                    const int32_t* __restrict__ sorted,
+                                                    const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  __shared__ int32_t lds_scan[256 / kWave + 1];
+  const int32_t v = rows[blockIdx.x];
+  const int32_t L = len[v];
+  const int32_t* S = sorted + seg_beg[blockIdx.x];
+  int32_t* D = adj + off[v];
+  int32_t carry = 0;
+  for (int base = 0; base < L; base += 256) {
+    const int i = base + threadIdx.x;
+    const int32_t x = i < L ? S[i] : kPad;
+    const bool u = i < L && (i == 0 || x != S[i - 1]);
+    __syncthreads();  // all reads of this chunk precede writes (S may alias D)
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, 256>(u ? 1 : 0, lds_scan, &tot);
+    if (u) D[carry + ex] = x;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) deg[v] = carry;
+}
+
+hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_t nrows,
+                             const int32_t* len, const int32_t* sorted, const int64_t* off,
+                             int32_t* adj, int32_t* deg, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  k_dedup_rows<<<nrows, 256, 0, s>>>(rows, seg_beg, len, sorted, off, adj, deg);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a4: orientation. Wave per row, grid-stride over rows.
+__global__ __launch_bounds__(256) void k_outdeg(int32_t n, const int64_t* __restrict__ off,
+                                                const int32_t* __restrict__ deg,
+                                                const int32_t* __restrict__ adj,
+                                                int32_t* __restrict__ dplus, int32_t* __restrict__ stats) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int l = lane_id();
+  int32_t mx_d = 0, mx_p = 0;
+  for (int64_t v = w0; v < n; v += nwaves) {
+    const int32_t dv = deg[v];
+    const int32_t* row = adj + off[v];
+    int32_t c = 0;
+    for (int32_t b = 0; b < dv; b += kWave) {
+      bool f = false;
+      if (b + l < dv) {
+        const int32_t w = row[b + l];
+        f = rank_below(dv, (int32_t)v, deg[w], w);
+      }
+      c += (int32_t)__popcll(__ballot(f));
+    }
+    if (l == 0) dplus[v] = c;
+    mx_d = max(mx_d, dv);
+    mx_p = max(mx_p, c);
+  }
+  if (l == 0) {
+    atomicMax(&stats[0], mx_d);
+    atomicMax(&stats[1], mx_p);
+  }
+}
+
+hipError_t launch_outdeg(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
+                         int32_t* dplus, int32_t* stats, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_outdeg<<<grid_for((int64_t)n * kWave, 256, 1u << 16), 256, 0, s>>>(n, off, deg, adj, dplus, stats);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_dag_fill(int32_t n, const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ deg,
+                                                  const int32_t* __restrict__ adj,
+                                                  const int64_t* __restrict__ doff,
+                                                  int32_t* __restrict__ dcol) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int l = lane_id();
+  for (int64_t v = w0; v < n; v += nwaves) {
+    const int32_t dv = deg[v];
+    const int32_t* row = adj + off[v];
+    int32_t* out = dcol + doff[v];
+    int32_t c = 0;
+    for (int32_t b = 0; b < dv; b += kWave) {
+      bool f = false;
+      int32_t w = 0;
+      if (b + l < dv) {
+        w = row[b + l];
+        f = rank_below(dv, (int32_t)v, deg[w], w);
+      }
+      const uint64_t mask = __ballot(f);
+      if (f) out[c + mask_below(mask)] = w;
+      c += (int32_t)__popcll(mask);
+    }
+  }
+}
+
+hipError_t launch_dag_fill(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
+                           const int64_t* doff, int32_t* dcol, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_dag_fill<<<grid_for((int64_t)n * kWave, 256, 1u << 16), 256, 0, s>>>(n, off, deg, adj, doff, dcol);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a5: node binning by out-degree.
+__global__ __launch_bounds__(256) void k_bin_nodes(int pass, int32_t n, const int32_t* __restrict__ dplus,
+                                                   const int32_t* __restrict__ limit,
+                                                   int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ bin_off,
+                                                   int32_t* __restrict__ list) {
+  int32_t lim[kNumBins - 1];
+#pragma unroll
+  for (int b = 0; b < kNumBins - 1; ++b) lim[b] = limit[b];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    const int32_t d = v < n ? dplus[v] : 0;
+    int b = kNumBins - 1;
+#pragma unroll
+    for (int q = kNumBins - 2; q >= 0; --q)
+      if (d <= lim[q]) b = q;
+    wave_append<kNumBins>(d >= 2, b, (int32_t)v, pass, cnt, bin_off, list);
+  }
+}
+
+hipError_t launch_bin_nodes(int pass, int32_t n, const int32_t* dplus, const int32_t* limit_dev,
+                            int32_t* cnt, const int64_t* bin_off, int32_t* list, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_bin_nodes<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(pass, n, dplus, limit_dev, cnt, bin_off, list);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sum over DAG edges u->w of d+(u) + d+(w): the list elements a merge-based
+// intersection reads (the algorithmic-bytes measure of the hot loop).
+__global__ __launch_bounds__(256) void k_list_elems(int32_t n, const int64_t* __restrict__ doff,
+                                                    const int32_t* __restrict__ dcol,
+                                                    unsigned long long* __restrict__ out) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int l = lane_id();
+  unsigned long long acc = 0;
+  for (int64_t u = w0; u < n; u += nwaves) {
+    const int64_t b = doff[u], e = doff[u + 1];
+    const unsigned long long du = (unsigned long long)(e - b);
+    for (int64_t p = b + l; p < e; p += kWave) {
+      const int32_t w = dcol[p];
+      acc += du + (unsigned long long)(doff[w + 1] - doff[w]);
+    }
+  }
+  acc = group_sum<unsigned long long, kWave>(acc);
+  if (l == 0 && acc) atomicAdd(out, acc);
+}
+
+hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* out,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_list_elems<<<grid_for((int64_t)n * kWave, 256, 1u << 14), 256, 0, s>>>(n, doff, dcol, out);
+  return hipGetLastError();
+}
+
+// Wave per listed node; the node's bin is found from bin_off.
+__global__ __launch_bounds__(256) void k_bin_elems(const int32_t* __restrict__ list,
+                                                   const int64_t* __restrict__ bin_off,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int32_t* __restrict__ dcol,
+                                                   unsigned long long* __restrict__ elems,
+                                                   unsigned long long* __restrict__ edges, int64_t total) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int l = lane_id();
+  unsigned long long acc[kNumBins] = {}, eacc[kNumBins] = {};
+  for (int64_t i = w0; i < total; i += nwaves) {
+    int b = 0;
+    while (b < kNumBins - 1 && i >= bin_off[b + 1]) ++b;
+    const int32_t u = list[i];
+    const int64_t beg = doff[u], end = doff[u + 1];
+    const unsigned long long du = (unsigned long long)(end - beg);
+    unsigned long long a = 0;
+    for (int64_t p = beg + l; p < end; p += kWave) {
+      const int32_t w = dcol[p];
+      a += du + (unsigned long long)(doff[w + 1] - doff[w]);
+    }
+#pragma unroll
+    for (int q = 0; q < kNumBins; ++q)
+      if (q == b) { acc[q] += a; eacc[q] += (l == 0) ? du : 0ull; }
+  }
+#pragma unroll
+  for (int q = 0; q < kNumBins; ++q) {
+    const unsigned long long a = group_sum<unsigned long long, kWave>(acc[q]);
+    const unsigned long long e = group_sum<unsigned long long, kWave>(eacc[q]);
+    if (l == 0 && a) atomicAdd(&elems[q], a);
+    if (l == 0 && e) atomicAdd(&edges[q], e);
+  }
+}
+
+hipError_t launch_bin_elems(const int32_t* list, const int64_t* bin_off, const int64_t* doff,
+                            const int32_t* dcol, unsigned long long* elems, unsigned long long* edges,
+                            int64_t total_listed, hipStream_t s) {
+  if (total_listed == 0) return hipSuccess;
+  k_bin_elems<<<grid_for(total_listed * kWave, 256, 1u << 14), 256, 0, s>>>(list, bin_off, doff, dcol, elems,
+                                                                            edges, total_listed);
+  return hipGetLastError();
+}
+
+// Streaming copy, 16 bytes per lane per iteration (the bandwidth probe).
+__global__ __launch_bounds__(256) void k_probe_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                    int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  k_probe_copy<<<grid_for(n16, 256 * 4, 8192), 256, 0, s>>>(static_cast<uint4*>(dst),
+                                                            static_cast<const uint4*>(src), n16);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_rows(const int32_t* __restrict__ rows, int32_t nr, const int64_t* __restrict__ off,
+                              const int32_t* __restrict__ len, int64_t* __restrict__ out_off,
+                              int32_t* __restrict__ out_len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nr) { out_off[i] = off[rows[i]]; out_len[i] = len[rows[i]]; }
+}
+
+hipError_t launch_gather_rows(const int32_t* rows, int32_t nr, const int64_t* off, const int32_t* len,
+                              int64_t* out_off, int32_t* out_len, hipStream_t s) {
+  if (nr == 0) return hipSuccess;
+  k_gather_rows<<<(nr + 255) / 256, 256, 0, s>>>(rows, nr, off, len, out_off, out_len);
+  return hipGetLastError();
+}
+
+}  // namespace tricc

@@ -1,0 +1,97 @@
+// Internal launchers of the gfx950 kernels (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tricc {
+
+// ---- CSR build (symmetrise, drop loops, sort rows, dedup) ----------------
+// Row length classes used by the segmented row sort.
+enum RowClass : int {
+  kRowTrivial = 0,  // len <= 1
+  kRow8, kRow16, kRow32, kRow64,  // register bitonic sort by a lane group
+  kRowLds4k,   // <= 4096, LDS bitonic sort, 256 threads
+  kRowLds32k,  // <= 32768, LDS bitonic sort, 512 threads
+  kRowLarge,   // > 32768: chunk sort + merge passes
+  kNumRowClasses
+};
+constexpr int kLargeChunk = 32768;
+
+hipError_t launch_degree_raw(const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t n,
+                             int32_t* cnt, int32_t* err, hipStream_t s);
+// out[0..n] = exclusive prefix sum of in[0..n), out[n] = total.
+// `tmp` needs scan_tmp_elems(n) int64 slots.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan_i32(const int32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw, const int64_t* off,
+                          int32_t* cur, int32_t* adj, hipStream_t s);
+// Classifies rows by raw length; pass 0 counts into cnt[kNumRowClasses],
+// pass 1 appends row ids at list[cls_off[c] + cursor[c]++]. Rows of length
+// <= 1 get deg = len directly.
+hipError_t launch_row_classes(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* cnt,
+                              const int64_t* cls_off, int32_t* list, hipStream_t s);
+// Sorts + dedups rows of one class in place; writes deg.
+hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const int64_t* off,
+                            const int32_t* len, int32_t* adj, int32_t* deg, hipStream_t s);
+// Large rows: sort chunks of kLargeChunk in place (no dedup).
+hipError_t launch_sort_chunks(const int64_t* chunk_beg, const int32_t* chunk_len, int32_t nchunks,
+                              int32_t* buf, hipStream_t s);
+// One merge pass: job k merges buf_in[a_beg, a_beg+la) with
+// buf_in[a_beg+la, a_beg+la+lb) into buf_out[out_beg, ...). tile_off is the
+// prefix of per-job tiles of kMergeTile outputs.
+constexpr int kMergeTile = 2048;
+hipError_t launch_merge_pass(const int64_t* a_beg, const int32_t* la, const int32_t* lb,
+                             const int64_t* out_beg, const int64_t* tile_off, int32_t njobs,
+                             int64_t ntiles, const int32_t* buf_in, int32_t* buf_out, hipStream_t s);
+// Dedups sorted large rows from `sorted` (segment seg_beg[i]) into adj at
+// off[row[i]], writes deg.
+hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_t nrows,
+                             const int32_t* len, const int32_t* sorted, const int64_t* off,
+                             int32_t* adj, int32_t* deg, hipStream_t s);
+
+// ---- Degree-order orientation --------------------------------------------
+// dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|; stats[0] = max d, stats[1] = max d+.
+hipError_t launch_outdeg(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
+                         int32_t* dplus, int32_t* stats, hipStream_t s);
+// Writes N+(v) (ascending id) at dcol[doff[v] ...].
+hipError_t launch_dag_fill(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
+                           const int64_t* doff, int32_t* dcol, hipStream_t s);
+
+hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* out,
+                             hipStream_t s);
+hipError_t launch_gather_rows(const int32_t* rows, int32_t nr, const int64_t* off, const int32_t* len,
+                              int64_t* out_off, int32_t* out_len, hipStream_t s);
+
+// ---- Work binning for the intersection kernels ---------------------------
+constexpr int kNumBins = 6;
+// Node u with d+(u) >= 2 goes to the first bin b with d+(u) <= limit[b];
+// bin kNumBins-1 takes the rest. Two passes like launch_row_classes.
+hipError_t launch_bin_nodes(int pass, int32_t n, const int32_t* dplus, const int32_t* limit_dev,
+                            int32_t* cnt, const int64_t* bin_off, int32_t* list, hipStream_t s);
+
+// per-bin sums of d+(u) + d+(w) over the bin's DAG edges, and of d+(u)
+hipError_t launch_bin_elems(const int32_t* list, const int64_t* bin_off, const int64_t* doff,
+                            const int32_t* dcol, unsigned long long* elems, unsigned long long* edges,
+                            int64_t total_listed, hipStream_t s);
+hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// ---- Intersection and epilogue --------------------------------------------
+struct BinLaunch {
+  int variant;  // kernel variant id (see count_kernels.hip)
+  const int32_t* list;
+  int32_t count;
+};
+hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
+                            unsigned long long* T, hipStream_t s);
+int count_variant_capacity(int variant);  // max d+(u) a variant accepts
+int count_variant_valid(int variant);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// cc[v] (fp32) from T and deg; block partials of the FP64 ratio sum and of T.
+int64_t epilogue_blocks(int64_t n);
+hipError_t launch_epilogue(int32_t n, const unsigned long long* T, const int32_t* deg, float* cc,
+                           double* part_cc, unsigned long long* part_T, hipStream_t s);
+hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const unsigned long long* part_T,
+                         unsigned long long* total, double* avg, hipStream_t s);
+
+}  // namespace tricc

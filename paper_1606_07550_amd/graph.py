@@ -1,0 +1,151 @@
+"""Python face of the single-graph path: build a graph from an edge list held
+in device memory, then count triangles and clustering coefficients.
+
+PyTorch supplies the device memory (tensors) and the stream; all computation
+runs in ``libtricc.so``.
+"""
+import ctypes
+
+import torch
+
+from . import _native as N
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def default_tuning():
+    t = N.Tuning()
+    N.check(N.lib().tricc_default_tuning(ctypes.byref(t)), "tricc_default_tuning")
+    return t
+
+
+def variant_capacity(v):
+    return N.lib().tricc_variant_capacity(v)
+
+
+def variant_count():
+    return N.lib().tricc_variant_count()
+
+
+def workspace_size(n, m_raw):
+    b = ctypes.c_size_t()
+    N.check(N.lib().tricc_graph_workspace_size(n, m_raw, ctypes.byref(b)), "tricc_graph_workspace_size")
+    return b.value
+
+
+def _as_tuning(tuning):
+    if tuning is None:
+        return None
+    if isinstance(tuning, dict):
+        return N.Tuning.from_dict(tuning)
+    return tuning
+
+
+class Graph:
+    """A graph built on the GPU from ``n`` and int32 device edge arrays.
+
+    Steps a1..a5 (validate, symmetrise, dedup, drop loops, sort rows, orient
+    by (degree, id), bin) run in the constructor, which synchronises the
+    stream. :meth:`count` runs the intersection kernels and the epilogue
+    asynchronously."""
+
+    def __init__(self, n, src, dst, tuning=None, stream=None, workspace=None):
+        if src.dtype != torch.int32 or dst.dtype != torch.int32:
+            raise TypeError("edge arrays must be int32")
+        if not (src.is_cuda and dst.is_cuda):
+            raise TypeError("edge arrays must be device tensors")
+        if src.shape != dst.shape or src.dim() != 1:
+            raise ValueError("src and dst must be 1-D of equal length")
+        src = src.contiguous()
+        dst = dst.contiguous()
+        self.n = int(n)
+        self.m_raw = int(src.numel())
+        self.device = src.device
+        need = workspace_size(self.n, self.m_raw)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.ws = workspace
+        self._h = ctypes.c_void_p()
+        t = _as_tuning(tuning)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_build(self.n, self.m_raw, _ptr(src), _ptr(dst), _ptr(self.ws),
+                                           self.ws.numel(), ctypes.byref(t) if t is not None else None,
+                                           _stream_ptr(stream), ctypes.byref(self._h))
+        N.check(rc, "tricc_graph_build")
+
+    @property
+    def info(self):
+        i = N.GraphInfo()
+        N.check(N.lib().tricc_graph_info_get(self._h, ctypes.byref(i)), "tricc_graph_info_get")
+        return i.as_dict()
+
+    def retune(self, tuning, stream=None):
+        t = _as_tuning(tuning)
+        N.check(N.lib().tricc_graph_retune(self._h, ctypes.byref(t), _stream_ptr(stream)), "tricc_graph_retune")
+
+    def count(self, out=None, stream=None):
+        """Returns dict(T=uint64[n] as int64 tensor, cc=float32[n],
+        total=uint64[1] as int64 tensor, avg=float64[1]), on the device."""
+        n = self.n
+        if out is None:
+            out = {
+                "T": torch.empty(max(n, 0), dtype=torch.int64, device=self.device),
+                "cc": torch.empty(max(n, 0), dtype=torch.float32, device=self.device),
+                "total": torch.empty(1, dtype=torch.int64, device=self.device),
+                "avg": torch.empty(1, dtype=torch.float64, device=self.device),
+            }
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_count(self._h, _ptr(out["T"]), _ptr(out["cc"]), _ptr(out["total"]),
+                                     _ptr(out["avg"]), _stream_ptr(stream))
+        N.check(rc, "tricc_count")
+        return out
+
+    def arrays(self):
+        """Device views (slices of the workspace) of the simple graph and DAG:
+        off[n+1] int64, deg[n] int32, adj int32, doff[n+1] int64, dcol[m] int32."""
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        N.check(N.lib().tricc_graph_arrays(self._h, *[ctypes.byref(p) for p in ptrs]), "tricc_graph_arrays")
+        base = self.ws.data_ptr()
+        n = self.n
+        info = self.info
+
+        def view(p, dtype, count):
+            off = p.value - base
+            esz = torch.empty((), dtype=dtype).element_size()
+            return self.ws[off:off + count * esz].view(dtype)
+
+        return {
+            "off": view(ptrs[0], torch.int64, n + 1),
+            "deg": view(ptrs[1], torch.int32, n),
+            "adj": view(ptrs[2], torch.int32, 2 * self.m_raw),
+            "doff": view(ptrs[3], torch.int64, n + 1),
+            "dcol": view(ptrs[4], torch.int32, info["m"]),
+        }
+
+    def close(self):
+        if self._h:
+            N.lib().tricc_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count(n, src, dst, tuning=None, stream=None):
+    """One pass of the whole single-graph path: build + count."""
+    g = Graph(n, src, dst, tuning=tuning, stream=stream)
+    out = g.count(stream=stream)
+    out["info"] = g.info
+    out["graph"] = g
+    return out

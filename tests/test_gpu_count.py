@@ -1,0 +1,260 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Counts are compared bit for bit; FP32 clustering coefficients within 1e-6
+relative of the FP64 oracle with exact zeros; the FP64 average within 1e-6
+relative (it is summed in FP64, so it is in fact much closer).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1606_07550_amd as P
+from paper_1606_07550_amd import _native as N
+from paper_1606_07550_amd import inputs as I
+from paper_1606_07550_amd.inputs import fixtures as F
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CC_RTOL = 1e-6
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+
+
+def gpu_count(n, s, d, tuning=None):
+    print(f"[gpu_count] n={n} m_raw={len(s)} tuning={tuning}", flush=True)
+    g = P.Graph(n, to_dev(s), to_dev(d), tuning=tuning)
+    out = g.count()
+    torch.cuda.synchronize()
+    r = {
+        "T": out["T"].cpu().numpy().view(np.uint64),
+        "cc": out["cc"].cpu().numpy(),
+        "total": int(out["total"].cpu().numpy().view(np.uint64)[0]),
+        "avg": float(out["avg"].cpu().item()),
+        "info": g.info,
+        "graph": g,
+    }
+    return r
+
+
+def check_against(r, ref, n):
+    np.testing.assert_array_equal(r["T"], ref["T"])
+    assert r["total"] == ref["total"]
+    cc_ref = ref["cc"]
+    np.testing.assert_allclose(r["cc"].astype(np.float64), cc_ref, rtol=CC_RTOL, atol=0)
+    assert np.array_equal(r["cc"] == 0, cc_ref == 0)
+    if n:
+        assert abs(r["avg"] - ref["avg"]) <= CC_RTOL * abs(ref["avg"])
+    else:
+        assert r["avg"] == 0.0
+    assert r["info"]["m"] == ref["m"]
+
+
+def parity(n, s, d, tuning=None, order=1):
+    ref = oracle.count(n, s, d, order=order)
+    r = gpu_count(n, s, d, tuning)
+    check_against(r, ref, n)
+    return r, ref
+
+
+FIXTURES = {
+    "K1": F.complete(1), "K2": F.complete(2), "K3": F.complete(3), "K7": F.complete(7), "K40": F.complete(40),
+    "ring3": F.ring(3), "ring50": F.ring(50), "star100": F.star(100), "path30": F.path(30),
+    "tree500": F.random_tree(500, 3), "grid": F.grid(20, 31), "Kab": F.complete_bipartite(9, 13),
+    "bip": F.random_bipartite(80, 70, 0.2, 4), "wheel33": F.wheel(33), "windmill12": F.windmill(12),
+    "lattice": F.ring_lattice(301, 10),
+    "union": F.disjoint_union(F.complete(9), F.wheel(7), F.ring(10), F.windmill(4)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_fixture_families(name):
+    parity(*FIXTURES[name])
+
+
+def test_golden_small_graphs():
+    import json
+    import os
+    from fractions import Fraction
+    with open(os.path.join(os.path.dirname(__file__), "golden", "small_graphs.json")) as f:
+        data = json.load(f)
+    for g in data["graphs"]:
+        e = np.array(g["edges"], dtype=np.int32).reshape(-1, 2)
+        r = gpu_count(g["n"], e[:, 0], e[:, 1])
+        assert r["total"] == g["total"]
+        np.testing.assert_array_equal(r["T"], np.array(g["T"], dtype=np.uint64))
+        np.testing.assert_allclose(r["cc"], [float(Fraction(c)) for c in g["cc"]], rtol=CC_RTOL)
+        assert r["avg"] == pytest.approx(float(Fraction(g["avg"])), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_er_config(seed):
+    """G(n=10^4, m=10^5): the small configuration."""
+    s, d = I.er(10_000, 100_000, seed)
+    parity(10_000, s, d)
+
+
+@pytest.mark.parametrize("scale", [6, 9, 12, 14, 16])
+def test_rmat_small_scales(scale):
+    n, s, d = I.rmat(scale, 16, seed=100 + scale)
+    parity(n, s, d)
+
+
+@pytest.mark.parametrize("n,k", [(200, 2), (5000, 7), (30000, 16)])
+def test_ba(n, k):
+    s, d = I.ba(n, k, n + k)
+    parity(n, s, d)
+
+
+def test_edge_cases():
+    e = np.zeros(0, np.int32)
+    for n in (0, 1, 5):
+        r = gpu_count(n, e, e)
+        assert r["total"] == 0 and r["avg"] == 0.0 and r["T"].size == n and not np.any(r["T"])
+    loops = np.arange(6, dtype=np.int32)
+    r = gpu_count(6, loops, loops)
+    assert r["info"]["m"] == 0 and r["total"] == 0
+    parity(2, np.array([0], np.int32), np.array([1], np.int32))
+    parity(3, np.array([0, 1, 2, 0, 0], np.int32), np.array([1, 2, 0, 1, 1], np.int32))
+
+
+def test_out_of_range_ids_are_rejected():
+    for bad in ([0, 5], [0, -1], [2**31 - 1, 0]):
+        with pytest.raises(N.TriccError) as ei:
+            P.Graph(5, to_dev(np.array(bad, np.int32)), to_dev(np.array([1, 2], np.int32)))
+        assert ei.value.status == N.TRICC_ERANGE
+
+
+def test_input_order_and_noise_invariance():
+    n, s, d = I.rmat(13, 16, seed=7)
+    r0, _ = parity(n, s, d)
+    r1 = gpu_count(*F.messy(n, s, d, seed=8))
+    np.testing.assert_array_equal(r1["T"], r0["T"])
+    np.testing.assert_array_equal(r1["cc"], r0["cc"])
+    assert r1["avg"] == r0["avg"]
+    n2, s2, d2, perm = F.relabel(n, s, d, seed=9)
+    r2 = gpu_count(n2, s2, d2)
+    np.testing.assert_array_equal(r2["T"][perm], r0["T"])
+
+
+def test_repeatable_bit_identical():
+    n, s, d = I.rmat(14, 16, seed=11)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    outs = []
+    for _ in range(3):
+        o = g.count()
+        torch.cuda.synchronize()
+        outs.append({k: v.clone().cpu() for k, v in o.items()})
+    for o in outs[1:]:
+        for k in o:
+            assert torch.equal(o[k], outs[0][k]), k
+
+
+def test_csr_and_dag_structure():
+    n, s, d = I.rmat(12, 16, seed=13)
+    ref = oracle.count(n, s, d, order=1)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    A = {k: v.cpu().numpy() for k, v in g.arrays().items()}
+    off, deg, adj = A["off"], A["deg"], A["adj"]
+    np.testing.assert_array_equal(deg, ref["deg"])
+    rows = [adj[off[v]:off[v] + deg[v]] for v in range(n)]
+    for v in range(n):
+        r = rows[v]
+        assert np.all(np.diff(r) > 0)  # sorted, unique
+        assert not np.any(r == v)
+    # symmetric
+    pairs = {(v, int(w)) for v in range(n) for w in rows[v]}
+    assert all((w, v) in pairs for (v, w) in pairs)
+    doff, dcol = A["doff"], A["dcol"]
+    m = ref["m"]
+    assert doff[-1] == m
+    dplus = np.diff(doff)
+    assert dplus.max() <= math.sqrt(2 * m)
+    for v in range(n):
+        out = dcol[doff[v]:doff[v + 1]]
+        assert np.all(np.diff(out) > 0)
+        assert all((deg[v], v) < (deg[w], w) for w in out.tolist())
+
+
+def _tuning_all_to(variant, limit_bins=None):
+    t = P.default_tuning()
+    for b in range(N.NUM_BINS - 1):
+        t.bin_limit[b] = 0
+    for b in range(N.NUM_BINS):
+        t.bin_variant[b] = variant
+    return t
+
+
+@pytest.mark.parametrize("variant", list(range(15)))
+def test_each_variant_owns_every_node(variant):
+    """Force one kernel variant to own every node of the DAG (all bins point
+    to it) on graphs whose out-degrees it can hold."""
+    cap = P.variant_capacity(variant)
+    cases = [F.disjoint_union(F.complete(min(cap + 1, 18) if cap < 1000 else 40), F.wheel(20), F.windmill(6))]
+    s, d = I.er(3000, 12000, variant + 1)
+    cases.append((3000, s, d))  # max d+ stays small
+    if cap >= 64:
+        n, s, d = I.rmat(13, 16, seed=200 + variant)
+        cases.append((n, s, d))
+    if cap >= 300:
+        n, s, d = I.rmat(16, 16, seed=300 + variant)
+        cases.append((n, s, d))
+    if cap >= 4096 or cap > 10**6:
+        cases.append(F.complete(300))
+    for n, s, d in cases:
+        ref = oracle.count(n, s, d, order=1)
+        r = gpu_count(n, s, d)
+        if r["info"]["max_outdeg"] > cap:
+            continue
+        r = gpu_count(n, s, d, tuning=_tuning_all_to(variant))
+        assert sum(r["info"]["bin_count"]) == r["info"]["bin_count"][N.NUM_BINS - 1]
+        check_against(r, ref, n)
+
+
+def test_retune_matches():
+    n, s, d = I.rmat(14, 16, seed=17)
+    ref = oracle.count(n, s, d, order=1)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    for var in (2, 5, 8, 14):
+        g.retune(_tuning_all_to(var) if P.variant_capacity(var) >= g.info["max_outdeg"] else P.default_tuning())
+        o = g.count()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o["T"].cpu().numpy().view(np.uint64), ref["T"])
+
+
+def test_tuning_capacity_violation_is_rejected():
+    n, s, d = I.rmat(12, 16, seed=19)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    assert g.info["max_outdeg"] > 16
+    with pytest.raises(N.TriccError) as ei:
+        g.retune(_tuning_all_to(0))
+    assert ei.value.status == N.TRICC_EINVAL
+    # the previous tuning stays in force
+    o = g.count()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o["T"].cpu().numpy().view(np.uint64), oracle.count(n, s, d)["T"])
+
+
+def test_long_rows_take_every_sort_path():
+    """A hub row above the LDS capacity (chunk sort + merge passes), rows in
+    the 4k..32k LDS class, and heavy duplication inside long rows."""
+    rng = np.random.default_rng(23)
+    n = 120_000
+    hub_leaves = rng.choice(np.arange(1, n), size=100_000, replace=False)
+    s = [np.zeros(100_000, np.int64), np.full(9000, 1, np.int64), np.full(20000, 2, np.int64)]
+    d = [hub_leaves, rng.integers(3, n, 9000), rng.integers(3, 3000, 20000)]  # node 2: many duplicates
+    # duplicate part of the hub row, and random edges among leaves
+    s.append(np.zeros(30_000, np.int64))
+    d.append(hub_leaves[:30_000])
+    s.append(rng.integers(1, n, 200_000))
+    d.append(rng.integers(1, n, 200_000))
+    s = np.concatenate(s).astype(np.int32)
+    d = np.concatenate(d).astype(np.int32)
+    perm = rng.permutation(s.size)
+    r, ref = parity(n, s[perm], d[perm])
+    assert r["info"]["large_rows"] >= 1
+    assert r["info"]["max_deg"] >= 100_000
