@@ -74,7 +74,7 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.binlist = take(sizeof(int32_t) * n);
   L.adj = take(sizeof(int32_t) * 2 * m_raw);
   L.tmp = take(sizeof(int32_t) * 2 * m_raw);
-  L.dcol = take(sizeof(int32_t) * m_raw);
+  L.dcol = take(sizeof(int32_t) * m_raw + 16);  // 16-byte loads may run 3 ids past the end
   L.part_cc = take(sizeof(double) * epilogue_blocks(n));
   L.part_T = take(sizeof(unsigned long long) * epilogue_blocks(n));
   L.meta = take(64 * (size_t)L.max_jobs + 4096);
@@ -335,7 +335,7 @@ int tricc_version(void) { return 100; }
 int tricc_default_tuning(tricc_tuning* out) {
   if (!out) return fail(TRICC_EINVAL, "null tuning");
   static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {0, 3, 6, 9, 11, 14};
+  static const int32_t var[kNumBins] = {17, 22, 23, 24, 21, 25};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   return TRICC_OK;

@@ -30,10 +30,279 @@ __device__ __forceinline__ void group_sync() {
   else wave_sync();
 }
 
+// Open-addressing table of NB buckets of 4 int32 keys (-1 = empty), probed
+// bucket by bucket: a lookup is normally one 16-byte LDS read.
+template <int NB>
+__device__ __forceinline__ int bucket_insert(int32_t* K, int32_t x) {
+  uint32_t b = hash_slot(x, __builtin_ctz(NB));
+  while (true) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (atomicCAS(&K[4 * b + j], -1, x) == -1) return (int)(4 * b + j);
+    b = (b + 1) & (NB - 1);
+  }
+}
+
+// Slot of x, or -1. `first` is the already-loaded bucket hash_slot(x).
+template <int NB>
+__device__ __forceinline__ int bucket_match(const int4* Kb, int32_t x, uint32_t b, int4 q) {
+  while (true) {
+    if (q.x == x) return (int)(4 * b);
+    if (q.y == x) return (int)(4 * b + 1);
+    if (q.z == x) return (int)(4 * b + 2);
+    if (q.w == x) return (int)(4 * b + 3);
+    if (q.w < 0) return -1;  // keys fill a bucket in order: an empty last slot ends the chain
+    b = (b + 1) & (NB - 1);
+    q = Kb[b];
+  }
+}
+
 template <int SLOTS>
 __device__ __forceinline__ int table_find(const int32_t* K, int32_t x) {
-  constexpr int bits = __builtin_ctz(SLOTS);
-  uint32_t h = hash_slot(x, bits);
+  constexpr int NB = SLOTS / 4;
+  const int4* Kb = reinterpret_cast<const int4*>(K);
+  const uint32_t b = hash_slot(x, __builtin_ctz(NB));
+  return bucket_match<NB>(Kb, x, b, Kb[b]);
+}
+
+}  // namespace
+
+// NT threads per block; groups of G lanes (G divides NT, or G == NT) each own
+// one node u; sub-groups of SG lanes stream one N+(w) each, in 16-byte chunks,
+// with the next chunk (possibly of the next w) loaded before the current one
+// is probed. The row bounds of every w in N+(u) and w's table slot are staged
+// in LDS up front.
+template <int NT, int G, int SG, int SLOTS>
+__global__ __launch_bounds__(NT) void k_count_hash(const int32_t* __restrict__ list, int32_t nlist,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int32_t* __restrict__ dcol,
+                                                   unsigned long long* __restrict__ T) {
+  static_assert(NT % G == 0 && G % SG == 0 && SG <= kWave && SLOTS % 4 == 0, "shape");
+  constexpr int GPB = NT / G;
+  constexpr int NSUB = G / SG;
+  constexpr int CAP = SLOTS / 2;
+  constexpr int NB = SLOTS / 4;
+  __shared__ int4 Ks[GPB][NB];
+  __shared__ uint32_t Cs[GPB][SLOTS];
+  __shared__ int32_t Wb[GPB][CAP];  // N+(w) begins (offsets < 2^30)
+  __shared__ int32_t Wn[GPB][CAP];  // |N+(w)|
+  __shared__ int32_t Ws[GPB][CAP];  // slot of w
+  __shared__ unsigned long long red[NT / kWave];
+  const int gi = threadIdx.x / G;
+  const int g = threadIdx.x % G;
+  const int idx = blockIdx.x * GPB + gi;
+  const int4* Kb = Ks[gi];
+  int32_t* K = reinterpret_cast<int32_t*>(Ks[gi]);
+  uint32_t* C = Cs[gi];
+  const bool active = idx < nlist;
+  unsigned long long tu = 0;
+  int32_t u = 0;
+  int64_t beg = 0;
+  int32_t len = 0;  // an inactive group runs every phase with an empty list,
+  if (active) {     // so barriers are reached by all threads of the block
+    u = list[idx];
+    beg = doff[u];
+    len = (int32_t)(doff[u + 1] - beg);
+  }
+  {
+    for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
+    group_sync<G>();
+    for (int i = g; i < len; i += G) {
+      const int32_t w = dcol[beg + i];
+      Ws[gi][i] = bucket_insert<NB>(K, w);
+      const int64_t b = doff[w];
+      Wb[gi][i] = (int32_t)b;
+      Wn[gi][i] = (int32_t)(doff[w + 1] - b);
+    }
+    group_sync<G>();
+    const int sub = g / SG, sg = g % SG;
+    int i = sub;
+    int32_t wb = 0, we = 0, ws = 0, cb = 0;
+    if (i < len) { wb = Wb[gi][i]; we = wb + Wn[gi][i]; ws = Ws[gi][i]; cb = wb & ~3; }
+    int4 cur = make_int4(-1, -1, -1, -1);
+    if (i < len && cb + 4 * sg < we) cur = *reinterpret_cast<const int4*>(dcol + cb + 4 * sg);
+    uint32_t cw = 0;
+    while (i < len) {
+      // next chunk: same w, or the first chunk of the sub-group's next w
+      const bool last = cb + 4 * SG >= we;  // uniform over the sub-group
+      int ni = i, nwb = wb, nwe = we, nws = ws, ncb = cb + 4 * SG;
+      if (last) {
+        ni = i + NSUB;
+        if (ni < len) { nwb = Wb[gi][ni]; nwe = nwb + Wn[gi][ni]; nws = Ws[gi][ni]; ncb = nwb & ~3; }
+      }
+      int4 nxt = make_int4(-1, -1, -1, -1);
+      if (ni < len && ncb + 4 * sg < nwe) nxt = *reinterpret_cast<const int4*>(dcol + ncb + 4 * sg);
+      // probe the four ids of this lane's chunk: issue the bucket reads together
+      const int32_t a = cb + 4 * sg;
+      const int32_t xs[4] = {cur.x, cur.y, cur.z, cur.w};
+      uint32_t hb[4];
+      int4 q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        hb[k] = hash_slot(xs[k], __builtin_ctz(NB));
+        if (a + k >= wb && a + k < we) q[k] = Kb[hb[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (a + k < wb || a + k >= we) continue;
+        const int s = bucket_match<NB>(Kb, xs[k], hb[k], q[k]);
+        if (s >= 0) { atomicAdd(&C[s], 1u); ++cw; }
+      }
+      if (last) {
+        if (cw) atomicAdd(&C[ws], cw);
+        tu += cw;
+        cw = 0;
+      }
+      i = ni; wb = nwb; we = nwe; ws = nws; cb = ncb; cur = nxt;
+    }
+    group_sync<G>();
+    for (int s = g; s < SLOTS; s += G) {
+      const int32_t k = K[s];
+      const uint32_t c = C[s];
+      if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
+    }
+  }
+  if constexpr (G <= kWave) {
+    tu = group_sum<unsigned long long, G>(tu);
+    if (active && g == 0 && tu) atomicAdd(&T[u], tu);
+  } else {
+    // per-group sum of the wave partials (a block may hold several groups)
+    constexpr int WPG = G / kWave;
+    tu = group_sum<unsigned long long, kWave>(tu);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = tu;
+    __syncthreads();
+    if (active && g == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
+      if (t) atomicAdd(&T[u], t);
+    }
+  }
+}
+
+// Wave-stream variant: every out-neighbour list N+(w) is streamed by one
+// full wavefront with wave-uniform loop bounds (held in scalar registers), so
+// the loop needs no divergence bookkeeping. The table is sparse (SLOTS >= 4x
+// the list), so a probe is one 16-byte LDS read and a few compares; the
+// overflow walk to the next bucket is rare. Hits are counted with a ballot
+// and a popcount into a wave-uniform total.
+template <int NB>
+__device__ __forceinline__ int bucket_slot(int4 q, uint32_t b, int32_t x) {
+  int slot = -1;
+  slot = (q.w == x) ? (int)(4 * b + 3) : slot;
+  slot = (q.z == x) ? (int)(4 * b + 2) : slot;
+  slot = (q.y == x) ? (int)(4 * b + 1) : slot;
+  slot = (q.x == x) ? (int)(4 * b) : slot;
+  return slot;
+}
+
+// Slot of x in the bucket table or -1. One 16-byte read unless x's home
+// bucket is full and does not hold x (rare in a sparse table).
+template <int NB>
+__device__ __forceinline__ int bucket_probe(const int4* Kb, int32_t x, bool valid) {
+  uint32_t b = hash_slot(x, __builtin_ctz(NB));
+  int4 q = Kb[b];
+  int slot = bucket_slot<NB>(q, b, x);
+  bool more = valid && slot < 0 && q.w >= 0;
+  while (more) {
+    b = (b + 1) & (NB - 1);
+    q = Kb[b];
+    slot = bucket_slot<NB>(q, b, x);
+    more = slot < 0 && q.w >= 0;
+  }
+  return valid ? slot : -1;
+}
+
+// U ids per lane per step: U independent loads are in flight before the
+// probes; loads past the end of the list are clamped to its last element
+// (same cache line) and masked out of the count.
+template <int NT, int G, int SLOTS, int CAP, int U>
+__global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ list, int32_t nlist,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int32_t* __restrict__ dcol,
+                                                   unsigned long long* __restrict__ T) {
+  static_assert(NT % G == 0 && G % kWave == 0 && SLOTS % 4 == 0 && SLOTS >= 2 * CAP, "shape");
+  constexpr int GPB = NT / G;
+  constexpr int WPG = G / kWave;
+  constexpr int NB = SLOTS / 4;
+  __shared__ int4 Ks[GPB][NB];
+  __shared__ uint32_t Cs[GPB][SLOTS];
+  __shared__ int32_t Wb[GPB][CAP];
+  __shared__ int32_t Wn[GPB][CAP];
+  __shared__ int32_t Ws[GPB][CAP];
+  __shared__ unsigned long long red[NT / kWave];
+  const int gi = threadIdx.x / G;
+  const int g = threadIdx.x % G;
+  const int wv = g / kWave;
+  const int lane = lane_id();
+  const int idx = blockIdx.x * GPB + gi;
+  const int4* Kb = Ks[gi];
+  int32_t* K = reinterpret_cast<int32_t*>(Ks[gi]);
+  uint32_t* C = Cs[gi];
+  const bool active = idx < nlist;
+  int32_t u = 0;
+  int64_t beg = 0;
+  int32_t len = 0;  // inactive groups run every phase with an empty list
+  if (active) {
+    u = list[idx];
+    beg = doff[u];
+    len = (int32_t)(doff[u + 1] - beg);
+  }
+  for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
+  group_sync<G>();
+  for (int i = g; i < len; i += G) {
+    const int32_t w = dcol[beg + i];
+    Ws[gi][i] = bucket_insert<NB>(K, w);
+    const int64_t b = doff[w];
+    Wb[gi][i] = (int32_t)b;
+    Wn[gi][i] = (int32_t)(doff[w + 1] - b);
+  }
+  group_sync<G>();
+  uint32_t tu = 0;  // wave-uniform
+  for (int i = wv; i < len; i += WPG) {
+    const int32_t wb = __builtin_amdgcn_readfirstlane(Wb[gi][i]);
+    const int32_t wn = __builtin_amdgcn_readfirstlane(Wn[gi][i]);
+    if (wn == 0) continue;
+    const int32_t* L = dcol + wb;
+    uint32_t cw = 0;
+    for (int32_t p = 0; p < wn; p += U * kWave) {
+      int32_t x[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) x[k] = L[min(p + k * kWave + lane, wn - 1)];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const bool v = p + k * kWave + lane < wn;
+        const int s = bucket_probe<NB>(Kb, x[k], v);
+        if (s >= 0) atomicAdd(&C[s], 1u);
+        cw += (uint32_t)__popcll(__ballot(s >= 0));
+      }
+    }
+    if (cw && lane == 0) atomicAdd(&C[Ws[gi][i]], cw);
+    tu += cw;
+  }
+  group_sync<G>();
+  for (int s = g; s < SLOTS; s += G) {
+    const int32_t k = K[s];
+    const uint32_t c = C[s];
+    if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
+  }
+  if constexpr (WPG == 1) {
+    if (active && lane == 0 && tu) atomicAdd(&T[u], (unsigned long long)tu);
+  } else {
+    if (lane == 0) red[threadIdx.x / kWave] = tu;
+    __syncthreads();
+    if (active && g == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
+      if (t) atomicAdd(&T[u], t);
+    }
+  }
+}
+
+// Plain variant: no staging, one id per lane per iteration, linear probing
+// over single slots. N+(w) bounds are read from HBM per w.
+template <int SLOTS>
+__device__ __forceinline__ int slot_find(const int32_t* K, int32_t x) {
+  uint32_t h = hash_slot(x, __builtin_ctz(SLOTS));
   while (true) {
     const int32_t k = K[h];
     if (k == x) return (int)h;
@@ -43,20 +312,16 @@ __device__ __forceinline__ int table_find(const int32_t* K, int32_t x) {
 }
 
 template <int SLOTS>
-__device__ __forceinline__ void table_insert(int32_t* K, int32_t x) {
-  constexpr int bits = __builtin_ctz(SLOTS);
-  uint32_t h = hash_slot(x, bits);
+__device__ __forceinline__ void slot_insert(int32_t* K, int32_t x) {
+  uint32_t h = hash_slot(x, __builtin_ctz(SLOTS));
   while (atomicCAS(&K[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
 }
 
-}  // namespace
-
-// NT threads per block; groups of G lanes (G divides NT, or G == NT).
 template <int NT, int G, int SG, int SLOTS>
-__global__ __launch_bounds__(NT) void k_count_hash(const int32_t* __restrict__ list, int32_t nlist,
-                                                   const int64_t* __restrict__ doff,
-                                                   const int32_t* __restrict__ dcol,
-                                                   unsigned long long* __restrict__ T) {
+__global__ __launch_bounds__(NT) void k_count_plain(const int32_t* __restrict__ list, int32_t nlist,
+                                                    const int64_t* __restrict__ doff,
+                                                    const int32_t* __restrict__ dcol,
+                                                    unsigned long long* __restrict__ T) {
   static_assert(NT % G == 0 && G % SG == 0 && SG <= kWave, "shape");
   constexpr int GPB = NT / G;
   constexpr int NSUB = G / SG;
@@ -71,39 +336,48 @@ __global__ __launch_bounds__(NT) void k_count_hash(const int32_t* __restrict__ l
   const bool active = idx < nlist;
   unsigned long long tu = 0;
   int32_t u = 0;
+  int64_t beg = 0;
+  int32_t len = 0;
   if (active) {
     u = list[idx];
-    const int64_t beg = doff[u];
-    const int32_t len = (int32_t)(doff[u + 1] - beg);
-    for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
-    group_sync<G>();
-    for (int i = g; i < len; i += G) table_insert<SLOTS>(K, dcol[beg + i]);
-    group_sync<G>();
-    const int sub = g / SG, sg = g % SG;
-    for (int i = sub; i < len; i += NSUB) {
-      const int32_t w = dcol[beg + i];
-      const int64_t wb = doff[w], we = doff[w + 1];
-      uint32_t cw = 0;
-      for (int64_t p = wb + sg; p < we; p += SG) {
-        const int s = table_find<SLOTS>(K, dcol[p]);
-        if (s >= 0) { atomicAdd(&C[s], 1u); ++cw; }
-      }
-      if (cw) atomicAdd(&C[table_find<SLOTS>(K, w)], cw);
-      tu += cw;
+    beg = doff[u];
+    len = (int32_t)(doff[u + 1] - beg);
+  }
+  for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
+  group_sync<G>();
+  for (int i = g; i < len; i += G) slot_insert<SLOTS>(K, dcol[beg + i]);
+  group_sync<G>();
+  const int sub = g / SG, sg = g % SG;
+  for (int i = sub; i < len; i += NSUB) {
+    const int32_t w = dcol[beg + i];
+    const int64_t wb = doff[w], we = doff[w + 1];
+    uint32_t cw = 0;
+    for (int64_t p = wb + sg; p < we; p += SG) {
+      const int s = slot_find<SLOTS>(K, dcol[p]);
+      if (s >= 0) { atomicAdd(&C[s], 1u); ++cw; }
     }
-    group_sync<G>();
-    for (int s = g; s < SLOTS; s += G) {
-      const int32_t k = K[s];
-      const uint32_t c = C[s];
-      if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
-    }
+    if (cw) atomicAdd(&C[slot_find<SLOTS>(K, w)], cw);
+    tu += cw;
+  }
+  group_sync<G>();
+  for (int s = g; s < SLOTS; s += G) {
+    const int32_t k = K[s];
+    const uint32_t c = C[s];
+    if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
   }
   if constexpr (G <= kWave) {
     tu = group_sum<unsigned long long, G>(tu);
     if (active && g == 0 && tu) atomicAdd(&T[u], tu);
   } else {
-    const unsigned long long t = block_sum<unsigned long long, NT>(tu, red);
-    if (threadIdx.x == 0 && active && t) atomicAdd(&T[u], t);
+    constexpr int WPG = G / kWave;
+    tu = group_sum<unsigned long long, kWave>(tu);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = tu;
+    __syncthreads();
+    if (active && g == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
+      if (t) atomicAdd(&T[u], t);
+    }
   }
 }
 
@@ -145,23 +419,36 @@ __global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict_
 
 // ---------------------------------------------------------------------------
 // Variant table. Capacity = SLOTS / 2 (table at most half full).
-struct VariantInfo { int nt, g, sg, slots; };
+struct VariantInfo { int nt, g, sg, slots, cap = 0; };
 static constexpr VariantInfo kVariants[] = {
-    {256, 16, 16, 32},      // 0: d+ <= 16
-    {256, 16, 8, 32},       // 1
-    {256, 64, 64, 128},     // 2: d+ <= 64
-    {256, 64, 32, 128},     // 3
-    {256, 64, 16, 128},     // 4
-    {256, 64, 64, 512},     // 5: d+ <= 256
-    {256, 64, 32, 512},     // 6
-    {256, 64, 16, 512},     // 7
-    {256, 256, 64, 2048},   // 8: d+ <= 1024
-    {256, 256, 32, 2048},   // 9
-    {256, 256, 16, 2048},   // 10
-    {512, 512, 64, 8192},   // 11: d+ <= 4096
-    {512, 512, 32, 8192},   // 12
-    {1024, 1024, 64, 16384},  // 13: d+ <= 8192 (128 KiB LDS)
-    {256, 256, 64, 0},      // 14: global fallback, any d+
+    {256, 16, 16, 32},       // 0: d+ <= 16
+    {256, 16, 8, 32},        // 1
+    {256, 64, 32, 128},      // 2: d+ <= 64
+    {256, 64, 16, 128},      // 3
+    {256, 128, 32, 512},     // 4: d+ <= 256
+    {256, 128, 16, 512},     // 5
+    {256, 256, 32, 512},     // 6
+    {512, 512, 32, 2048},    // 7: d+ <= 1024
+    {512, 512, 64, 2048},    // 8
+    {512, 512, 16, 2048},    // 9
+    {1024, 1024, 32, 8192},  // 10: d+ <= 4096
+    {1024, 1024, 64, 8192},  // 11
+    // plain kernel (no staging, single-slot probing)
+    {256, 16, 16, 32},       // 12: d+ <= 16
+    {256, 64, 32, 128},      // 13: d+ <= 64
+    {256, 64, 32, 512},      // 14: d+ <= 256
+    {256, 256, 32, 2048},    // 15: d+ <= 1024
+    {512, 512, 64, 8192},    // 16: d+ <= 4096
+    // wave-stream kernel (one wavefront per list, sparse bucket table)
+    {256, 64, 64, 128, 16},       // 17: d+ <= 16
+    {256, 64, 64, 512, 64},       // 18: d+ <= 64
+    {256, 256, 64, 2048, 256},    // 19: d+ <= 256
+    {512, 512, 64, 8192, 1024},   // 20: d+ <= 1024
+    {1024, 1024, 64, 8192, 4096}, // 21: d+ <= 4096
+    {256, 64, 64, 256, 64},       // 22: d+ <= 64, denser table
+    {256, 256, 64, 1024, 256},    // 23: d+ <= 256, denser table
+    {512, 512, 64, 4096, 1024},   // 24: d+ <= 1024, denser table
+    {256, 256, 64, 0},       // 25: global fallback, any d+
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = kNumVariants - 1;
@@ -169,7 +456,8 @@ constexpr int kVariantGlobal = kNumVariants - 1;
 int count_variant_valid(int v) { return v >= 0 && v < kNumVariants; }
 int count_variant_capacity(int v) {
   if (!count_variant_valid(v)) return -1;
-  return kVariants[v].slots ? kVariants[v].slots / 2 : 0x7fffffff;
+  if (!kVariants[v].slots) return 0x7fffffff;
+  return kVariants[v].cap ? kVariants[v].cap : kVariants[v].slots / 2;
 }
 
 template <int NT, int G, int SG, int SLOTS>
@@ -180,24 +468,51 @@ static void launch_hash(const BinLaunch& b, const int64_t* doff, const int32_t* 
   k_count_hash<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
 }
 
+template <int NT, int G, int SLOTS, int CAP, int U = 4>
+static void launch_wave(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
+                        unsigned long long* T, hipStream_t s) {
+  constexpr int GPB = NT / G;
+  const unsigned grid = (unsigned)((b.count + GPB - 1) / GPB);
+  k_count_wave<NT, G, SLOTS, CAP, U><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
+}
+
+template <int NT, int G, int SG, int SLOTS>
+static void launch_plain(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
+                         unsigned long long* T, hipStream_t s) {
+  constexpr int GPB = NT / G;
+  const unsigned grid = (unsigned)((b.count + GPB - 1) / GPB);
+  k_count_plain<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
+}
+
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s) {
   if (b.count <= 0) return hipSuccess;
   switch (b.variant) {
     case 0: launch_hash<256, 16, 16, 32>(b, doff, dcol, T, s); break;
     case 1: launch_hash<256, 16, 8, 32>(b, doff, dcol, T, s); break;
-    case 2: launch_hash<256, 64, 64, 128>(b, doff, dcol, T, s); break;
-    case 3: launch_hash<256, 64, 32, 128>(b, doff, dcol, T, s); break;
-    case 4: launch_hash<256, 64, 16, 128>(b, doff, dcol, T, s); break;
-    case 5: launch_hash<256, 64, 64, 512>(b, doff, dcol, T, s); break;
-    case 6: launch_hash<256, 64, 32, 512>(b, doff, dcol, T, s); break;
-    case 7: launch_hash<256, 64, 16, 512>(b, doff, dcol, T, s); break;
-    case 8: launch_hash<256, 256, 64, 2048>(b, doff, dcol, T, s); break;
-    case 9: launch_hash<256, 256, 32, 2048>(b, doff, dcol, T, s); break;
-    case 10: launch_hash<256, 256, 16, 2048>(b, doff, dcol, T, s); break;
-    case 11: launch_hash<512, 512, 64, 8192>(b, doff, dcol, T, s); break;
-    case 12: launch_hash<512, 512, 32, 8192>(b, doff, dcol, T, s); break;
-    case 13: launch_hash<1024, 1024, 64, 16384>(b, doff, dcol, T, s); break;
+    case 2: launch_hash<256, 64, 32, 128>(b, doff, dcol, T, s); break;
+    case 3: launch_hash<256, 64, 16, 128>(b, doff, dcol, T, s); break;
+    case 4: launch_hash<256, 128, 32, 512>(b, doff, dcol, T, s); break;
+    case 5: launch_hash<256, 128, 16, 512>(b, doff, dcol, T, s); break;
+    case 6: launch_hash<256, 256, 32, 512>(b, doff, dcol, T, s); break;
+    case 7: launch_hash<512, 512, 32, 2048>(b, doff, dcol, T, s); break;
+    case 8: launch_hash<512, 512, 64, 2048>(b, doff, dcol, T, s); break;
+    case 9: launch_hash<512, 512, 16, 2048>(b, doff, dcol, T, s); break;
+    case 10: launch_hash<1024, 1024, 32, 8192>(b, doff, dcol, T, s); break;
+    case 11: launch_hash<1024, 1024, 64, 8192>(b, doff, dcol, T, s); break;
+    case 12: launch_plain<256, 16, 16, 32>(b, doff, dcol, T, s); break;
+    case 13: launch_plain<256, 64, 32, 128>(b, doff, dcol, T, s); break;
+    case 14: launch_plain<256, 64, 32, 512>(b, doff, dcol, T, s); break;
+    case 15: launch_plain<256, 256, 32, 2048>(b, doff, dcol, T, s); break;
+    case 16: launch_plain<512, 512, 64, 8192>(b, doff, dcol, T, s); break;
+    case 17: launch_wave<256, 64, 128, 16>(b, doff, dcol, T, s); break;
+    case 18: launch_wave<256, 64, 512, 64>(b, doff, dcol, T, s); break;
+    case 19: launch_wave<256, 256, 2048, 256>(b, doff, dcol, T, s); break;
+    case 20: launch_wave<512, 512, 8192, 1024>(b, doff, dcol, T, s); break;
+    case 21: launch_wave<1024, 1024, 8192, 4096>(b, doff, dcol, T, s); break;
+    case 22: launch_wave<256, 64, 256, 64>(b, doff, dcol, T, s); break;
+    case 23: launch_wave<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
+    case 24: launch_wave<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;
