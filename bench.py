@@ -168,7 +168,7 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
-    info = g.info
+    info = g.stats()
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
 
     # count-only timing (a6..a7) with events

@@ -70,10 +70,11 @@ typedef struct tricc_graph_info {
   int64_t max_deg;             /* max d(v) */
   int64_t max_outdeg;          /* max d+(v) */
   int64_t bin_count[TRICC_NUM_BINS];
-  uint64_t list_elems;         /* sum over DAG edges u->w of d+(u) + d+(w) */
+  uint64_t list_elems;         /* sum over DAG edges u->w of d+(u) + d+(w) (*) */
   int64_t large_rows;          /* rows sorted by the chunk + merge path */
-  uint64_t bin_list_elems[TRICC_NUM_BINS]; /* list_elems of the nodes of each bin */
-  int64_t bin_edges[TRICC_NUM_BINS];       /* sum of d+(u) over the nodes of each bin */
+  uint64_t bin_list_elems[TRICC_NUM_BINS]; /* list_elems of the nodes of each bin (*) */
+  int64_t bin_edges[TRICC_NUM_BINS];       /* sum of d+(u) over the nodes of each bin (*) */
+  /* (*) zero until tricc_graph_stats has run */
 } tricc_graph_info;
 
 typedef struct tricc_graph tricc_graph;
@@ -115,7 +116,13 @@ int tricc_graph_build(int32_t n, int64_t m_raw, const int32_t* d_src, const int3
 
 int tricc_graph_info_get(const tricc_graph* g, tricc_graph_info* out);
 
-/* Re-bins the graph's nodes with another tuning. Synchronises `stream`. */
+/* Fills the fields of tricc_graph_info marked (*): the algorithmic sizes of
+ * the intersection work, from which its algorithmic bytes follow. Not part
+ * of the counting path. Synchronises `stream`. */
+int tricc_graph_stats(tricc_graph* g, void* stream);
+
+/* Re-bins the graph's nodes with another tuning (clears the (*) fields).
+ * Synchronises `stream`. */
 int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream);
 
 /*

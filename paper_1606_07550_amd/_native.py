@@ -73,6 +73,7 @@ _SIGS = {
                                          ctypes.POINTER(Tuning), _P, ctypes.POINTER(_P)]),
     "tricc_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(GraphInfo)]),
     "tricc_graph_retune": (ctypes.c_int, [_P, ctypes.POINTER(Tuning), _P]),
+    "tricc_graph_stats": (ctypes.c_int, [_P, _P]),
     "tricc_count": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "tricc_count_begin": (ctypes.c_int, [_P, _P, _P]),
     "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),

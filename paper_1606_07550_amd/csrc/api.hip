@@ -54,7 +54,8 @@ constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, total;
+      part_T, meta, cls_hist, cls_off, total;
+  int64_t cls_nblk;
   int64_t max_jobs;
 };
 
@@ -69,7 +70,11 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.deg = take(sizeof(int32_t) * n);
   L.dplus = take(sizeof(int32_t) * n);
   L.doff = take(sizeof(int64_t) * (n + 1));
-  L.scan_tmp = take(sizeof(int64_t) * scan_tmp_elems(n + 1));
+  L.cls_nblk = classify_blocks(n) > 0 ? classify_blocks(n) : 1;
+  const int64_t cls_elems = (int64_t)kNumRowClasses * L.cls_nblk;
+  L.scan_tmp = take(sizeof(int64_t) * std::max(scan_tmp_elems(n + 1), scan_tmp_elems(cls_elems + 1)));
+  L.cls_hist = take(sizeof(int32_t) * cls_elems);
+  L.cls_off = take(sizeof(int64_t) * (cls_elems + 1));
   L.rowlist = take(sizeof(int32_t) * n);
   L.binlist = take(sizeof(int32_t) * n);
   L.adj = take(sizeof(int32_t) * 2 * m_raw);
@@ -203,6 +208,20 @@ int sort_large_rows(tricc_graph* g, int32_t nl, const int32_t* rows_dev) {
   return TRICC_OK;
 }
 
+// Runs a two-pass classification; h_off receives nc + 1 class offsets.
+template <typename Launch>
+int classify(tricc_graph* g, int nc, Launch launch, int64_t* d_cls_off, int64_t* h_off) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  int32_t* hist = g->at<int32_t>(L.cls_hist);
+  int64_t* off = g->at<int64_t>(L.cls_off);
+  HIPCHK(launch(0, hist, off));
+  HIPCHK(launch_scan_i32(hist, (int64_t)nc * L.cls_nblk, off, g->at<int64_t>(L.scan_tmp), s));
+  HIPCHK(launch_class_offsets(off, L.cls_nblk, nc, d_cls_off, s));
+  HIPCHK(launch(1, hist, off));
+  return sync_copy(h_off, d_cls_off, sizeof(int64_t) * (nc + 1), s);
+}
+
 int bin_nodes(tricc_graph* g) {
   hipStream_t s = g->stream;
   const Layout& L = g->L;
@@ -210,32 +229,23 @@ int bin_nodes(tricc_graph* g) {
   const int32_t n = g->n;
   int rc = upload(hdr + kHdrLimits, g->tuning.bin_limit, sizeof(int32_t) * (kNumBins - 1), s);
   if (rc) return rc;
-  HIPCHK(hipMemsetAsync(hdr + kHdrBinCnt, 0, sizeof(int32_t) * kNumBins, s));
   int64_t* d_bin_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrBinOff * 4);
-  HIPCHK(launch_bin_nodes(0, n, g->at<int32_t>(L.dplus), hdr + kHdrLimits, hdr + kHdrBinCnt, d_bin_off,
-                          g->at<int32_t>(L.binlist), s));
-  int32_t cnt[kNumBins];
-  if ((rc = sync_copy(cnt, hdr + kHdrBinCnt, sizeof(cnt), s))) return rc;
-  g->bin_off[0] = 0;
-  for (int b = 0; b < kNumBins; ++b) g->bin_off[b + 1] = g->bin_off[b] + cnt[b];
-  if ((rc = upload(d_bin_off, g->bin_off, sizeof(g->bin_off), s))) return rc;
-  HIPCHK(hipMemsetAsync(hdr + kHdrBinCnt, 0, sizeof(int32_t) * kNumBins, s));
-  HIPCHK(launch_bin_nodes(1, n, g->at<int32_t>(L.dplus), hdr + kHdrLimits, hdr + kHdrBinCnt, d_bin_off,
-                          g->at<int32_t>(L.binlist), s));
-  unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinElems * 4);
-  unsigned long long* d_edges = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinEdges * 4);
-  HIPCHK(hipMemsetAsync(d_elems, 0, sizeof(unsigned long long) * 2 * kNumBins, s));
-  HIPCHK(launch_bin_elems(g->at<int32_t>(L.binlist), d_bin_off, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
-                          d_elems, d_edges, g->bin_off[kNumBins], s));
-  unsigned long long be[2 * kNumBins];
-  if ((rc = sync_copy(be, d_elems, sizeof(be), s))) return rc;
-  for (int b = 0; b < kNumBins; ++b) {
-    g->info.bin_list_elems[b] = be[b];
-    g->info.bin_edges[b] = (int64_t)be[kNumBins + b];
+  const int32_t* dplus = g->at<int32_t>(L.dplus);
+  int32_t* binlist = g->at<int32_t>(L.binlist);
+  auto launch = [&](int pass, int32_t* hist, const int64_t* off) {
+    return launch_classify_bins(pass, n, dplus, hdr + kHdrLimits, hist, off, L.cls_nblk, binlist, s);
+  };
+  if (n == 0) {
+    for (int b = 0; b <= kNumBins; ++b) g->bin_off[b] = 0;
+  } else if ((rc = classify(g, kNumBins, launch, d_bin_off, g->bin_off))) {
+    return rc;
   }
   for (int b = 0; b < kNumBins; ++b) {
-    g->info.bin_count[b] = cnt[b];
-    if (!cnt[b]) continue;
+    const int64_t cnt = g->bin_off[b + 1] - g->bin_off[b];
+    g->info.bin_count[b] = cnt;
+    g->info.bin_list_elems[b] = 0;
+    g->info.bin_edges[b] = 0;
+    if (!cnt) continue;
     int64_t bound = g->info.max_outdeg;
     if (b < kNumBins - 1) bound = std::min<int64_t>(bound, g->tuning.bin_limit[b]);
     const int cap = count_variant_capacity(g->tuning.bin_variant[b]);
@@ -243,6 +253,33 @@ int bin_nodes(tricc_graph* g) {
       return fail(TRICC_EINVAL, "tuning: bin %d holds out-degrees up to %lld but variant %d accepts %d", b,
                   (long long)bound, g->tuning.bin_variant[b], cap);
   }
+  g->info.list_elems = 0;
+  return TRICC_OK;
+}
+
+// Algorithmic-size statistics (not needed for counting).
+int graph_stats(tricc_graph* g) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinElems * 4);
+  unsigned long long* d_edges = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinEdges * 4);
+  unsigned long long* d_all = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrListElems * 4);
+  HIPCHK(hipMemsetAsync(d_elems, 0, sizeof(unsigned long long) * 2 * kNumBins, s));
+  HIPCHK(hipMemsetAsync(d_all, 0, sizeof(unsigned long long), s));
+  int64_t* d_bin_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrBinOff * 4);
+  HIPCHK(launch_bin_elems(g->at<int32_t>(L.binlist), d_bin_off, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
+                          d_elems, d_edges, g->bin_off[kNumBins], s));
+  HIPCHK(launch_list_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), d_all, s));
+  unsigned long long be[2 * kNumBins];
+  int rc = sync_copy(be, d_elems, sizeof(be), s);
+  if (rc) return rc;
+  unsigned long long all = 0;
+  if ((rc = sync_copy(&all, d_all, sizeof(all), s))) return rc;
+  for (int b = 0; b < kNumBins; ++b) {
+    g->info.bin_list_elems[b] = be[b];
+    g->info.bin_edges[b] = (int64_t)be[kNumBins + b];
+  }
+  g->info.list_elems = all;
   return TRICC_OK;
 }
 
@@ -273,40 +310,38 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   HIPCHK(launch_scatter(src, dst, m_raw, raw_off, len, adj, s));
   int32_t* rowlist = g->at<int32_t>(L.rowlist);
   int64_t* d_cls_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrClsOff * 4);
-  HIPCHK(launch_row_classes(0, n, len, deg, hdr + kHdrRowCnt, d_cls_off, rowlist, s));
+  int64_t cls_off[kNumRowClasses + 1] = {};
+  if (n > 0) {
+    auto launch = [&](int pass, int32_t* hist, const int64_t* off) {
+      return launch_classify_rows(pass, n, len, deg, hist, off, L.cls_nblk, rowlist, s);
+    };
+    if ((rc = classify(g, kNumRowClasses, launch, d_cls_off, cls_off))) return rc;
+  }
   int32_t cnt[kNumRowClasses];
-  if ((rc = sync_copy(cnt, hdr + kHdrRowCnt, sizeof(cnt), s))) return rc;
-  int64_t cls_off[kNumRowClasses + 1];
-  cls_off[0] = 0;
-  for (int c = 0; c < kNumRowClasses; ++c) cls_off[c + 1] = cls_off[c] + cnt[c];
-  if ((rc = upload(d_cls_off, cls_off, sizeof(cls_off), s))) return rc;
-  HIPCHK(hipMemsetAsync(hdr + kHdrRowCnt, 0, sizeof(int32_t) * kNumRowClasses, s));
-  HIPCHK(launch_row_classes(1, n, len, deg, hdr + kHdrRowCnt, d_cls_off, rowlist, s));
+  for (int c = 0; c < kNumRowClasses; ++c) cnt[c] = (int32_t)(cls_off[c + 1] - cls_off[c]);
   for (int c = kRow8; c <= kRowLds32k; ++c)
     HIPCHK(launch_sort_rows(c, rowlist + cls_off[c], cnt[c], raw_off, len, adj, deg, s));
   g->info.large_rows = 0;
   if (cnt[kRowLarge] > 0)
     if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
-  // a4: orientation
+  // a4: orientation (rows longer than 64 raw entries are the classes from kRowLds4k on)
   int32_t* dplus = g->at<int32_t>(L.dplus);
   int64_t* doff = g->at<int64_t>(L.doff);
-  HIPCHK(launch_outdeg(n, raw_off, deg, adj, dplus, hdr + kHdrStats, s));
+  int32_t* dcol = g->at<int32_t>(L.dcol);
+  const int32_t* long_rows = rowlist + cls_off[kRowLds4k];
+  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds4k]);
+  HIPCHK(launch_orient(0, n, raw_off, len, deg, adj, long_rows, nlong, dplus, doff, dcol, hdr + kHdrStats, s));
   HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
-  HIPCHK(launch_dag_fill(n, raw_off, deg, adj, doff, g->at<int32_t>(L.dcol), s));
-  unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrListElems * 4);
-  HIPCHK(launch_list_elems(n, doff, g->at<int32_t>(L.dcol), d_elems, s));
+  HIPCHK(launch_orient(1, n, raw_off, len, deg, adj, long_rows, nlong, dplus, doff, dcol, hdr + kHdrStats, s));
   int32_t stats[2];
   if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
   int64_t m = 0;
   if ((rc = sync_copy(&m, doff + n, sizeof(m), s))) return rc;
-  unsigned long long elems = 0;
-  if ((rc = sync_copy(&elems, d_elems, sizeof(elems), s))) return rc;
   g->info.n = n;
   g->info.m_raw = m_raw;
   g->info.m = m;
   g->info.max_deg = stats[0];
   g->info.max_outdeg = stats[1];
-  g->info.list_elems = elems;
   // a5: binning
   return bin_nodes(g);
 }
@@ -395,6 +430,12 @@ int tricc_graph_info_get(const tricc_graph* g, tricc_graph_info* out) {
   if (!g || !out) return fail(TRICC_EINVAL, "null argument");
   *out = g->info;
   return TRICC_OK;
+}
+
+int tricc_graph_stats(tricc_graph* g, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  g->stream = static_cast<hipStream_t>(stream);
+  return graph_stats(g);
 }
 
 int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream) {

@@ -155,7 +155,7 @@ hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw,
 }
 
 // ---------------------------------------------------------------------------
-// Row classes by raw length (wave-aggregated appends).
+// Row classes by raw length.
 __device__ __forceinline__ int row_class(int32_t len) {
   if (len <= 1) return kRowTrivial;
   if (len <= 8) return kRow8;
@@ -167,42 +167,87 @@ __device__ __forceinline__ int row_class(int32_t len) {
   return kRowLarge;
 }
 
-// Appends `item` to class `cls` for every active lane; one atomic per class per wave.
-template <int NC>
-__device__ __forceinline__ void wave_append(bool active, int cls, int32_t item, int pass, int32_t* cnt,
-                                            const int64_t* cls_off, int32_t* list) {
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const uint64_t mask = __ballot(active && cls == c);
-    if (!mask) continue;
-    const int leader = __builtin_ctzll(mask);
-    int32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&cnt[c], (int32_t)__popcll(mask));
-    base = __shfl(base, leader, kWave);
-    if (pass == 1 && active && cls == c) list[cls_off[c] + base + mask_below(mask)] = item;
-  }
-}
+// Classification of [0, n) into classes with per-block histograms: pass 0
+// counts each block's members per class (LDS atomics) into
+// hist[c * nblk + blk]; the host scans hist; pass 1 writes each member at
+// off[c * nblk + blk] + its rank inside the block. No global atomics.
+constexpr int kClsThreads = 256;
+constexpr int64_t kClsChunk = 4096;
 
-__global__ __launch_bounds__(256) void k_row_classes(int pass, int32_t n, const int32_t* __restrict__ len,
-                                                     int32_t* __restrict__ deg, int32_t* __restrict__ cnt,
-                                                     const int64_t* __restrict__ cls_off,
-                                                     int32_t* __restrict__ list) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    const bool in = v < n;
-    const int32_t L = in ? len[v] : 0;
+int64_t classify_blocks(int64_t n) { return (n + kClsChunk - 1) / kClsChunk; }
+
+struct RowClassOf {  // by raw row length; trivial rows are not listed
+  const int32_t* len;
+  int32_t* deg;
+  __device__ int operator()(int64_t v, int pass) const {
+    const int32_t L = len[v];
     const int c = row_class(L);
-    if (pass == 0 && in && c == kRowTrivial) deg[v] = L;
-    // trivial rows are not listed
-    wave_append<kNumRowClasses>(in && c != kRowTrivial, c, (int32_t)v, pass, cnt, cls_off, list);
+    if (c == kRowTrivial) {
+      if (pass == 0) deg[v] = L;
+      return -1;
+    }
+    return c;
+  }
+};
+
+struct NodeBinOf {  // by DAG out-degree; nodes with d+ < 2 are not listed
+  const int32_t* dplus;
+  const int32_t* limit;
+  __device__ int operator()(int64_t v, int) const {
+    const int32_t d = dplus[v];
+    if (d < 2) return -1;
+    int b = kNumBins - 1;
+#pragma unroll
+    for (int q = kNumBins - 2; q >= 0; --q)
+      if (d <= limit[q]) b = q;
+    return b;
+  }
+};
+
+template <int NC, class F>
+__global__ __launch_bounds__(kClsThreads) void k_classify(int pass, int64_t n, F f, int32_t* __restrict__ hist,
+                                                          const int64_t* __restrict__ off, int64_t nblk,
+                                                          int32_t* __restrict__ list) {
+  __shared__ int32_t cnt[NC];
+  if (threadIdx.x < NC) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * kClsChunk;
+  const int64_t b1 = min(n, b0 + kClsChunk);
+  for (int64_t v = b0 + threadIdx.x; v < b1; v += kClsThreads) {
+    const int c = f(v, pass);
+    if (c < 0) continue;
+    const int32_t r = atomicAdd(&cnt[c], 1);
+    if (pass == 1) list[off[(int64_t)c * nblk + blockIdx.x] + r] = (int32_t)v;
+  }
+  if (pass == 0) {
+    __syncthreads();
+    if (threadIdx.x < NC) hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
   }
 }
 
-hipError_t launch_row_classes(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* cnt,
-                              const int64_t* cls_off, int32_t* list, hipStream_t s) {
+__global__ void k_class_offsets(const int64_t* __restrict__ off, int64_t nblk, int nc, int64_t* __restrict__ cls_off) {
+  const int c = threadIdx.x;
+  if (c <= nc) cls_off[c] = off[(int64_t)c * nblk];
+}
+
+hipError_t launch_classify_rows(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* hist,
+                                const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_row_classes<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(pass, n, len, deg, cnt, cls_off, list);
+  k_classify<kNumRowClasses, RowClassOf><<<(unsigned)nblk, kClsThreads, 0, s>>>(pass, n, RowClassOf{len, deg}, hist,
+                                                                               off, nblk, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify_bins(int pass, int32_t n, const int32_t* dplus, const int32_t* limit, int32_t* hist,
+                                const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_classify<kNumBins, NodeBinOf><<<(unsigned)nblk, kClsThreads, 0, s>>>(pass, n, NodeBinOf{dplus, limit}, hist, off,
+                                                                        nblk, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_offsets(const int64_t* off, int64_t nblk, int nc, int64_t* cls_off, hipStream_t s) {
+  k_class_offsets<<<1, 64, 0, s>>>(off, nblk, nc, cls_off);
   return hipGetLastError();
 }
 
@@ -409,104 +454,113 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 }
 
 // ---------------------------------------------------------------------------
-// a4: orientation. Wave per row, grid-stride over rows.
-__global__ __launch_bounds__(256) void k_outdeg(int32_t n, const int64_t* __restrict__ off,
-                                                const int32_t* __restrict__ deg,
-                                                const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ dplus, int32_t* __restrict__ stats) {
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int l = lane_id();
+// a4: orientation. pass 0 counts d+(v), pass 1 writes N+(v) in id order.
+// Rows of raw length <= kOrientShort: a group of kOrientG lanes per row,
+// grid-stride; longer rows (listed contiguously by the row classes): one
+// block per row.
+constexpr int kOrientG = 8;
+constexpr int32_t kOrientShort = 64;
+
+template <typename T>
+__device__ __forceinline__ T block_max(T x, T* lds) {
+  constexpr int NW = 256 / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = x;
+  __syncthreads();
+  T r = lds[0];
+  for (int i = 1; i < NW; ++i) r = max(r, lds[i]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ len,
+                                                      const int32_t* __restrict__ deg,
+                                                      const int32_t* __restrict__ adj,
+                                                      int32_t* __restrict__ dplus,
+                                                      const int64_t* __restrict__ doff,
+                                                      int32_t* __restrict__ dcol, int32_t* __restrict__ stats) {
+  constexpr int G = kOrientG;
+  __shared__ int32_t red[256 / kWave];
+  const int64_t ngroups = (int64_t)gridDim.x * (256 / G);
+  const int g = threadIdx.x % G;
+  const int shift = lane_id() & ~(G - 1);
   int32_t mx_d = 0, mx_p = 0;
-  for (int64_t v = w0; v < n; v += nwaves) {
+  for (int64_t v = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; v < n; v += ngroups) {
+    if (len[v] > kOrientShort) continue;
     const int32_t dv = deg[v];
     const int32_t* row = adj + off[v];
     int32_t c = 0;
-    for (int32_t b = 0; b < dv; b += kWave) {
+    int64_t ob = 0;
+    if (pass == 1) ob = doff[v];
+    for (int32_t b = 0; b < dv; b += G) {
       bool f = false;
-      if (b + l < dv) {
-        const int32_t w = row[b + l];
+      int32_t w = 0;
+      if (b + g < dv) {
+        w = row[b + g];
         f = rank_below(dv, (int32_t)v, deg[w], w);
       }
-      c += (int32_t)__popcll(__ballot(f));
+      const uint32_t mask = (uint32_t)(__ballot(f) >> shift) & ((1u << G) - 1);
+      if (pass == 1 && f) dcol[ob + c + __popc(mask & ((1u << g) - 1))] = w;
+      c += __popc(mask);
     }
-    if (l == 0) dplus[v] = c;
+    if (pass == 0 && g == 0) dplus[v] = c;
     mx_d = max(mx_d, dv);
     mx_p = max(mx_p, c);
   }
-  if (l == 0) {
-    atomicMax(&stats[0], mx_d);
-    atomicMax(&stats[1], mx_p);
-  }
-}
-
-hipError_t launch_outdeg(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
-                         int32_t* dplus, int32_t* stats, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_outdeg<<<grid_for((int64_t)n * kWave, 256, 1u << 16), 256, 0, s>>>(n, off, deg, adj, dplus, stats);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_dag_fill(int32_t n, const int64_t* __restrict__ off,
-                                                  const int32_t* __restrict__ deg,
-                                                  const int32_t* __restrict__ adj,
-                                                  const int64_t* __restrict__ doff,
-                                                  int32_t* __restrict__ dcol) {
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int l = lane_id();
-  for (int64_t v = w0; v < n; v += nwaves) {
-    const int32_t dv = deg[v];
-    const int32_t* row = adj + off[v];
-    int32_t* out = dcol + doff[v];
-    int32_t c = 0;
-    for (int32_t b = 0; b < dv; b += kWave) {
-      bool f = false;
-      int32_t w = 0;
-      if (b + l < dv) {
-        w = row[b + l];
-        f = rank_below(dv, (int32_t)v, deg[w], w);
-      }
-      const uint64_t mask = __ballot(f);
-      if (f) out[c + mask_below(mask)] = w;
-      c += (int32_t)__popcll(mask);
+  if (pass == 0) {
+    mx_d = block_max(mx_d, red);
+    mx_p = block_max(mx_p, red);
+    if (threadIdx.x == 0) {
+      atomicMax(&stats[0], mx_d);
+      atomicMax(&stats[1], mx_p);
     }
   }
 }
 
-hipError_t launch_dag_fill(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
-                           const int64_t* doff, int32_t* dcol, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_dag_fill<<<grid_for((int64_t)n * kWave, 256, 1u << 16), 256, 0, s>>>(n, off, deg, adj, doff, dcol);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// a5: node binning by out-degree.
-__global__ __launch_bounds__(256) void k_bin_nodes(int pass, int32_t n, const int32_t* __restrict__ dplus,
-                                                   const int32_t* __restrict__ limit,
-                                                   int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ bin_off,
-                                                   int32_t* __restrict__ list) {
-  int32_t lim[kNumBins - 1];
-#pragma unroll
-  for (int b = 0; b < kNumBins - 1; ++b) lim[b] = limit[b];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    const int32_t d = v < n ? dplus[v] : 0;
-    int b = kNumBins - 1;
-#pragma unroll
-    for (int q = kNumBins - 2; q >= 0; --q)
-      if (d <= lim[q]) b = q;
-    wave_append<kNumBins>(d >= 2, b, (int32_t)v, pass, cnt, bin_off, list);
+__global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __restrict__ rows,
+                                                     const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ deg,
+                                                     const int32_t* __restrict__ adj,
+                                                     int32_t* __restrict__ dplus,
+                                                     const int64_t* __restrict__ doff,
+                                                     int32_t* __restrict__ dcol, int32_t* __restrict__ stats) {
+  __shared__ int32_t lds[256 / kWave + 1];
+  const int32_t v = rows[blockIdx.x];
+  const int32_t dv = deg[v];
+  const int32_t* row = adj + off[v];
+  int64_t ob = 0;
+  if (pass == 1) ob = doff[v];
+  int32_t c = 0;
+  for (int32_t b = 0; b < dv; b += 256) {
+    const int32_t i = b + threadIdx.x;
+    bool f = false;
+    int32_t w = 0;
+    if (i < dv) {
+      w = row[i];
+      f = rank_below(dv, v, deg[w], w);
+    }
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, 256>(f ? 1 : 0, lds, &tot);
+    if (pass == 1 && f) dcol[ob + c + ex] = w;
+    c += tot;
+  }
+  if (pass == 0 && threadIdx.x == 0) {
+    dplus[v] = c;
+    atomicMax(&stats[0], dv);
+    atomicMax(&stats[1], c);
   }
 }
 
-hipError_t launch_bin_nodes(int pass, int32_t n, const int32_t* dplus, const int32_t* limit_dev,
-                            int32_t* cnt, const int64_t* bin_off, int32_t* list, hipStream_t s) {
+hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
+                         const int32_t* adj, const int32_t* long_rows, int32_t nlong, int32_t* dplus,
+                         const int64_t* doff, int32_t* dcol, int32_t* stats, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_bin_nodes<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(pass, n, dplus, limit_dev, cnt, bin_off, list);
+  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(pass, n, off, len, deg, adj, dplus,
+                                                                             doff, dcol, stats);
+  if (nlong > 0)
+    k_orient_long<<<nlong, 256, 0, s>>>(pass, long_rows, off, deg, adj, dplus, doff, dcol, stats);
   return hipGetLastError();
 }
 

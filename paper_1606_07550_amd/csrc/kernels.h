@@ -26,11 +26,15 @@ hipError_t launch_scan_i32(const int32_t* in, int64_t n, int64_t* out, int64_t* 
 hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw, const int64_t* off,
                           int32_t* cur, int32_t* adj, hipStream_t s);
-// Classifies rows by raw length; pass 0 counts into cnt[kNumRowClasses],
-// pass 1 appends row ids at list[cls_off[c] + cursor[c]++]. Rows of length
-// <= 1 get deg = len directly.
-hipError_t launch_row_classes(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* cnt,
-                              const int64_t* cls_off, int32_t* list, hipStream_t s);
+// Classification with per-block histograms (see build_kernels.hip): pass 0
+// fills hist[c * nblk + blk]; after an exclusive scan of hist into off,
+// pass 1 writes the members of class c at list[off[c * nblk] ...].
+int64_t classify_blocks(int64_t n);
+// rows by raw length (rows of length <= 1 are not listed; pass 0 sets their deg)
+hipError_t launch_classify_rows(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* hist,
+                                const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
+// cls_off[c] = off[c * nblk] for c = 0..nc
+hipError_t launch_class_offsets(const int64_t* off, int64_t nblk, int nc, int64_t* cls_off, hipStream_t s);
 // Sorts + dedups rows of one class in place; writes deg.
 hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const int64_t* off,
                             const int32_t* len, int32_t* adj, int32_t* deg, hipStream_t s);
@@ -51,12 +55,12 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
                              int32_t* adj, int32_t* deg, hipStream_t s);
 
 // ---- Degree-order orientation --------------------------------------------
-// dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|; stats[0] = max d, stats[1] = max d+.
-hipError_t launch_outdeg(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
-                         int32_t* dplus, int32_t* stats, hipStream_t s);
-// Writes N+(v) (ascending id) at dcol[doff[v] ...].
-hipError_t launch_dag_fill(int32_t n, const int64_t* off, const int32_t* deg, const int32_t* adj,
-                           const int64_t* doff, int32_t* dcol, hipStream_t s);
+// pass 0: dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|, stats[0] = max d,
+// stats[1] = max d+; pass 1: writes N+(v) (ascending id) at dcol[doff[v]..].
+// Rows of raw length > 64 must be listed in long_rows.
+hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
+                         const int32_t* adj, const int32_t* long_rows, int32_t nlong, int32_t* dplus,
+                         const int64_t* doff, int32_t* dcol, int32_t* stats, hipStream_t s);
 
 hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* out,
                              hipStream_t s);
@@ -66,10 +70,9 @@ hipError_t launch_gather_rows(const int32_t* rows, int32_t nr, const int64_t* of
 // ---- Work binning for the intersection kernels ---------------------------
 constexpr int kNumBins = 6;
 // Node u with d+(u) >= 2 goes to the first bin b with d+(u) <= limit[b];
-// bin kNumBins-1 takes the rest. Two passes like launch_row_classes.
-hipError_t launch_bin_nodes(int pass, int32_t n, const int32_t* dplus, const int32_t* limit_dev,
-                            int32_t* cnt, const int64_t* bin_off, int32_t* list, hipStream_t s);
-
+// bin kNumBins-1 takes the rest.
+hipError_t launch_classify_bins(int pass, int32_t n, const int32_t* dplus, const int32_t* limit, int32_t* hist,
+                                const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
 // per-bin sums of d+(u) + d+(w) over the bin's DAG edges, and of d+(u)
 hipError_t launch_bin_elems(const int32_t* list, const int64_t* bin_off, const int64_t* doff,
                             const int32_t* dcol, unsigned long long* elems, unsigned long long* edges,

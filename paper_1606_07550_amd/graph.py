@@ -87,6 +87,12 @@ class Graph:
         N.check(N.lib().tricc_graph_info_get(self._h, ctypes.byref(i)), "tricc_graph_info_get")
         return i.as_dict()
 
+    def stats(self, stream=None):
+        """Computes the algorithmic sizes of the intersection work (list_elems,
+        bin_list_elems, bin_edges of :attr:`info`); synchronises."""
+        N.check(N.lib().tricc_graph_stats(self._h, _stream_ptr(stream)), "tricc_graph_stats")
+        return self.info
+
     def retune(self, tuning, stream=None):
         t = _as_tuning(tuning)
         N.check(N.lib().tricc_graph_retune(self._h, ctypes.byref(t), _stream_ptr(stream)), "tricc_graph_retune")

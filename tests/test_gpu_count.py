@@ -178,6 +178,11 @@ def test_csr_and_dag_structure():
         out = dcol[doff[v]:doff[v + 1]]
         assert np.all(np.diff(out) > 0)
         assert all((deg[v], v) < (deg[w], w) for w in out.tolist())
+    # algorithmic sizes: sum over DAG edges u->w of d+(u) + d+(w)
+    info = g.stats()
+    src_of = np.repeat(np.arange(n), dplus)
+    assert info["list_elems"] == int((dplus[src_of] + dplus[dcol]).sum())
+    assert sum(info["bin_edges"]) == int(dplus[dplus >= 2].sum())
 
 
 def _tuning_all_to(variant, limit_bins=None):
