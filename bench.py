@@ -82,6 +82,20 @@ def probe_bandwidth(torch, N, nbytes=2 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
+def measured_traffic(workload, variant):
+    """HBM traffic per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on this workload and variant
+    with the current intersection-kernel source; else None."""
+    from paper_1606_07550_amd import profiling
+    rec = profiling.read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                              f"traffic_{workload}.md"))
+    if not rec:
+        return None
+    if rec.get("count_kernels_sha256") != profiling.count_source_sha256() or int(rec.get("variant", -1)) != variant:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(scale):
     import oracle
     from paper_1606_07550_amd import inputs as I
@@ -192,6 +206,7 @@ def main():
     a6_ms = sum(avg_bin_ms)
     tuning_used = (tuning or P.default_tuning()).as_dict()
     variant = tuning_used["bin_variant"][dom]
+    traffic = measured_traffic(cfg["workload"], variant)
     bw, _ = probe_bandwidth(torch, N)
     line = {
         "metric": METRIC,
@@ -214,7 +229,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": f"intersection bin {dom} (variant {variant})",
             "kernel_ms": avg_bin_ms[dom],
             "alg_bytes_per_launch": dom_bytes,

@@ -2,13 +2,87 @@
 
     python -m paper_1606_07550_amd.profiling kernels <results.db> [--top N]
     python -m paper_1606_07550_amd.profiling counters <results.db> [--kernel SUBSTR]
+    python -m paper_1606_07550_amd.profiling traffic --fetch F.db --write W.db \
+        --kernel SUBSTR --variant V --workload NAME --command "..."
 
 ``kernels`` prints per-kernel call counts and durations (the same figures as
 ``rocprofv3 --stats``); ``counters`` prints the per-dispatch mean of every
-PMC counter collected with ``--pmc``, per kernel.
+PMC counter collected with ``--pmc``, per kernel. ``traffic`` turns a
+FETCH_SIZE run and a WRITE_SIZE run into bytes per launch of one kernel,
+each scaled by what the same counter reads for the library's streaming copy
+kernel (k_probe_copy) of a known size, and prints a summary whose
+``key: value`` lines the benchmark reads back (it uses them only while the
+intersection kernels' source hash still matches).
 """
 import argparse
+import hashlib
+import os
 import sqlite3
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+COUNT_SOURCE = os.path.join(PKG, "csrc", "count_kernels.hip")
+PROBE_BYTES = 2 << 30  # size of the copy the benchmark's bandwidth probe runs
+
+
+def count_source_sha256():
+    with open(COUNT_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _per_kernel(db, counter):
+    c = sqlite3.connect(db)
+    return {k: (n, v) for k, n, v in c.execute(
+        "select kernel_name, count(*), avg(value) from counters_collection where counter_name=? "
+        "group by kernel_name", (counter,))}
+
+
+def traffic_summary(fetch_db, write_db, kernel, variant, workload, command):
+    f = _per_kernel(fetch_db, "FETCH_SIZE")
+    w = _per_kernel(write_db, "WRITE_SIZE")
+    probe = [k for k in f if "k_probe_copy" in k][0]
+    fscale = PROBE_BYTES / (f[probe][1] * 1024.0)
+    wscale = PROBE_BYTES / (w[probe][1] * 1024.0)
+    ks = [k for k in f if kernel in k]
+    if len(ks) != 1:
+        raise SystemExit(f"kernel substring {kernel!r} matches {len(ks)} kernels")
+    k = ks[0]
+    fb = f[k][1] * 1024.0 * fscale
+    wb = w[k][1] * 1024.0 * wscale
+    lines = [
+        f"# Memory traffic of {k.split('(')[0].replace('void ', '')} — {workload}",
+        "",
+        "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, L2 to fabric) from two separate rocprofv3 --pmc runs,",
+        "each scaled by the ratio of the true bytes of the library's streaming copy kernel (k_probe_copy,",
+        f"{PROBE_BYTES} bytes read and written per launch, run inside the same benchmark) to what the same",
+        f"counter reads for it: FETCH x{fscale:.3f}, WRITE x{wscale:.3f}.",
+        "",
+        "Commands (from /tmp, repository at /root/repo):",
+        f"    {command.replace('PMC', 'FETCH_SIZE')}",
+        f"    {command.replace('PMC', 'WRITE_SIZE')}",
+        "",
+        f"kernel: {k.split('(')[0].replace('void ', '')}",
+        f"variant: {variant}",
+        f"workload: {workload}",
+        f"dispatches: {f[k][0]}",
+        f"fetch_bytes_per_launch: {fb:.0f}",
+        f"write_bytes_per_launch: {wb:.0f}",
+        f"traffic_bytes_per_launch: {fb + wb:.0f}",
+        f"count_kernels_sha256: {count_source_sha256()}",
+    ]
+    return "\n".join(lines)
+
+
+def read_traffic(path):
+    """Parses a summary written by traffic_summary; None if missing."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ": " in line and not line.startswith(("#", " ")):
+                key, val = line.rstrip("\n").split(": ", 1)
+                out[key.strip()] = val.strip()
+    return out
 
 
 def kernel_stats(db, top=40):
@@ -39,12 +113,22 @@ def counter_stats(db, kernel=None):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["kernels", "counters"])
-    ap.add_argument("db")
+    ap.add_argument("what", choices=["kernels", "counters", "traffic"])
+    ap.add_argument("db", nargs="?")
     ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--kernel", default=None)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--variant", type=int)
+    ap.add_argument("--workload")
+    ap.add_argument("--command", default="")
     a = ap.parse_args()
-    print(kernel_stats(a.db, a.top) if a.what == "kernels" else counter_stats(a.db, a.kernel))
+    if a.what == "kernels":
+        print(kernel_stats(a.db, a.top))
+    elif a.what == "counters":
+        print(counter_stats(a.db, a.kernel))
+    else:
+        print(traffic_summary(a.fetch, a.write, a.kernel, a.variant, a.workload, a.command))
 
 
 if __name__ == "__main__":
