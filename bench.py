@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="JSON file with bin_limit / bin_variant")
     ap.add_argument("--out", default=None, help="also append the JSON line to this file")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-graphs leg")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--autotune", action="store_true", help="search tunings first (cached per arch/workload)")
     return ap.parse_args()
 
 
@@ -94,6 +98,84 @@ def measured_traffic(workload, variant):
     if rec.get("count_kernels_sha256") != profiling.count_source_sha256() or int(rec.get("variant", -1)) != variant:
         return None
     return float(rec["traffic_bytes_per_launch"])
+
+
+def batched_leg(args, torch, P, N):
+    """4096 independent BA / ER graphs (n log-uniform in [64, 65536]): one
+    persistent launch captured in a hipGraph, against per-graph launches of
+    the single-graph path on the same graphs."""
+    from paper_1606_07550_amd import autotune
+    from paper_1606_07550_amd import inputs as I
+    dev = torch.device("cuda:0")
+    G = args.batch_graphs
+    t0 = time.perf_counter()
+    bt = I.batch(G, 4096)
+    log(f"generated batch G={G} nodes={bt['node_off'][-1]} pairs={bt['edge_off'][-1]} "
+        f"in {time.perf_counter() - t0:.1f}s")
+    src = torch.from_numpy(bt["src"]).to(dev)
+    dst = torch.from_numpy(bt["dst"]).to(dev)
+    key = f"batched-{G}"
+    tuning = autotune.default_or_cached_batch(key)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = P.Batch(bt["node_off"], bt["edge_off"], src, dst, tuning=tuning)
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    if args.autotune:
+        tuning, _ = autotune.tune_batch(b, key=key, log=log)
+    b.plan()
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.batch_reps):
+        b.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / args.batch_reps
+    info = b.info
+    # algorithmic bytes of the whole batch, from the union graph
+    gptr = N.lib().tricc_batch_graph(b._h)
+    N.check(N.lib().tricc_graph_stats(gptr, ctypes.c_void_p(stream.cuda_stream)), "tricc_graph_stats")
+    gi = N.GraphInfo()
+    N.check(N.lib().tricc_graph_info_get(gptr, ctypes.byref(gi)), "tricc_graph_info_get")
+    n_tot = int(bt["node_off"][-1])
+    alg = 4 * gi.list_elems + 4 * gi.m + 8 * (n_tot + G) + 12 * n_tot
+    tri = int(b.out["graph_tri"].sum().item())
+    # per-graph launches of the single-graph path on the same graphs
+    log("building per-graph handles for the baseline ...")
+    graphs = []
+    for g in range(G):
+        e_a, e_b = bt["edge_off"][g], bt["edge_off"][g + 1]
+        graphs.append(P.Graph(int(bt["n"][g]), src[e_a:e_b], dst[e_a:e_b]))
+    outs = [{"T": torch.empty(gr.n, dtype=torch.int64, device=dev),
+             "cc": torch.empty(gr.n, dtype=torch.float32, device=dev),
+             "total": torch.empty(1, dtype=torch.int64, device=dev),
+             "avg": torch.empty(1, dtype=torch.float64, device=dev)} for gr in graphs]
+    for gr, o in zip(graphs, outs):
+        gr.count(out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gr, o in zip(graphs, outs):
+        gr.count(out=o)
+    torch.cuda.synchronize()
+    per_graph_ms = 1e3 * (time.perf_counter() - t0)
+    tri_pg = sum(int(o["total"].item()) for o in outs)
+    del graphs, outs
+    return {
+        "workload": f"batched-{G}", "graphs": G, "nodes": n_tot, "pairs": int(bt["edge_off"][-1]), "m": int(gi.m),
+        "triangles": tri, "triangles_match_per_graph": tri == tri_pg,
+        "graphs_per_s": G / (launch_ms * 1e-3), "launch_ms": launch_ms, "edges_per_s": gi.m / (launch_ms * 1e-3),
+        "alg_bytes": alg, "achieved_GBps": alg / (launch_ms * 1e-3) / 1e9,
+        "frac": alg / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "per_graph_launches": {"graphs_per_s": G / (per_graph_ms * 1e-3), "ms": per_graph_ms},
+        "speedup_vs_per_graph": per_graph_ms / launch_ms,
+        "build_ms": build_ms, "tuning": tuning, "grid": info["grid"],
+        "lists": {"merge": info["merge_nodes"], "wave": info["wave_nodes"], "block": info["block_nodes"],
+                  "hub": info["hub_nodes"]},
+    }
 
 
 def cpu_baseline(scale):
@@ -242,6 +324,11 @@ def main():
         "build_ms": 1e3 * build_s / args.steps,
         "probe_copy_GBps": bw,
     }
+    del src, dst, ws, T, cc, g
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched leg ...")
+        line["batched"] = batched_leg(args, torch, P, N)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on its sample ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)

@@ -163,6 +163,77 @@ int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_
 
 void tricc_graph_free(tricc_graph* g);
 
+/* ---------------------------------------------------------------------------
+ * Batched graphs: many independent graphs counted by one persistent launch.
+ *
+ * The batch is G graphs packed back to back: graph g has nodes with local
+ * ids [0, n_g) and its input pairs at positions [h_edge_off[g],
+ * h_edge_off[g+1]) of d_src / d_dst (local ids). h_node_off is the prefix
+ * of the n_g (h_node_off[0] = 0, h_node_off[G] = total nodes). Each graph
+ * gets the same definitions as a single graph (top of this file); node v of
+ * graph g is position h_node_off[g] + v of the per-node outputs.
+ */
+typedef struct tricc_batch tricc_batch;
+
+typedef struct tricc_batch_tuning {
+  int32_t merge_limit;     /* nodes with d+ <= merge_limit: 8-lane two-pointer merge (0..wave_limit) */
+  int32_t wave_limit;      /* other nodes with d+ <= wave_limit: one wavefront each (2..64) */
+  int32_t persist_variant; /* 0: nodes up to d+ 256 in one block's table; 1: up to 1024 */
+  int32_t blocks_per_cu;   /* persistent grid = compute units x this; 0 = occupancy limit */
+} tricc_batch_tuning;
+
+typedef struct tricc_batch_info {
+  int32_t num_graphs;
+  int64_t total_nodes;
+  int64_t total_pairs;
+  int64_t m;                  /* undirected simple edges over all graphs */
+  int64_t max_outdeg;
+  int64_t merge_nodes, wave_nodes, block_nodes, hub_nodes; /* the persistent kernel's lists */
+  int32_t grid;               /* persistent blocks */
+  int32_t planned;            /* a hipGraph is instantiated */
+} tricc_batch_info;
+
+int tricc_batch_default_tuning(tricc_batch_tuning* out);
+int tricc_batch_workspace_size(int32_t num_graphs, int64_t total_nodes, int64_t total_pairs, size_t* bytes);
+
+/* Builds the disjoint union of the batch on the device (validate, map local
+ * to global ids, then the a1..a5 build of a single graph) and bins its nodes
+ * for the persistent kernel. h_node_off / h_edge_off: host int64[G+1].
+ * Synchronises `stream`. TRICC_ERANGE if a local id is outside [0, n_g). */
+int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64_t* h_edge_off,
+                      const int32_t* d_src, const int32_t* d_dst, void* d_ws, size_t ws_bytes,
+                      const tricc_batch_tuning* tuning, void* stream, tricc_batch** out);
+
+/* Binds the outputs and captures the count into a hipGraph: clear (a
+ * kernel), the persistent intersection kernel, the per-graph epilogue.
+ *   d_node_tri  device uint64[total_nodes] (per-node counts; also the
+ *               kernel's accumulator)
+ *   d_node_cc   device float[total_nodes]
+ *   d_graph_tri device uint64[G]   triangles of each graph
+ *   d_graph_avg device double[G]   average CC of each graph over its n_g
+ *               nodes, summed in a fixed order that depends only on the graph
+ * The buffers must stay valid while the plan is used. Synchronises. */
+int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
+                     double* d_graph_avg, void* stream);
+
+/* One hipGraphLaunch of the planned count. Asynchronous. Calls on one
+ * batch must not overlap (they share the accumulators). */
+int tricc_batch_run(tricc_batch* b, void* stream);
+
+/* The same three kernels launched directly (no graph). Asynchronous. */
+int tricc_batch_run_eager(tricc_batch* b, void* stream);
+
+/* New tuning: re-bins and drops the plan (plan again before running).
+ * Synchronises. */
+int tricc_batch_retune(tricc_batch* b, const tricc_batch_tuning* tuning, void* stream);
+
+int tricc_batch_info_get(const tricc_batch* b, tricc_batch_info* out);
+
+/* The union graph (for inspection or for counting it with tricc_count). */
+const tricc_graph* tricc_batch_graph(const tricc_batch* b);
+
+void tricc_batch_free(tricc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

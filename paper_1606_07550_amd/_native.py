@@ -57,6 +57,30 @@ class GraphInfo(ctypes.Structure):
                 "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges)}
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("merge_limit", ctypes.c_int32), ("wave_limit", ctypes.c_int32),
+                ("persist_variant", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(int(d.get("merge_limit", 0)), int(d["wave_limit"]), int(d["persist_variant"]),
+                   int(d["blocks_per_cu"]))
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int32), ("total_nodes", ctypes.c_int64), ("total_pairs", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("max_outdeg", ctypes.c_int64), ("merge_nodes", ctypes.c_int64),
+                ("wave_nodes", ctypes.c_int64),
+                ("block_nodes", ctypes.c_int64), ("hub_nodes", ctypes.c_int64), ("grid", ctypes.c_int32),
+                ("planned", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _LIB = None
 
 # name -> (restype, argtypes)
@@ -82,6 +106,18 @@ _SIGS = {
     "tricc_graph_arrays": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                           ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "tricc_graph_free": (None, [_P]),
+    "tricc_batch_default_tuning": (ctypes.c_int, [ctypes.POINTER(BatchTuning)]),
+    "tricc_batch_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "tricc_batch_build": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                         ctypes.POINTER(BatchTuning), _P, ctypes.POINTER(_P)]),
+    "tricc_batch_plan": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_batch_run": (ctypes.c_int, [_P, _P]),
+    "tricc_batch_run_eager": (ctypes.c_int, [_P, _P]),
+    "tricc_batch_retune": (ctypes.c_int, [_P, ctypes.POINTER(BatchTuning), _P]),
+    "tricc_batch_info_get": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
+    "tricc_batch_graph": (_P, [_P]),
+    "tricc_batch_free": (None, [_P]),
 }
 
 

@@ -117,6 +117,8 @@ int upload(void* d, const void* h, size_t bytes, hipStream_t s) {
   return TRICC_OK;
 }
 
+void tricc_default_tuning_impl(tricc_tuning* out);
+
 int check_tuning(const tricc_tuning* t) {
   for (int b = 0; b < kNumBins; ++b)
     if (!count_variant_valid(t->bin_variant[b]))
@@ -348,6 +350,15 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
 
 }  // namespace
 
+namespace {
+void tricc_default_tuning_impl(tricc_tuning* out) {
+  static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
+  static const int32_t var[kNumBins] = {17, 22, 23, 24, 21, 28};
+  std::memcpy(out->bin_limit, lim, sizeof(lim));
+  std::memcpy(out->bin_variant, var, sizeof(var));
+}
+}  // namespace
+
 extern "C" {
 
 const char* tricc_status_str(int status) {
@@ -369,10 +380,7 @@ int tricc_version(void) { return 100; }
 
 int tricc_default_tuning(tricc_tuning* out) {
   if (!out) return fail(TRICC_EINVAL, "null tuning");
-  static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {17, 22, 23, 24, 21, 25};
-  std::memcpy(out->bin_limit, lim, sizeof(lim));
-  std::memcpy(out->bin_variant, var, sizeof(var));
+  tricc_default_tuning_impl(out);
   return TRICC_OK;
 }
 
@@ -520,5 +528,290 @@ int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_
 }
 
 void tricc_graph_free(tricc_graph* g) { delete g; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched graphs
+// ===========================================================================
+struct tricc_batch {
+  int32_t G = 0;
+  int64_t n_total = 0, m_total = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t* d_node_off = nullptr;
+  int64_t* d_edge_off = nullptr;
+  int32_t* d_queue = nullptr;
+  int32_t* d_err = nullptr;
+  int32_t* gsrc = nullptr;
+  int32_t* gdst = nullptr;
+  tricc_graph g;
+  tricc_batch_tuning tuning{};
+  unsigned grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long* T = nullptr;
+  float* cc = nullptr;
+  unsigned long long* graph_tri = nullptr;
+  double* graph_avg = nullptr;
+  bool bound = false;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t hdr, node_off, edge_off, gsrc, gdst, graph_ws, total;
+};
+
+BatchLayout make_batch_layout(int64_t G, int64_t n_total, int64_t m_total) {
+  BatchLayout L{};
+  size_t p = 0;
+  auto take = [&](size_t bytes) { size_t at = p; p = align_up(p + std::max<size_t>(bytes, 1)); return at; };
+  L.hdr = take(256);
+  L.node_off = take(sizeof(int64_t) * (G + 1));
+  L.edge_off = take(sizeof(int64_t) * (G + 1));
+  L.gsrc = take(sizeof(int32_t) * m_total);
+  L.gdst = take(sizeof(int32_t) * m_total);
+  L.graph_ws = p;
+  L.total = p + make_layout(n_total, m_total).total;
+  return L;
+}
+
+int check_batch_tuning(const tricc_batch_tuning* t) {
+  if (t->persist_variant < 0 || t->persist_variant >= persist_variant_count())
+    return fail(TRICC_EINVAL, "batch tuning: unknown persistent variant %d", t->persist_variant);
+  if (t->wave_limit < 2 || t->wave_limit > persist_wave_cap(t->persist_variant))
+    return fail(TRICC_EINVAL, "batch tuning: wave_limit %d outside [2, %d]", t->wave_limit,
+                persist_wave_cap(t->persist_variant));
+  if (t->merge_limit < 0 || t->merge_limit > t->wave_limit)
+    return fail(TRICC_EINVAL, "batch tuning: merge_limit %d outside [0, wave_limit]", t->merge_limit);
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(TRICC_EINVAL, "batch tuning: blocks_per_cu");
+  return TRICC_OK;
+}
+
+// Bins of the union graph for the persistent kernel: bin 0 = merge nodes
+// (d+ <= merge_limit), bin 1 = single-wave nodes, bin 2 = block nodes,
+// bin 5 = hubs (global fallback); bins 3..4 stay empty. The single-graph
+// variants are set so that tricc_count also works on the union.
+void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
+  const int32_t cb = persist_block_cap(bt.persist_variant);
+  const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, cb, cb};
+  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, 24, 24, 28};
+  std::memcpy(t->bin_limit, lim, sizeof(lim));
+  std::memcpy(t->bin_variant, var, sizeof(var));
+}
+
+int batch_bin(tricc_batch* b) {
+  batch_graph_tuning(b->tuning, &b->g.tuning);
+  int rc = bin_nodes(&b->g);
+  if (rc) return rc;
+  int dev = 0, cus = 0, occ = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, persist_kernel(b->tuning.persist_variant), 256, 0));
+  if (occ < 1) occ = 1;
+  const int per = b->tuning.blocks_per_cu > 0 ? std::min(b->tuning.blocks_per_cu, occ) : occ;
+  b->grid = (unsigned)std::max(1, cus * per);
+  return TRICC_OK;
+}
+
+int batch_launch(tricc_batch* b, hipStream_t s) {
+  tricc_graph* g = &b->g;
+  const Layout& L = g->L;
+  const int32_t* binlist = g->at<int32_t>(L.binlist);
+  HIPCHK(launch_batch_zero(b->T, b->n_total, b->d_queue, s));
+  const int32_t nm = (int32_t)(g->bin_off[1] - g->bin_off[0]);
+  const int32_t nw = (int32_t)(g->bin_off[2] - g->bin_off[1]);
+  const int32_t nbk = (int32_t)(g->bin_off[3] - g->bin_off[2]);
+  const int32_t ng = (int32_t)(g->bin_off[kNumBins] - g->bin_off[kNumBins - 1]);
+  HIPCHK(launch_count_persist(b->tuning.persist_variant, b->grid, binlist + g->bin_off[kNumBins - 1], ng,
+                              binlist + g->bin_off[2], nbk, binlist + g->bin_off[1], nw, binlist + g->bin_off[0], nm,
+                              b->d_queue, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, s));
+  HIPCHK(launch_graph_epilogue(b->G, b->d_node_off, b->T, g->at<int32_t>(L.deg), b->cc, b->graph_tri, b->graph_avg,
+                               s));
+  return TRICC_OK;
+}
+
+void batch_drop_plan(tricc_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tricc_batch_default_tuning(tricc_batch_tuning* out) {
+  if (!out) return fail(TRICC_EINVAL, "null tuning");
+  out->merge_limit = 32;
+  out->wave_limit = 64;
+  out->persist_variant = 0;
+  out->blocks_per_cu = 0;
+  return TRICC_OK;
+}
+
+int tricc_batch_workspace_size(int32_t num_graphs, int64_t total_nodes, int64_t total_pairs, size_t* bytes) {
+  if (!bytes) return fail(TRICC_EINVAL, "null bytes");
+  if (num_graphs < 0) return fail(TRICC_EINVAL, "negative graph count");
+  if (total_nodes < 0 || total_nodes >= 0x7fffffff) return fail(TRICC_EINVAL, "total nodes out of range");
+  if (total_pairs < 0) return fail(TRICC_EINVAL, "negative pair count");
+  if (total_pairs > (int64_t(1) << 30)) return fail(TRICC_EOVERFLOW, "total pairs above 2^30");
+  *bytes = make_batch_layout(num_graphs, total_nodes, total_pairs).total;
+  return TRICC_OK;
+}
+
+int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64_t* h_edge_off, const int32_t* d_src,
+                      const int32_t* d_dst, void* d_ws, size_t ws_bytes, const tricc_batch_tuning* tuning,
+                      void* stream, tricc_batch** out) {
+  g_err[0] = 0;
+  if (!out) return fail(TRICC_EINVAL, "null out");
+  *out = nullptr;
+  if (num_graphs < 0 || (num_graphs > 0 && (!h_node_off || !h_edge_off)))
+    return fail(TRICC_EINVAL, "bad graph count or offsets");
+  const int64_t n_total = num_graphs ? h_node_off[num_graphs] : 0;
+  const int64_t m_total = num_graphs ? h_edge_off[num_graphs] : 0;
+  if (num_graphs && (h_node_off[0] != 0 || h_edge_off[0] != 0))
+    return fail(TRICC_EINVAL, "offsets must start at 0");
+  for (int32_t k = 0; k < num_graphs; ++k)
+    if (h_node_off[k + 1] < h_node_off[k] || h_edge_off[k + 1] < h_edge_off[k])
+      return fail(TRICC_EINVAL, "offsets must be non-decreasing");
+  size_t need = 0;
+  int rc = tricc_batch_workspace_size(num_graphs, n_total, m_total, &need);
+  if (rc) return rc;
+  if (m_total > 0 && (!d_src || !d_dst)) return fail(TRICC_EINVAL, "null edge arrays");
+  if (!d_ws) return fail(TRICC_EINVAL, "null workspace");
+  if (ws_bytes < need) return fail(TRICC_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(TRICC_EINVAL, "workspace not 256-byte aligned");
+  tricc_batch_tuning bt;
+  if (tuning) bt = *tuning; else tricc_batch_default_tuning(&bt);
+  if ((rc = check_batch_tuning(&bt))) return rc;
+
+  tricc_batch* b = new (std::nothrow) tricc_batch();
+  if (!b) return fail(TRICC_ENOMEM, "host allocation failed");
+  const BatchLayout BL = make_batch_layout(num_graphs, n_total, m_total);
+  char* ws = static_cast<char*>(d_ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  b->G = num_graphs;
+  b->n_total = n_total;
+  b->m_total = m_total;
+  b->ws = ws;
+  b->ws_bytes = ws_bytes;
+  b->d_queue = reinterpret_cast<int32_t*>(ws + BL.hdr);
+  b->d_err = reinterpret_cast<int32_t*>(ws + BL.hdr + 64);
+  b->d_node_off = reinterpret_cast<int64_t*>(ws + BL.node_off);
+  b->d_edge_off = reinterpret_cast<int64_t*>(ws + BL.edge_off);
+  b->gsrc = reinterpret_cast<int32_t*>(ws + BL.gsrc);
+  b->gdst = reinterpret_cast<int32_t*>(ws + BL.gdst);
+  b->tuning = bt;
+  tricc_graph* g = &b->g;
+  g->n = (int32_t)n_total;
+  g->m_raw = m_total;
+  g->ws = ws + BL.graph_ws;
+  g->L = make_layout(n_total, m_total);
+  g->stream = s;
+  std::memset(&g->info, 0, sizeof(g->info));
+  batch_graph_tuning(bt, &g->tuning);
+  auto bail = [&](int code) { delete b; return code; };
+  if (hipMemsetAsync(ws + BL.hdr, 0, 256, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
+  if ((rc = upload(b->d_node_off, h_node_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
+  if ((rc = upload(b->d_edge_off, h_edge_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
+  if (launch_batch_relabel(num_graphs, b->d_node_off, b->d_edge_off, d_src, d_dst, m_total, b->gsrc, b->gdst,
+                           b->d_err, s) != hipSuccess)
+    return bail(fail(TRICC_EHIP, "relabel launch failed"));
+  int32_t err = 0;
+  if ((rc = sync_copy(&err, b->d_err, sizeof(err), s))) return bail(rc);
+  if (err) return bail(fail(TRICC_ERANGE, "a local node id is outside its graph's [0, n_g)"));
+  if ((rc = build_impl(g, b->gsrc, b->gdst))) return bail(rc);
+  if ((rc = batch_bin(b))) return bail(rc);
+  *out = b;
+  return TRICC_OK;
+}
+
+int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri, double* d_graph_avg,
+                     void* stream) {
+  if (!b) return fail(TRICC_EINVAL, "null batch");
+  if ((b->n_total > 0 && (!d_node_tri || !d_node_cc)) || (b->G > 0 && (!d_graph_tri || !d_graph_avg)))
+    return fail(TRICC_EINVAL, "null output");
+  batch_drop_plan(b);
+  b->T = reinterpret_cast<unsigned long long*>(d_node_tri);
+  b->cc = d_node_cc;
+  b->graph_tri = reinterpret_cast<unsigned long long*>(d_graph_tri);
+  b->graph_avg = d_graph_avg;
+  b->bound = true;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipStreamSynchronize(s));
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = TRICC_OK;
+  if (e == hipSuccess) {
+    rc = batch_launch(b, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (rc == TRICC_OK && e2 != hipSuccess) rc = fail(TRICC_EHIP, "end capture: %s", hipGetErrorString(e2));
+    if (rc == TRICC_OK) {
+      b->graph = graph;
+      e2 = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) rc = fail(TRICC_EHIP, "graph instantiate: %s", hipGetErrorString(e2));
+    } else if (graph) {
+      (void)hipGraphDestroy(graph);
+    }
+  } else {
+    rc = fail(TRICC_EHIP, "begin capture: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc) batch_drop_plan(b);
+  return rc;
+}
+
+int tricc_batch_run(tricc_batch* b, void* stream) {
+  if (!b) return fail(TRICC_EINVAL, "null batch");
+  if (!b->exec) return fail(TRICC_EINVAL, "batch not planned");
+  HIPCHK(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
+int tricc_batch_run_eager(tricc_batch* b, void* stream) {
+  if (!b) return fail(TRICC_EINVAL, "null batch");
+  if (!b->bound) return fail(TRICC_EINVAL, "batch outputs not bound (plan first)");
+  return batch_launch(b, static_cast<hipStream_t>(stream));
+}
+
+int tricc_batch_retune(tricc_batch* b, const tricc_batch_tuning* tuning, void* stream) {
+  if (!b || !tuning) return fail(TRICC_EINVAL, "null argument");
+  int rc = check_batch_tuning(tuning);
+  if (rc) return rc;
+  batch_drop_plan(b);
+  b->tuning = *tuning;
+  b->g.stream = static_cast<hipStream_t>(stream);
+  return batch_bin(b);
+}
+
+int tricc_batch_info_get(const tricc_batch* b, tricc_batch_info* out) {
+  if (!b || !out) return fail(TRICC_EINVAL, "null argument");
+  const tricc_graph& g = b->g;
+  out->num_graphs = b->G;
+  out->total_nodes = b->n_total;
+  out->total_pairs = b->m_total;
+  out->m = g.info.m;
+  out->max_outdeg = g.info.max_outdeg;
+  out->merge_nodes = g.bin_off[1] - g.bin_off[0];
+  out->wave_nodes = g.bin_off[2] - g.bin_off[1];
+  out->block_nodes = g.bin_off[3] - g.bin_off[2];
+  out->hub_nodes = g.bin_off[kNumBins] - g.bin_off[kNumBins - 1];
+  out->grid = (int32_t)b->grid;
+  out->planned = b->exec != nullptr;
+  return TRICC_OK;
+}
+
+const tricc_graph* tricc_batch_graph(const tricc_batch* b) { return b ? &b->g : nullptr; }
+
+void tricc_batch_free(tricc_batch* b) {
+  if (!b) return;
+  batch_drop_plan(b);
+  delete b;
+}
 
 }  // extern "C"

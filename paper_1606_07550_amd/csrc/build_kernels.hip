@@ -652,6 +652,46 @@ hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream
   return hipGetLastError();
 }
 
+// Packed batch -> disjoint union: the graph of edge e is found by binary
+// search over edge_off (G + 1 entries).
+__global__ __launch_bounds__(256) void k_batch_relabel(int32_t G, const int64_t* __restrict__ node_off,
+                                                       const int64_t* __restrict__ edge_off,
+                                                       const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ dst, int64_t m_raw,
+                                                       int32_t* __restrict__ gsrc, int32_t* __restrict__ gdst,
+                                                       int32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_raw; e += stride) {
+    int32_t lo = 0, hi = G - 1;  // last g with edge_off[g] <= e
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (edge_off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int64_t base = node_off[lo];
+    const int64_t ng = node_off[lo + 1] - base;
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= ng || v >= ng) {
+      bad = true;
+      gsrc[e] = (int32_t)base;  // keeps the union well formed; the build is refused anyway
+      gdst[e] = (int32_t)base;
+      continue;
+    }
+    gsrc[e] = (int32_t)(base + u);
+    gdst[e] = (int32_t)(base + v);
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1);
+}
+
+hipError_t launch_batch_relabel(int32_t num_graphs, const int64_t* node_off, const int64_t* edge_off,
+                                const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t* gsrc,
+                                int32_t* gdst, int32_t* err, hipStream_t s) {
+  if (m_raw == 0) return hipSuccess;
+  k_batch_relabel<<<grid_for(m_raw, 256 * 8, 1u << 16), 256, 0, s>>>(num_graphs, node_off, edge_off, src, dst,
+                                                                     m_raw, gsrc, gdst, err);
+  return hipGetLastError();
+}
+
 __global__ void k_gather_rows(const int32_t* __restrict__ rows, int32_t nr, const int64_t* __restrict__ off,
                               const int32_t* __restrict__ len, int64_t* __restrict__ out_off,
                               int32_t* __restrict__ out_len) {

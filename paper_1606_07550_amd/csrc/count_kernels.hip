@@ -212,55 +212,54 @@ __device__ __forceinline__ int bucket_probe(const int4* Kb, int32_t x, bool vali
   return valid ? slot : -1;
 }
 
-// U ids per lane per step: U independent loads are in flight before the
-// probes; loads past the end of the list are clamped to its last element
-// (same cache line) and masked out of the count.
-template <int NT, int G, int SLOTS, int CAP, int U>
-__global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ list, int32_t nlist,
-                                                   const int64_t* __restrict__ doff,
-                                                   const int32_t* __restrict__ dcol,
-                                                   unsigned long long* __restrict__ T) {
-  static_assert(NT % G == 0 && G % kWave == 0 && SLOTS % 4 == 0 && SLOTS >= 2 * CAP, "shape");
-  constexpr int GPB = NT / G;
+// LDS of one node group of the wave-stream kernel.
+template <int SLOTS, int CAP>
+struct WaveGroupLds {
+  int4 K[SLOTS / 4];     // bucket table of N+(u)
+  uint32_t C[SLOTS];     // per-slot triangle credits
+  int32_t Wb[CAP];       // N+(w) begins (offsets < 2^30)
+  int32_t Wn[CAP];       // |N+(w)|
+  int32_t Ws[CAP];       // slot of w
+};
+
+// One node u (u < 0: inactive group) counted by a group of G lanes (G a
+// multiple of 64; when G > 64 the group is the whole block). U ids per lane
+// per step: U independent loads are in flight before the probes; loads past
+// the end of a list are clamped to its last element (same cache line) and
+// masked out of the count.
+template <int G, int SLOTS, int CAP, int U>
+__device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, CAP>& S,
+                                                unsigned long long* red, const int64_t* __restrict__ doff,
+                                                const int32_t* __restrict__ dcol,
+                                                unsigned long long* __restrict__ T) {
+  static_assert(G % kWave == 0 && SLOTS % 4 == 0 && SLOTS >= 2 * CAP, "shape");
   constexpr int WPG = G / kWave;
   constexpr int NB = SLOTS / 4;
-  __shared__ int4 Ks[GPB][NB];
-  __shared__ uint32_t Cs[GPB][SLOTS];
-  __shared__ int32_t Wb[GPB][CAP];
-  __shared__ int32_t Wn[GPB][CAP];
-  __shared__ int32_t Ws[GPB][CAP];
-  __shared__ unsigned long long red[NT / kWave];
-  const int gi = threadIdx.x / G;
   const int g = threadIdx.x % G;
   const int wv = g / kWave;
   const int lane = lane_id();
-  const int idx = blockIdx.x * GPB + gi;
-  const int4* Kb = Ks[gi];
-  int32_t* K = reinterpret_cast<int32_t*>(Ks[gi]);
-  uint32_t* C = Cs[gi];
-  const bool active = idx < nlist;
-  int32_t u = 0;
+  const bool active = u >= 0;
+  int32_t* K = reinterpret_cast<int32_t*>(S.K);
   int64_t beg = 0;
-  int32_t len = 0;  // inactive groups run every phase with an empty list
+  int32_t len = 0;  // an inactive group runs every phase with an empty list
   if (active) {
-    u = list[idx];
     beg = doff[u];
     len = (int32_t)(doff[u + 1] - beg);
   }
-  for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
+  for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
   group_sync<G>();
   for (int i = g; i < len; i += G) {
     const int32_t w = dcol[beg + i];
-    Ws[gi][i] = bucket_insert<NB>(K, w);
+    S.Ws[i] = bucket_insert<NB>(K, w);
     const int64_t b = doff[w];
-    Wb[gi][i] = (int32_t)b;
-    Wn[gi][i] = (int32_t)(doff[w + 1] - b);
+    S.Wb[i] = (int32_t)b;
+    S.Wn[i] = (int32_t)(doff[w + 1] - b);
   }
   group_sync<G>();
   uint32_t tu = 0;  // wave-uniform
   for (int i = wv; i < len; i += WPG) {
-    const int32_t wb = __builtin_amdgcn_readfirstlane(Wb[gi][i]);
-    const int32_t wn = __builtin_amdgcn_readfirstlane(Wn[gi][i]);
+    const int32_t wb = __builtin_amdgcn_readfirstlane(S.Wb[i]);
+    const int32_t wn = __builtin_amdgcn_readfirstlane(S.Wn[i]);
     if (wn == 0) continue;
     const int32_t* L = dcol + wb;
     uint32_t cw = 0;
@@ -271,31 +270,102 @@ __global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ l
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const bool v = p + k * kWave + lane < wn;
-        const int s = bucket_probe<NB>(Kb, x[k], v);
-        if (s >= 0) atomicAdd(&C[s], 1u);
+        const int s = bucket_probe<NB>(S.K, x[k], v);
+        if (s >= 0) atomicAdd(&S.C[s], 1u);
         cw += (uint32_t)__popcll(__ballot(s >= 0));
       }
     }
-    if (cw && lane == 0) atomicAdd(&C[Ws[gi][i]], cw);
+    if (cw && lane == 0) atomicAdd(&S.C[S.Ws[i]], cw);
     tu += cw;
   }
   group_sync<G>();
   for (int s = g; s < SLOTS; s += G) {
     const int32_t k = K[s];
-    const uint32_t c = C[s];
+    const uint32_t c = S.C[s];
     if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
   }
   if constexpr (WPG == 1) {
     if (active && lane == 0 && tu) atomicAdd(&T[u], (unsigned long long)tu);
   } else {
-    if (lane == 0) red[threadIdx.x / kWave] = tu;
+    if (lane == 0) red[wv] = tu;
     __syncthreads();
     if (active && g == 0) {
       unsigned long long t = 0;
-      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
+      for (int k = 0; k < WPG; ++k) t += red[k];
       if (t) atomicAdd(&T[u], t);
     }
+    __syncthreads();  // red and the table may be reused by the caller
   }
+}
+
+template <int NT, int G, int SLOTS, int CAP, int U>
+__global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ list, int32_t nlist,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int32_t* __restrict__ dcol,
+                                                   unsigned long long* __restrict__ T) {
+  static_assert(NT % G == 0 && (G == kWave || G == NT), "groups are single waves or whole blocks");
+  constexpr int GPB = NT / G;
+  __shared__ WaveGroupLds<SLOTS, CAP> lds[GPB];
+  __shared__ unsigned long long red[NT / kWave];
+  const int gi = threadIdx.x / G;
+  const int idx = blockIdx.x * GPB + gi;
+  node_count_wave<G, SLOTS, CAP, U>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T);
+}
+
+// Merge variant for short lists: a group of G lanes owns node u and each
+// lane takes whole out-edges u->w, merging the sorted lists N+(u) and N+(w)
+// straight from memory (the classic two-pointer intersection; N+(u) is
+// re-read by every lane of the group, from cache). Hits go to T with global
+// atomics, which suits graphs with few triangles per edge.
+template <int G>
+__device__ __forceinline__ void node_count_merge(int32_t u, const int64_t* __restrict__ doff,
+                                                 const int32_t* __restrict__ dcol,
+                                                 unsigned long long* __restrict__ T) {
+  const int g = threadIdx.x % G;
+  unsigned long long tu = 0;
+  if (u >= 0) {
+    const int64_t ub = doff[u];
+    const int32_t nu = (int32_t)(doff[u + 1] - ub);
+    const int32_t* U = dcol + ub;
+    for (int32_t i = g; i < nu; i += G) {
+      const int32_t w = U[i];
+      const int64_t wb = doff[w];
+      const int32_t nw = (int32_t)(doff[w + 1] - wb);
+      const int32_t* W = dcol + wb;
+      int32_t a = 0, b = 0;
+      uint32_t c = 0;
+      int32_t xa = nu > 0 ? U[0] : 0, xb = nw > 0 ? W[0] : 0;
+      while (a < nu && b < nw) {
+        if (xa == xb) {
+          atomicAdd(&T[xa], 1ull);
+          ++c;
+          ++a;
+          ++b;
+          xa = a < nu ? U[a] : 0;
+          xb = b < nw ? W[b] : 0;
+        } else if (xa < xb) {
+          ++a;
+          xa = a < nu ? U[a] : 0;
+        } else {
+          ++b;
+          xb = b < nw ? W[b] : 0;
+        }
+      }
+      if (c) atomicAdd(&T[w], (unsigned long long)c);
+      tu += c;
+    }
+  }
+  tu = group_sum<unsigned long long, G>(tu);
+  if (u >= 0 && g == 0 && tu) atomicAdd(&T[u], tu);
+}
+
+template <int NT, int G>
+__global__ __launch_bounds__(NT) void k_count_merge(const int32_t* __restrict__ list, int32_t nlist,
+                                                    const int64_t* __restrict__ doff,
+                                                    const int32_t* __restrict__ dcol,
+                                                    unsigned long long* __restrict__ T) {
+  const int idx = (blockIdx.x * NT + threadIdx.x) / G;
+  node_count_merge<G>(idx < nlist ? list[idx] : -1, doff, dcol, T);
 }
 
 // Plain variant: no staging, one id per lane per iteration, linear probing
@@ -381,14 +451,13 @@ __global__ __launch_bounds__(NT) void k_count_plain(const int32_t* __restrict__ 
   }
 }
 
-// Fallback for out-lists of any length: one block per node, N+(u) stays in
-// global memory and is binary-searched; hits are credited with global atomics.
-__global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict__ list, int32_t nlist,
-                                                      const int64_t* __restrict__ doff,
-                                                      const int32_t* __restrict__ dcol,
-                                                      unsigned long long* __restrict__ T) {
-  __shared__ unsigned long long red[256 / kWave];
-  const int32_t u = list[blockIdx.x];
+// Fallback for out-lists of any length: one block of 256 per node, N+(u)
+// stays in global memory and is binary-searched; hits are credited with
+// global atomics.
+__device__ __forceinline__ void node_count_global(int32_t u, unsigned long long* red,
+                                                  const int64_t* __restrict__ doff,
+                                                  const int32_t* __restrict__ dcol,
+                                                  unsigned long long* __restrict__ T) {
   const int64_t beg = doff[u];
   const int32_t len = (int32_t)(doff[u + 1] - beg);
   const int32_t* U = dcol + beg;
@@ -415,6 +484,154 @@ __global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict_
   }
   const unsigned long long t = block_sum<unsigned long long, 256>(tu, red);
   if (threadIdx.x == 0 && t) atomicAdd(&T[u], t);
+}
+
+__global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict__ list, int32_t nlist,
+                                                      const int64_t* __restrict__ doff,
+                                                      const int32_t* __restrict__ dcol,
+                                                      unsigned long long* __restrict__ T) {
+  __shared__ unsigned long long red[256 / kWave];
+  node_count_global(list[blockIdx.x], red, doff, dcol, T);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form (batched graphs): one launch covers every node of the
+// DAG. Blocks of 256 pull chunks from an atomic work queue, heaviest first:
+// nodes above the block table's capacity (global fallback), then nodes for a
+// whole block (d+ <= CB), then four single-wave nodes (d+ <= CW) at a time,
+// then 32 short-list nodes at a time for the 8-lane merge.
+template <int SW, int CW, int SB, int CB>
+__global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict__ glist, int32_t ng,
+                                                       const int32_t* __restrict__ blist, int32_t nbk,
+                                                       const int32_t* __restrict__ wlist, int32_t nw,
+                                                       const int32_t* __restrict__ mlist, int32_t nm,
+                                                       int32_t* __restrict__ queue,
+                                                       const int64_t* __restrict__ doff,
+                                                       const int32_t* __restrict__ dcol,
+                                                       unsigned long long* __restrict__ T) {
+  using BL = WaveGroupLds<SB, CB>;
+  using WL = WaveGroupLds<SW, CW>;
+  constexpr size_t kBytes = sizeof(BL) > 4 * sizeof(WL) ? sizeof(BL) : 4 * sizeof(WL);
+  __shared__ __align__(16) unsigned char smem[kBytes];
+  __shared__ unsigned long long red[256 / kWave];
+  __shared__ int32_t chunk;
+  constexpr int kMergeG = 8;
+  constexpr int kMergePerChunk = 256 / kMergeG;
+  const int64_t nwc = ((int64_t)nw + 3) / 4;
+  const int64_t total = (int64_t)ng + nbk + nwc + ((int64_t)nm + kMergePerChunk - 1) / kMergePerChunk;
+  while (true) {
+    if (threadIdx.x == 0) chunk = atomicAdd(queue, 1);
+    __syncthreads();
+    const int64_t c = chunk;
+    __syncthreads();
+    if (c >= total) break;
+    if (c < ng) {
+      node_count_global(glist[c], red, doff, dcol, T);
+    } else if (c < (int64_t)ng + nbk) {
+      node_count_wave<256, SB, CB, 4>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
+    } else if (c < (int64_t)ng + nbk + nwc) {
+      const int wv = threadIdx.x / kWave;
+      const int64_t k = (c - ng - nbk) * 4 + wv;
+      node_count_wave<kWave, SW, CW, 4>(k < nw ? wlist[k] : -1, reinterpret_cast<WL*>(smem)[wv], red, doff, dcol,
+                                         T);
+    } else {
+      const int64_t k = (c - ng - nbk - nwc) * kMergePerChunk + threadIdx.x / kMergeG;
+      node_count_merge<kMergeG>(k < nm ? mlist[k] : -1, doff, dcol, T);
+    }
+    __syncthreads();
+  }
+}
+
+struct PersistShape { int sw, cw, sb, cb; };
+static constexpr PersistShape kPersist[] = {
+    {256, 64, 1024, 256},   // 0: block nodes up to d+ 256
+    {256, 64, 4096, 1024},  // 1: block nodes up to d+ 1024
+};
+int persist_variant_count() { return (int)(sizeof(kPersist) / sizeof(kPersist[0])); }
+int persist_wave_cap(int v) { return kPersist[v].cw; }
+int persist_block_cap(int v) { return kPersist[v].cb; }
+
+const void* persist_kernel(int v) {
+  switch (v) {
+    case 0: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256>);
+    case 1: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024>);
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
+                                int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
+                                hipStream_t s) {
+  switch (v) {
+    case 0:
+      k_count_persist<256, 64, 1024, 256><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue, doff,
+                                                               dcol, T);
+      break;
+    case 1:
+      k_count_persist<256, 64, 4096, 1024><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                doff, dcol, T);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Clears T[n] and the work-queue counter (a kernel, so that it can sit in a
+// captured graph).
+__global__ __launch_bounds__(256) void k_batch_zero(unsigned long long* __restrict__ T, int64_t n,
+                                                    int32_t* __restrict__ queue) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) *queue = 0;
+  for (int64_t i = i0; i < n; i += stride) T[i] = 0ull;
+}
+
+hipError_t launch_batch_zero(unsigned long long* T, int64_t n, int32_t* queue, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  k_batch_zero<<<(unsigned)g, 256, 0, s>>>(T, n, queue);
+  return hipGetLastError();
+}
+
+// Per-graph epilogue: one block per graph g owns nodes [node_off[g],
+// node_off[g+1]): CC(v) as in the single-graph epilogue, the graph's
+// triangle total (sum of T / 3) and its average CC over its n_g nodes, each
+// summed in a fixed order that depends only on the graph.
+__global__ __launch_bounds__(256) void k_graph_epilogue(const int64_t* __restrict__ node_off,
+                                                        const unsigned long long* __restrict__ T,
+                                                        const int32_t* __restrict__ deg, float* __restrict__ cc,
+                                                        unsigned long long* __restrict__ graph_tri,
+                                                        double* __restrict__ graph_avg) {
+  __shared__ double red_d[256 / kWave];
+  __shared__ unsigned long long red_t[256 / kWave];
+  const int64_t nb = node_off[blockIdx.x], ne = node_off[blockIdx.x + 1];
+  double acc = 0.0;
+  unsigned long long tacc = 0;
+  for (int64_t v = nb + threadIdx.x; v < ne; v += 256) {
+    const unsigned long long t = T[v];
+    const int64_t d = deg[v];
+    double r = 0.0;
+    if (d >= 2) r = (2.0 * (double)t) / ((double)d * (double)(d - 1));
+    cc[v] = (float)r;
+    acc += r;
+    tacc += t;
+  }
+  const double sd = block_sum<double, 256>(acc, red_d);
+  const unsigned long long st = block_sum<unsigned long long, 256>(tacc, red_t);
+  if (threadIdx.x == 0) {
+    graph_tri[blockIdx.x] = st / 3ull;
+    graph_avg[blockIdx.x] = ne > nb ? sd / (double)(ne - nb) : 0.0;
+  }
+}
+
+hipError_t launch_graph_epilogue(int32_t num_graphs, const int64_t* node_off, const unsigned long long* T,
+                                 const int32_t* deg, float* cc, unsigned long long* graph_tri, double* graph_avg,
+                                 hipStream_t s) {
+  if (num_graphs <= 0) return hipSuccess;
+  k_graph_epilogue<<<num_graphs, 256, 0, s>>>(node_off, T, deg, cc, graph_tri, graph_avg);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -448,7 +665,11 @@ static constexpr VariantInfo kVariants[] = {
     {256, 64, 64, 256, 64},       // 22: d+ <= 64, denser table
     {256, 256, 64, 1024, 256},    // 23: d+ <= 256, denser table
     {512, 512, 64, 4096, 1024},   // 24: d+ <= 1024, denser table
-    {256, 256, 64, 0},       // 25: global fallback, any d+
+    // merge kernel (lane group per node, two-pointer merge per out-edge)
+    {256, 4, 0, -1, 1 << 20},     // 25: any d+ (short lists)
+    {256, 8, 0, -1, 1 << 20},     // 26
+    {256, 16, 0, -1, 1 << 20},    // 27
+    {256, 256, 64, 0},       // 28: global fallback, any d+
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = kNumVariants - 1;
@@ -457,6 +678,7 @@ int count_variant_valid(int v) { return v >= 0 && v < kNumVariants; }
 int count_variant_capacity(int v) {
   if (!count_variant_valid(v)) return -1;
   if (!kVariants[v].slots) return 0x7fffffff;
+  if (kVariants[v].slots < 0) return kVariants[v].cap;  // table-free kernels
   return kVariants[v].cap ? kVariants[v].cap : kVariants[v].slots / 2;
 }
 
@@ -513,6 +735,9 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 22: launch_wave<256, 64, 256, 64>(b, doff, dcol, T, s); break;
     case 23: launch_wave<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
     case 24: launch_wave<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
+    case 25: k_count_merge<256, 4><<<(unsigned)(((int64_t)b.count * 4 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
+    case 26: k_count_merge<256, 8><<<(unsigned)(((int64_t)b.count * 8 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
+    case 27: k_count_merge<256, 16><<<(unsigned)(((int64_t)b.count * 16 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;

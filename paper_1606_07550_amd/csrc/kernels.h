@@ -97,4 +97,26 @@ hipError_t launch_epilogue(int32_t n, const unsigned long long* T, const int32_t
 hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const unsigned long long* part_T,
                          unsigned long long* total, double* avg, hipStream_t s);
 
+// ---- Batched graphs ---------------------------------------------------------
+// Persistent intersection kernel over four node lists (hubs -> global
+// fallback, block nodes, single-wave nodes, short-list merge nodes); queue
+// must be 0 at launch.
+int persist_variant_count();
+int persist_wave_cap(int v);   // largest d+ of a single-wave node
+int persist_block_cap(int v);  // largest d+ of a block node
+const void* persist_kernel(int v);
+hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
+                                int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
+                                hipStream_t s);
+hipError_t launch_batch_zero(unsigned long long* T, int64_t n, int32_t* queue, hipStream_t s);
+hipError_t launch_graph_epilogue(int32_t num_graphs, const int64_t* node_off, const unsigned long long* T,
+                                 const int32_t* deg, float* cc, unsigned long long* graph_tri, double* graph_avg,
+                                 hipStream_t s);
+// Local -> global ids of a packed batch: edge e of graph g gets node_off[g]
+// added; err is set if a local id is outside [0, n_g).
+hipError_t launch_batch_relabel(int32_t num_graphs, const int64_t* node_off, const int64_t* edge_off,
+                                const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t* gsrc,
+                                int32_t* gdst, int32_t* err, hipStream_t s);
+
 }  // namespace tricc

@@ -1,0 +1,165 @@
+"""GPU parity of the batched path: per-graph results against the oracle run
+on each graph alone; hipGraph replays against eager launches; batched
+against single-graph results; every persistent variant and work split."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1606_07550_amd as P
+from paper_1606_07550_amd import _native as N
+from paper_1606_07550_amd import inputs as I
+from paper_1606_07550_amd.inputs import fixtures as F
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CC_RTOL = 1e-6
+
+
+def pack(graphs):
+    """[(n, src, dst)] -> node_off, edge_off, src, dst (local ids)."""
+    node_off = np.zeros(len(graphs) + 1, np.int64)
+    edge_off = np.zeros(len(graphs) + 1, np.int64)
+    for i, (n, s, d) in enumerate(graphs):
+        node_off[i + 1] = node_off[i] + n
+        edge_off[i + 1] = edge_off[i] + len(s)
+    src = np.concatenate([g[1] for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
+    dst = np.concatenate([g[2] for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
+    return node_off, edge_off, src, dst
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+
+
+def to_host(out):
+    return {
+        "T": out["T"].cpu().numpy().view(np.uint64),
+        "cc": out["cc"].cpu().numpy(),
+        "graph_tri": out["graph_tri"].cpu().numpy().view(np.uint64),
+        "graph_avg": out["graph_avg"].cpu().numpy(),
+    }
+
+
+def check_batch(r, graphs, node_off):
+    for gi, (n, s, d) in enumerate(graphs):
+        ref = oracle.count(n, s, d)
+        a, b = node_off[gi], node_off[gi + 1]
+        np.testing.assert_array_equal(r["T"][a:b], ref["T"], err_msg=f"graph {gi}")
+        assert r["graph_tri"][gi] == ref["total"], gi
+        np.testing.assert_allclose(r["cc"][a:b].astype(np.float64), ref["cc"], rtol=CC_RTOL, atol=0)
+        assert np.array_equal(r["cc"][a:b] == 0, ref["cc"] == 0)
+        assert abs(r["graph_avg"][gi] - ref["avg"]) <= CC_RTOL * abs(ref["avg"]), gi
+
+
+def mixed_graphs():
+    b = I.batch(48, 77, nmin=64, nmax=3000)
+    graphs = []
+    for g in range(48):
+        e0, e1 = b["edge_off"][g], b["edge_off"][g + 1]
+        graphs.append((int(b["n"][g]), b["src"][e0:e1], b["dst"][e0:e1]))
+    graphs += [F.complete(300), F.wheel(40), F.star(500), (7, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+               (0, np.zeros(0, np.int32), np.zeros(0, np.int32)), F.messy(*F.windmill(9), seed=3)]
+    n, s, d = I.rmat(12, 16, seed=5)
+    graphs.append((n, s, d))
+    return graphs
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    graphs = mixed_graphs()
+    return graphs, pack(graphs)
+
+
+def test_batch_matches_oracle(mixed):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    print(f"[batch] G={len(graphs)} nodes={node_off[-1]} pairs={edge_off[-1]}", flush=True)
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst))
+    info = b.info
+    assert info["hub_nodes"] > 0  # K_300 has out-degrees above 256
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(to_host(b.out), graphs, node_off)
+
+
+def test_graph_replays_match_eager(mixed):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst))
+    b.plan()
+    b.run_eager()
+    torch.cuda.synchronize()
+    ref = to_host(b.out)
+    scratch = torch.zeros(1 << 20, device=DEV)
+    for rep in range(4):
+        scratch.add_(1.0)  # unrelated eager work between replays
+        b.out["T"].fill_(7)
+        b.out["graph_avg"].fill_(-1.0)
+        b.run()
+        torch.cuda.synchronize()
+        r = to_host(b.out)
+        for k in ref:
+            np.testing.assert_array_equal(r[k], ref[k], err_msg=f"replay {rep} field {k}")
+
+
+@pytest.mark.parametrize("tun", [
+    {"merge_limit": 0, "wave_limit": 64, "persist_variant": 0, "blocks_per_cu": 0},
+    {"merge_limit": 0, "wave_limit": 16, "persist_variant": 0, "blocks_per_cu": 1},
+    {"merge_limit": 2, "wave_limit": 2, "persist_variant": 1, "blocks_per_cu": 2},
+    {"merge_limit": 40, "wave_limit": 40, "persist_variant": 1, "blocks_per_cu": 0},
+    {"merge_limit": 64, "wave_limit": 64, "persist_variant": 0, "blocks_per_cu": 4},
+    {"merge_limit": 8, "wave_limit": 32, "persist_variant": 0, "blocks_per_cu": 0},
+])
+def test_tunings_agree(mixed, tun):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst), tuning=tun)
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(to_host(b.out), graphs, node_off)
+    # retune back to the default and compare
+    b.retune(P.default_batch_tuning())
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(to_host(b.out), graphs, node_off)
+
+
+def test_batched_equals_single_graph(mixed):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst))
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    r = to_host(b.out)
+    for gi in (0, 5, 17, len(graphs) - 1):
+        n, s, d = graphs[gi]
+        g = P.Graph(n, dev(s), dev(d))
+        o = g.count()
+        torch.cuda.synchronize()
+        a, e = node_off[gi], node_off[gi + 1]
+        np.testing.assert_array_equal(o["T"].cpu().numpy().view(np.uint64), r["T"][a:e])
+        np.testing.assert_array_equal(o["cc"].cpu().numpy(), r["cc"][a:e])
+        assert int(o["total"].cpu().numpy().view(np.uint64)[0]) == r["graph_tri"][gi]
+        assert abs(o["avg"].item() - r["graph_avg"][gi]) <= 1e-12 * max(1e-300, abs(r["graph_avg"][gi]))
+
+
+def test_bad_local_id_is_rejected():
+    graphs = [F.complete(5), (4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))]
+    node_off, edge_off, src, dst = pack(graphs)
+    with pytest.raises(N.TriccError) as ei:
+        P.Batch(node_off, edge_off, dev(src), dev(dst))
+    assert ei.value.status == N.TRICC_ERANGE
+
+
+def test_empty_batch_members():
+    graphs = [(0, np.zeros(0, np.int32), np.zeros(0, np.int32)), (3, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+              F.complete(4)]
+    node_off, edge_off, src, dst = pack(graphs)
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst))
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    r = to_host(b.out)
+    assert list(r["graph_tri"]) == [0, 0, 4]
+    assert r["graph_avg"][0] == 0.0 and r["graph_avg"][1] == 0.0 and r["graph_avg"][2] == 1.0
