@@ -216,6 +216,11 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
 int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
                      double* d_graph_avg, void* stream);
 
+/* Binds the outputs without capturing a graph (for tricc_batch_run_eager
+ * only; a later tricc_batch_plan rebinds). Same buffers as tricc_batch_plan. */
+int tricc_batch_bind(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
+                     double* d_graph_avg);
+
 /* One hipGraphLaunch of the planned count. Asynchronous. Calls on one
  * batch must not overlap (they share the accumulators). */
 int tricc_batch_run(tricc_batch* b, void* stream);
@@ -233,6 +238,70 @@ int tricc_batch_info_get(const tricc_batch* b, tricc_batch_info* out);
 const tricc_graph* tricc_batch_graph(const tricc_batch* b);
 
 void tricc_batch_free(tricc_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Query server: triangle count and average clustering coefficient of
+ * induced subgraphs G[S] of a graph resident on the device (subgraph
+ * extraction, Section 4's table of methods; ids keep their identity,
+ * Section 3.1). Degrees are taken inside G[S] and the average is over |S|.
+ *
+ * The server runs `slots` worker threads, each with its own HIP stream and
+ * an equal slice of the caller's device workspace. A worker takes every
+ * waiting query that fits its slice (arrival order, at most
+ * max_batch_queries) and runs extraction, build and count for them as one
+ * batch; queries that arrive meanwhile are taken by the next free worker
+ * (continuous batching), and the workers' device work overlaps. A query's
+ * result does not depend on which other queries share its batch.
+ */
+typedef struct tricc_server tricc_server;
+
+typedef struct tricc_result {
+  uint64_t qid;
+  int64_t k;            /* |S| */
+  uint64_t triangles;   /* triangles of G[S] */
+  double avg_cc;        /* (1/|S|) sum over S of CC in G[S] (FP64, fixed order) */
+  int64_t m;            /* edges of G[S] */
+  double t_arrival;     /* as submitted (server clock, seconds) */
+  double t_start;       /* batch start */
+  double t_done;        /* results on the host */
+  int32_t batch_size;   /* queries in the same batch */
+  int32_t status;       /* TRICC_OK or the error of the batch */
+} tricc_result;
+
+/* `resident` must outlive the server. d_ws / ws_bytes: device workspace,
+ * split into `slots` equal slices (1..16); it is also the admission budget:
+ * the sum of the admitted, unfinished queries' device bytes never exceeds
+ * ws_bytes. Starts the workers. */
+int tricc_server_create(const tricc_graph* resident, void* d_ws, size_t ws_bytes, int32_t slots,
+                        int32_t max_batch_queries, tricc_server** out);
+
+/* Seconds since the server was created (steady clock). */
+double tricc_server_now(const tricc_server* s);
+
+/* Device bytes a query would need (its admission cost); 0 on bad input. */
+size_t tricc_server_query_bytes(const tricc_server* s, const int32_t* h_nodes, int64_t k);
+
+/* Admits query (qid, S = h_nodes[0..k)) with arrival time t_arrival (server
+ * clock). The node list is copied. Errors: TRICC_EBUSY when the memory
+ * budget is in use (retry after results come back), TRICC_ENOMEM when the
+ * query can never fit one slot, TRICC_ERANGE / TRICC_EINVAL for ids outside
+ * [0, n) or repeated ids. Thread-safe. */
+int tricc_server_submit(tricc_server* s, uint64_t qid, const int32_t* h_nodes, int64_t k, double t_arrival);
+
+/* Moves up to `cap` finished results into out; *n_out = how many. */
+int tricc_server_poll(tricc_server* s, tricc_result* out, int32_t cap, int32_t* n_out);
+
+/* Blocks until every admitted query has finished; returns the first batch
+ * error, if any. */
+int tricc_server_drain(tricc_server* s);
+
+int tricc_server_stats(const tricc_server* s, int64_t* waiting, int64_t* in_flight, size_t* outstanding_bytes);
+
+/* Error text of the calling thread's last failed server call. */
+const char* tricc_server_last_error(void);
+
+/* Stops the workers (after the queries in progress) and frees the server. */
+void tricc_server_free(tricc_server* s);
 
 #ifdef __cplusplus
 }

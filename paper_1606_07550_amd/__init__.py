@@ -10,3 +10,4 @@ that needs it does, and raises if it is not built.
 from .graph import Graph, count, default_tuning, variant_capacity, variant_count, workspace_size  # noqa: F401
 from ._native import TriccError  # noqa: F401
 from .batch import Batch, batch_workspace_size, default_batch_tuning  # noqa: F401
+from .serve import Server  # noqa: F401

@@ -81,6 +81,16 @@ class BatchInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class QueryResult(ctypes.Structure):
+    _fields_ = [("qid", ctypes.c_uint64), ("k", ctypes.c_int64), ("triangles", ctypes.c_uint64),
+                ("avg_cc", ctypes.c_double), ("m", ctypes.c_int64), ("t_arrival", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("batch_size", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _LIB = None
 
 # name -> (restype, argtypes)
@@ -112,12 +122,24 @@ _SIGS = {
     "tricc_batch_build": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                          ctypes.POINTER(BatchTuning), _P, ctypes.POINTER(_P)]),
     "tricc_batch_plan": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_batch_bind": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "tricc_batch_run": (ctypes.c_int, [_P, _P]),
     "tricc_batch_run_eager": (ctypes.c_int, [_P, _P]),
     "tricc_batch_retune": (ctypes.c_int, [_P, ctypes.POINTER(BatchTuning), _P]),
     "tricc_batch_info_get": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
     "tricc_batch_graph": (_P, [_P]),
     "tricc_batch_free": (None, [_P]),
+    "tricc_server_create": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(_P)]),
+    "tricc_server_now": (ctypes.c_double, [_P]),
+    "tricc_server_query_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int64]),
+    "tricc_server_submit": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_int64, ctypes.c_double]),
+    "tricc_server_poll": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "tricc_server_drain": (ctypes.c_int, [_P]),
+    "tricc_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "tricc_server_last_error": (ctypes.c_char_p, []),
+    "tricc_server_free": (None, [_P]),
 }
 
 

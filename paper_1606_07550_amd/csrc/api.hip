@@ -766,6 +766,20 @@ int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uin
   return rc;
 }
 
+int tricc_batch_bind(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
+                     double* d_graph_avg) {
+  if (!b) return fail(TRICC_EINVAL, "null batch");
+  if ((b->n_total > 0 && (!d_node_tri || !d_node_cc)) || (b->G > 0 && (!d_graph_tri || !d_graph_avg)))
+    return fail(TRICC_EINVAL, "null output");
+  batch_drop_plan(b);
+  b->T = reinterpret_cast<unsigned long long*>(d_node_tri);
+  b->cc = d_node_cc;
+  b->graph_tri = reinterpret_cast<unsigned long long*>(d_graph_tri);
+  b->graph_avg = d_graph_avg;
+  b->bound = true;
+  return TRICC_OK;
+}
+
 int tricc_batch_run(tricc_batch* b, void* stream) {
   if (!b) return fail(TRICC_EINVAL, "null batch");
   if (!b->exec) return fail(TRICC_EINVAL, "batch not planned");
