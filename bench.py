@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 METRIC = "triangle-count edges/s vs HBM roofline; batched graphs/s; p50/p99 query latency"
 HBM_PEAK_GBPS = 8000.0
 
@@ -46,6 +48,11 @@ def parse():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--autotune", action="store_true", help="search tunings first (cached per arch/workload)")
+    ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
+    ap.add_argument("--serve-queries", type=int, default=20000)
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-gb", type=float, default=24.0, help="server workspace (GB), also the admission budget")
+    ap.add_argument("--serve-tune", action="store_true", help="pick the server's batch tuning on a sample first")
     return ap.parse_args()
 
 
@@ -175,6 +182,92 @@ def batched_leg(args, torch, P, N):
         "build_ms": build_ms, "tuning": tuning, "grid": info["grid"],
         "lists": {"merge": info["merge_nodes"], "wave": info["wave_nodes"], "block": info["block_nodes"],
                   "hub": info["hub_nodes"]},
+    }
+
+
+def run_trace(P, N, g, queries, arrivals, slots, max_batch, budget, tuning=None):
+    """Replays a query trace against a fresh server. arrivals: offsets in
+    seconds from the start (None: all at once). Latency = completion seen on
+    the host - scheduled arrival (includes queueing and admission waits)."""
+    srv = P.Server(g, budget, slots=slots, max_batch_queries=max_batch)
+    if tuning is not None:
+        srv.set_tuning(tuning)
+    Q = len(queries)
+    t0 = srv.now() + 0.01
+    results = {}
+    i = 0
+    while len(results) < Q:
+        now = srv.now()
+        progressed = False
+        while i < Q and (arrivals is None or t0 + arrivals[i] <= now):
+            ta = t0 + (arrivals[i] if arrivals is not None else 0.0)
+            if srv.submit(i, queries[i], t_arrival=ta) == N.TRICC_EBUSY:
+                break
+            i += 1
+            progressed = True
+        for r in srv.poll():
+            results[r["qid"]] = r
+            progressed = True
+        if not progressed:
+            time.sleep(0.0002)
+    srv.drain()
+    srv.close()
+    bad = sum(1 for r in results.values() if r["status"] != 0)
+    lat = np.array([r["t_done"] - r["t_arrival"] for r in results.values()])
+    t_end = max(r["t_done"] for r in results.values())
+    t_first = t0 + (arrivals[0] if arrivals is not None else 0.0)
+    return {
+        "queries": Q, "failed": bad, "qps": Q / (t_end - t_first),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_batch": float(np.mean([r["batch_size"] for r in results.values()])),
+        "triangles": int(sum(r["triangles"] for r in results.values())),
+        "edges": int(sum(r["m"] for r in results.values())),
+        "edges_per_s": sum(r["m"] for r in results.values()) / (t_end - t_first),
+    }
+
+
+def serving_leg(args, torch, P, N):
+    """Resident R-MAT scale 22 (edge factor 16, same a,b,c,d); BFS-ball
+    queries of log-uniform size in [16, 100000] (seed 2022). Saturation
+    throughput, then an open-loop Poisson trace at 0.8 x saturation, against
+    a FIFO server that runs one query per launch."""
+    from paper_1606_07550_amd import inputs as I
+    dev = torch.device("cuda:0")
+    n, s, d = I.rmat(22, 16, seed=22)
+    t0 = time.perf_counter()
+    Q = args.serve_queries
+    off, nodes, _ = I.bfs_queries(n, s, d, Q, seed=2022)
+    log(f"generated {Q} BFS-ball queries ({off[-1]} nodes) in {time.perf_counter() - t0:.1f}s")
+    queries = [nodes[off[q]:off[q + 1]] for q in range(Q)]
+    g = P.Graph(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev))
+    budget = int(args.serve_gb * 1e9)
+    tuning = None
+    if args.serve_tune:
+        best = None
+        for ml in (0, 4, 16, 32):
+            for pv in (0, 1):
+                t = {"merge_limit": ml, "wave_limit": 64, "persist_variant": pv, "blocks_per_cu": 0}
+                r = run_trace(P, N, g, queries[:max(200, Q // 10)], None, args.serve_slots, 256, budget, t)
+                log(f"serve tuning {t}: {r['qps']:.1f} q/s")
+                if best is None or r["qps"] > best[0]:
+                    best = (r["qps"], t)
+        tuning = best[1]
+    sat = run_trace(P, N, g, queries, None, args.serve_slots, 256, budget, tuning)
+    log(f"saturation: {sat}")
+    lam = 0.8 * sat["qps"]
+    arr = I.poisson_arrivals(Q, lam, 4)
+    arr = arr - arr[0]
+    open_loop = run_trace(P, N, g, queries, arr, args.serve_slots, 256, budget, tuning)
+    log(f"poisson at {lam:.1f}/s: {open_loop}")
+    fifo_sat = run_trace(P, N, g, queries, None, 1, 1, budget, tuning)
+    log(f"fifo saturation: {fifo_sat}")
+    return {
+        "workload": f"serving-rmat22-{Q}", "resident": {"n": n, "m": g.info["m"]},
+        "queries": Q, "query_nodes": int(off[-1]), "slots": args.serve_slots, "budget_bytes": budget,
+        "tuning": tuning,
+        "saturation": sat, "lambda_qps": lam, "poisson": open_loop,
+        "fifo_per_query": {"saturation": fifo_sat},
+        "p50_ms": open_loop["p50_ms"], "p99_ms": open_loop["p99_ms"], "qps": open_loop["qps"],
     }
 
 
@@ -329,6 +422,9 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         line["batched"] = batched_leg(args, torch, P, N)
+    if args.serving:
+        log("serving leg ...")
+        line["serving"] = serving_leg(args, torch, P, N)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on its sample ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)

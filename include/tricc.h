@@ -188,7 +188,8 @@ typedef struct tricc_batch_info {
   int64_t total_pairs;
   int64_t m;                  /* undirected simple edges over all graphs */
   int64_t max_outdeg;
-  int64_t merge_nodes, wave_nodes, block_nodes, hub_nodes; /* the persistent kernel's lists */
+  int64_t merge_nodes, wave_nodes, block_nodes; /* the persistent kernel's lists */
+  int64_t hub_nodes;          /* nodes above the block table: large-table kernels and the fallback */
   int32_t grid;               /* persistent blocks */
   int32_t planned;            /* a hipGraph is instantiated */
 } tricc_batch_info;
@@ -274,6 +275,10 @@ typedef struct tricc_result {
  * ws_bytes. Starts the workers. */
 int tricc_server_create(const tricc_graph* resident, void* d_ws, size_t ws_bytes, int32_t slots,
                         int32_t max_batch_queries, tricc_server** out);
+
+/* Batch tuning for batches started after this call (default: the batch
+ * default). Thread-safe. */
+int tricc_server_set_tuning(tricc_server* s, const tricc_batch_tuning* tuning);
 
 /* Seconds since the server was created (steady clock). */
 double tricc_server_now(const tricc_server* s);

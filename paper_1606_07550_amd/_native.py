@@ -132,6 +132,7 @@ _SIGS = {
     "tricc_server_create": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.POINTER(_P)]),
     "tricc_server_now": (ctypes.c_double, [_P]),
+    "tricc_server_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(BatchTuning)]),
     "tricc_server_query_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int64]),
     "tricc_server_submit": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_int64, ctypes.c_double]),
     "tricc_server_poll": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),

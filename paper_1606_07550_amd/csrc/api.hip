@@ -589,14 +589,18 @@ int check_batch_tuning(const tricc_batch_tuning* t) {
   return TRICC_OK;
 }
 
-// Bins of the union graph for the persistent kernel: bin 0 = merge nodes
-// (d+ <= merge_limit), bin 1 = single-wave nodes, bin 2 = block nodes,
-// bin 5 = hubs (global fallback); bins 3..4 stay empty. The single-graph
-// variants are set so that tricc_count also works on the union.
+// Bins of the union graph: bin 0 = merge nodes (d+ <= merge_limit), bin 1
+// = single-wave nodes (d+ <= wave_limit), bin 2 = block nodes (d+ <= the
+// persistent block table's capacity): all three, and bin 5 (d+ > 4096,
+// global fallback), run in the persistent kernel; bins 3 (up to 1024) and 4
+// (up to 4096) run before it with the large-table kernel variants. The
+// single-graph variants are set so that tricc_count also works on the union.
+constexpr int kBatchVarBin3 = 24;  // 512 threads, table for d+ <= 1024
+constexpr int kBatchVarBin4 = 21;  // 1024 threads, table for d+ <= 4096
 void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
   const int32_t cb = persist_block_cap(bt.persist_variant);
-  const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, cb, cb};
-  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, 24, 24, 28};
+  const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, std::max(cb, 1024), 4096};
+  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 28};
   std::memcpy(t->bin_limit, lim, sizeof(lim));
   std::memcpy(t->bin_variant, var, sizeof(var));
 }
@@ -620,6 +624,11 @@ int batch_launch(tricc_batch* b, hipStream_t s) {
   const Layout& L = g->L;
   const int32_t* binlist = g->at<int32_t>(L.binlist);
   HIPCHK(launch_batch_zero(b->T, b->n_total, b->d_queue, s));
+  // the heaviest nodes first, with the large LDS tables
+  for (int bin = 4; bin >= 3; --bin) {
+    BinLaunch bl{g->tuning.bin_variant[bin], binlist + g->bin_off[bin], (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin])};
+    HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, s));
+  }
   const int32_t nm = (int32_t)(g->bin_off[1] - g->bin_off[0]);
   const int32_t nw = (int32_t)(g->bin_off[2] - g->bin_off[1]);
   const int32_t nbk = (int32_t)(g->bin_off[3] - g->bin_off[2]);
@@ -814,7 +823,7 @@ int tricc_batch_info_get(const tricc_batch* b, tricc_batch_info* out) {
   out->merge_nodes = g.bin_off[1] - g.bin_off[0];
   out->wave_nodes = g.bin_off[2] - g.bin_off[1];
   out->block_nodes = g.bin_off[3] - g.bin_off[2];
-  out->hub_nodes = g.bin_off[kNumBins] - g.bin_off[kNumBins - 1];
+  out->hub_nodes = g.bin_off[kNumBins] - g.bin_off[3];  // large-table bins and the fallback
   out->grid = (int32_t)b->grid;
   out->planned = b->exec != nullptr;
   return TRICC_OK;

@@ -145,6 +145,7 @@ struct tricc_server {
   std::vector<int32_t> stamp;  // host-side id check
   int64_t stamp_epoch = 0;
   std::chrono::steady_clock::time_point t0;
+  tricc_batch_tuning tuning{};
   int first_error = TRICC_OK;
   char first_error_text[512] = "";
   double now() const {
@@ -162,8 +163,7 @@ namespace {
 
 // Runs one batch on a slot; fills results. Returns a TRICC status.
 int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, std::vector<tricc_result>& out,
-              std::vector<char>& pinned_guard) {
-  (void)pinned_guard;
+              const tricc_batch_tuning& bt) {
   const int32_t G = (int32_t)B.size();
   int64_t N = 0, D = 0, M = 0, Tsl = 0;
   std::vector<int64_t> qoff(G + 1, 0), toff(G + 1, 0);
@@ -224,8 +224,6 @@ int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, 
   SCHK(launch_serve_pairs(1, G, d_qoff, nodes, coff, C, d_toff, tab, S->off, S->deg, S->adj, cnt, pos, psrc, pdst,
                           st));
   tricc_batch* b = nullptr;
-  tricc_batch_tuning bt;
-  tricc_batch_default_tuning(&bt);
   int rc = tricc_batch_build(G, qoff.data(), hq.data(), psrc, pdst, at(L.batch), S->slot_bytes - L.batch, &bt, st, &b);
   if (rc) return rc;
   rc = tricc_batch_bind(b, T, cc, gtri, gavg);
@@ -262,13 +260,14 @@ void worker_main(tricc_server* S, int slot) {
   hipStream_t st;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
   char* ws = S->ws + (size_t)slot * S->slot_bytes;
-  std::vector<char> guard;
   while (true) {
     std::vector<Query> B;
+    tricc_batch_tuning bt;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !S->waiting.empty(); });
       if (S->waiting.empty() && S->stop) break;
+      bt = S->tuning;
       // continuous batching: everything waiting that fits this slot, in order
       int64_t G = 0, N = 0, D = 0, M = 0, Tsl = 0;
       while (!S->waiting.empty() && G < S->max_batch) {
@@ -287,7 +286,7 @@ void worker_main(tricc_server* S, int slot) {
     }
     const double t_start = S->now();
     std::vector<tricc_result> res;
-    const int rc = run_batch(S, ws, st, B, res, guard);
+    const int rc = run_batch(S, ws, st, B, res, bt);
     size_t freed = 0;
     for (const Query& q : B) freed += q.cost;
     std::lock_guard<std::mutex> lk(S->mu);
@@ -359,9 +358,21 @@ int tricc_server_create(const tricc_graph* resident, void* d_ws, size_t ws_bytes
   S->nslots = slots;
   S->max_batch = max_batch_queries;
   S->stamp.assign(info.n, -1);
+  tricc_batch_default_tuning(&S->tuning);
   S->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < slots; ++i) S->workers.emplace_back(worker_main, S, i);
   *out = S;
+  return TRICC_OK;
+}
+
+int tricc_server_set_tuning(tricc_server* s, const tricc_batch_tuning* tuning) {
+  if (!s || !tuning) return sfail(TRICC_EINVAL, "null argument");
+  if (tuning->merge_limit < 0 || tuning->wave_limit < tuning->merge_limit || tuning->wave_limit < 2 ||
+      tuning->wave_limit > 64 || tuning->persist_variant < 0 || tuning->persist_variant > 1 ||
+      tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64)
+    return sfail(TRICC_EINVAL, "bad batch tuning");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->tuning = *tuning;
   return TRICC_OK;
 }
 

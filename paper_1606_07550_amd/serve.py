@@ -39,6 +39,10 @@ class Server:
                                              ctypes.byref(self._h))
         _check(rc, "tricc_server_create")
 
+    def set_tuning(self, tuning):
+        t = N.BatchTuning.from_dict(tuning) if isinstance(tuning, dict) else tuning
+        _check(N.lib().tricc_server_set_tuning(self._h, ctypes.byref(t)), "tricc_server_set_tuning")
+
     def now(self):
         return N.lib().tricc_server_now(self._h)
 
