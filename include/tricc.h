@@ -57,10 +57,17 @@ extern "C" {
  * out-degree d+(u) >= 2 in the degree-ordered DAG goes to the first bin b
  * with d+(u) <= bin_limit[b] (bins 0..4), else to bin 5; bin b runs the
  * kernel variant bin_variant[b]. A variant's capacity (the largest d+ it
- * accepts, tricc_variant_capacity) must cover the largest d+ of its bin. */
+ * accepts, tricc_variant_capacity) must cover the largest d+ of its bin.
+ *
+ * min_side = 1: every DAG edge u->w is counted by streaming the shorter of
+ * the two out-lists: edges with d+(u) < d+(w) <= bin_limit[4] are counted
+ * from w (its out-list is the LDS table, u's out-list is streamed). This
+ * needs the min-side kernel variants (tricc_variant_min_side) in bins 0..4;
+ * with min_side = 0 those variants count every edge from its tail. */
 typedef struct tricc_tuning {
   int32_t bin_limit[TRICC_NUM_BINS - 1];
   int32_t bin_variant[TRICC_NUM_BINS];
+  int32_t min_side;
 } tricc_tuning;
 
 typedef struct tricc_graph_info {
@@ -72,8 +79,9 @@ typedef struct tricc_graph_info {
   int64_t bin_count[TRICC_NUM_BINS];
   uint64_t list_elems;         /* sum over DAG edges u->w of d+(u) + d+(w) (*) */
   int64_t large_rows;          /* rows sorted by the chunk + merge path */
-  uint64_t bin_list_elems[TRICC_NUM_BINS]; /* list_elems of the nodes of each bin (*) */
-  int64_t bin_edges[TRICC_NUM_BINS];       /* sum of d+(u) over the nodes of each bin (*) */
+  uint64_t bin_list_elems[TRICC_NUM_BINS]; /* d+(u) + d+(w) over the edges each bin's kernel counts (*) */
+  int64_t bin_edges[TRICC_NUM_BINS];       /* DAG edges counted by each bin's kernel (*) */
+  int64_t bin_in_items[TRICC_NUM_BINS];    /* in-list work items of each bin (min-side) */
   /* (*) zero until tricc_graph_stats has run */
 } tricc_graph_info;
 
@@ -91,6 +99,8 @@ int tricc_default_tuning(tricc_tuning* out);
 int tricc_variant_capacity(int variant);
 /* Number of kernel variants (valid ids are 0 .. count-1). */
 int tricc_variant_count(void);
+/* 1 if the variant implements both sides of the min-side split. */
+int tricc_variant_min_side(int variant);
 
 /* Bytes of device workspace tricc_graph_build needs for (n, m_raw). */
 int tricc_graph_workspace_size(int32_t n, int64_t m_raw, size_t* bytes);

@@ -28,10 +28,12 @@ class TriccError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_limit", ctypes.c_int32 * (NUM_BINS - 1)),
-                ("bin_variant", ctypes.c_int32 * NUM_BINS)]
+                ("bin_variant", ctypes.c_int32 * NUM_BINS),
+                ("min_side", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"bin_limit": list(self.bin_limit), "bin_variant": list(self.bin_variant)}
+        return {"bin_limit": list(self.bin_limit), "bin_variant": list(self.bin_variant),
+                "min_side": self.min_side}
 
     @classmethod
     def from_dict(cls, d):
@@ -40,6 +42,7 @@ class Tuning(ctypes.Structure):
             t.bin_limit[i] = int(v)
         for i, v in enumerate(d["bin_variant"]):
             t.bin_variant[i] = int(v)
+        t.min_side = int(d.get("min_side", 0))
         return t
 
 
@@ -48,13 +51,14 @@ class GraphInfo(ctypes.Structure):
                 ("max_deg", ctypes.c_int64), ("max_outdeg", ctypes.c_int64),
                 ("bin_count", ctypes.c_int64 * NUM_BINS), ("list_elems", ctypes.c_uint64),
                 ("large_rows", ctypes.c_int64), ("bin_list_elems", ctypes.c_uint64 * NUM_BINS),
-                ("bin_edges", ctypes.c_int64 * NUM_BINS)]
+                ("bin_edges", ctypes.c_int64 * NUM_BINS), ("bin_in_items", ctypes.c_int64 * NUM_BINS)]
 
     def as_dict(self):
         return {"n": self.n, "m_raw": self.m_raw, "m": self.m, "max_deg": self.max_deg,
                 "max_outdeg": self.max_outdeg, "bin_count": list(self.bin_count),
                 "list_elems": int(self.list_elems), "large_rows": self.large_rows,
-                "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges)}
+                "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges),
+                "bin_in_items": list(self.bin_in_items)}
 
 
 class BatchTuning(ctypes.Structure):
@@ -102,6 +106,7 @@ _SIGS = {
     "tricc_default_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "tricc_variant_capacity": (ctypes.c_int, [ctypes.c_int]),
     "tricc_variant_count": (ctypes.c_int, []),
+    "tricc_variant_min_side": (ctypes.c_int, [ctypes.c_int]),
     "tricc_graph_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "tricc_graph_build": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
                                          ctypes.POINTER(Tuning), _P, ctypes.POINTER(_P)]),

@@ -80,26 +80,32 @@ def _bin_ms(graph, T, b, reps):
     return _time(run, reps)
 
 
-def tune_single(graph, reps=3, key=None, log=None):
-    """Tunes a built :class:`Graph` in place; returns (tuning dict, ms)."""
+def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
+    """Tunes a built :class:`Graph` in place; returns (tuning dict, ms).
+    With min_side on, bins 0..4 only take min-side variants."""
     T = torch.zeros(max(graph.n, 1), dtype=torch.int64, device=graph.device)
     best_total, best = None, None
     max_outdeg = graph.info["max_outdeg"]
-    for limits in LIMIT_SETS:
+    ms_ok = [bool(N.lib().tricc_variant_min_side(v)) for v in range(variant_count())]
+    for ms, limits in [(m, lim) for m in min_side for lim in LIMIT_SETS]:
         t = default_tuning().as_dict()
         t["bin_limit"] = list(limits)
+        t["min_side"] = ms
         # start from variants that fit, then improve bin by bin
         for b in range(N.NUM_BINS):
             bound = max_outdeg if b == N.NUM_BINS - 1 else min(limits[b], max_outdeg)
             if variant_capacity(t["bin_variant"][b]) < bound:
-                t["bin_variant"][b] = variant_count() - 1  # the global fallback fits anything
+                fits = [v for v in range(variant_count()) if variant_capacity(v) >= bound
+                        and (not ms or b == N.NUM_BINS - 1 or ms_ok[v])]
+                t["bin_variant"][b] = min(fits, key=variant_capacity)
         graph.retune(t)
         total = 0.0
         for b in range(N.NUM_BINS):
             if graph.info["bin_count"][b] == 0:
                 continue
             bound = max_outdeg if b == N.NUM_BINS - 1 else min(limits[b], max_outdeg)
-            cands = [v for v in range(variant_count()) if variant_capacity(v) >= bound]
+            cands = [v for v in range(variant_count()) if variant_capacity(v) >= bound
+                     and (not ms or b == N.NUM_BINS - 1 or ms_ok[v])]
             best_v, best_ms = None, None
             for v in cands:
                 t2 = dict(t, bin_variant=list(t["bin_variant"]))
@@ -111,7 +117,7 @@ def tune_single(graph, reps=3, key=None, log=None):
             t["bin_variant"][b] = best_v
             total += best_ms
         if log:
-            log(f"limits {limits}: {total:.2f} ms {t['bin_variant']}")
+            log(f"min_side {ms} limits {limits}: {total:.2f} ms {t['bin_variant']}")
         if best_total is None or total < best_total:
             best_total, best = total, t
     graph.retune(best)

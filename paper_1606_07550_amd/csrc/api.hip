@@ -49,12 +49,15 @@ enum : int {
   kHdrBinOff = 96,    // int64[kNumBins + 1] at byte 384
   kHdrBinElems = 128, // u64[kNumBins] at byte 512
   kHdrBinEdges = 140, // u64[kNumBins] at byte 560, right after the elems
+  kHdrInOff = 160,    // int64[kNumBins + 1] at byte 640: in-list bin boundaries
+  kHdrInCap = 176,    // int32[kNumBins] at byte 704: chunk size of each bin
+  kHdrInItems = 184,  // int64[kNumBins + 1] at byte 736: chunk prefix at the boundaries
 };
 constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, cls_hist, cls_off, total;
+      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, total;
   int64_t cls_nblk;
   int64_t max_jobs;
 };
@@ -83,6 +86,12 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.part_cc = take(sizeof(double) * epilogue_blocks(n));
   L.part_T = take(sizeof(unsigned long long) * epilogue_blocks(n));
   L.meta = take(64 * (size_t)L.max_jobs + 4096);
+  L.din = take(sizeof(int32_t) * n);
+  L.dinoff = take(sizeof(int64_t) * (n + 1));
+  L.dincol = take(sizeof(int32_t) * m_raw + 16);
+  L.inlist = take(sizeof(int32_t) * n);
+  L.inch = take(sizeof(int32_t) * n);
+  L.incoff = take(sizeof(int64_t) * (n + 1));
   L.total = p;
   return L;
 }
@@ -98,6 +107,8 @@ struct tricc_graph {
   tricc_tuning tuning;
   tricc_graph_info info;
   int64_t bin_off[kNumBins + 1];
+  int64_t in_off[kNumBins + 1];    // in-list nodes of each bin (min-side)
+  int64_t in_items[kNumBins + 1];  // chunk prefix at the in-list bin boundaries
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   int32_t* hdr32() const { return at<int32_t>(L.hdr); }
 };
@@ -125,6 +136,12 @@ int check_tuning(const tricc_tuning* t) {
       return fail(TRICC_EINVAL, "tuning: bin %d has unknown variant %d", b, t->bin_variant[b]);
   for (int b = 0; b < kNumBins - 1; ++b)
     if (t->bin_limit[b] < 0) return fail(TRICC_EINVAL, "tuning: negative bin limit");
+  if (t->min_side != 0 && t->min_side != 1) return fail(TRICC_EINVAL, "tuning: min_side must be 0 or 1");
+  if (t->min_side)
+    for (int b = 0; b < kNumBins - 1; ++b)
+      if (!count_variant_min_side(t->bin_variant[b]))
+        return fail(TRICC_EINVAL, "tuning: min_side needs min-side variants in bins 0..4 (bin %d has %d)", b,
+                    t->bin_variant[b]);
   return TRICC_OK;
 }
 
@@ -256,6 +273,28 @@ int bin_nodes(tricc_graph* g) {
                   (long long)bound, g->tuning.bin_variant[b], cap);
   }
   g->info.list_elems = 0;
+  // in-list items (min-side): owners by d+(w), chunks of the bin variant's capacity
+  for (int b = 0; b <= kNumBins; ++b) g->in_off[b] = g->in_items[b] = 0;
+  if (g->tuning.min_side && n > 0) {
+    int64_t* d_in_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrInOff * 4);
+    int32_t* inlist = g->at<int32_t>(L.inlist);
+    auto launch_in = [&](int pass, int32_t* hist, const int64_t* off) {
+      return launch_classify_inbins(pass, n, dplus, g->at<int32_t>(L.deg), hdr + kHdrLimits, hist, off, L.cls_nblk,
+                                    inlist, s);
+    };
+    if ((rc = classify(g, kNumBins, launch_in, d_in_off, g->in_off))) return rc;
+    int32_t caps[kNumBins];
+    for (int b = 0; b < kNumBins; ++b) caps[b] = std::max(1, std::min(1 << 20, count_variant_capacity(g->tuning.bin_variant[b])));
+    if ((rc = upload(hdr + kHdrInCap, caps, sizeof(caps), s))) return rc;
+    const int64_t nin = g->in_off[kNumBins];
+    HIPCHK(launch_in_chunks(inlist, nin, g->at<int32_t>(L.din), hdr + kHdrInCap, d_in_off, g->at<int32_t>(L.inch), s));
+    int64_t* incoff = g->at<int64_t>(L.incoff);
+    HIPCHK(launch_scan_i32(g->at<int32_t>(L.inch), nin, incoff, g->at<int64_t>(L.scan_tmp), s));
+    int64_t* d_items = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrInItems * 4);
+    HIPCHK(launch_gather_offsets(incoff, d_in_off, kNumBins + 1, d_items, s));
+    if ((rc = sync_copy(g->in_items, d_items, sizeof(g->in_items), s))) return rc;
+  }
+  for (int b = 0; b < kNumBins; ++b) g->info.bin_in_items[b] = g->in_items[b + 1] - g->in_items[b];
   return TRICC_OK;
 }
 
@@ -268,9 +307,8 @@ int graph_stats(tricc_graph* g) {
   unsigned long long* d_all = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrListElems * 4);
   HIPCHK(hipMemsetAsync(d_elems, 0, sizeof(unsigned long long) * 2 * kNumBins, s));
   HIPCHK(hipMemsetAsync(d_all, 0, sizeof(unsigned long long), s));
-  int64_t* d_bin_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrBinOff * 4);
-  HIPCHK(launch_bin_elems(g->at<int32_t>(L.binlist), d_bin_off, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
-                          d_elems, d_edges, g->bin_off[kNumBins], s));
+  HIPCHK(launch_bin_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), g->hdr32() + kHdrLimits,
+                          g->tuning.min_side ? g->tuning.bin_limit[kNumBins - 2] : 0, d_elems, d_edges, s));
   HIPCHK(launch_list_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), d_all, s));
   unsigned long long be[2 * kNumBins];
   int rc = sync_copy(be, d_elems, sizeof(be), s);
@@ -326,15 +364,24 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   g->info.large_rows = 0;
   if (cnt[kRowLarge] > 0)
     if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
-  // a4: orientation (rows longer than 64 raw entries are the classes from kRowLds4k on)
+  // a4: orientation (rows longer than 64 raw entries: class kRowLds4k is
+  // medium, the classes above it are long)
   int32_t* dplus = g->at<int32_t>(L.dplus);
   int64_t* doff = g->at<int64_t>(L.doff);
   int32_t* dcol = g->at<int32_t>(L.dcol);
-  const int32_t* long_rows = rowlist + cls_off[kRowLds4k];
-  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds4k]);
-  HIPCHK(launch_orient(0, n, raw_off, len, deg, adj, long_rows, nlong, dplus, doff, dcol, hdr + kHdrStats, s));
+  const int32_t* med_rows = rowlist + cls_off[kRowLds4k];
+  const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRowLds4k]);
+  const int32_t* long_rows = rowlist + cls_off[kRowLds32k];
+  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds32k]);
+  HIPCHK(launch_orient(0, n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, doff, dcol,
+                       hdr + kHdrStats, nullptr, nullptr, s));
   HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
-  HIPCHK(launch_orient(1, n, raw_off, len, deg, adj, long_rows, nlong, dplus, doff, dcol, hdr + kHdrStats, s));
+  int32_t* din = g->at<int32_t>(L.din);
+  int64_t* dinoff = g->at<int64_t>(L.dinoff);
+  HIPCHK(launch_indeg(n, deg, dplus, din, s));
+  HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
+  HIPCHK(launch_orient(1, n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, doff, dcol,
+                       hdr + kHdrStats, dinoff, g->at<int32_t>(L.dincol), s));
   int32_t stats[2];
   if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
   int64_t m = 0;
@@ -353,9 +400,10 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
   static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {17, 22, 23, 24, 21, 28};
+  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 33};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
+  out->min_side = 1;
 }
 }  // namespace
 
@@ -385,6 +433,8 @@ int tricc_default_tuning(tricc_tuning* out) {
 }
 
 int tricc_variant_capacity(int variant) { return count_variant_capacity(variant); }
+
+int tricc_variant_min_side(int variant) { return count_variant_min_side(variant); }
 
 int tricc_variant_count(void) {
   int v = 0;
@@ -473,10 +523,19 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
   if (!g) return fail(TRICC_EINVAL, "null graph");
   if (bin < 0 || bin >= kNumBins) return fail(TRICC_EINVAL, "bin %d out of range", bin);
   const int32_t count = (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin]);
-  if (count == 0) return TRICC_OK;
+  if (count == 0 && g->in_items[bin + 1] == g->in_items[bin]) return TRICC_OK;
   if (!d_node_tri) return fail(TRICC_EINVAL, "null output");
   const Layout& L = g->L;
   BinLaunch bl{g->tuning.bin_variant[bin], g->at<int32_t>(L.binlist) + g->bin_off[bin], count};
+  if (g->tuning.min_side && count_variant_min_side(bl.variant)) {
+    bl.in_list = g->at<int32_t>(L.inlist) + g->in_off[bin];
+    bl.in_coff = g->at<int64_t>(L.incoff) + g->in_off[bin];
+    bl.in_nodes = (int32_t)(g->in_off[bin + 1] - g->in_off[bin]);
+    bl.in_items = g->in_items[bin + 1] - g->in_items[bin];
+    bl.w_max = g->tuning.bin_limit[kNumBins - 2];
+    bl.dinoff = g->at<int64_t>(L.dinoff);
+    bl.dincol = g->at<int32_t>(L.dincol);
+  }
   HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
                           reinterpret_cast<unsigned long long*>(d_node_tri), static_cast<hipStream_t>(stream)));
   return TRICC_OK;
@@ -600,9 +659,10 @@ constexpr int kBatchVarBin4 = 21;  // 1024 threads, table for d+ <= 4096
 void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
   const int32_t cb = persist_block_cap(bt.persist_variant);
   const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, std::max(cb, 1024), 4096};
-  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 28};
+  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 33};
   std::memcpy(t->bin_limit, lim, sizeof(lim));
   std::memcpy(t->bin_variant, var, sizeof(var));
+  t->min_side = 0;
 }
 
 int batch_bin(tricc_batch* b) {

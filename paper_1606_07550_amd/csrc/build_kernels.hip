@@ -204,6 +204,21 @@ struct NodeBinOf {  // by DAG out-degree; nodes with d+ < 2 are not listed
   }
 };
 
+struct InBinOf {  // in-list pass owners: 3 <= d+(w) <= limit[4], at least one in-neighbour
+  const int32_t* dplus;
+  const int32_t* deg;
+  const int32_t* limit;
+  __device__ int operator()(int64_t v, int) const {
+    const int32_t d = dplus[v];
+    if (d < 3 || deg[v] - d < 1 || d > limit[kNumBins - 2]) return -1;
+    int b = kNumBins - 2;
+#pragma unroll
+    for (int q = kNumBins - 3; q >= 0; --q)
+      if (d <= limit[q]) b = q;
+    return b;
+  }
+};
+
 template <int NC, class F>
 __global__ __launch_bounds__(kClsThreads) void k_classify(int pass, int64_t n, F f, int32_t* __restrict__ hist,
                                                           const int64_t* __restrict__ off, int64_t nblk,
@@ -243,6 +258,25 @@ hipError_t launch_classify_bins(int pass, int32_t n, const int32_t* dplus, const
   if (n == 0) return hipSuccess;
   k_classify<kNumBins, NodeBinOf><<<(unsigned)nblk, kClsThreads, 0, s>>>(pass, n, NodeBinOf{dplus, limit}, hist, off,
                                                                         nblk, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify_inbins(int pass, int32_t n, const int32_t* dplus, const int32_t* deg, const int32_t* limit,
+                                  int32_t* hist, const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_classify<kNumBins, InBinOf><<<(unsigned)nblk, kClsThreads, 0, s>>>(pass, n, InBinOf{dplus, deg, limit}, hist, off,
+                                                                      nblk, list);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_offsets(const int64_t* __restrict__ prefix, const int64_t* __restrict__ at, int k,
+                                 int64_t* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i < k) out[i] = prefix[at[i]];
+}
+
+hipError_t launch_gather_offsets(const int64_t* prefix, const int64_t* at, int k, int64_t* out, hipStream_t s) {
+  k_gather_offsets<<<1, 64, 0, s>>>(prefix, at, k, out);
   return hipGetLastError();
 }
 
@@ -480,7 +514,9 @@ __global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const
                                                       const int32_t* __restrict__ adj,
                                                       int32_t* __restrict__ dplus,
                                                       const int64_t* __restrict__ doff,
-                                                      int32_t* __restrict__ dcol, int32_t* __restrict__ stats) {
+                                                      int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
+                                                      const int64_t* __restrict__ dinoff,
+                                                      int32_t* __restrict__ dincol) {
   constexpr int G = kOrientG;
   __shared__ int32_t red[256 / kWave];
   const int64_t ngroups = (int64_t)gridDim.x * (256 / G);
@@ -492,8 +528,11 @@ __global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const
     const int32_t dv = deg[v];
     const int32_t* row = adj + off[v];
     int32_t c = 0;
-    int64_t ob = 0;
-    if (pass == 1) ob = doff[v];
+    int64_t ob = 0, ib = 0;
+    if (pass == 1) {
+      ob = doff[v];
+      if (dincol) ib = dinoff[v];
+    }
     for (int32_t b = 0; b < dv; b += G) {
       bool f = false;
       int32_t w = 0;
@@ -502,7 +541,9 @@ __global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const
         f = rank_below(dv, (int32_t)v, deg[w], w);
       }
       const uint32_t mask = (uint32_t)(__ballot(f) >> shift) & ((1u << G) - 1);
-      if (pass == 1 && f) dcol[ob + c + __popc(mask & ((1u << g) - 1))] = w;
+      const int32_t below = __popc(mask & ((1u << g) - 1));
+      if (pass == 1 && f) dcol[ob + c + below] = w;
+      if (pass == 1 && dincol && !f && b + g < dv) dincol[ib + (b + g) - (c + below)] = w;
       c += __popc(mask);
     }
     if (pass == 0 && g == 0) dplus[v] = c;
@@ -525,13 +566,18 @@ __global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __
                                                      const int32_t* __restrict__ adj,
                                                      int32_t* __restrict__ dplus,
                                                      const int64_t* __restrict__ doff,
-                                                     int32_t* __restrict__ dcol, int32_t* __restrict__ stats) {
+                                                     int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
+                                                     const int64_t* __restrict__ dinoff,
+                                                     int32_t* __restrict__ dincol) {
   __shared__ int32_t lds[256 / kWave + 1];
   const int32_t v = rows[blockIdx.x];
   const int32_t dv = deg[v];
   const int32_t* row = adj + off[v];
-  int64_t ob = 0;
-  if (pass == 1) ob = doff[v];
+  int64_t ob = 0, ib = 0;
+  if (pass == 1) {
+    ob = doff[v];
+    if (dincol) ib = dinoff[v];
+  }
   int32_t c = 0;
   for (int32_t b = 0; b < dv; b += 256) {
     const int32_t i = b + threadIdx.x;
@@ -544,6 +590,7 @@ __global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __
     int32_t tot;
     const int32_t ex = block_excl_scan<int32_t, 256>(f ? 1 : 0, lds, &tot);
     if (pass == 1 && f) dcol[ob + c + ex] = w;
+    if (pass == 1 && dincol && !f && i < dv) dincol[ib + i - (c + ex)] = w;
     c += tot;
   }
   if (pass == 0 && threadIdx.x == 0) {
@@ -553,14 +600,104 @@ __global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __
   }
 }
 
+// Rows of medium length: one wavefront per row (grid-stride), ballot-ordered
+// compaction, no block barriers.
+__global__ __launch_bounds__(256) void k_orient_medium(int pass, const int32_t* __restrict__ rows, int32_t nrows,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ deg,
+                                                       const int32_t* __restrict__ adj,
+                                                       int32_t* __restrict__ dplus,
+                                                       const int64_t* __restrict__ doff,
+                                                       int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
+                                                       const int64_t* __restrict__ dinoff,
+                                                       int32_t* __restrict__ dincol) {
+  __shared__ int32_t red[256 / kWave];
+  const int64_t nwaves = (int64_t)gridDim.x * (256 / kWave);
+  const int l = lane_id();
+  int32_t mx_d = 0, mx_p = 0;
+  for (int64_t r = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; r < nrows; r += nwaves) {
+    const int32_t v = rows[r];
+    const int32_t dv = deg[v];
+    const int32_t* row = adj + off[v];
+    int64_t ob = 0, ib = 0;
+    if (pass == 1) {
+      ob = doff[v];
+      if (dincol) ib = dinoff[v];
+    }
+    int32_t c = 0;
+    for (int32_t b = 0; b < dv; b += kWave) {
+      bool f = false;
+      int32_t w = 0;
+      if (b + l < dv) {
+        w = row[b + l];
+        f = rank_below(dv, v, deg[w], w);
+      }
+      const uint64_t m = __ballot(f);
+      const int32_t below = mask_below(m);
+      if (pass == 1 && f) dcol[ob + c + below] = w;
+      if (pass == 1 && dincol && !f && b + l < dv) dincol[ib + (b + l) - (c + below)] = w;
+      c += (int32_t)__popcll(m);
+    }
+    if (pass == 0 && l == 0) dplus[v] = c;
+    mx_d = max(mx_d, dv);
+    mx_p = max(mx_p, c);
+  }
+  if (pass == 0) {
+    mx_d = block_max(mx_d, red);
+    mx_p = block_max(mx_p, red);
+    if (threadIdx.x == 0) {
+      atomicMax(&stats[0], mx_d);
+      atomicMax(&stats[1], mx_p);
+    }
+  }
+}
+
 hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
-                         const int32_t* adj, const int32_t* long_rows, int32_t nlong, int32_t* dplus,
-                         const int64_t* doff, int32_t* dcol, int32_t* stats, hipStream_t s) {
+                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
+                         int32_t nlong, int32_t* dplus, const int64_t* doff, int32_t* dcol, int32_t* stats,
+                         const int64_t* dinoff, int32_t* dincol, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(pass, n, off, len, deg, adj, dplus,
-                                                                             doff, dcol, stats);
+                                                                             doff, dcol, stats, dinoff, dincol);
+  if (nmedium > 0)
+    k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(
+        pass, medium_rows, nmedium, off, deg, adj, dplus, doff, dcol, stats, dinoff, dincol);
   if (nlong > 0)
-    k_orient_long<<<nlong, 256, 0, s>>>(pass, long_rows, off, deg, adj, dplus, doff, dcol, stats);
+    k_orient_long<<<nlong, 256, 0, s>>>(pass, long_rows, off, deg, adj, dplus, doff, dcol, stats, dinoff, dincol);
+  return hipGetLastError();
+}
+
+// d-(v) = d(v) - d+(v)
+__global__ __launch_bounds__(256) void k_indeg(int32_t n, const int32_t* __restrict__ deg,
+                                               const int32_t* __restrict__ dplus, int32_t* __restrict__ din) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) din[v] = deg[v] - dplus[v];
+}
+
+hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_indeg<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(n, deg, dplus, din);
+  return hipGetLastError();
+}
+
+// Work items of the in-list pass: the nodes w of one bin (listed
+// contiguously) each get ceil(d-(w) / chunk) items.
+__global__ __launch_bounds__(256) void k_in_chunks(const int32_t* __restrict__ list, int64_t nlist,
+                                                   const int32_t* __restrict__ din, const int32_t* __restrict__ cap_of,
+                                                   const int64_t* __restrict__ bin_off, int32_t* __restrict__ nch) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nlist; i += stride) {
+    int b = 0;
+    while (b < kNumBins - 1 && i >= bin_off[b + 1]) ++b;
+    const int32_t c = max(1, cap_of[b]);
+    nch[i] = (din[list[i]] + c - 1) / c;
+  }
+}
+
+hipError_t launch_in_chunks(const int32_t* list, int64_t nlist, const int32_t* din, const int32_t* cap_of,
+                            const int64_t* bin_off, int32_t* nch, hipStream_t s) {
+  if (nlist == 0) return hipSuccess;
+  k_in_chunks<<<grid_for(nlist, 256, 1u << 14), 256, 0, s>>>(list, nlist, din, cap_of, bin_off, nch);
   return hipGetLastError();
 }
 
@@ -593,31 +730,42 @@ hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol
   return hipGetLastError();
 }
 
-// Wave per listed node; the node's bin is found from bin_off.
-__global__ __launch_bounds__(256) void k_bin_elems(const int32_t* __restrict__ list,
-                                                   const int64_t* __restrict__ bin_off,
-                                                   const int64_t* __restrict__ doff,
+// Per-bin algorithmic sizes: every DAG edge u->w with d+(u) >= 2 is charged
+// to the bin whose kernel counts it: w's bin (by d+(w)) when the min-side
+// rule hands it to w's in-list (d+(u) < d+(w) <= w_max), else u's bin.
+// elems[b] += d+(u) + d+(w), edges[b] += 1. Wave per node, grid-stride.
+__device__ __forceinline__ int bin_of(int32_t d, const int32_t* lim) {
+  int b = kNumBins - 1;
+#pragma unroll
+  for (int q = kNumBins - 2; q >= 0; --q)
+    if (d <= lim[q]) b = q;
+  return b;
+}
+
+__global__ __launch_bounds__(256) void k_bin_elems(int32_t n, const int64_t* __restrict__ doff,
                                                    const int32_t* __restrict__ dcol,
+                                                   const int32_t* __restrict__ limit, int32_t w_max,
                                                    unsigned long long* __restrict__ elems,
-                                                   unsigned long long* __restrict__ edges, int64_t total) {
+                                                   unsigned long long* __restrict__ edges) {
+  int32_t lim[kNumBins - 1];
+#pragma unroll
+  for (int q = 0; q < kNumBins - 1; ++q) lim[q] = limit[q];
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int l = lane_id();
   unsigned long long acc[kNumBins] = {}, eacc[kNumBins] = {};
-  for (int64_t i = w0; i < total; i += nwaves) {
-    int b = 0;
-    while (b < kNumBins - 1 && i >= bin_off[b + 1]) ++b;
-    const int32_t u = list[i];
+  for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n; u += nwaves) {
     const int64_t beg = doff[u], end = doff[u + 1];
-    const unsigned long long du = (unsigned long long)(end - beg);
-    unsigned long long a = 0;
+    const int32_t du = (int32_t)(end - beg);
+    if (du < 2) continue;
+    const int bu = bin_of(du, lim);
     for (int64_t p = beg + l; p < end; p += kWave) {
       const int32_t w = dcol[p];
-      a += du + (unsigned long long)(doff[w + 1] - doff[w]);
-    }
+      const int32_t dw = (int32_t)(doff[w + 1] - doff[w]);
+      const int b = (du < dw && dw <= w_max) ? bin_of(dw, lim) : bu;
 #pragma unroll
-    for (int q = 0; q < kNumBins; ++q)
-      if (q == b) { acc[q] += a; eacc[q] += (l == 0) ? du : 0ull; }
+      for (int q = 0; q < kNumBins; ++q)
+        if (q == b) { acc[q] += (unsigned long long)(du + dw); eacc[q] += 1; }
+    }
   }
 #pragma unroll
   for (int q = 0; q < kNumBins; ++q) {
@@ -628,12 +776,10 @@ __global__ __launch_bounds__(256) void k_bin_elems(const int32_t* __restrict__ l
   }
 }
 
-hipError_t launch_bin_elems(const int32_t* list, const int64_t* bin_off, const int64_t* doff,
-                            const int32_t* dcol, unsigned long long* elems, unsigned long long* edges,
-                            int64_t total_listed, hipStream_t s) {
-  if (total_listed == 0) return hipSuccess;
-  k_bin_elems<<<grid_for(total_listed * kWave, 256, 1u << 14), 256, 0, s>>>(list, bin_off, doff, dcol, elems,
-                                                                            edges, total_listed);
+hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* limit,
+                            int32_t w_max, unsigned long long* elems, unsigned long long* edges, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_bin_elems<<<grid_for((int64_t)n * kWave, 256, 1u << 14), 256, 0, s>>>(n, doff, dcol, limit, w_max, elems, edges);
   return hipGetLastError();
 }
 

@@ -227,11 +227,36 @@ struct WaveGroupLds {
 // per step: U independent loads are in flight before the probes; loads past
 // the end of a list are clamped to its last element (same cache line) and
 // masked out of the count.
+// One wavefront streams the list L[0..n) (16-byte-aligned dcol ids) against
+// the bucket table: credits each hit's slot, returns the wave's hit count
+// (wave-uniform).
+template <int NB, int U>
+__device__ __forceinline__ uint32_t stream_probe(const int32_t* __restrict__ L, int32_t n, const int4* Kb,
+                                                 uint32_t* C) {
+  const int lane = lane_id();
+  uint32_t cw = 0;
+  for (int32_t p = 0; p < n; p += U * kWave) {
+    int32_t x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) x[k] = L[min(p + k * kWave + lane, n - 1)];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const bool v = p + k * kWave + lane < n;
+      const int s = bucket_probe<NB>(Kb, x[k], v);
+      if (s >= 0) atomicAdd(&C[s], 1u);
+      cw += (uint32_t)__popcll(__ballot(s >= 0));
+    }
+  }
+  return cw;
+}
+
+// w_max > 0 (min-side mode): edges u->w with d+(u) < d+(w) <= w_max are left
+// to w's in-list pass (node_count_inw), which then streams the shorter list.
 template <int G, int SLOTS, int CAP, int U>
 __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, CAP>& S,
                                                 unsigned long long* red, const int64_t* __restrict__ doff,
                                                 const int32_t* __restrict__ dcol,
-                                                unsigned long long* __restrict__ T) {
+                                                unsigned long long* __restrict__ T, int32_t w_max = 0) {
   static_assert(G % kWave == 0 && SLOTS % 4 == 0 && SLOTS >= 2 * CAP, "shape");
   constexpr int WPG = G / kWave;
   constexpr int NB = SLOTS / 4;
@@ -261,20 +286,8 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
     const int32_t wb = __builtin_amdgcn_readfirstlane(S.Wb[i]);
     const int32_t wn = __builtin_amdgcn_readfirstlane(S.Wn[i]);
     if (wn == 0) continue;
-    const int32_t* L = dcol + wb;
-    uint32_t cw = 0;
-    for (int32_t p = 0; p < wn; p += U * kWave) {
-      int32_t x[U];
-#pragma unroll
-      for (int k = 0; k < U; ++k) x[k] = L[min(p + k * kWave + lane, wn - 1)];
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const bool v = p + k * kWave + lane < wn;
-        const int s = bucket_probe<NB>(S.K, x[k], v);
-        if (s >= 0) atomicAdd(&S.C[s], 1u);
-        cw += (uint32_t)__popcll(__ballot(s >= 0));
-      }
-    }
+    if (len < wn && wn <= w_max) continue;  // edge u->w is counted from w's in-list
+    const uint32_t cw = stream_probe<NB, U>(dcol + wb, wn, S.K, S.C);
     if (cw && lane == 0) atomicAdd(&S.C[S.Ws[i]], cw);
     tu += cw;
   }
@@ -310,6 +323,119 @@ __global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ l
   const int gi = threadIdx.x / G;
   const int idx = blockIdx.x * GPB + gi;
   node_count_wave<G, SLOTS, CAP, U>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T);
+}
+
+// In-list side of the min-side split: a group owns node w and one chunk of
+// at most CAP of its in-neighbours u (rank(u) < rank(w)). N+(w) is the LDS
+// table; for every in-neighbour with 2 <= d+(u) < d+(w) one wavefront
+// streams N+(u) against it. A hit x is the triangle u < w < x: x is credited
+// in the table, w in the group total, u with one global atomic per in-edge.
+template <int G, int SLOTS, int CAP, int U>
+__device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGroupLds<SLOTS, CAP>& S,
+                                               unsigned long long* red, const int64_t* __restrict__ doff,
+                                               const int32_t* __restrict__ dcol,
+                                               const int64_t* __restrict__ dinoff,
+                                               const int32_t* __restrict__ dincol,
+                                               unsigned long long* __restrict__ T) {
+  constexpr int WPG = G / kWave;
+  constexpr int NB = SLOTS / 4;
+  const int g = threadIdx.x % G;
+  const int wv = g / kWave;
+  const int lane = lane_id();
+  const bool active = w >= 0;
+  int32_t* K = reinterpret_cast<int32_t*>(S.K);
+  int64_t beg = 0, ib = 0;
+  int32_t len = 0, nin = 0;
+  if (active) {
+    beg = doff[w];
+    len = (int32_t)(doff[w + 1] - beg);
+    ib = dinoff[w] + chunk * CAP;
+    nin = (int32_t)min((int64_t)CAP, dinoff[w + 1] - ib);
+  }
+  for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
+  group_sync<G>();
+  for (int i = g; i < len; i += G) bucket_insert<NB>(K, dcol[beg + i]);
+  for (int i = g; i < nin; i += G) {
+    const int32_t u = dincol[ib + i];
+    const int64_t b = doff[u];
+    const int32_t nu = (int32_t)(doff[u + 1] - b);
+    S.Wb[i] = (int32_t)b;
+    S.Wn[i] = (nu >= 2 && nu < len) ? nu : 0;
+    S.Ws[i] = u;
+  }
+  group_sync<G>();
+  uint32_t tw = 0;  // wave-uniform
+  for (int i = wv; i < nin; i += WPG) {
+    const int32_t ub = __builtin_amdgcn_readfirstlane(S.Wb[i]);
+    const int32_t un = __builtin_amdgcn_readfirstlane(S.Wn[i]);
+    if (un == 0) continue;
+    const uint32_t cu = stream_probe<NB, U>(dcol + ub, un, S.K, S.C);
+    if (cu && lane == 0) atomicAdd(&T[S.Ws[i]], (unsigned long long)cu);
+    tw += cu;
+  }
+  group_sync<G>();
+  for (int s = g; s < SLOTS; s += G) {
+    const int32_t k = K[s];
+    const uint32_t c = S.C[s];
+    if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
+  }
+  if constexpr (WPG == 1) {
+    if (active && lane == 0 && tw) atomicAdd(&T[w], (unsigned long long)tw);
+  } else {
+    if (lane == 0) red[wv] = tw;
+    __syncthreads();
+    if (active && g == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < WPG; ++k) t += red[k];
+      if (t) atomicAdd(&T[w], t);
+    }
+    __syncthreads();
+  }
+}
+
+// One bin in min-side mode: the first ceil(nu/GPB) blocks count the bin's
+// nodes from their out-lists (skipping edges owned by in-lists), the rest run
+// the bin's in-list chunks. In-list items: the nodes inl[0..nin) with chunk
+// prefix inc[0..nin] (inc[0] need not be 0).
+struct InItems {
+  const int32_t* list;
+  const int64_t* coff;
+  int32_t nodes;
+  int64_t items;
+};
+
+template <int NT, int G, int SLOTS, int CAP, int U>
+__global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ list, int32_t nlist, InItems in,
+                                                 int32_t w_max, const int64_t* __restrict__ doff,
+                                                 const int32_t* __restrict__ dcol,
+                                                 const int64_t* __restrict__ dinoff,
+                                                 const int32_t* __restrict__ dincol,
+                                                 unsigned long long* __restrict__ T) {
+  static_assert(NT % G == 0 && (G == kWave || G == NT), "groups are single waves or whole blocks");
+  constexpr int GPB = NT / G;
+  __shared__ WaveGroupLds<SLOTS, CAP> lds[GPB];
+  __shared__ unsigned long long red[NT / kWave];
+  const int gi = threadIdx.x / G;
+  const int64_t nbu = ((int64_t)nlist + GPB - 1) / GPB;
+  if ((int64_t)blockIdx.x < nbu) {
+    const int64_t idx = (int64_t)blockIdx.x * GPB + gi;
+    node_count_wave<G, SLOTS, CAP, U>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, w_max);
+    return;
+  }
+  const int64_t j = ((int64_t)blockIdx.x - nbu) * GPB + gi;
+  int32_t w = -1;
+  int64_t chunk = 0;
+  if (j < in.items) {
+    const int64_t gc = in.coff[0] + j;
+    int32_t lo = 0, hi = in.nodes - 1;  // last p with coff[p] <= gc
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (in.coff[mid] <= gc) lo = mid; else hi = mid - 1;
+    }
+    w = in.list[lo];
+    chunk = gc - in.coff[lo];
+  }
+  node_count_inw<G, SLOTS, CAP, U>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T);
 }
 
 // Merge variant for short lists: a group of G lanes owns node u and each
@@ -669,7 +795,13 @@ static constexpr VariantInfo kVariants[] = {
     {256, 4, 0, -1, 1 << 20},     // 25: any d+ (short lists)
     {256, 8, 0, -1, 1 << 20},     // 26
     {256, 16, 0, -1, 1 << 20},    // 27
-    {256, 256, 64, 0},       // 28: global fallback, any d+
+    // min-side wave-stream kernels (out-list side + in-list side per bin)
+    {256, 64, 64, 128, 16},       // 28: d+ <= 16
+    {256, 64, 64, 256, 64},       // 29: d+ <= 64
+    {256, 256, 64, 1024, 256},    // 30: d+ <= 256
+    {512, 512, 64, 4096, 1024},   // 31: d+ <= 1024
+    {1024, 1024, 64, 8192, 4096}, // 32: d+ <= 4096
+    {256, 256, 64, 0},       // 33: global fallback, any d+
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = kNumVariants - 1;
@@ -706,9 +838,23 @@ static void launch_plain(const BinLaunch& b, const int64_t* doff, const int32_t*
   k_count_plain<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
 }
 
+template <int NT, int G, int SLOTS, int CAP, int U = 4>
+static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
+                      hipStream_t s) {
+  constexpr int GPB = NT / G;
+  const int64_t nbu = ((int64_t)b.count + GPB - 1) / GPB;
+  const int64_t nbw = (b.in_items + GPB - 1) / GPB;
+  if (nbu + nbw == 0) return;
+  InItems in{b.in_list, b.in_coff, b.in_nodes, b.in_items};
+  k_count_ms<NT, G, SLOTS, CAP, U><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
+                                                                        b.dinoff, b.dincol, T);
+}
+
+int count_variant_min_side(int v) { return v >= 28 && v <= 32; }
+
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s) {
-  if (b.count <= 0) return hipSuccess;
+  if (b.count <= 0 && b.in_items <= 0) return hipSuccess;
   switch (b.variant) {
     case 0: launch_hash<256, 16, 16, 32>(b, doff, dcol, T, s); break;
     case 1: launch_hash<256, 16, 8, 32>(b, doff, dcol, T, s); break;
@@ -738,6 +884,11 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 25: k_count_merge<256, 4><<<(unsigned)(((int64_t)b.count * 4 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
     case 26: k_count_merge<256, 8><<<(unsigned)(((int64_t)b.count * 8 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
     case 27: k_count_merge<256, 16><<<(unsigned)(((int64_t)b.count * 16 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
+    case 28: launch_ms<256, 64, 128, 16>(b, doff, dcol, T, s); break;
+    case 29: launch_ms<256, 64, 256, 64>(b, doff, dcol, T, s); break;
+    case 30: launch_ms<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
+    case 31: launch_ms<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
+    case 32: launch_ms<1024, 1024, 8192, 4096>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;

@@ -33,6 +33,8 @@ int64_t classify_blocks(int64_t n);
 // rows by raw length (rows of length <= 1 are not listed; pass 0 sets their deg)
 hipError_t launch_classify_rows(int pass, int32_t n, const int32_t* len, int32_t* deg, int32_t* hist,
                                 const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
+// out[i] = prefix[at[i]] for i < k (k <= 64)
+hipError_t launch_gather_offsets(const int64_t* prefix, const int64_t* at, int k, int64_t* out, hipStream_t s);
 // cls_off[c] = off[c * nblk] for c = 0..nc
 hipError_t launch_class_offsets(const int64_t* off, int64_t nblk, int nc, int64_t* cls_off, hipStream_t s);
 // Sorts + dedups rows of one class in place; writes deg.
@@ -57,10 +59,21 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 // ---- Degree-order orientation --------------------------------------------
 // pass 0: dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|, stats[0] = max d,
 // stats[1] = max d+; pass 1: writes N+(v) (ascending id) at dcol[doff[v]..].
-// Rows of raw length > 64 must be listed in long_rows.
+// Rows of raw length > 64 must be listed: medium_rows (a wavefront each) and
+// long_rows (a block each) together.
+// With dincol != NULL, pass 1 also writes the in-list N-(v) = {w in N(v):
+// (d(w),w) < (d(v),v)} (ascending id) at dincol[dinoff[v]..].
 hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
-                         const int32_t* adj, const int32_t* long_rows, int32_t nlong, int32_t* dplus,
-                         const int64_t* doff, int32_t* dcol, int32_t* stats, hipStream_t s);
+                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
+                         int32_t nlong, int32_t* dplus, const int64_t* doff, int32_t* dcol, int32_t* stats,
+                         const int64_t* dinoff, int32_t* dincol, hipStream_t s);
+hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, hipStream_t s);
+// in-list pass owners by d+(w) into bins 0..kNumBins-2 (see InBinOf)
+hipError_t launch_classify_inbins(int pass, int32_t n, const int32_t* dplus, const int32_t* deg, const int32_t* limit,
+                                  int32_t* hist, const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
+// nch[i] = ceil(d-(list[i]) / cap_of[bin of i])
+hipError_t launch_in_chunks(const int32_t* list, int64_t nlist, const int32_t* din, const int32_t* cap_of,
+                            const int64_t* bin_off, int32_t* nch, hipStream_t s);
 
 hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* out,
                              hipStream_t s);
@@ -73,10 +86,10 @@ constexpr int kNumBins = 6;
 // bin kNumBins-1 takes the rest.
 hipError_t launch_classify_bins(int pass, int32_t n, const int32_t* dplus, const int32_t* limit, int32_t* hist,
                                 const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
-// per-bin sums of d+(u) + d+(w) over the bin's DAG edges, and of d+(u)
-hipError_t launch_bin_elems(const int32_t* list, const int64_t* bin_off, const int64_t* doff,
-                            const int32_t* dcol, unsigned long long* elems, unsigned long long* edges,
-                            int64_t total_listed, hipStream_t s);
+// per-bin sums of d+(u) + d+(w) and of edges over the DAG edges each bin's
+// kernel counts (min-side ownership with w_max; w_max = 0 disables it)
+hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* limit,
+                            int32_t w_max, unsigned long long* elems, unsigned long long* edges, hipStream_t s);
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // ---- Intersection and epilogue --------------------------------------------
@@ -84,11 +97,20 @@ struct BinLaunch {
   int variant;  // kernel variant id (see count_kernels.hip)
   const int32_t* list;
   int32_t count;
+  // min-side variants only: the bin's in-list items and the ownership bound
+  const int32_t* in_list = nullptr;
+  const int64_t* in_coff = nullptr;
+  int32_t in_nodes = 0;
+  int64_t in_items = 0;
+  int32_t w_max = 0;
+  const int64_t* dinoff = nullptr;
+  const int32_t* dincol = nullptr;
 };
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s);
 int count_variant_capacity(int variant);  // max d+(u) a variant accepts
 int count_variant_valid(int variant);
+int count_variant_min_side(int variant);  // out-list + in-list kernel
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 // cc[v] (fp32) from T and deg; block partials of the FP64 ratio sum and of T.
 int64_t epilogue_blocks(int64_t n);

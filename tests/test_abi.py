@@ -86,3 +86,20 @@ def test_build_rejects_bad_arguments_before_device_work():
     assert L.tricc_graph_build(4, 0, None, None, ctypes.c_void_p(256), 1 << 20, ctypes.byref(t), None,
                                ctypes.byref(h)) == N.TRICC_EINVAL
     assert not h.value
+
+
+def test_min_side_variants_and_tuning_check():
+    from paper_1606_07550_amd import default_tuning, variant_count
+    L = N.lib()
+    ms = [v for v in range(variant_count()) if L.tricc_variant_min_side(v)]
+    assert len(ms) == 5
+    t = default_tuning()
+    assert t.min_side == 1 and all(L.tricc_variant_min_side(t.bin_variant[b]) for b in range(N.NUM_BINS - 1))
+    bad = default_tuning()
+    bad.bin_variant[1] = 17  # a wave-stream variant without the in-list side
+    h = ctypes.c_void_p()
+    assert L.tricc_graph_build(4, 0, None, None, ctypes.c_void_p(256), 1 << 30, ctypes.byref(bad), None,
+                               ctypes.byref(h)) == N.TRICC_EINVAL
+    assert "min_side" in N.last_error()
+    bad.min_side = 0
+    L.tricc_default_tuning(ctypes.byref(t))

@@ -191,7 +191,43 @@ def _tuning_all_to(variant, limit_bins=None):
         t.bin_limit[b] = 0
     for b in range(N.NUM_BINS):
         t.bin_variant[b] = variant
+    t.min_side = 0
     return t
+
+
+MIN_SIDE_TUNINGS = [
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 1},
+    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [28, 28, 28, 28, 29, 33], "min_side": 1},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 0},
+]
+
+
+@pytest.mark.parametrize("ti", range(len(MIN_SIDE_TUNINGS)))
+def test_min_side_split(ti):
+    """Edges counted from the shorter out-list (in-list side for w) under
+    several limit sets; in-lists longer than one chunk occur in R-MAT."""
+    tun = MIN_SIDE_TUNINGS[ti]
+    cases = [I.rmat(14, 16, seed=41), I.rmat(16, 16, seed=42), F.complete(300),
+             F.disjoint_union(F.complete(40), F.wheel(30), F.windmill(7))]
+    s, d = I.ba(20000, 9, 43)
+    cases.append((20000, s, d))
+    for n, s, d in cases:
+        ref = oracle.count(n, s, d, order=1)
+        g = P.Graph(n, to_dev(s), to_dev(d))
+        mo = g.info["max_outdeg"]
+        if mo > tun["bin_limit"][4] and tun["bin_variant"][5] != P.variant_count() - 1:
+            continue
+        g.retune(tun)
+        if tun["min_side"] and n > 1000:
+            assert sum(g.info["bin_in_items"]) > 0
+        o = g.count()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o["T"].cpu().numpy().view(np.uint64), ref["T"])
+        assert int(o["total"].cpu().numpy().view(np.uint64)[0]) == ref["total"]
+        info = g.stats()
+        dplus = np.diff(g.arrays()["doff"].cpu().numpy())
+        assert sum(info["bin_edges"]) == int(dplus[dplus >= 2].sum())
 
 
 @pytest.mark.parametrize("variant", list(range(P.variant_count())))
