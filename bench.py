@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-graphs leg")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
-    ap.add_argument("--autotune", action="store_true", help="search tunings first (cached per arch/workload)")
+    ap.add_argument("--autotune", action="store_true", help="search the batched tuning first (cached per arch)")
+    ap.add_argument("--autotune-single", action="store_true",
+                    help="search the single-graph bin tuning first (cached per arch/workload)")
     ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
     ap.add_argument("--serve-queries", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=3)
@@ -303,10 +305,21 @@ def main():
     src = torch.from_numpy(s).to(dev)
     dst = torch.from_numpy(d).to(dev)
     del s, d
+    from paper_1606_07550_amd import autotune
     tuning = None
     if args.tuning:
         with open(args.tuning) as f:
             tuning = N.Tuning.from_dict(json.load(f))
+    elif args.autotune_single:
+        g0 = P.Graph(n, src, dst)
+        best, ms = autotune.tune_single(g0, key=cfg["workload"], log=log)
+        log(f"autotuned {cfg['workload']}: {best} ({ms:.2f} ms of intersection kernels)")
+        tuning = N.Tuning.from_dict(best)
+        del g0
+    else:
+        rec = autotune.lookup(cfg["workload"])
+        if rec:
+            tuning = N.Tuning.from_dict(rec["tuning"])
     ws = torch.empty(P.workspace_size(n, src.numel()), dtype=torch.uint8, device=dev)
     T = torch.empty(n, dtype=torch.int64, device=dev)
     cc = torch.empty(n, dtype=torch.float32, device=dev)

@@ -25,10 +25,10 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.j
 
 LIMIT_SETS = [
     [16, 64, 256, 1024, 4096],
-    [8, 64, 256, 1024, 4096],
-    [16, 32, 128, 1024, 4096],
-    [16, 64, 128, 512, 4096],
     [32, 64, 256, 1024, 4096],
+    [32, 64, 256, 1024, 2048],
+    [16, 64, 256, 512, 2048],
+    [16, 32, 128, 1024, 4096],
 ]
 
 
@@ -111,9 +111,9 @@ def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
                 t2 = dict(t, bin_variant=list(t["bin_variant"]))
                 t2["bin_variant"][b] = v
                 graph.retune(t2)
-                ms = _bin_ms(graph, T, b, reps)
-                if best_ms is None or ms < best_ms:
-                    best_v, best_ms = v, ms
+                bin_ms = _bin_ms(graph, T, b, reps)
+                if best_ms is None or bin_ms < best_ms:
+                    best_v, best_ms = v, bin_ms
             t["bin_variant"][b] = best_v
             total += best_ms
         if log:

@@ -400,7 +400,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
   static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 33};
+  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 36};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;
@@ -659,7 +659,7 @@ constexpr int kBatchVarBin4 = 21;  // 1024 threads, table for d+ <= 4096
 void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
   const int32_t cb = persist_block_cap(bt.persist_variant);
   const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, std::max(cb, 1024), 4096};
-  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 33};
+  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 36};
   std::memcpy(t->bin_limit, lim, sizeof(lim));
   std::memcpy(t->bin_variant, var, sizeof(var));
   t->min_side = 0;

@@ -220,7 +220,57 @@ struct WaveGroupLds {
   int32_t Wb[CAP];       // N+(w) begins (offsets < 2^30)
   int32_t Wn[CAP];       // |N+(w)|
   int32_t Ws[CAP];       // slot of w
+  uint32_t Wc[CAP];      // hits per streamed list (packed phase)
 };
+
+// Lists shorter than this are streamed packed: a wavefront covers several
+// short lists per step instead of one list per step.
+constexpr int32_t kPackShort = 64;
+
+// Packed streaming of the short lists among items [i0, i1) of a group: a
+// window of up to 64 lists sits in the lanes (begin, length, inclusive
+// prefix of lengths); each step gives every lane one id of the window's
+// concatenation, found by a shuffle binary search over the prefixes. A hit
+// credits its table slot and its list's counter Wc. Returns the wave's hits.
+template <int NB>
+__device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const int32_t* Wb, const int32_t* Wn,
+                                                  uint32_t* Wc, const int32_t* __restrict__ dcol, const int4* Kb,
+                                                  uint32_t* C) {
+  const int lane = lane_id();
+  uint32_t hits = 0;
+  for (int32_t base = i0; base < i1; base += kWave) {
+    const int32_t li = base + lane;
+    int32_t nb = 0, bb = 0;
+    if (li < i1) {
+      nb = Wn[li];
+      bb = Wb[li];
+      if (nb >= kPackShort) nb = 0;  // long lists are streamed one by one
+    }
+    const int32_t incl = wave_incl_scan(nb);
+    const int32_t total = __shfl(incl, kWave - 1, kWave);
+    const int32_t excl = incl - nb;
+    for (int32_t t0 = 0; t0 < total; t0 += kWave) {
+      const int32_t t = t0 + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1) {
+        const int32_t v = __shfl(incl, k + step - 1, kWave);
+        if (v <= t) k += step;
+      }
+      const int32_t kb = __shfl(bb, k, kWave);
+      const int32_t ke = __shfl(excl, k, kWave);
+      const bool valid = t < total;
+      const int32_t x = valid ? dcol[kb + (t - ke)] : -1;
+      const int s = bucket_probe<NB>(Kb, x, valid);
+      if (s >= 0) {
+        atomicAdd(&C[s], 1u);
+        atomicAdd(&Wc[base + k], 1u);
+      }
+      hits += (uint32_t)__popcll(__ballot(s >= 0));
+    }
+  }
+  return hits;
+}
 
 // One node u (u < 0: inactive group) counted by a group of G lanes (G a
 // multiple of 64; when G > 64 the group is the whole block). U ids per lane
@@ -277,20 +327,26 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
     const int32_t w = dcol[beg + i];
     S.Ws[i] = bucket_insert<NB>(K, w);
     const int64_t b = doff[w];
+    const int32_t wn = (int32_t)(doff[w + 1] - b);
     S.Wb[i] = (int32_t)b;
-    S.Wn[i] = (int32_t)(doff[w + 1] - b);
+    // edges u->w with d+(u) < d+(w) <= w_max are counted from w's in-list
+    S.Wn[i] = (len < wn && wn <= w_max) ? 0 : wn;
+    S.Wc[i] = 0;
   }
   group_sync<G>();
   uint32_t tu = 0;  // wave-uniform
   for (int i = wv; i < len; i += WPG) {
     const int32_t wb = __builtin_amdgcn_readfirstlane(S.Wb[i]);
     const int32_t wn = __builtin_amdgcn_readfirstlane(S.Wn[i]);
-    if (wn == 0) continue;
-    if (len < wn && wn <= w_max) continue;  // edge u->w is counted from w's in-list
+    if (wn < kPackShort) continue;  // short lists: packed phase below
     const uint32_t cw = stream_probe<NB, U>(dcol + wb, wn, S.K, S.C);
     if (cw && lane == 0) atomicAdd(&S.C[S.Ws[i]], cw);
     tu += cw;
   }
+  tu += stream_packed<NB>(wv * len / WPG, (wv + 1) * len / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
+  group_sync<G>();
+  for (int i = g; i < len; i += G)
+    if (S.Wc[i]) atomicAdd(&S.C[S.Ws[i]], S.Wc[i]);
   group_sync<G>();
   for (int s = g; s < SLOTS; s += G) {
     const int32_t k = K[s];
@@ -362,18 +418,22 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
     S.Wb[i] = (int32_t)b;
     S.Wn[i] = (nu >= 2 && nu < len) ? nu : 0;
     S.Ws[i] = u;
+    S.Wc[i] = 0;
   }
   group_sync<G>();
   uint32_t tw = 0;  // wave-uniform
   for (int i = wv; i < nin; i += WPG) {
     const int32_t ub = __builtin_amdgcn_readfirstlane(S.Wb[i]);
     const int32_t un = __builtin_amdgcn_readfirstlane(S.Wn[i]);
-    if (un == 0) continue;
+    if (un < kPackShort) continue;  // short lists: packed phase below
     const uint32_t cu = stream_probe<NB, U>(dcol + ub, un, S.K, S.C);
     if (cu && lane == 0) atomicAdd(&T[S.Ws[i]], (unsigned long long)cu);
     tw += cu;
   }
+  tw += stream_packed<NB>(wv * nin / WPG, (wv + 1) * nin / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
   group_sync<G>();
+  for (int i = g; i < nin; i += G)
+    if (S.Wc[i]) atomicAdd(&T[S.Ws[i]], (unsigned long long)S.Wc[i]);
   for (int s = g; s < SLOTS; s += G) {
     const int32_t k = K[s];
     const uint32_t c = S.C[s];
@@ -801,7 +861,10 @@ static constexpr VariantInfo kVariants[] = {
     {256, 256, 64, 1024, 256},    // 30: d+ <= 256
     {512, 512, 64, 4096, 1024},   // 31: d+ <= 1024
     {1024, 1024, 64, 8192, 4096}, // 32: d+ <= 4096
-    {256, 256, 64, 0},       // 33: global fallback, any d+
+    {512, 512, 64, 2048, 1024},   // 33: d+ <= 1024, denser table
+    {512, 512, 64, 4096, 2048},   // 34: d+ <= 2048
+    {256, 256, 64, 512, 256},     // 35: d+ <= 256, denser table
+    {256, 256, 64, 0},       // 36: global fallback, any d+
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = kNumVariants - 1;
@@ -850,7 +913,7 @@ static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dc
                                                                         b.dinoff, b.dincol, T);
 }
 
-int count_variant_min_side(int v) { return v >= 28 && v <= 32; }
+int count_variant_min_side(int v) { return v >= 28 && v <= 35; }
 
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s) {
@@ -889,6 +952,9 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 30: launch_ms<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
     case 31: launch_ms<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
     case 32: launch_ms<1024, 1024, 8192, 4096>(b, doff, dcol, T, s); break;
+    case 33: launch_ms<512, 512, 2048, 1024>(b, doff, dcol, T, s); break;
+    case 34: launch_ms<512, 512, 4096, 2048>(b, doff, dcol, T, s); break;
+    case 35: launch_ms<256, 256, 512, 256>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;

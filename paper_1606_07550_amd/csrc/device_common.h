@@ -81,9 +81,15 @@ __device__ __forceinline__ T block_sum(T x, T* lds) {
   return r;  // valid in thread 0
 }
 
-// Multiplicative hash of a node id onto `bits` bits (Knuth).
+// Hash of a node id onto `bits` bits (1 <= bits <= 20): fold the high bits
+// into the low 24, multiply by an odd 24-bit constant (both operands fit 24
+// bits, so this is the full-rate 24-bit multiply) and keep the top bits of
+// the low word, each of which depends on all 24 folded bits. Unsigned
+// throughout: a signed product shifted right would sign-extend past the
+// table.
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int bits) {
-  return ((uint32_t)x * 0x9E3779B1u) >> (32 - bits);
+  const uint32_t y = ((uint32_t)x ^ ((uint32_t)x >> 12)) & 0xFFFFFFu;
+  return (y * 0x9E3779u) >> (32 - bits);
 }
 
 // Degree-order rank test: (d(a), a) < (d(b), b).

@@ -196,10 +196,11 @@ def _tuning_all_to(variant, limit_bins=None):
 
 
 MIN_SIDE_TUNINGS = [
-    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 1},
-    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 1},
-    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [28, 28, 28, 28, 29, 33], "min_side": 1},
-    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 33], "min_side": 0},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 1},
+    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [28, 28, 28, 28, 29, 36], "min_side": 1},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 0},
+    {"bin_limit": [32, 64, 256, 1024, 2048], "bin_variant": [29, 29, 35, 33, 34, 36], "min_side": 1},
 ]
 
 
