@@ -57,7 +57,7 @@ constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, total;
+      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, total;
   int64_t cls_nblk;
   int64_t max_jobs;
 };
@@ -92,6 +92,7 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.inlist = take(sizeof(int32_t) * n);
   L.inch = take(sizeof(int32_t) * n);
   L.incoff = take(sizeof(int64_t) * (n + 1));
+  L.part = take(2 * sizeof(uint32_t) * kPartMaxParts + 2 * sizeof(int64_t) * (kPartMaxParts + 1));
   L.total = p;
   return L;
 }
@@ -338,16 +339,42 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
 
   HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
   HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
-  // a1: validate + raw degrees
-  HIPCHK(launch_degree_raw(src, dst, m_raw, n, len, hdr + kHdrErr, s));
+  const int pbits = m_raw > 0 ? part_bits(n) : -1;
   int32_t err = 0;
-  if ((rc = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return rc;
-  if (err) return fail(TRICC_ERANGE, "edge list holds a node id outside [0, %d)", n);
-  // a2: row offsets
-  HIPCHK(launch_scan_i32(len, n, raw_off, scan_tmp, s));
-  HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
-  // a3: scatter (len ends equal to the raw row lengths again), sort, dedup
-  HIPCHK(launch_scatter(src, dst, m_raw, raw_off, len, adj, s));
+  if (pbits >= 0) {
+    // a1-a3 partitioned: validate, stage every entry in its partition's
+    // slice (other endpoint in tmp, local row in the not yet used dcol
+    // area), then raw lengths, row offsets and unsorted rows per partition
+    const int32_t P = (int32_t)((n + (int64_t(1) << pbits) - 1) >> pbits);
+    uint32_t* ptotal = g->at<uint32_t>(L.part);
+    uint32_t* pcur = ptotal + kPartMaxParts;
+    int64_t* pstart = reinterpret_cast<int64_t*>(pcur + kPartMaxParts);
+    int64_t* cstart = pstart + kPartMaxParts + 1;
+    int32_t* pv = g->at<int32_t>(L.tmp);
+    uint16_t* pu = g->at<uint16_t>(L.dcol);
+    int32_t* cur = g->at<int32_t>(L.binlist);
+    HIPCHK(hipMemsetAsync(ptotal, 0, 2 * sizeof(uint32_t) * kPartMaxParts, s));
+    HIPCHK(launch_part_count(src, dst, m_raw, n, pbits, P, ptotal, hdr + kHdrErr, s));
+    if ((rc = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return rc;
+    if (err) return fail(TRICC_ERANGE, "edge list holds a node id outside [0, %d)", n);
+    HIPCHK(launch_part_scan(ptotal, P, pstart, cstart, s));
+    HIPCHK(launch_part_place(src, dst, m_raw, pbits, P, pstart, pcur, pv, pu, s));
+    HIPCHK(launch_part_rows(0, pbits, P, n, 2 * m_raw, pstart, cstart, pu, pv, len, raw_off, cur, adj, s));
+    HIPCHK(launch_scan_i32(len, n, raw_off, scan_tmp, s));
+    HIPCHK(hipMemsetAsync(cur, 0, sizeof(int32_t) * (size_t)n, s));
+    HIPCHK(launch_part_rows(1, pbits, P, n, 2 * m_raw, pstart, cstart, pu, pv, len, raw_off, cur, adj, s));
+  } else {
+    // a1: validate + raw degrees
+    HIPCHK(launch_degree_raw(src, dst, m_raw, n, len, hdr + kHdrErr, s));
+    if ((rc = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return rc;
+    if (err) return fail(TRICC_ERANGE, "edge list holds a node id outside [0, %d)", n);
+    // a2: row offsets
+    HIPCHK(launch_scan_i32(len, n, raw_off, scan_tmp, s));
+    HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
+    // a3: scatter (len ends equal to the raw row lengths again)
+    HIPCHK(launch_scatter(src, dst, m_raw, raw_off, len, adj, s));
+  }
+  // a3: row sort and dedup
   int32_t* rowlist = g->at<int32_t>(L.rowlist);
   int64_t* d_cls_off = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrClsOff * 4);
   int64_t cls_off[kNumRowClasses + 1] = {};

@@ -155,6 +155,234 @@ hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw,
 }
 
 // ---------------------------------------------------------------------------
+// a1-a3, partitioned: the same raw rows without a global atomic per entry.
+// Node v lies in partition v >> pbits (2^pbits consecutive ids, at most
+// kPartMax partitions). Pass A counts each partition's entries with LDS
+// histograms (and checks the ids); pass B moves every entry, i.e. each pair
+// seen from each of its endpoints, into its partition's slice of a staging
+// array (other endpoint in pv, the row as a 16-bit local index in pu),
+// reserving one range per (tile, partition); passes C and D take one chunk
+// of one partition per block with one LDS counter per node of the
+// partition: C adds up the raw row lengths, D reserves each row's range and
+// places the entries. Self loops are dropped in A and B.
+constexpr int kPartMax = kPartMaxParts;
+constexpr int kPartMinBits = 10, kPartMaxBits = 14;
+constexpr int kPartNT = 1024;
+constexpr int kPartPairs = 16;  // pairs per thread per tile in pass B
+constexpr int64_t kPartTile = (int64_t)kPartNT * kPartPairs;
+constexpr int kRowsNT = 1024;
+constexpr int kRowsUnroll = 4;
+constexpr int64_t kRowsChunk = int64_t(1) << 18;  // entries per block in C and D
+
+int part_bits(int64_t n) {
+  if (n <= 0) return -1;
+  int b = kPartMinBits;
+  while (b < kPartMaxBits && ((n + (int64_t(1) << b) - 1) >> b) > 1024) ++b;
+  return ((n + (int64_t(1) << b) - 1) >> b) <= kPartMax ? b : -1;
+}
+
+__global__ __launch_bounds__(kPartNT) void k_part_count(const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ dst, int64_t m_raw, int32_t n,
+                                                       int pbits, int32_t P, uint32_t* __restrict__ ptotal,
+                                                       int32_t* __restrict__ err) {
+  __shared__ uint32_t hist[kPartMax];
+  for (int b = threadIdx.x; b < P; b += kPartNT) hist[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kPartNT;
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * kPartNT + threadIdx.x; e < m_raw; e += stride) {
+    const int32_t u = src[e], v = dst[e];
+    if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) { bad = true; continue; }
+    if (u == v) continue;
+    atomicAdd(&hist[u >> pbits], 1u);
+    atomicAdd(&hist[v >> pbits], 1u);
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < P; b += kPartNT)
+    if (hist[b]) atomicAdd(&ptotal[b], hist[b]);
+}
+
+// Single block: pstart = exclusive scan of the partition sizes, cstart =
+// exclusive scan of their chunk counts (ceil(size / kRowsChunk)).
+__global__ __launch_bounds__(1024) void k_part_scan(const uint32_t* __restrict__ ptotal, int32_t P,
+                                                    int64_t* __restrict__ pstart, int64_t* __restrict__ cstart) {
+  __shared__ int64_t lds[1024 / kWave + 1];
+  int64_t c0 = 0, c1 = 0;
+  for (int32_t base = 0; base < P; base += 1024) {
+    const int32_t i = base + threadIdx.x;
+    const int64_t t = i < P ? (int64_t)ptotal[i] : 0;
+    const int64_t ch = (t + kRowsChunk - 1) / kRowsChunk;
+    int64_t tot0, tot1;
+    const int64_t e0 = block_excl_scan<int64_t, 1024>(t, lds, &tot0);
+    const int64_t e1 = block_excl_scan<int64_t, 1024>(ch, lds, &tot1);
+    if (i < P) {
+      pstart[i] = c0 + e0;
+      cstart[i] = c1 + e1;
+    }
+    c0 += tot0;
+    c1 += tot1;
+  }
+  if (threadIdx.x == 0) {
+    pstart[P] = c0;
+    cstart[P] = c1;
+  }
+}
+
+// Pass B: ids are known to be in range (pass A checked them).
+__global__ __launch_bounds__(kPartNT) void k_part_place(const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ dst, int64_t m_raw, int pbits,
+                                                       int32_t P, const int64_t* __restrict__ pstart,
+                                                       uint32_t* __restrict__ pcur, int32_t* __restrict__ pv,
+                                                       uint16_t* __restrict__ pu) {
+  __shared__ uint32_t hist[kPartMax];
+  __shared__ int64_t hoff[kPartMax];
+  const int64_t ntiles = (m_raw + kPartTile - 1) / kPartTile;
+  const int32_t lmask = (1 << pbits) - 1;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int b = threadIdx.x; b < P; b += kPartNT) hist[b] = 0;
+    __syncthreads();
+    const int64_t base = tile * kPartTile + threadIdx.x;
+    int32_t a[kPartPairs], c[kPartPairs];
+#pragma unroll
+    for (int k = 0; k < kPartPairs; ++k) {
+      const int64_t e = base + (int64_t)k * kPartNT;
+      a[k] = -1;
+      c[k] = -1;
+      if (e < m_raw) {
+        a[k] = src[e];
+        c[k] = dst[e];
+      }
+    }
+    uint32_t ra[kPartPairs], rc[kPartPairs];
+#pragma unroll
+    for (int k = 0; k < kPartPairs; ++k) {
+      if (a[k] == c[k]) a[k] = -1;  // self loop or past the end
+      if (a[k] >= 0) {
+        ra[k] = atomicAdd(&hist[a[k] >> pbits], 1u);
+        rc[k] = atomicAdd(&hist[c[k] >> pbits], 1u);
+      }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < P; b += kPartNT) {
+      const uint32_t h = hist[b];
+      if (h) hoff[b] = pstart[b] + atomicAdd(&pcur[b], h);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPartPairs; ++k) {
+      if (a[k] < 0) continue;
+      const int64_t p = hoff[a[k] >> pbits] + ra[k];
+      pv[p] = c[k];
+      pu[p] = (uint16_t)(a[k] & lmask);
+      const int64_t q = hoff[c[k] >> pbits] + rc[k];
+      pv[q] = a[k];
+      pu[q] = (uint16_t)(c[k] & lmask);
+    }
+    __syncthreads();  // hist and hoff are reused by the next tile
+  }
+}
+
+// Passes C (pass 0) and D (pass 1). Block c takes chunk c; blocks past the
+// last chunk exit. A partition held by one chunk writes its rows directly;
+// one spread over several chunks combines them with global atomics (len for
+// C, the zeroed cursors cur for D).
+__global__ __launch_bounds__(kRowsNT) void k_part_rows(int pass, int pbits, int32_t P, int32_t n,
+                                                      const int64_t* __restrict__ pstart,
+                                                      const int64_t* __restrict__ cstart,
+                                                      const uint16_t* __restrict__ pu,
+                                                      const int32_t* __restrict__ pv, int32_t* __restrict__ len,
+                                                      const int64_t* __restrict__ raw_off,
+                                                      int32_t* __restrict__ cur, int32_t* __restrict__ adj) {
+  __shared__ uint32_t cnt[1 << kPartMaxBits];
+  const int64_t c = blockIdx.x;
+  if (c >= cstart[P]) return;
+  // partition of chunk c: the last p with cstart[p] <= c (empty partitions
+  // share their start with the next one and are skipped)
+  int32_t lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (cstart[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int32_t p = lo;
+  const int64_t pb = pstart[p];
+  const int64_t i0 = pb + (c - cstart[p]) * kRowsChunk;
+  const int64_t i1 = min(pstart[p + 1], i0 + kRowsChunk);
+  const bool single = cstart[p + 1] - cstart[p] == 1;
+  const int32_t v0 = p << pbits;
+  const int32_t W = min(1 << pbits, n - v0);
+  for (int j = threadIdx.x; j < W; j += kRowsNT) cnt[j] = 0;
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kRowsNT * kRowsUnroll) {
+    uint16_t r[kRowsUnroll];
+#pragma unroll
+    for (int k = 0; k < kRowsUnroll; ++k) r[k] = i + k * kRowsNT < i1 ? pu[i + k * kRowsNT] : 0xffff;
+#pragma unroll
+    for (int k = 0; k < kRowsUnroll; ++k)
+      if (r[k] != 0xffff) atomicAdd(&cnt[r[k]], 1u);
+  }
+  __syncthreads();
+  if (pass == 0) {
+    for (int j = threadIdx.x; j < W; j += kRowsNT) {
+      const uint32_t k = cnt[j];
+      if (!k) continue;
+      if (single) len[v0 + j] = (int32_t)k;
+      else atomicAdd(&len[v0 + j], (int32_t)k);
+    }
+    return;
+  }
+  for (int j = threadIdx.x; j < W; j += kRowsNT) {
+    const uint32_t k = cnt[j];
+    if (!k) continue;
+    const int32_t at = single ? 0 : atomicAdd(&cur[v0 + j], (int32_t)k);
+    cnt[j] = (uint32_t)(raw_off[v0 + j] - pb) + (uint32_t)at;
+  }
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kRowsNT * kRowsUnroll) {
+    uint16_t r[kRowsUnroll];
+    int32_t x[kRowsUnroll];
+#pragma unroll
+    for (int k = 0; k < kRowsUnroll; ++k) {
+      const bool ok = i + k * kRowsNT < i1;
+      r[k] = ok ? pu[i + k * kRowsNT] : 0xffff;
+      x[k] = ok ? pv[i + k * kRowsNT] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsUnroll; ++k)
+      if (r[k] != 0xffff) adj[pb + atomicAdd(&cnt[r[k]], 1u)] = x[k];
+  }
+}
+
+hipError_t launch_part_count(const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t n, int pbits, int32_t P,
+                             uint32_t* ptotal, int32_t* err, hipStream_t s) {
+  if (m_raw == 0) return hipSuccess;
+  k_part_count<<<grid_for(m_raw, kPartNT * 16, 2048), kPartNT, 0, s>>>(src, dst, m_raw, n, pbits, P, ptotal, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_scan(const uint32_t* ptotal, int32_t P, int64_t* pstart, int64_t* cstart, hipStream_t s) {
+  k_part_scan<<<1, 1024, 0, s>>>(ptotal, P, pstart, cstart);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_place(const int32_t* src, const int32_t* dst, int64_t m_raw, int pbits, int32_t P,
+                             const int64_t* pstart, uint32_t* pcur, int32_t* pv, uint16_t* pu, hipStream_t s) {
+  if (m_raw == 0) return hipSuccess;
+  k_part_place<<<grid_for(m_raw, (int)kPartTile, 4096), kPartNT, 0, s>>>(src, dst, m_raw, pbits, P, pstart, pcur,
+                                                                         pv, pu);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_rows(int pass, int pbits, int32_t P, int32_t n, int64_t max_entries, const int64_t* pstart,
+                            const int64_t* cstart, const uint16_t* pu, const int32_t* pv, int32_t* len,
+                            const int64_t* raw_off, int32_t* cur, int32_t* adj, hipStream_t s) {
+  // every partition has at most ceil(size / chunk) <= size / chunk + 1 chunks
+  const int64_t blocks = max_entries / kRowsChunk + P + 1;
+  k_part_rows<<<(unsigned)blocks, kRowsNT, 0, s>>>(pass, pbits, P, n, pstart, cstart, pu, pv, len, raw_off, cur, adj);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Row classes by raw length.
 __device__ __forceinline__ int row_class(int32_t len) {
   if (len <= 1) return kRowTrivial;

@@ -26,6 +26,23 @@ hipError_t launch_scan_i32(const int32_t* in, int64_t n, int64_t* out, int64_t* 
 hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_scatter(const int32_t* src, const int32_t* dst, int64_t m_raw, const int64_t* off,
                           int32_t* cur, int32_t* adj, hipStream_t s);
+// Partitioned raw rows (same result as degree_raw + scan + scatter, rows
+// unsorted): part_bits(n) is log2 of the nodes per partition, or -1 where
+// the partitioned path does not apply (n == 0 or more than kPartMax
+// partitions). Staging: pv and pu hold 2 * m_raw entries; ptotal and pcur
+// P zeroed counters; pstart and cstart P + 1 slots.
+constexpr int kPartMaxParts = 4096;
+int part_bits(int64_t n);
+hipError_t launch_part_count(const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t n, int pbits, int32_t P,
+                             uint32_t* ptotal, int32_t* err, hipStream_t s);
+hipError_t launch_part_scan(const uint32_t* ptotal, int32_t P, int64_t* pstart, int64_t* cstart, hipStream_t s);
+hipError_t launch_part_place(const int32_t* src, const int32_t* dst, int64_t m_raw, int pbits, int32_t P,
+                             const int64_t* pstart, uint32_t* pcur, int32_t* pv, uint16_t* pu, hipStream_t s);
+// pass 0: len (zeroed) = raw row lengths; pass 1 (after raw_off = scan of
+// len, cur zeroed): adj rows filled.
+hipError_t launch_part_rows(int pass, int pbits, int32_t P, int32_t n, int64_t max_entries, const int64_t* pstart,
+                            const int64_t* cstart, const uint16_t* pu, const int32_t* pv, int32_t* len,
+                            const int64_t* raw_off, int32_t* cur, int32_t* adj, hipStream_t s);
 // Classification with per-block histograms (see build_kernels.hip): pass 0
 // fills hist[c * nblk + blk]; after an exclusive scan of hist into off,
 // pass 1 writes the members of class c at list[off[c * nblk] ...].

@@ -300,3 +300,36 @@ def test_long_rows_take_every_sort_path():
     r, ref = parity(n, s[perm], d[perm])
     assert r["info"]["large_rows"] >= 1
     assert r["info"]["max_deg"] >= 100_000
+
+
+def test_partition_spread_over_several_blocks():
+    """The raw rows are built per id range (1024 ids here); a range with more
+    entries than one block takes (2^18) is split over blocks that combine
+    their row lengths and cursors. Two hubs share the first range; edges
+    straddle range boundaries; self loops and duplicates are mixed in."""
+    rng = np.random.default_rng(31)
+    n = 700_000
+    hub_a = rng.choice(np.arange(1024, n), size=600_000, replace=False)
+    hub_b = rng.choice(np.arange(1024, n), size=150_000, replace=False)
+    b = np.arange(1024, n, 1024)
+    s = [np.full(600_000, 5), np.full(150_000, 1000), hub_a[:40_000], rng.integers(0, n, 300_000), b - 1,
+         np.arange(0, n, 997)]
+    d = [hub_a, hub_b, np.full(40_000, 5), rng.integers(0, n, 300_000), b, np.arange(0, n, 997)]
+    s = np.concatenate(s).astype(np.int32)
+    d = np.concatenate(d).astype(np.int32)
+    perm = rng.permutation(s.size)
+    r, ref = parity(n, s[perm], d[perm])
+    assert r["info"]["max_deg"] >= 600_000
+    assert ref["deg"][5] >= 600_000
+
+
+def test_build_beyond_partitioned_range():
+    """More ids than the per-range build covers (4096 ranges of 2^14 ids):
+    the build takes the per-entry path. Small components sit at both ends
+    and in the middle of a 70M-id range."""
+    n = 70_000_000
+    comps = [(0, F.complete(6)), (35_000_000, F.wheel(9)), (n - 40, F.windmill(5)), (n - 12, F.complete(12))]
+    s = np.concatenate([c[1] + o for o, c in comps]).astype(np.int32)
+    d = np.concatenate([c[2] + o for o, c in comps]).astype(np.int32)
+    r, ref = parity(n, s, d)
+    assert r["total"] == 20 + 9 + 5 + 220
