@@ -185,31 +185,36 @@ __global__ __launch_bounds__(NT) void k_count_hash(const int32_t* __restrict__ l
 // the list), so a probe is one 16-byte LDS read and a few compares; the
 // overflow walk to the next bucket is rare. Hits are counted with a ballot
 // and a popcount into a wave-uniform total.
+// Looks x up in the bucket table: true when the lane is valid and x is in
+// the table, with *off the byte offset inside the counter array C of x's
+// slot (slot j of bucket b is counter 4b + j, at byte 16b + 4j). One 16-byte
+// read unless x's home bucket is full and does not hold x (rare in a sparse
+// table). The matching slot comes from four compares whose lane masks are
+// combined on the scalar unit.
 template <int NB>
-__device__ __forceinline__ int bucket_slot(int4 q, uint32_t b, int32_t x) {
-  int slot = -1;
-  slot = (q.w == x) ? (int)(4 * b + 3) : slot;
-  slot = (q.z == x) ? (int)(4 * b + 2) : slot;
-  slot = (q.y == x) ? (int)(4 * b + 1) : slot;
-  slot = (q.x == x) ? (int)(4 * b) : slot;
-  return slot;
-}
-
-// Slot of x in the bucket table or -1. One 16-byte read unless x's home
-// bucket is full and does not hold x (rare in a sparse table).
-template <int NB>
-__device__ __forceinline__ int bucket_probe(const int4* Kb, int32_t x, bool valid) {
+__device__ __forceinline__ bool bucket_credit(const int4* Kb, int32_t x, bool valid, int* off) {
   uint32_t b = hash_slot(x, __builtin_ctz(NB));
   int4 q = Kb[b];
-  int slot = bucket_slot<NB>(q, b, x);
-  bool more = valid && slot < 0 && q.w >= 0;
+  bool e1 = q.y == x, e2 = q.z == x, e3 = q.w == x;
+  bool hit = (q.x == x) | e1 | e2 | e3;
+  int o = (int)(b << 4) + ((e1 | e3) ? 4 : 0) + ((e2 | e3) ? 8 : 0);
+  bool more = valid & !hit & (q.w >= 0);
   while (more) {
     b = (b + 1) & (NB - 1);
     q = Kb[b];
-    slot = bucket_slot<NB>(q, b, x);
-    more = slot < 0 && q.w >= 0;
+    e1 = q.y == x;
+    e2 = q.z == x;
+    e3 = q.w == x;
+    hit = (q.x == x) | e1 | e2 | e3;
+    o = (int)(b << 4) + ((e1 | e3) ? 4 : 0) + ((e2 | e3) ? 8 : 0);
+    more = !hit & (q.w >= 0);
   }
-  return valid ? slot : -1;
+  *off = o;
+  return valid & hit;
+}
+
+__device__ __forceinline__ void credit(uint32_t* C, int off) {
+  atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(C) + off), 1u);
 }
 
 // LDS of one node group of the wave-stream kernel.
@@ -221,6 +226,8 @@ struct WaveGroupLds {
   int32_t Wn[CAP];       // |N+(w)|
   int32_t Ws[CAP];       // slot of w
   uint32_t Wc[CAP];      // hits per streamed list (packed phase)
+  int32_t Wl[CAP];       // indices of the lists streamed one by one
+  int32_t nlong;         // number of such lists
 };
 
 // Lists shorter than this are streamed packed: a wavefront covers several
@@ -261,45 +268,98 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
       const int32_t ke = __shfl(excl, k, kWave);
       const bool valid = t < total;
       const int32_t x = valid ? dcol[kb + (t - ke)] : -1;
-      const int s = bucket_probe<NB>(Kb, x, valid);
-      if (s >= 0) {
-        atomicAdd(&C[s], 1u);
+      int off;
+      const bool hit = bucket_credit<NB>(Kb, x, valid, &off);
+      hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+      if (hit) {
+        credit(C, off);
         atomicAdd(&Wc[base + k], 1u);
       }
-      hits += (uint32_t)__popcll(__ballot(s >= 0));
     }
   }
   return hits;
 }
 
-// One node u (u < 0: inactive group) counted by a group of G lanes (G a
-// multiple of 64; when G > 64 the group is the whole block). U ids per lane
-// per step: U independent loads are in flight before the probes; loads past
-// the end of a list are clamped to its last element (same cache line) and
-// masked out of the count.
-// One wavefront streams the list L[0..n) (16-byte-aligned dcol ids) against
-// the bucket table: credits each hit's slot, returns the wave's hit count
-// (wave-uniform).
-template <int NB, int U>
-__device__ __forceinline__ uint32_t stream_probe(const int32_t* __restrict__ L, int32_t n, const int4* Kb,
-                                                 uint32_t* C) {
-  const int lane = lane_id();
-  uint32_t cw = 0;
-  for (int32_t p = 0; p < n; p += U * kWave) {
-    int32_t x[U];
+// U chunks of 64 ids of L[p..n) into x, through a raw buffer view of
+// L[p..n): the offsets are lane * 4 + k * 256, which its range check covers
+// exactly, so lanes past n read 0 without a memory access. All U loads are
+// issued, which keeps the wait counts of the caller's pipeline exact.
+template <int U>
+__device__ __forceinline__ void load_chunk(int32_t (&x)[U], const int32_t* L, int32_t p, int32_t n, int lane) {
+  static_assert(U * kWave * 4 <= 4096, "per-load offsets must fit the 12-bit immediate field");
+  const int32_t left = n > p ? n - p : 0;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(L + p), (short)0, left * 4, kRawBufferWord3);
 #pragma unroll
-    for (int k = 0; k < U; ++k) x[k] = L[min(p + k * kWave + lane, n - 1)];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const bool v = p + k * kWave + lane < n;
-      const int s = bucket_probe<NB>(Kb, x[k], v);
-      if (s >= 0) atomicAdd(&C[s], 1u);
-      cw += (uint32_t)__popcll(__ballot(s >= 0));
-    }
-  }
-  return cw;
+  for (int k = 0; k < U; ++k) x[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4 + k * kWave * 4, 0, 0);
 }
 
+// One wavefront streams the long lists Wl[j] (j = j0, j0 + step, ... < nl)
+// against the bucket table, U loads of 64 ids per step: the next step's
+// loads (same list, or the first chunk of the next one) are in flight while
+// the current chunk is probed. Base and length of a list are wave-uniform
+// (scalar registers). Each hit credits its table slot; done(i, hits)
+// receives list i's hit count (wave-uniform). Returns the wave's hits.
+template <int NB, int U, typename Done>
+__device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_t nl, const int32_t* Wl,
+                                                const int32_t* Wb, const int32_t* Wn,
+                                                const int32_t* __restrict__ dcol, const int4* Kb, uint32_t* C,
+                                                Done done) {
+  // j0 is the wave's index inside its group: uniform, but not provably so
+  int32_t j = __builtin_amdgcn_readfirstlane(j0);
+  if (j >= nl) return 0;
+  const int lane = lane_id();
+  int32_t i = __builtin_amdgcn_readfirstlane(Wl[j]);
+  int32_t b = __builtin_amdgcn_readfirstlane(Wb[i]);
+  int32_t n = __builtin_amdgcn_readfirstlane(Wn[i]);
+  int32_t p = 0;
+  uint32_t total = 0, cw = 0;
+  // one pipeline step: load the chunk after (i, p) into nxt, probe cur;
+  // false once the last list is done. Two register sets alternate, so no
+  // copy has to wait for the loads in flight.
+  auto advance = [&](int32_t (&cur)[U], int32_t (&nxt)[U]) -> bool {
+    int32_t nj = j, ni = i, nb = b, nn = n, np = p + U * kWave;
+    if (np >= n) {  // list i ends with this chunk
+      nj = j + step;
+      np = 0;
+      nn = 0;
+      if (nj < nl) {
+        ni = __builtin_amdgcn_readfirstlane(Wl[nj]);
+        nb = __builtin_amdgcn_readfirstlane(Wb[ni]);
+        nn = __builtin_amdgcn_readfirstlane(Wn[ni]);
+      }
+    }
+    load_chunk<U>(nxt, dcol + nb, np, nn, lane);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (p + k * kWave >= n) break;
+      int off;
+      const bool hit = bucket_credit<NB>(Kb, cur[k], lane < n - p - k * kWave, &off);
+      cw += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+      if (hit) credit(C, off);
+    }
+    if (np == 0) {
+      done(i, cw);
+      total += cw;
+      cw = 0;
+      if (nj >= nl) return false;
+    }
+    j = nj;
+    i = ni;
+    b = nb;
+    n = nn;
+    p = np;
+    return true;
+  };
+  int32_t x[U], y[U];
+  load_chunk<U>(x, dcol + b, 0, n, lane);
+  while (advance(x, y) && advance(y, x)) {
+  }
+  return total;
+}
+
+// One node u (u < 0: inactive group) counted by a group of G lanes (G a
+// multiple of 64; when G > 64 the group is the whole block).
 // w_max > 0 (min-side mode): edges u->w with d+(u) < d+(w) <= w_max are left
 // to w's in-list pass (node_count_inw), which then streams the shorter list.
 template <int G, int SLOTS, int CAP, int U>
@@ -322,27 +382,25 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
     len = (int32_t)(doff[u + 1] - beg);
   }
   for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
+  if (g == 0) S.nlong = 0;
   group_sync<G>();
   for (int i = g; i < len; i += G) {
     const int32_t w = dcol[beg + i];
     S.Ws[i] = bucket_insert<NB>(K, w);
     const int64_t b = doff[w];
-    const int32_t wn = (int32_t)(doff[w + 1] - b);
-    S.Wb[i] = (int32_t)b;
+    int32_t wn = (int32_t)(doff[w + 1] - b);
     // edges u->w with d+(u) < d+(w) <= w_max are counted from w's in-list
-    S.Wn[i] = (len < wn && wn <= w_max) ? 0 : wn;
+    if (len < wn && wn <= w_max) wn = 0;
+    S.Wb[i] = (int32_t)b;
+    S.Wn[i] = wn;
     S.Wc[i] = 0;
+    if (wn >= kPackShort) S.Wl[atomicAdd(&S.nlong, 1)] = i;
   }
   group_sync<G>();
-  uint32_t tu = 0;  // wave-uniform
-  for (int i = wv; i < len; i += WPG) {
-    const int32_t wb = __builtin_amdgcn_readfirstlane(S.Wb[i]);
-    const int32_t wn = __builtin_amdgcn_readfirstlane(S.Wn[i]);
-    if (wn < kPackShort) continue;  // short lists: packed phase below
-    const uint32_t cw = stream_probe<NB, U>(dcol + wb, wn, S.K, S.C);
+  const int32_t nl = __builtin_amdgcn_readfirstlane(S.nlong);
+  uint32_t tu = stream_long<NB, U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, S.K, S.C, [&](int32_t i, uint32_t cw) {
     if (cw && lane == 0) atomicAdd(&S.C[S.Ws[i]], cw);
-    tu += cw;
-  }
+  });  // wave-uniform
   tu += stream_packed<NB>(wv * len / WPG, (wv + 1) * len / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
   group_sync<G>();
   for (int i = g; i < len; i += G)
@@ -409,27 +467,25 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
     nin = (int32_t)min((int64_t)CAP, dinoff[w + 1] - ib);
   }
   for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
+  if (g == 0) S.nlong = 0;
   group_sync<G>();
   for (int i = g; i < len; i += G) bucket_insert<NB>(K, dcol[beg + i]);
   for (int i = g; i < nin; i += G) {
     const int32_t u = dincol[ib + i];
     const int64_t b = doff[u];
-    const int32_t nu = (int32_t)(doff[u + 1] - b);
+    int32_t nu = (int32_t)(doff[u + 1] - b);
+    if (nu < 2 || nu >= len) nu = 0;
     S.Wb[i] = (int32_t)b;
-    S.Wn[i] = (nu >= 2 && nu < len) ? nu : 0;
+    S.Wn[i] = nu;
     S.Ws[i] = u;
     S.Wc[i] = 0;
+    if (nu >= kPackShort) S.Wl[atomicAdd(&S.nlong, 1)] = i;
   }
   group_sync<G>();
-  uint32_t tw = 0;  // wave-uniform
-  for (int i = wv; i < nin; i += WPG) {
-    const int32_t ub = __builtin_amdgcn_readfirstlane(S.Wb[i]);
-    const int32_t un = __builtin_amdgcn_readfirstlane(S.Wn[i]);
-    if (un < kPackShort) continue;  // short lists: packed phase below
-    const uint32_t cu = stream_probe<NB, U>(dcol + ub, un, S.K, S.C);
+  const int32_t nl = __builtin_amdgcn_readfirstlane(S.nlong);
+  uint32_t tw = stream_long<NB, U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, S.K, S.C, [&](int32_t i, uint32_t cu) {
     if (cu && lane == 0) atomicAdd(&T[S.Ws[i]], (unsigned long long)cu);
-    tw += cu;
-  }
+  });  // wave-uniform
   tw += stream_packed<NB>(wv * nin / WPG, (wv + 1) * nin / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
   group_sync<G>();
   for (int i = g; i < nin; i += G)
@@ -901,7 +957,7 @@ static void launch_plain(const BinLaunch& b, const int64_t* doff, const int32_t*
   k_count_plain<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
 }
 
-template <int NT, int G, int SLOTS, int CAP, int U = 4>
+template <int NT, int G, int SLOTS, int CAP, int U = 8>
 static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
                       hipStream_t s) {
   constexpr int GPB = NT / G;

@@ -81,16 +81,19 @@ __device__ __forceinline__ T block_sum(T x, T* lds) {
   return r;  // valid in thread 0
 }
 
-// Hash of a node id onto `bits` bits (1 <= bits <= 20): fold the high bits
-// into the low 24, multiply by an odd 24-bit constant (both operands fit 24
-// bits, so this is the full-rate 24-bit multiply) and keep the top bits of
-// the low word, each of which depends on all 24 folded bits. Unsigned
-// throughout: a signed product shifted right would sign-extend past the
-// table.
+// Hash of a node id onto `bits` bits (1 <= bits <= 20): multiply the low 24
+// bits by an odd 24-bit constant with the full-rate 24-bit multiplier and
+// keep the top bits of the low product word, each of which depends on all 24
+// input bits. Ids that differ only above bit 23 share a home bucket, which
+// costs a probe step at most. Unsigned throughout: a signed product shifted
+// right would sign-extend past the table.
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int bits) {
-  const uint32_t y = ((uint32_t)x ^ ((uint32_t)x >> 12)) & 0xFFFFFFu;
-  return (y * 0x9E3779u) >> (32 - bits);
+  return (((uint32_t)x & 0xFFFFFFu) * 0x9E3779u) >> (32 - bits);
 }
+
+// Third dword of a raw (unformatted, stride 0) gfx9 buffer resource: 32-bit
+// data, loads past num_records bytes return 0 without a memory access.
+constexpr int32_t kRawBufferWord3 = 0x00020000;
 
 // Degree-order rank test: (d(a), a) < (d(b), b).
 __device__ __forceinline__ bool rank_below(int32_t da, int32_t a, int32_t db, int32_t b) {
