@@ -247,7 +247,9 @@ def serving_leg(args, torch, P, N):
     if args.serve_tune:
         best = None
         for ml in (0, 4, 16, 32):
-            for pv in (0, 1):
+            for pv in (0, 1, 2, 3):
+                if pv >= 2 and ml > 16:
+                    continue  # the packed small-node path takes d+ <= 16
                 t = {"merge_limit": ml, "wave_limit": 64, "persist_variant": pv, "blocks_per_cu": 0}
                 r = run_trace(P, N, g, queries[:max(200, Q // 10)], None, args.serve_slots, 256, budget, t)
                 log(f"serve tuning {t}: {r['qps']:.1f} q/s")

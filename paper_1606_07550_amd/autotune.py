@@ -3,8 +3,9 @@
 Single graph: coordinate search over each bin's kernel variant (among those
 whose capacity covers the bin) and over a few sets of bin limits, timing
 each bin's kernel alone with events on its stream.
-Batch: grid search over the persistent kernel's work split (wave_limit),
-block-table capacity (persist_variant) and grid size (blocks_per_cu),
+Batch: grid search over the persistent kernel's work split (merge_limit,
+wave_limit), its variant (block-table capacity, short-list path) and grid
+size (blocks_per_cu),
 timing whole graph launches.
 
 Results are cached in ``tuning_cache.json`` next to this file, keyed by
@@ -126,8 +127,8 @@ def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
     return best, best_total
 
 
-BATCH_SPACE = [(ml, wl, pv, bpc) for pv in (0, 1) for wl in (32, 64) for ml in (0, 8, 16, 32, 64)
-               for bpc in (0, 4) if ml <= wl]
+BATCH_SPACE = [(ml, wl, pv, bpc) for pv in (0, 1, 2, 3) for wl in (32, 64) for ml in (0, 8, 16, 32, 64)
+               for bpc in (0, 4) if ml <= wl and (pv < 2 or ml <= 16)]
 
 
 def tune_batch(batch, reps=3, key=None, log=None):

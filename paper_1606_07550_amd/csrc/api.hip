@@ -671,6 +671,9 @@ int check_batch_tuning(const tricc_batch_tuning* t) {
                 persist_wave_cap(t->persist_variant));
   if (t->merge_limit < 0 || t->merge_limit > t->wave_limit)
     return fail(TRICC_EINVAL, "batch tuning: merge_limit %d outside [0, wave_limit]", t->merge_limit);
+  if (t->merge_limit > persist_merge_cap(t->persist_variant))
+    return fail(TRICC_EINVAL, "batch tuning: merge_limit %d above %d for persistent variant %d", t->merge_limit,
+                persist_merge_cap(t->persist_variant), t->persist_variant);
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(TRICC_EINVAL, "batch tuning: blocks_per_cu");
   return TRICC_OK;
 }
@@ -741,9 +744,9 @@ extern "C" {
 
 int tricc_batch_default_tuning(tricc_batch_tuning* out) {
   if (!out) return fail(TRICC_EINVAL, "null tuning");
-  out->merge_limit = 32;
+  out->merge_limit = 16;
   out->wave_limit = 64;
-  out->persist_variant = 0;
+  out->persist_variant = 2;
   out->blocks_per_cu = 0;
   return TRICC_OK;
 }

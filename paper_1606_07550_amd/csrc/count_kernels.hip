@@ -234,6 +234,9 @@ struct WaveGroupLds {
 // short lists per step instead of one list per step.
 constexpr int32_t kPackShort = 64;
 
+// Lanes per node on the packed small-node path (nodes with d+ <= kSmallGS).
+constexpr int kSmallGS = 16;
+
 // Packed streaming of the short lists among items [i0, i1) of a group: a
 // window of up to 64 lists sits in the lanes (begin, length, inclusive
 // prefix of lengths); each step gives every lane one id of the window's
@@ -737,12 +740,95 @@ __global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Several short-list nodes per wavefront: GS lanes per node (d+(u) <= GS),
+// 64 / GS nodes per wave. Lane j of a node's lanes owns the out-edge to the
+// j-th entry w of N+(u); each node has a bucket table of 4 * GS slots in
+// LDS. The 64 lanes' lists N+(w) are streamed packed (one id per lane per
+// step, its list found by a shuffle binary search over the lanes' length
+// prefix) and each id is probed against the table of its list's node, so a
+// wave keeps 64 independent loads in flight instead of walking dependent
+// merge chains. Credits: x per table slot, w per list, u per node.
+template <int GS>
+struct SmallLds {
+  int4 K[kWave / GS][GS];          // GS buckets (4 * GS slots) per node
+  uint32_t C[kWave / GS][4 * GS];  // per-slot credits
+  uint32_t Wc[kWave];              // hits per lane's list
+};
+
+template <int GS>
+__device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ list, int64_t first, int64_t nlist,
+                                                  SmallLds<GS>& S, const int64_t* __restrict__ doff,
+                                                  const int32_t* __restrict__ dcol,
+                                                  unsigned long long* __restrict__ T) {
+  static_assert(kWave % GS == 0 && GS >= 4, "GS divides the wave");
+  constexpr int NB = GS;
+  const int lane = lane_id();
+  const int nd = lane / GS, j = lane % GS;
+  int32_t* K = reinterpret_cast<int32_t*>(S.K[nd]);
+  uint32_t* C = S.C[nd];
+  for (int s = j; s < 4 * GS; s += GS) {
+    K[s] = -1;
+    C[s] = 0;
+  }
+  S.Wc[lane] = 0;
+  const int64_t idx = first + nd;
+  int32_t u = -1, nu = 0, w = -1, wb = 0, wn = 0;
+  int64_t ub = 0;
+  if (idx < nlist) {
+    u = list[idx];
+    ub = doff[u];
+    nu = (int32_t)(doff[u + 1] - ub);
+  }
+  wave_sync();
+  if (j < nu) {
+    w = dcol[ub + j];
+    bucket_insert<NB>(K, w);
+    const int64_t b = doff[w];
+    wb = (int32_t)b;
+    wn = (int32_t)(doff[w + 1] - b);
+  }
+  wave_sync();
+  const int32_t incl = wave_incl_scan(wn);
+  const int32_t total = __shfl(incl, kWave - 1, kWave);
+  const int32_t excl = incl - wn;
+  for (int32_t t0 = 0; t0 < total; t0 += kWave) {
+    const int32_t t = t0 + lane;
+    int k = 0;
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1) {
+      const int32_t v = __shfl(incl, k + step - 1, kWave);
+      if (v <= t) k += step;
+    }
+    const int32_t kb = __shfl(wb, k, kWave);
+    const int32_t ke = __shfl(excl, k, kWave);
+    const bool valid = t < total;
+    const int32_t x = valid ? dcol[kb + (t - ke)] : -1;
+    int off;
+    if (bucket_credit<NB>(S.K[k / GS], x, valid, &off)) {
+      credit(S.C[k / GS], off);
+      atomicAdd(&S.Wc[k], 1u);
+    }
+  }
+  wave_sync();
+  const uint32_t c = S.Wc[lane];
+  if (c) atomicAdd(&T[w], (unsigned long long)c);
+  const uint32_t tu = group_sum<uint32_t, GS>(c);
+  if (j == 0 && tu) atomicAdd(&T[u], (unsigned long long)tu);
+  for (int s = j; s < 4 * GS; s += GS) {
+    const int32_t key = K[s];
+    const uint32_t cs = C[s];
+    if (key >= 0 && cs) atomicAdd(&T[key], (unsigned long long)cs);
+  }
+}
+
 // Persistent form (batched graphs): one launch covers every node of the
 // DAG. Blocks of 256 pull chunks from an atomic work queue, heaviest first:
 // nodes above the block table's capacity (global fallback), then nodes for a
 // whole block (d+ <= CB), then four single-wave nodes (d+ <= CW) at a time,
-// then 32 short-list nodes at a time for the 8-lane merge.
-template <int SW, int CW, int SB, int CB>
+// then the short-list nodes: 32 at a time for the 8-lane merge (SMALL == 0)
+// or 16 at a time, four per wave, on the packed small-node path (SMALL ==
+// 1, d+ <= 16).
+template <int SW, int CW, int SB, int CB, int SMALL = 0>
 __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict__ glist, int32_t ng,
                                                        const int32_t* __restrict__ blist, int32_t nbk,
                                                        const int32_t* __restrict__ wlist, int32_t nw,
@@ -753,12 +839,14 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
                                                        unsigned long long* __restrict__ T) {
   using BL = WaveGroupLds<SB, CB>;
   using WL = WaveGroupLds<SW, CW>;
-  constexpr size_t kBytes = sizeof(BL) > 4 * sizeof(WL) ? sizeof(BL) : 4 * sizeof(WL);
+  using SL = SmallLds<kSmallGS>;
+  constexpr size_t kB0 = sizeof(BL) > 4 * sizeof(WL) ? sizeof(BL) : 4 * sizeof(WL);
+  constexpr size_t kBytes = kB0 > 4 * sizeof(SL) ? kB0 : 4 * sizeof(SL);
   __shared__ __align__(16) unsigned char smem[kBytes];
   __shared__ unsigned long long red[256 / kWave];
   __shared__ int32_t chunk;
   constexpr int kMergeG = 8;
-  constexpr int kMergePerChunk = 256 / kMergeG;
+  constexpr int kMergePerChunk = SMALL ? 4 * (kWave / kSmallGS) : 256 / kMergeG;
   const int64_t nwc = ((int64_t)nw + 3) / 4;
   const int64_t total = (int64_t)ng + nbk + nwc + ((int64_t)nm + kMergePerChunk - 1) / kMergePerChunk;
   while (true) {
@@ -776,6 +864,10 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
       const int64_t k = (c - ng - nbk) * 4 + wv;
       node_count_wave<kWave, SW, CW, 4>(k < nw ? wlist[k] : -1, reinterpret_cast<WL*>(smem)[wv], red, doff, dcol,
                                          T);
+    } else if constexpr (SMALL) {
+      const int wv = threadIdx.x / kWave;
+      const int64_t k = (c - ng - nbk - nwc) * kMergePerChunk + wv * (kWave / kSmallGS);
+      nodes_count_small<kSmallGS>(mlist, k, nm, reinterpret_cast<SL*>(smem)[wv], doff, dcol, T);
     } else {
       const int64_t k = (c - ng - nbk - nwc) * kMergePerChunk + threadIdx.x / kMergeG;
       node_count_merge<kMergeG>(k < nm ? mlist[k] : -1, doff, dcol, T);
@@ -784,19 +876,24 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
   }
 }
 
-struct PersistShape { int sw, cw, sb, cb; };
+struct PersistShape { int sw, cw, sb, cb, small; };
 static constexpr PersistShape kPersist[] = {
-    {256, 64, 1024, 256},   // 0: block nodes up to d+ 256
-    {256, 64, 4096, 1024},  // 1: block nodes up to d+ 1024
+    {256, 64, 1024, 256, 0},   // 0: block nodes up to d+ 256, 8-lane merge
+    {256, 64, 4096, 1024, 0},  // 1: block nodes up to d+ 1024, 8-lane merge
+    {256, 64, 1024, 256, 1},   // 2: as 0, short lists on the packed small-node path
+    {256, 64, 4096, 1024, 1},  // 3: as 1, short lists on the packed small-node path
 };
 int persist_variant_count() { return (int)(sizeof(kPersist) / sizeof(kPersist[0])); }
 int persist_wave_cap(int v) { return kPersist[v].cw; }
 int persist_block_cap(int v) { return kPersist[v].cb; }
+int persist_merge_cap(int v) { return kPersist[v].small ? kSmallGS : kPersist[v].cw; }
 
 const void* persist_kernel(int v) {
   switch (v) {
     case 0: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256>);
     case 1: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024>);
+    case 2: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 1>);
+    case 3: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024, 1>);
     default: return nullptr;
   }
 }
@@ -813,6 +910,14 @@ hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int3
     case 1:
       k_count_persist<256, 64, 4096, 1024><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
                                                                 doff, dcol, T);
+      break;
+    case 2:
+      k_count_persist<256, 64, 1024, 256, 1><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                  doff, dcol, T);
+      break;
+    case 3:
+      k_count_persist<256, 64, 4096, 1024, 1><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
+                                                                   queue, doff, dcol, T);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -143,6 +143,7 @@ hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const uns
 int persist_variant_count();
 int persist_wave_cap(int v);   // largest d+ of a single-wave node
 int persist_block_cap(int v);  // largest d+ of a block node
+int persist_merge_cap(int v);  // largest merge_limit the variant accepts
 const void* persist_kernel(int v);
 hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
                                 int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,

@@ -109,6 +109,9 @@ def test_graph_replays_match_eager(mixed):
     {"merge_limit": 40, "wave_limit": 40, "persist_variant": 1, "blocks_per_cu": 0},
     {"merge_limit": 64, "wave_limit": 64, "persist_variant": 0, "blocks_per_cu": 4},
     {"merge_limit": 8, "wave_limit": 32, "persist_variant": 0, "blocks_per_cu": 0},
+    {"merge_limit": 16, "wave_limit": 64, "persist_variant": 2, "blocks_per_cu": 0},
+    {"merge_limit": 16, "wave_limit": 32, "persist_variant": 3, "blocks_per_cu": 2},
+    {"merge_limit": 3, "wave_limit": 8, "persist_variant": 2, "blocks_per_cu": 1},
 ])
 def test_tunings_agree(mixed, tun):
     graphs, (node_off, edge_off, src, dst) = mixed
@@ -123,6 +126,14 @@ def test_tunings_agree(mixed, tun):
     b.run()
     torch.cuda.synchronize()
     check_batch(to_host(b.out), graphs, node_off)
+
+
+def test_small_node_path_limit_is_enforced(mixed):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    b = P.Batch(node_off, edge_off, dev(src), dev(dst))
+    with pytest.raises(N.TriccError) as ei:
+        b.retune({"merge_limit": 17, "wave_limit": 64, "persist_variant": 2, "blocks_per_cu": 0})
+    assert ei.value.status == N.TRICC_EINVAL
 
 
 def test_batched_equals_single_graph(mixed):
