@@ -82,6 +82,8 @@ typedef struct tricc_graph_info {
   uint64_t bin_list_elems[TRICC_NUM_BINS]; /* d+(u) + d+(w) over the edges each bin's kernel counts (*) */
   int64_t bin_edges[TRICC_NUM_BINS];       /* DAG edges counted by each bin's kernel (*) */
   int64_t bin_in_items[TRICC_NUM_BINS];    /* in-list work items of each bin (min-side) */
+  int64_t n_deg2;              /* nodes with d(v) >= 2; the average CC over these nodes alone is
+                                  avg * n / n_deg2 (every other node has CC 0) */
   /* (*) zero until tricc_graph_stats has run */
 } tricc_graph_info;
 
@@ -123,6 +125,32 @@ int tricc_graph_workspace_size(int32_t n, int64_t m_raw, size_t* bytes);
 int tricc_graph_build(int32_t n, int64_t m_raw, const int32_t* d_src, const int32_t* d_dst,
                       void* d_ws, size_t ws_bytes, const tricc_tuning* tuning, void* stream,
                       tricc_graph** out);
+
+/*
+ * Steps a1..a5 from a graph the caller holds as a CSR: row v is
+ * d_col[d_rowptr[v] .. d_rowptr[v+1]) (the paper's per-node sorted
+ * neighbour vectors, Section 5.1, laid end to end).
+ *   n, nnz      nodes and entries (d_rowptr[n] must equal nnz <= 2^30)
+ *   d_rowptr    device int64[n+1], from 0, non-decreasing; d_col device int32[nnz]
+ *   assume_simple_sorted_symmetric
+ *     0: each entry w of row v is taken as the pair (v, w) and goes through
+ *        the full build (symmetrise, dedup, self loops dropped), exactly as
+ *        tricc_graph_build on those pairs.
+ *     1: the caller asserts that every row is strictly ascending, holds no
+ *        self loop, and that w is in row v iff v is in row w; the rows are
+ *        copied and the sort is skipped. Ranges, order and loops are checked;
+ *        symmetry is not (an asymmetric CSR gives undefined counts, never an
+ *        access outside the workspace).
+ *   d_ws, ws_bytes  at least tricc_graph_workspace_size(n, nnz); the caller's
+ *                   arrays are only read
+ * Synchronises `stream`. Errors: TRICC_EINVAL for malformed row offsets, a
+ * row that is not strictly ascending or holds its own id (mode 1), bad sizes
+ * or tuning; TRICC_ERANGE for an id outside [0, n); TRICC_ENOMEM for a short
+ * workspace. No handle is made on error.
+ */
+int tricc_graph_from_csr(int32_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_col,
+                         int assume_simple_sorted_symmetric, void* d_ws, size_t ws_bytes,
+                         const tricc_tuning* tuning, void* stream, tricc_graph** out);
 
 int tricc_graph_info_get(const tricc_graph* g, tricc_graph_info* out);
 

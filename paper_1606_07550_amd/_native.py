@@ -51,14 +51,15 @@ class GraphInfo(ctypes.Structure):
                 ("max_deg", ctypes.c_int64), ("max_outdeg", ctypes.c_int64),
                 ("bin_count", ctypes.c_int64 * NUM_BINS), ("list_elems", ctypes.c_uint64),
                 ("large_rows", ctypes.c_int64), ("bin_list_elems", ctypes.c_uint64 * NUM_BINS),
-                ("bin_edges", ctypes.c_int64 * NUM_BINS), ("bin_in_items", ctypes.c_int64 * NUM_BINS)]
+                ("bin_edges", ctypes.c_int64 * NUM_BINS), ("bin_in_items", ctypes.c_int64 * NUM_BINS),
+                ("n_deg2", ctypes.c_int64)]
 
     def as_dict(self):
         return {"n": self.n, "m_raw": self.m_raw, "m": self.m, "max_deg": self.max_deg,
                 "max_outdeg": self.max_outdeg, "bin_count": list(self.bin_count),
                 "list_elems": int(self.list_elems), "large_rows": self.large_rows,
                 "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges),
-                "bin_in_items": list(self.bin_in_items)}
+                "bin_in_items": list(self.bin_in_items), "n_deg2": self.n_deg2}
 
 
 class BatchTuning(ctypes.Structure):
@@ -110,6 +111,8 @@ _SIGS = {
     "tricc_graph_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "tricc_graph_build": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
                                          ctypes.POINTER(Tuning), _P, ctypes.POINTER(_P)]),
+    "tricc_graph_from_csr": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, ctypes.c_int, _P,
+                                            ctypes.c_size_t, ctypes.POINTER(Tuning), _P, ctypes.POINTER(_P)]),
     "tricc_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(GraphInfo)]),
     "tricc_graph_retune": (ctypes.c_int, [_P, ctypes.POINTER(Tuning), _P]),
     "tricc_graph_stats": (ctypes.c_int, [_P, _P]),

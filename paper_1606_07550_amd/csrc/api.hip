@@ -41,6 +41,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 enum : int {
   kHdrErr = 0,
   kHdrStats = 4,      // [0] max d, [1] max d+
+  kHdrDeg2 = 6,       // nodes with d >= 2
   kHdrRowCnt = 8,     // [kNumRowClasses]
   kHdrBinCnt = 16,    // [kNumBins]
   kHdrLimits = 24,    // [kNumBins - 1]
@@ -324,7 +325,10 @@ int graph_stats(tricc_graph* g) {
   return TRICC_OK;
 }
 
-int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
+// Builds a1-a5. With presorted set, adj, raw_off, len and deg already hold
+// simple, sorted, symmetric rows (a caller CSR that was checked) and a1-a3
+// reduce to the row classification that the orientation needs.
+int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool presorted = false) {
   hipStream_t s = g->stream;
   const Layout& L = g->L;
   const int32_t n = g->n;
@@ -337,11 +341,13 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   int32_t* adj = g->at<int32_t>(L.adj);
   int rc;
 
-  HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
-  HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
-  const int pbits = m_raw > 0 ? part_bits(n) : -1;
+  if (!presorted) HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
+  if (!presorted) HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
+  const int pbits = m_raw > 0 && !presorted ? part_bits(n) : -1;
   int32_t err = 0;
-  if (pbits >= 0) {
+  if (presorted) {
+    // rows in place
+  } else if (pbits >= 0) {
     // a1-a3 partitioned: validate, stage every entry in its partition's
     // slice (other endpoint in tmp, local row in the not yet used dcol
     // area), then raw lengths, row offsets and unsorted rows per partition
@@ -386,11 +392,13 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   }
   int32_t cnt[kNumRowClasses];
   for (int c = 0; c < kNumRowClasses; ++c) cnt[c] = (int32_t)(cls_off[c + 1] - cls_off[c]);
-  for (int c = kRow8; c <= kRowLds32k; ++c)
-    HIPCHK(launch_sort_rows(c, rowlist + cls_off[c], cnt[c], raw_off, len, adj, deg, s));
   g->info.large_rows = 0;
-  if (cnt[kRowLarge] > 0)
-    if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
+  if (!presorted) {
+    for (int c = kRow8; c <= kRowLds32k; ++c)
+      HIPCHK(launch_sort_rows(c, rowlist + cls_off[c], cnt[c], raw_off, len, adj, deg, s));
+    if (cnt[kRowLarge] > 0)
+      if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
+  }
   // a4: orientation (rows longer than 64 raw entries: class kRowLds4k is
   // medium, the classes above it are long)
   int32_t* dplus = g->at<int32_t>(L.dplus);
@@ -405,11 +413,11 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
   int32_t* din = g->at<int32_t>(L.din);
   int64_t* dinoff = g->at<int64_t>(L.dinoff);
-  HIPCHK(launch_indeg(n, deg, dplus, din, s));
+  HIPCHK(launch_indeg(n, deg, dplus, din, hdr + kHdrDeg2, s));
   HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
   HIPCHK(launch_orient(1, n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, doff, dcol,
                        hdr + kHdrStats, dinoff, g->at<int32_t>(L.dincol), s));
-  int32_t stats[2];
+  int32_t stats[3];  // max d, max d+, nodes with d >= 2
   if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
   int64_t m = 0;
   if ((rc = sync_copy(&m, doff + n, sizeof(m), s))) return rc;
@@ -418,6 +426,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst) {
   g->info.m = m;
   g->info.max_deg = stats[0];
   g->info.max_outdeg = stats[1];
+  g->info.n_deg2 = stats[2];
   // a5: binning
   return bin_nodes(g);
 }
@@ -503,6 +512,70 @@ int tricc_graph_build(int32_t n, int64_t m_raw, const int32_t* d_src, const int3
   g->tuning = t;
   std::memset(&g->info, 0, sizeof(g->info));
   rc = build_impl(g, d_src, d_dst);
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return TRICC_OK;
+}
+
+int tricc_graph_from_csr(int32_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_col,
+                         int assume_simple_sorted_symmetric, void* d_ws, size_t ws_bytes, const tricc_tuning* tuning,
+                         void* stream, tricc_graph** out) {
+  g_err[0] = 0;
+  if (!out) return fail(TRICC_EINVAL, "null out");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = tricc_graph_workspace_size(n, nnz, &need);
+  if (rc) return rc;
+  if (!d_rowptr || (nnz > 0 && !d_col)) return fail(TRICC_EINVAL, "null CSR arrays");
+  if (!d_ws) return fail(TRICC_EINVAL, "null workspace");
+  if (ws_bytes < need) return fail(TRICC_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(TRICC_EINVAL, "workspace not 256-byte aligned");
+  tricc_tuning t;
+  if (tuning) t = *tuning; else tricc_default_tuning(&t);
+  if ((rc = check_tuning(&t))) return rc;
+  tricc_graph* g = new (std::nothrow) tricc_graph();
+  if (!g) return fail(TRICC_ENOMEM, "host allocation failed");
+  g->n = n;
+  g->m_raw = nnz;
+  g->ws = static_cast<char*>(d_ws);
+  g->L = make_layout(n, nnz);
+  g->stream = static_cast<hipStream_t>(stream);
+  g->tuning = t;
+  std::memset(&g->info, 0, sizeof(g->info));
+  auto run = [&]() -> int {
+    const Layout& L = g->L;
+    hipStream_t s = g->stream;
+    int32_t* hdr = g->hdr32();
+    int32_t err = 0;
+    int r;
+    HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
+    if (!assume_simple_sorted_symmetric) {
+      // rows as (v, w) pairs through the full build; the pair sources sit in
+      // the in-list area, which the build writes only after a3
+      HIPCHK(launch_csr_bounds(n, nnz, d_rowptr, nullptr, nullptr, hdr + kHdrErr, s));
+      if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+      if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
+      int32_t* src = g->at<int32_t>(L.dincol);
+      HIPCHK(launch_csr_expand(n, d_rowptr, src, s));
+      return build_impl(g, src, d_col);
+    }
+    int64_t* raw_off = g->at<int64_t>(L.raw_off);
+    int32_t* adj = g->at<int32_t>(L.adj);
+    HIPCHK(hipMemcpyAsync(raw_off, d_rowptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_csr_bounds(n, nnz, raw_off, g->at<int32_t>(L.len), g->at<int32_t>(L.deg), hdr + kHdrErr, s));
+    if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+    if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
+    if (nnz > 0) HIPCHK(hipMemcpyAsync(adj, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_csr_rows(n, raw_off, adj, hdr + kHdrErr, s));
+    if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+    if (err & 1) return fail(TRICC_ERANGE, "CSR holds a node id outside [0, %d)", n);
+    if (err) return fail(TRICC_EINVAL, "CSR row not strictly ascending or holding its own id");
+    return build_impl(g, nullptr, nullptr, true);
+  };
+  rc = run();
   if (rc) {
     delete g;
     return rc;

@@ -896,15 +896,94 @@ hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t*
 }
 
 // d-(v) = d(v) - d+(v)
+// d-(v) = d(v) - d+(v); *deg2 (zeroed) += the number of nodes with d >= 2.
 __global__ __launch_bounds__(256) void k_indeg(int32_t n, const int32_t* __restrict__ deg,
-                                               const int32_t* __restrict__ dplus, int32_t* __restrict__ din) {
+                                               const int32_t* __restrict__ dplus, int32_t* __restrict__ din,
+                                               int32_t* __restrict__ deg2) {
+  __shared__ int32_t red[256 / kWave];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) din[v] = deg[v] - dplus[v];
+  int32_t c = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t d = deg[v];
+    din[v] = d - dplus[v];
+    c += d >= 2;
+  }
+  const int32_t t = block_sum<int32_t, 256>(c, red);
+  if (threadIdx.x == 0 && t) atomicAdd(deg2, t);
 }
 
-hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, hipStream_t s) {
+hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, int32_t* deg2,
+                        hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_indeg<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(n, deg, dplus, din);
+  k_indeg<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(n, deg, dplus, din, deg2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Graphs handed over as a CSR (rows d_col[rowptr[v] .. rowptr[v+1])).
+// k_csr_bounds: rowptr[0] == 0, non-decreasing, rowptr[n] == nnz (else bit
+// 4 of err); len = deg = row lengths. Rows are read only after this passed.
+__global__ __launch_bounds__(256) void k_csr_bounds(int32_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
+                                                    int32_t* __restrict__ len, int32_t* __restrict__ deg,
+                                                    int32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t b = rowptr[v], e = rowptr[v + 1];
+    if (b > e || b < 0 || e > nnz || (v == 0 && b != 0) || (v == n - 1 && e != nnz)) bad = true;
+    const int32_t l = bad ? 0 : (int32_t)(e - b);
+    if (len) len[v] = l;
+    if (deg) deg[v] = l;
+  }
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0 && (rowptr[0] != 0 || nnz != 0)) bad = true;
+  if (__ballot(bad) && lane_id() == 0) atomicOr(err, 4);
+}
+
+// One wavefront per row: ids in [0, n) (else bit 1), strictly ascending and
+// without the row's own id (else bit 2).
+__global__ __launch_bounds__(256) void k_csr_rows(int32_t n, const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col, int32_t* __restrict__ err) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  bool range = false, order = false;
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; v < n; v += nw) {
+    const int64_t b = rowptr[v], e = rowptr[v + 1];
+    for (int64_t i = b + lane; i < e; i += kWave) {
+      const int32_t x = col[i];
+      if ((uint32_t)x >= (uint32_t)n) range = true;
+      if (x == (int32_t)v || (i > b && col[i - 1] >= x)) order = true;
+    }
+  }
+  const uint64_t r = __ballot(range), o = __ballot(order);
+  if (lane == 0 && (r | o)) atomicOr(err, (r ? 1 : 0) | (o ? 2 : 0));
+}
+
+// src[i] = v for every entry i of row v: the CSR as a list of (v, w) pairs.
+__global__ __launch_bounds__(256) void k_csr_expand(int32_t n, const int64_t* __restrict__ rowptr,
+                                                    int32_t* __restrict__ src) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; v < n; v += nw) {
+    const int64_t b = rowptr[v], e = rowptr[v + 1];
+    for (int64_t i = b + lane; i < e; i += kWave) src[i] = (int32_t)v;
+  }
+}
+
+hipError_t launch_csr_bounds(int32_t n, int64_t nnz, const int64_t* rowptr, int32_t* len, int32_t* deg, int32_t* err,
+                             hipStream_t s) {
+  k_csr_bounds<<<grid_for(n > 0 ? n : 1, 256, 1u << 16), 256, 0, s>>>(n, nnz, rowptr, len, deg, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_rows(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* err, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_csr_rows<<<grid_for(n, 4, 1u << 16), 256, 0, s>>>(n, rowptr, col, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_expand(int32_t n, const int64_t* rowptr, int32_t* src, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_csr_expand<<<grid_for(n, 4, 1u << 16), 256, 0, s>>>(n, rowptr, src);
   return hipGetLastError();
 }
 

@@ -84,7 +84,16 @@ hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t*
                          const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
                          int32_t nlong, int32_t* dplus, const int64_t* doff, int32_t* dcol, int32_t* stats,
                          const int64_t* dinoff, int32_t* dincol, hipStream_t s);
-hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, hipStream_t s);
+// din = deg - dplus; *deg2 (zeroed) += nodes with deg >= 2
+hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, int32_t* deg2,
+                        hipStream_t s);
+// Caller CSR: bounds check (err bit 4; sets len and deg when non-null), row
+// check (bit 1: id out of range, bit 2: not strictly ascending or a self
+// loop; only after the bounds check passed), expansion into (v, w) pairs.
+hipError_t launch_csr_bounds(int32_t n, int64_t nnz, const int64_t* rowptr, int32_t* len, int32_t* deg, int32_t* err,
+                             hipStream_t s);
+hipError_t launch_csr_rows(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* err, hipStream_t s);
+hipError_t launch_csr_expand(int32_t n, const int64_t* rowptr, int32_t* src, hipStream_t s);
 // in-list pass owners by d+(w) into bins 0..kNumBins-2 (see InBinOf)
 hipError_t launch_classify_inbins(int pass, int32_t n, const int32_t* dplus, const int32_t* deg, const int32_t* limit,
                                   int32_t* hist, const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);

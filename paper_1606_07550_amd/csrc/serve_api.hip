@@ -367,8 +367,10 @@ int tricc_server_create(const tricc_graph* resident, void* d_ws, size_t ws_bytes
 
 int tricc_server_set_tuning(tricc_server* s, const tricc_batch_tuning* tuning) {
   if (!s || !tuning) return sfail(TRICC_EINVAL, "null argument");
-  if (tuning->merge_limit < 0 || tuning->wave_limit < tuning->merge_limit || tuning->wave_limit < 2 ||
-      tuning->wave_limit > 64 || tuning->persist_variant < 0 || tuning->persist_variant > 1 ||
+  const int pv = tuning->persist_variant;
+  if (pv < 0 || pv >= tricc::persist_variant_count() || tuning->merge_limit < 0 ||
+      tuning->wave_limit < tuning->merge_limit || tuning->wave_limit < 2 ||
+      tuning->wave_limit > tricc::persist_wave_cap(pv) || tuning->merge_limit > tricc::persist_merge_cap(pv) ||
       tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64)
     return sfail(TRICC_EINVAL, "bad batch tuning");
   std::lock_guard<std::mutex> lk(s->mu);

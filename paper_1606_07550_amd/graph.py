@@ -81,6 +81,40 @@ class Graph:
                                            _stream_ptr(stream), ctypes.byref(self._h))
         N.check(rc, "tricc_graph_build")
 
+    @classmethod
+    def from_csr(cls, n, rowptr, col, assume_simple_sorted_symmetric=False, tuning=None, stream=None,
+                 workspace=None):
+        """A graph built from a device CSR: row v is col[rowptr[v]:rowptr[v+1]]
+        (rowptr int64[n+1], col int32). With assume_simple_sorted_symmetric
+        the rows are taken as they are (strictly ascending, no self loops,
+        symmetric) and the sort is skipped; otherwise every entry is a pair
+        (v, w) for the full build."""
+        if rowptr.dtype != torch.int64 or col.dtype != torch.int32:
+            raise TypeError("rowptr must be int64 and col int32")
+        if not (rowptr.is_cuda and col.is_cuda):
+            raise TypeError("CSR arrays must be device tensors")
+        if rowptr.dim() != 1 or rowptr.numel() != int(n) + 1 or col.dim() != 1:
+            raise ValueError("rowptr must hold n + 1 offsets and col must be 1-D")
+        rowptr = rowptr.contiguous()
+        col = col.contiguous()
+        self = cls.__new__(cls)
+        self.n = int(n)
+        self.m_raw = int(col.numel())
+        self.device = rowptr.device
+        need = workspace_size(self.n, self.m_raw)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.ws = workspace
+        self._h = ctypes.c_void_p()
+        t = _as_tuning(tuning)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_from_csr(self.n, self.m_raw, _ptr(rowptr), _ptr(col),
+                                              1 if assume_simple_sorted_symmetric else 0, _ptr(self.ws),
+                                              self.ws.numel(), ctypes.byref(t) if t is not None else None,
+                                              _stream_ptr(stream), ctypes.byref(self._h))
+        N.check(rc, "tricc_graph_from_csr")
+        return self
+
     @property
     def info(self):
         i = N.GraphInfo()

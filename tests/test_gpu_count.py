@@ -333,3 +333,76 @@ def test_build_beyond_partitioned_range():
     d = np.concatenate([c[2] + o for o, c in comps]).astype(np.int32)
     r, ref = parity(n, s, d)
     assert r["total"] == 20 + 9 + 5 + 220
+
+
+def _csr_of(n, s, d):
+    """Host CSR whose row v lists w for every pair (v, w), in input order."""
+    order = np.argsort(s, kind="stable")
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, s.astype(np.int64) + 1, 1)
+    return np.cumsum(rowptr), d[order].astype(np.int32)
+
+
+def to_dev64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).to(DEV)
+
+
+def test_from_csr_trusted_rows_match_pair_build():
+    """A simple, sorted, symmetric CSR (the one the pair build produces) taken
+    as it is: same counts, same arrays, no sort."""
+    n, s, d = I.rmat(12, 16, seed=41)
+    ref = oracle.count(n, s, d)
+    g0 = P.Graph(n, to_dev(s), to_dev(d))
+    A = {k: v.cpu().numpy() for k, v in g0.arrays().items()}
+    rows = [A["adj"][A["off"][v]:A["off"][v] + A["deg"][v]] for v in range(n)]
+    rowptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    g = P.Graph.from_csr(n, to_dev64(rowptr), to_dev(col), assume_simple_sorted_symmetric=True)
+    o = g.count()
+    torch.cuda.synchronize()
+    r = {"T": o["T"].cpu().numpy().view(np.uint64), "cc": o["cc"].cpu().numpy(),
+         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info}
+    check_against(r, ref, n)
+    B = {k: v.cpu().numpy() for k, v in g.arrays().items()}
+    np.testing.assert_array_equal(B["deg"], A["deg"])
+    np.testing.assert_array_equal(B["doff"], A["doff"])
+    np.testing.assert_array_equal(B["dcol"], A["dcol"])
+    assert g.info["n_deg2"] == int((ref["deg"] >= 2).sum()) == g0.info["n_deg2"]
+
+
+def test_from_csr_general_rows_take_the_full_build():
+    """Rows in any order with duplicates, self loops and one-sided entries:
+    every entry is a pair (v, w)."""
+    n, s, d = F.messy(*I.rmat(11, 8, seed=43), seed=44)
+    rowptr, col = _csr_of(n, s, d)
+    ref = oracle.count(n, s, d)
+    g = P.Graph.from_csr(n, to_dev64(rowptr), to_dev(col))
+    o = g.count()
+    torch.cuda.synchronize()
+    r = {"T": o["T"].cpu().numpy().view(np.uint64), "cc": o["cc"].cpu().numpy(),
+         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info}
+    check_against(r, ref, n)
+    # empty graph and isolated ids
+    g = P.Graph.from_csr(5, to_dev64(np.zeros(6, np.int64)), to_dev(np.zeros(0, np.int32)), True)
+    assert g.count()["total"].item() == 0 and g.info["n_deg2"] == 0
+
+
+def test_from_csr_rejects_malformed_input():
+    col = to_dev(np.array([1, 2, 0, 2, 0, 1], np.int32))
+    good = np.array([0, 2, 4, 6], np.int64)
+    assert P.Graph.from_csr(3, to_dev64(good), col, True).info["m"] == 3
+    for bad in ([0, 3, 2, 6], [1, 2, 4, 6], [0, 2, 4, 5]):
+        for trusted in (False, True):
+            with pytest.raises(N.TriccError) as ei:
+                P.Graph.from_csr(3, to_dev64(np.array(bad, np.int64)), col, trusted)
+            assert ei.value.status == N.TRICC_EINVAL, (bad, trusted)
+    with pytest.raises(N.TriccError) as ei:  # row 0 not ascending
+        P.Graph.from_csr(3, to_dev64(good), to_dev(np.array([2, 1, 0, 2, 0, 1], np.int32)), True)
+    assert ei.value.status == N.TRICC_EINVAL
+    with pytest.raises(N.TriccError) as ei:  # self loop in a trusted row
+        P.Graph.from_csr(3, to_dev64(good), to_dev(np.array([0, 2, 0, 2, 0, 1], np.int32)), True)
+    assert ei.value.status == N.TRICC_EINVAL
+    for trusted in (False, True):
+        with pytest.raises(N.TriccError) as ei:
+            P.Graph.from_csr(3, to_dev64(good), to_dev(np.array([1, 2, 0, 7, 0, 1], np.int32)), trusted)
+        assert ei.value.status == N.TRICC_ERANGE

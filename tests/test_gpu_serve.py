@@ -128,3 +128,26 @@ def test_bad_queries_rejected(resident):
     r = collect(srv, 1)[3]
     assert r["k"] == 0 and r["triangles"] == 0 and r["avg_cc"] == 0.0
     srv.close()
+
+
+@pytest.mark.parametrize("tun", [
+    {"merge_limit": 16, "wave_limit": 64, "persist_variant": 2, "blocks_per_cu": 0},
+    {"merge_limit": 4, "wave_limit": 32, "persist_variant": 3, "blocks_per_cu": 1},
+    {"merge_limit": 32, "wave_limit": 64, "persist_variant": 1, "blocks_per_cu": 0},
+    {"merge_limit": 0, "wave_limit": 64, "persist_variant": 0, "blocks_per_cu": 0},
+])
+def test_every_batch_variant_serves(resident, tun):
+    n, s, d, g, queries = resident
+    srv = P.Server(g, 1 << 30, slots=2)
+    srv.set_tuning(tun)
+    picks = list(range(6)) + [len(queries) - 3]
+    for q in picks:
+        assert srv.submit(q, queries[q]) == N.TRICC_OK
+    srv.drain()
+    res = collect(srv, len(picks))
+    for q in picks:
+        ref = oracle.induced(n, s, d, queries[q])
+        assert res[q]["status"] == 0 and res[q]["triangles"] == ref["total"], (tun, q)
+    with pytest.raises(Exception):
+        srv.set_tuning({"merge_limit": 17, "wave_limit": 64, "persist_variant": 2, "blocks_per_cu": 0})
+    srv.close()
