@@ -915,7 +915,8 @@ __global__ __launch_bounds__(256) void k_indeg(int32_t n, const int32_t* __restr
 hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, int32_t* deg2,
                         hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_indeg<<<grid_for(n, 256, 1u << 16), 256, 0, s>>>(n, deg, dplus, din, deg2);
+  // few blocks: each ends with one atomic on the shared counter
+  k_indeg<<<grid_for(n, 256 * 16, 2048), 256, 0, s>>>(n, deg, dplus, din, deg2);
   return hipGetLastError();
 }
 
