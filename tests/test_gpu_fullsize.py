@@ -1,0 +1,155 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (its cached tuning, or the default):
+- R-MAT 20: every node against the oracle;
+- R-MAT 24: sampled nodes (high-degree and random ones) against the
+  oracle's per-node count from the raw edge list, plus identities that hold
+  at any size (sum of T(v) = 3T, T(v) <= C(d(v), 2), CC(v) from T(v) and
+  d(v) as the epilogue defines it, the average);
+- the 4,096-graph batch: sampled graphs against the oracle, every graph's
+  total against its per-node counts;
+- serving on R-MAT 22: sampled queries (the largest and random ones) of the
+  20,000-query trace against the oracle's induced-subgraph count.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1606_07550_amd as P
+from paper_1606_07550_amd import autotune
+from paper_1606_07550_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CC_RTOL = 1e-6
+
+
+def say(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+
+
+def single_tuning(workload):
+    rec = autotune.lookup(workload)
+    return rec["tuning"] if rec else None
+
+
+def run_single(n, s, d, workload):
+    g = P.Graph(n, dev(s), dev(d), tuning=single_tuning(workload))
+    o = g.count()
+    torch.cuda.synchronize()
+    return g, {
+        "T": o["T"].cpu().numpy().view(np.uint64),
+        "cc": o["cc"].cpu().numpy(),
+        "total": int(o["total"].cpu().numpy().view(np.uint64)[0]),
+        "avg": float(o["avg"].item()),
+        "deg": g.arrays()["deg"].cpu().numpy(),
+    }
+
+
+def check_identities(r):
+    T, deg = r["T"], r["deg"].astype(np.int64)
+    assert int(T.sum()) == 3 * r["total"]
+    assert np.all(T.astype(np.float64) <= deg * (deg - 1) / 2)
+    dd = deg.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(deg >= 2, 2.0 * T.astype(np.float64) / (dd * (dd - 1.0)), 0.0)
+    np.testing.assert_array_equal(r["cc"], ratio.astype(np.float32))  # one rounding of the FP64 ratio
+    assert abs(r["avg"] - ratio.mean()) <= 1e-12 * max(abs(ratio.mean()), 1e-300)
+
+
+def test_rmat20_every_node():
+    n, s, d = I.rmat(20, 16, seed=20)
+    say(f"rmat20 n={n} m_raw={s.size}")
+    _, r = run_single(n, s, d, "rmat20")
+    ref = oracle.count(n, s, d, order=1)
+    np.testing.assert_array_equal(r["T"], ref["T"])
+    assert r["total"] == ref["total"]
+    np.testing.assert_allclose(r["cc"].astype(np.float64), ref["cc"], rtol=CC_RTOL, atol=0)
+    assert np.array_equal(r["cc"] == 0, ref["cc"] == 0)
+    assert abs(r["avg"] - ref["avg"]) <= CC_RTOL * abs(ref["avg"])
+    check_identities(r)
+
+
+def test_rmat24_sampled_nodes_and_identities():
+    n, s, d = I.rmat(24, 16, seed=24)
+    say(f"rmat24 n={n} m_raw={s.size}")
+    g, r = run_single(n, s, d, "rmat24")
+    say(f"rmat24 total={r['total']} m={g.info['m']}")
+    check_identities(r)
+    deg = r["deg"]
+    rng = np.random.default_rng(2424)
+    # high-degree nodes whose neighbour pairs the oracle can still list
+    # (the largest hubs are covered by the every-node check at R-MAT 20)
+    big = rng.choice(np.flatnonzero((deg >= 1000) & (deg <= 20000)), size=12, replace=False)
+    rest = rng.choice(np.flatnonzero(deg >= 1), size=200, replace=False)
+    samples = np.unique(np.concatenate([big, rest, [0, n - 1]])).astype(np.int32)
+    say(f"rmat24 oracle on {samples.size} sampled nodes (degrees up to {deg[samples].max()}) ...")
+    ref = oracle.sampled(n, s, d, samples)
+    say(f"rmat24 oracle on {samples.size} sampled nodes done")
+    np.testing.assert_array_equal(deg[samples], ref["deg"])
+    np.testing.assert_array_equal(r["T"][samples], ref["T"])
+
+
+def test_batch_4096_sampled_graphs_and_totals():
+    G = 4096
+    bt = I.batch(G, 4096)
+    node_off, edge_off = bt["node_off"], bt["edge_off"]
+    say(f"batch G={G} nodes={node_off[-1]} pairs={edge_off[-1]}")
+    b = P.Batch(node_off, edge_off, dev(bt["src"]), dev(bt["dst"]),
+                tuning=autotune.default_or_cached_batch(f"batched-{G}"))
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    T = b.out["T"].cpu().numpy().view(np.uint64)
+    cc = b.out["cc"].cpu().numpy()
+    gtri = b.out["graph_tri"].cpu().numpy().view(np.uint64)
+    gavg = b.out["graph_avg"].cpu().numpy()
+    nonempty = np.flatnonzero(np.diff(node_off) > 0)
+    sums = np.add.reduceat(T.astype(np.uint64), node_off[nonempty].astype(np.int64))
+    np.testing.assert_array_equal(sums, 3 * gtri[nonempty])
+    rng = np.random.default_rng(4096)
+    sizes = np.diff(edge_off)
+    picks = np.unique(np.concatenate([np.argsort(sizes)[-6:], rng.choice(G, size=40, replace=False)]))
+    for gi in picks:
+        a, e = int(node_off[gi]), int(node_off[gi + 1])
+        e0, e1 = int(edge_off[gi]), int(edge_off[gi + 1])
+        ref = oracle.count(e - a, bt["src"][e0:e1], bt["dst"][e0:e1])
+        np.testing.assert_array_equal(T[a:e], ref["T"], err_msg=f"graph {gi}")
+        assert gtri[gi] == ref["total"], gi
+        np.testing.assert_allclose(cc[a:e].astype(np.float64), ref["cc"], rtol=CC_RTOL, atol=0)
+        assert abs(gavg[gi] - ref["avg"]) <= CC_RTOL * abs(ref["avg"]), gi
+    say(f"batch: {picks.size} graphs against the oracle")
+
+
+def test_serving_rmat22_sampled_queries():
+    n, s, d = I.rmat(22, 16, seed=22)
+    Q = 20000
+    off, nodes, _ = I.bfs_queries(n, s, d, Q, seed=2022)
+    say(f"serving resident n={n}, {Q} queries, {off[-1]} query nodes")
+    g = P.Graph(n, dev(s), dev(d))
+    srv = P.Server(g, int(24e9), slots=3, max_batch_queries=256)
+    srv.set_tuning({"merge_limit": 16, "wave_limit": 64, "persist_variant": 2, "blocks_per_cu": 0})
+    sizes = np.diff(off)
+    rng = np.random.default_rng(22)
+    picks = np.unique(np.concatenate([np.argsort(sizes)[-4:], rng.choice(Q, size=20, replace=False)]))
+    for q in picks:
+        assert srv.submit(int(q), nodes[off[q]:off[q + 1]]) == 0
+    srv.drain()
+    res = {}
+    for r in srv.poll():
+        res[r["qid"]] = r
+    assert len(res) == picks.size
+    for q in picks:
+        S = nodes[off[q]:off[q + 1]]
+        ref = oracle.induced(n, s, d, S)
+        r = res[int(q)]
+        assert r["status"] == 0 and r["k"] == S.size
+        assert r["triangles"] == ref["total"], q
+        assert r["m"] == ref["m"], q
+        assert abs(r["avg_cc"] - ref["avg"]) <= CC_RTOL * abs(ref["avg"]), q
+    srv.close()
+    say(f"serving: {picks.size} queries against the oracle (largest k = {sizes.max()})")
