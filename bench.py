@@ -246,10 +246,11 @@ def serving_leg(args, torch, P, N):
     tuning = None
     if args.serve_tune:
         best = None
-        for ml in (0, 4, 16, 32):
-            for pv in (0, 1, 2, 3):
-                if pv >= 2 and ml > 16:
-                    continue  # the packed small-node path takes d+ <= 16
+        from paper_1606_07550_amd.autotune import MERGE_CAP
+        for ml in (0, 4, 8, 16, 32):
+            for pv in sorted(MERGE_CAP):
+                if ml > MERGE_CAP[pv]:
+                    continue  # above the variant's short-list path
                 t = {"merge_limit": ml, "wave_limit": 64, "persist_variant": pv, "blocks_per_cu": 0}
                 r = run_trace(P, N, g, queries[:max(200, Q // 10)], None, args.serve_slots, 256, budget, t)
                 log(f"serve tuning {t}: {r['qps']:.1f} q/s")

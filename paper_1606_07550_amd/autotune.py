@@ -127,8 +127,10 @@ def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
     return best, best_total
 
 
-BATCH_SPACE = [(ml, wl, pv, bpc) for pv in (0, 1, 2, 3) for wl in (32, 64) for ml in (0, 8, 16, 32, 64)
-               for bpc in (0, 4) if ml <= wl and (pv < 2 or ml <= 16)]
+# largest merge_limit of each persistent variant's short-list path
+MERGE_CAP = {0: 64, 1: 64, 2: 16, 3: 16, 4: 32, 5: 8}
+BATCH_SPACE = [(ml, wl, pv, bpc) for pv in sorted(MERGE_CAP) for wl in (32, 64) for ml in (0, 8, 16, 32, 64)
+               for bpc in (0, 4) if ml <= wl and ml <= MERGE_CAP[pv]]
 
 
 def tune_batch(batch, reps=3, key=None, log=None):

@@ -233,8 +233,10 @@ struct WaveGroupLds {
 // Lists shorter than this are streamed packed: a wavefront covers several
 // short lists per step instead of one list per step.
 constexpr int32_t kPackShort = 64;
+// Steps of 64 ids whose gathers are issued together in the packed streams.
+constexpr int kPackUnroll = 4;
 
-// Lanes per node on the packed small-node path (nodes with d+ <= kSmallGS).
+// Lanes per node on the packed small-node path by default (d+ <= kSmallGS).
 constexpr int kSmallGS = 16;
 
 // Packed streaming of the short lists among items [i0, i1) of a group: a
@@ -259,24 +261,34 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
     const int32_t incl = wave_incl_scan(nb);
     const int32_t total = __shfl(incl, kWave - 1, kWave);
     const int32_t excl = incl - nb;
-    for (int32_t t0 = 0; t0 < total; t0 += kWave) {
-      const int32_t t = t0 + lane;
-      int k = 0;
+    for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
+      // kPackUnroll independent gathers in flight before the probes
+      int32_t x[kPackUnroll];
+      int kk[kPackUnroll];
 #pragma unroll
-      for (int step = kWave / 2; step > 0; step >>= 1) {
-        const int32_t v = __shfl(incl, k + step - 1, kWave);
-        if (v <= t) k += step;
+      for (int r = 0; r < kPackUnroll; ++r) {
+        const int32_t t = t0 + r * kWave + lane;
+        int k = 0;
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1) {
+          const int32_t v = __shfl(incl, k + step - 1, kWave);
+          if (v <= t) k += step;
+        }
+        const int32_t kb = __shfl(bb, k, kWave);
+        const int32_t ke = __shfl(excl, k, kWave);
+        x[r] = t < total ? dcol[kb + (t - ke)] : -1;
+        kk[r] = k;
       }
-      const int32_t kb = __shfl(bb, k, kWave);
-      const int32_t ke = __shfl(excl, k, kWave);
-      const bool valid = t < total;
-      const int32_t x = valid ? dcol[kb + (t - ke)] : -1;
-      int off;
-      const bool hit = bucket_credit<NB>(Kb, x, valid, &off);
-      hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
-      if (hit) {
-        credit(C, off);
-        atomicAdd(&Wc[base + k], 1u);
+#pragma unroll
+      for (int r = 0; r < kPackUnroll; ++r) {
+        if (t0 + r * kWave >= total) break;
+        int off;
+        const bool hit = bucket_credit<NB>(Kb, x[r], t0 + r * kWave + lane < total, &off);
+        hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+        if (hit) {
+          credit(C, off);
+          atomicAdd(&Wc[base + kk[r]], 1u);
+        }
       }
     }
   }
@@ -791,22 +803,32 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
   const int32_t incl = wave_incl_scan(wn);
   const int32_t total = __shfl(incl, kWave - 1, kWave);
   const int32_t excl = incl - wn;
-  for (int32_t t0 = 0; t0 < total; t0 += kWave) {
-    const int32_t t = t0 + lane;
-    int k = 0;
+  for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
+    // kPackUnroll independent gathers in flight before the probes
+    int32_t x[kPackUnroll];
+    int kk[kPackUnroll];
 #pragma unroll
-    for (int step = kWave / 2; step > 0; step >>= 1) {
-      const int32_t v = __shfl(incl, k + step - 1, kWave);
-      if (v <= t) k += step;
+    for (int r = 0; r < kPackUnroll; ++r) {
+      const int32_t t = t0 + r * kWave + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1) {
+        const int32_t v = __shfl(incl, k + step - 1, kWave);
+        if (v <= t) k += step;
+      }
+      const int32_t kb = __shfl(wb, k, kWave);
+      const int32_t ke = __shfl(excl, k, kWave);
+      x[r] = t < total ? dcol[kb + (t - ke)] : -1;
+      kk[r] = k;
     }
-    const int32_t kb = __shfl(wb, k, kWave);
-    const int32_t ke = __shfl(excl, k, kWave);
-    const bool valid = t < total;
-    const int32_t x = valid ? dcol[kb + (t - ke)] : -1;
-    int off;
-    if (bucket_credit<NB>(S.K[k / GS], x, valid, &off)) {
-      credit(S.C[k / GS], off);
-      atomicAdd(&S.Wc[k], 1u);
+#pragma unroll
+    for (int r = 0; r < kPackUnroll; ++r) {
+      if (t0 + r * kWave >= total) break;
+      int off;
+      if (bucket_credit<NB>(S.K[kk[r] / GS], x[r], t0 + r * kWave + lane < total, &off)) {
+        credit(S.C[kk[r] / GS], off);
+        atomicAdd(&S.Wc[kk[r]], 1u);
+      }
     }
   }
   wave_sync();
@@ -822,12 +844,19 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
 }
 
 // Persistent form (batched graphs): one launch covers every node of the
-// DAG. Blocks of 256 pull chunks from an atomic work queue, heaviest first:
-// nodes above the block table's capacity (global fallback), then nodes for a
-// whole block (d+ <= CB), then four single-wave nodes (d+ <= CW) at a time,
-// then the short-list nodes: 32 at a time for the 8-lane merge (SMALL == 0)
-// or 16 at a time, four per wave, on the packed small-node path (SMALL ==
-// 1, d+ <= 16).
+// DAG, in two phases.
+// Phase 1, whole blocks: nodes above the block table's capacity (global
+// fallback), then nodes for a whole block (d+ <= CB), one per pull from
+// queue[0].
+// Phase 2, single wavefronts on their own (no block barrier): single-wave
+// nodes (d+ <= CW), then groups of short-list nodes: 8 at a time for the
+// 8-lane merge (SMALL == 0) or 64 / SMALL at a time on the packed
+// small-node path with SMALL lanes per node (d+ <= SMALL). A wave takes
+// kPersistGrab items per atomic on queue[1] and issues its next grab before
+// running the current items, so the atomic's latency hides behind their
+// loads. Each wave owns a private LDS region in phase 2.
+constexpr int kPersistGrab = 8;
+
 template <int SW, int CW, int SB, int CB, int SMALL = 0>
 __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict__ glist, int32_t ng,
                                                        const int32_t* __restrict__ blist, int32_t nbk,
@@ -839,40 +868,47 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
                                                        unsigned long long* __restrict__ T) {
   using BL = WaveGroupLds<SB, CB>;
   using WL = WaveGroupLds<SW, CW>;
-  using SL = SmallLds<kSmallGS>;
-  constexpr size_t kB0 = sizeof(BL) > 4 * sizeof(WL) ? sizeof(BL) : 4 * sizeof(WL);
-  constexpr size_t kBytes = kB0 > 4 * sizeof(SL) ? kB0 : 4 * sizeof(SL);
+  constexpr int kGS = SMALL ? SMALL : kSmallGS;
+  using SL = SmallLds<kGS>;
+  constexpr size_t kWaveBytes = ((sizeof(WL) > sizeof(SL) ? sizeof(WL) : sizeof(SL)) + 15) / 16 * 16;
+  constexpr size_t kBytes = sizeof(BL) > 4 * kWaveBytes ? sizeof(BL) : 4 * kWaveBytes;
   __shared__ __align__(16) unsigned char smem[kBytes];
   __shared__ unsigned long long red[256 / kWave];
   __shared__ int32_t chunk;
-  constexpr int kMergeG = 8;
-  constexpr int kMergePerChunk = SMALL ? 4 * (kWave / kSmallGS) : 256 / kMergeG;
-  const int64_t nwc = ((int64_t)nw + 3) / 4;
-  const int64_t total = (int64_t)ng + nbk + nwc + ((int64_t)nm + kMergePerChunk - 1) / kMergePerChunk;
+  const int32_t n1 = ng + nbk;
   while (true) {
     if (threadIdx.x == 0) chunk = atomicAdd(queue, 1);
     __syncthreads();
-    const int64_t c = chunk;
+    const int32_t c = chunk;
     __syncthreads();
-    if (c >= total) break;
-    if (c < ng) {
-      node_count_global(glist[c], red, doff, dcol, T);
-    } else if (c < (int64_t)ng + nbk) {
-      node_count_wave<256, SB, CB, 4>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
-    } else if (c < (int64_t)ng + nbk + nwc) {
-      const int wv = threadIdx.x / kWave;
-      const int64_t k = (c - ng - nbk) * 4 + wv;
-      node_count_wave<kWave, SW, CW, 4>(k < nw ? wlist[k] : -1, reinterpret_cast<WL*>(smem)[wv], red, doff, dcol,
-                                         T);
-    } else if constexpr (SMALL) {
-      const int wv = threadIdx.x / kWave;
-      const int64_t k = (c - ng - nbk - nwc) * kMergePerChunk + wv * (kWave / kSmallGS);
-      nodes_count_small<kSmallGS>(mlist, k, nm, reinterpret_cast<SL*>(smem)[wv], doff, dcol, T);
-    } else {
-      const int64_t k = (c - ng - nbk - nwc) * kMergePerChunk + threadIdx.x / kMergeG;
-      node_count_merge<kMergeG>(k < nm ? mlist[k] : -1, doff, dcol, T);
+    if (c >= n1) break;
+    if (c < ng) node_count_global(glist[c], red, doff, dcol, T);
+    else node_count_wave<256, SB, CB, 4>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
+    __syncthreads();
+  }
+  constexpr int NPW = SMALL ? kWave / kGS : kWave / 8;  // short-list nodes per wave item
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  unsigned char* mine = smem + wv * kWaveBytes;
+  const int32_t n2 = nw + (int32_t)(((int64_t)nm + NPW - 1) / NPW);
+  int32_t got = 0;
+  if (lane == 0) got = atomicAdd(queue + 1, kPersistGrab);
+  int32_t cur = __builtin_amdgcn_readfirstlane(got);
+  while (cur < n2) {
+    int32_t nxt = 0;
+    if (lane == 0) nxt = atomicAdd(queue + 1, kPersistGrab);
+    const int32_t end = min(cur + kPersistGrab, n2);
+    for (int32_t it = cur; it < end; ++it) {
+      if (it < nw) {
+        node_count_wave<kWave, SW, CW, 4>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T);
+      } else if constexpr (SMALL != 0) {
+        nodes_count_small<kGS>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol, T);
+      } else {
+        const int64_t k = (int64_t)(it - nw) * NPW + lane / 8;
+        node_count_merge<8>(k < nm ? mlist[k] : -1, doff, dcol, T);
+      }
     }
-    __syncthreads();
+    cur = __builtin_amdgcn_readlane(nxt, 0);
   }
 }
 
@@ -880,20 +916,24 @@ struct PersistShape { int sw, cw, sb, cb, small; };
 static constexpr PersistShape kPersist[] = {
     {256, 64, 1024, 256, 0},   // 0: block nodes up to d+ 256, 8-lane merge
     {256, 64, 4096, 1024, 0},  // 1: block nodes up to d+ 1024, 8-lane merge
-    {256, 64, 1024, 256, 1},   // 2: as 0, short lists on the packed small-node path
-    {256, 64, 4096, 1024, 1},  // 3: as 1, short lists on the packed small-node path
+    {256, 64, 1024, 256, 16},  // 2: as 0, short lists on the packed small-node path (16 lanes per node)
+    {256, 64, 4096, 1024, 16}, // 3: as 1, short lists on the packed small-node path
+    {256, 64, 1024, 256, 32},  // 4: as 2 with 32 lanes per node (d+ <= 32)
+    {256, 64, 1024, 256, 8},   // 5: as 2 with 8 lanes per node (d+ <= 8)
 };
 int persist_variant_count() { return (int)(sizeof(kPersist) / sizeof(kPersist[0])); }
 int persist_wave_cap(int v) { return kPersist[v].cw; }
 int persist_block_cap(int v) { return kPersist[v].cb; }
-int persist_merge_cap(int v) { return kPersist[v].small ? kSmallGS : kPersist[v].cw; }
+int persist_merge_cap(int v) { return kPersist[v].small ? kPersist[v].small : kPersist[v].cw; }
 
 const void* persist_kernel(int v) {
   switch (v) {
     case 0: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256>);
     case 1: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024>);
-    case 2: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 1>);
-    case 3: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024, 1>);
+    case 2: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 16>);
+    case 3: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024, 16>);
+    case 4: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 32>);
+    case 5: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 8>);
     default: return nullptr;
   }
 }
@@ -912,25 +952,36 @@ hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int3
                                                                 doff, dcol, T);
       break;
     case 2:
-      k_count_persist<256, 64, 1024, 256, 1><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
-                                                                  doff, dcol, T);
+      k_count_persist<256, 64, 1024, 256, 16><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                   doff, dcol, T);
       break;
     case 3:
-      k_count_persist<256, 64, 4096, 1024, 1><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
-                                                                   queue, doff, dcol, T);
+      k_count_persist<256, 64, 4096, 1024, 16><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
+                                                                    queue, doff, dcol, T);
+      break;
+    case 4:
+      k_count_persist<256, 64, 1024, 256, 32><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                   doff, dcol, T);
+      break;
+    case 5:
+      k_count_persist<256, 64, 1024, 256, 8><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                  doff, dcol, T);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Clears T[n] and the work-queue counter (a kernel, so that it can sit in a
+// Clears T[n] and the two work-queue counters (a kernel, so that it can sit in a
 // captured graph).
 __global__ __launch_bounds__(256) void k_batch_zero(unsigned long long* __restrict__ T, int64_t n,
                                                     int32_t* __restrict__ queue) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 == 0) *queue = 0;
+  if (i0 == 0) {
+    queue[0] = 0;
+    queue[1] = 0;
+  }
   for (int64_t i = i0; i < n; i += stride) T[i] = 0ull;
 }
 

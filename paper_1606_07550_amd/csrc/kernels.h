@@ -147,8 +147,8 @@ hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const uns
 
 // ---- Batched graphs ---------------------------------------------------------
 // Persistent intersection kernel over four node lists (hubs -> global
-// fallback, block nodes, single-wave nodes, short-list merge nodes); queue
-// must be 0 at launch.
+// fallback, block nodes, single-wave nodes, short-list nodes); queue[0] and
+// queue[1] must be 0 at launch (launch_batch_zero clears both).
 int persist_variant_count();
 int persist_wave_cap(int v);   // largest d+ of a single-wave node
 int persist_block_cap(int v);  // largest d+ of a block node
