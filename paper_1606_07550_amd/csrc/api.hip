@@ -408,15 +408,17 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
   const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRowLds4k]);
   const int32_t* long_rows = rowlist + cls_off[kRowLds32k];
   const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds32k]);
-  HIPCHK(launch_orient(0, n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, doff, dcol,
-                       hdr + kHdrStats, nullptr, nullptr, s));
+  // one pass partitions every row into tmp (free again after a3), then
+  // the scans place the out- and in-lists
+  int32_t* part = g->at<int32_t>(L.tmp);
+  HIPCHK(launch_orient(n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, part, hdr + kHdrStats, s));
   HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
   int32_t* din = g->at<int32_t>(L.din);
   int64_t* dinoff = g->at<int64_t>(L.dinoff);
   HIPCHK(launch_indeg(n, deg, dplus, din, hdr + kHdrDeg2, s));
   HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
-  HIPCHK(launch_orient(1, n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, doff, dcol,
-                       hdr + kHdrStats, dinoff, g->at<int32_t>(L.dincol), s));
+  HIPCHK(launch_orient_copy(n, raw_off, len, deg, dplus, part, med_rows, nmed, long_rows, nlong, doff, dcol, dinoff,
+                            g->at<int32_t>(L.dincol), s));
   int32_t stats[3];  // max d, max d+, nodes with d >= 2
   if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
   int64_t m = 0;

@@ -716,10 +716,14 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 }
 
 // ---------------------------------------------------------------------------
-// a4: orientation. pass 0 counts d+(v), pass 1 writes N+(v) in id order.
-// Rows of raw length <= kOrientShort: a group of kOrientG lanes per row,
-// grid-stride; longer rows (listed contiguously by the row classes): one
-// block per row.
+// a4: orientation in one pass over every row plus a copy. The pass counts
+// d+(v) and partitions row v into the same span of `part`: N+(v) (ascending)
+// from the front, N-(v) from the back in reverse order. After d+ and d- are
+// scanned, the copy streams both parts to dcol[doff[v]..] and
+// dincol[dinoff[v]..], each ascending. Rows of raw length <= kOrientShort:
+// a group of kOrientG lanes per row, grid-stride; medium rows: a wavefront
+// each; long rows: a block each (both listed contiguously by the row
+// classes).
 constexpr int kOrientG = 8;
 constexpr int32_t kOrientShort = 64;
 
@@ -736,15 +740,12 @@ __device__ __forceinline__ T block_max(T x, T* lds) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* __restrict__ off,
                                                       const int32_t* __restrict__ len,
                                                       const int32_t* __restrict__ deg,
                                                       const int32_t* __restrict__ adj,
-                                                      int32_t* __restrict__ dplus,
-                                                      const int64_t* __restrict__ doff,
-                                                      int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
-                                                      const int64_t* __restrict__ dinoff,
-                                                      int32_t* __restrict__ dincol) {
+                                                      int32_t* __restrict__ dplus, int32_t* __restrict__ part,
+                                                      int32_t* __restrict__ stats) {
   constexpr int G = kOrientG;
   __shared__ int32_t red[256 / kWave];
   const int64_t ngroups = (int64_t)gridDim.x * (256 / G);
@@ -754,13 +755,10 @@ __global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const
   for (int64_t v = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; v < n; v += ngroups) {
     if (len[v] > kOrientShort) continue;
     const int32_t dv = deg[v];
-    const int32_t* row = adj + off[v];
+    const int64_t rb = off[v];
+    const int32_t* row = adj + rb;
+    int32_t* prow = part + rb;
     int32_t c = 0;
-    int64_t ob = 0, ib = 0;
-    if (pass == 1) {
-      ob = doff[v];
-      if (dincol) ib = dinoff[v];
-    }
     for (int32_t b = 0; b < dv; b += G) {
       bool f = false;
       int32_t w = 0;
@@ -770,42 +768,34 @@ __global__ __launch_bounds__(256) void k_orient_short(int pass, int32_t n, const
       }
       const uint32_t mask = (uint32_t)(__ballot(f) >> shift) & ((1u << G) - 1);
       const int32_t below = __popc(mask & ((1u << g) - 1));
-      if (pass == 1 && f) dcol[ob + c + below] = w;
-      if (pass == 1 && dincol && !f && b + g < dv) dincol[ib + (b + g) - (c + below)] = w;
+      if (f) prow[c + below] = w;
+      else if (b + g < dv) prow[dv - 1 - ((b + g) - (c + below))] = w;
       c += __popc(mask);
     }
-    if (pass == 0 && g == 0) dplus[v] = c;
+    if (g == 0) dplus[v] = c;
     mx_d = max(mx_d, dv);
     mx_p = max(mx_p, c);
   }
-  if (pass == 0) {
-    mx_d = block_max(mx_d, red);
-    mx_p = block_max(mx_p, red);
-    if (threadIdx.x == 0) {
-      atomicMax(&stats[0], mx_d);
-      atomicMax(&stats[1], mx_p);
-    }
+  mx_d = block_max(mx_d, red);
+  mx_p = block_max(mx_p, red);
+  if (threadIdx.x == 0) {
+    atomicMax(&stats[0], mx_d);
+    atomicMax(&stats[1], mx_p);
   }
 }
 
-__global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_orient_long(const int32_t* __restrict__ rows,
                                                      const int64_t* __restrict__ off,
                                                      const int32_t* __restrict__ deg,
                                                      const int32_t* __restrict__ adj,
-                                                     int32_t* __restrict__ dplus,
-                                                     const int64_t* __restrict__ doff,
-                                                     int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
-                                                     const int64_t* __restrict__ dinoff,
-                                                     int32_t* __restrict__ dincol) {
+                                                     int32_t* __restrict__ dplus, int32_t* __restrict__ part,
+                                                     int32_t* __restrict__ stats) {
   __shared__ int32_t lds[256 / kWave + 1];
   const int32_t v = rows[blockIdx.x];
   const int32_t dv = deg[v];
-  const int32_t* row = adj + off[v];
-  int64_t ob = 0, ib = 0;
-  if (pass == 1) {
-    ob = doff[v];
-    if (dincol) ib = dinoff[v];
-  }
+  const int64_t rb = off[v];
+  const int32_t* row = adj + rb;
+  int32_t* prow = part + rb;
   int32_t c = 0;
   for (int32_t b = 0; b < dv; b += 256) {
     const int32_t i = b + threadIdx.x;
@@ -817,11 +807,11 @@ __global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __
     }
     int32_t tot;
     const int32_t ex = block_excl_scan<int32_t, 256>(f ? 1 : 0, lds, &tot);
-    if (pass == 1 && f) dcol[ob + c + ex] = w;
-    if (pass == 1 && dincol && !f && i < dv) dincol[ib + i - (c + ex)] = w;
+    if (f) prow[c + ex] = w;
+    else if (i < dv) prow[dv - 1 - (i - (c + ex))] = w;
     c += tot;
   }
-  if (pass == 0 && threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
     dplus[v] = c;
     atomicMax(&stats[0], dv);
     atomicMax(&stats[1], c);
@@ -830,15 +820,12 @@ __global__ __launch_bounds__(256) void k_orient_long(int pass, const int32_t* __
 
 // Rows of medium length: one wavefront per row (grid-stride), ballot-ordered
 // compaction, no block barriers.
-__global__ __launch_bounds__(256) void k_orient_medium(int pass, const int32_t* __restrict__ rows, int32_t nrows,
+__global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict__ rows, int32_t nrows,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ deg,
                                                        const int32_t* __restrict__ adj,
-                                                       int32_t* __restrict__ dplus,
-                                                       const int64_t* __restrict__ doff,
-                                                       int32_t* __restrict__ dcol, int32_t* __restrict__ stats,
-                                                       const int64_t* __restrict__ dinoff,
-                                                       int32_t* __restrict__ dincol) {
+                                                       int32_t* __restrict__ dplus, int32_t* __restrict__ part,
+                                                       int32_t* __restrict__ stats) {
   __shared__ int32_t red[256 / kWave];
   const int64_t nwaves = (int64_t)gridDim.x * (256 / kWave);
   const int l = lane_id();
@@ -846,12 +833,9 @@ __global__ __launch_bounds__(256) void k_orient_medium(int pass, const int32_t* 
   for (int64_t r = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; r < nrows; r += nwaves) {
     const int32_t v = rows[r];
     const int32_t dv = deg[v];
-    const int32_t* row = adj + off[v];
-    int64_t ob = 0, ib = 0;
-    if (pass == 1) {
-      ob = doff[v];
-      if (dincol) ib = dinoff[v];
-    }
+    const int64_t rb = off[v];
+    const int32_t* row = adj + rb;
+    int32_t* prow = part + rb;
     int32_t c = 0;
     for (int32_t b = 0; b < dv; b += kWave) {
       bool f = false;
@@ -862,36 +846,101 @@ __global__ __launch_bounds__(256) void k_orient_medium(int pass, const int32_t* 
       }
       const uint64_t m = __ballot(f);
       const int32_t below = mask_below(m);
-      if (pass == 1 && f) dcol[ob + c + below] = w;
-      if (pass == 1 && dincol && !f && b + l < dv) dincol[ib + (b + l) - (c + below)] = w;
+      if (f) prow[c + below] = w;
+      else if (b + l < dv) prow[dv - 1 - ((b + l) - (c + below))] = w;
       c += (int32_t)__popcll(m);
     }
-    if (pass == 0 && l == 0) dplus[v] = c;
+    if (l == 0) dplus[v] = c;
     mx_d = max(mx_d, dv);
     mx_p = max(mx_p, c);
   }
-  if (pass == 0) {
-    mx_d = block_max(mx_d, red);
-    mx_p = block_max(mx_p, red);
-    if (threadIdx.x == 0) {
-      atomicMax(&stats[0], mx_d);
-      atomicMax(&stats[1], mx_p);
-    }
+  mx_d = block_max(mx_d, red);
+  mx_p = block_max(mx_p, red);
+  if (threadIdx.x == 0) {
+    atomicMax(&stats[0], mx_d);
+    atomicMax(&stats[1], mx_p);
   }
 }
 
-hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
-                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
-                         int32_t nlong, int32_t* dplus, const int64_t* doff, int32_t* dcol, int32_t* stats,
-                         const int64_t* dinoff, int32_t* dincol, hipStream_t s) {
+// Copy of the partitioned rows: N+(v) = part[off[v] .. off[v] + d+(v)) to
+// dcol[doff[v] ..]; N-(v) = part[off[v] + d(v) - 1 - k], k < d-(v), to
+// dincol[dinoff[v] + k] (ascending again). G lanes per row (G = 8, 64 or
+// 256), rows short (all rows of raw length <= kOrientShort, grid-stride),
+// or listed.
+template <int G>
+__device__ __forceinline__ void orient_copy_row(int32_t v, int g, const int64_t* __restrict__ off,
+                                                const int32_t* __restrict__ deg,
+                                                const int32_t* __restrict__ dplus,
+                                                const int32_t* __restrict__ part, const int64_t* __restrict__ doff,
+                                                int32_t* __restrict__ dcol, const int64_t* __restrict__ dinoff,
+                                                int32_t* __restrict__ dincol) {
+  const int32_t dv = deg[v], dp = dplus[v];
+  const int32_t* prow = part + off[v];
+  int32_t* out = dcol + doff[v];
+  for (int32_t k = g; k < dp; k += G) out[k] = prow[k];
+  if (!dincol) return;
+  int32_t* in = dincol + dinoff[v];
+  for (int32_t k = g; k < dv - dp; k += G) in[k] = prow[dv - 1 - k];
+}
+
+__global__ __launch_bounds__(256) void k_orient_copy_short(int32_t n, const int64_t* __restrict__ off,
+                                                           const int32_t* __restrict__ len,
+                                                           const int32_t* __restrict__ deg,
+                                                           const int32_t* __restrict__ dplus,
+                                                           const int32_t* __restrict__ part,
+                                                           const int64_t* __restrict__ doff,
+                                                           int32_t* __restrict__ dcol,
+                                                           const int64_t* __restrict__ dinoff,
+                                                           int32_t* __restrict__ dincol) {
+  constexpr int G = kOrientG;
+  const int64_t ngroups = (int64_t)gridDim.x * (256 / G);
+  for (int64_t v = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; v < n; v += ngroups) {
+    if (len[v] > kOrientShort) continue;
+    orient_copy_row<G>((int32_t)v, threadIdx.x % G, off, deg, dplus, part, doff, dcol, dinoff, dincol);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_orient_copy_listed(const int32_t* __restrict__ rows, int32_t nrows,
+                                                            const int64_t* __restrict__ off,
+                                                            const int32_t* __restrict__ deg,
+                                                            const int32_t* __restrict__ dplus,
+                                                            const int32_t* __restrict__ part,
+                                                            const int64_t* __restrict__ doff,
+                                                            int32_t* __restrict__ dcol,
+                                                            const int64_t* __restrict__ dinoff,
+                                                            int32_t* __restrict__ dincol) {
+  const int64_t ngroups = (int64_t)gridDim.x * (256 / G);
+  for (int64_t r = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; r < nrows; r += ngroups)
+    orient_copy_row<G>(rows[r], threadIdx.x % G, off, deg, dplus, part, doff, dcol, dinoff, dincol);
+}
+
+hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
+                         const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
+                         int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(pass, n, off, len, deg, adj, dplus,
-                                                                             doff, dcol, stats, dinoff, dincol);
+  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, adj, dplus, part,
+                                                                             stats);
   if (nmedium > 0)
-    k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(
-        pass, medium_rows, nmedium, off, deg, adj, dplus, doff, dcol, stats, dinoff, dincol);
+    k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(medium_rows, nmedium, off, deg,
+                                                                                   adj, dplus, part, stats);
+  if (nlong > 0) k_orient_long<<<nlong, 256, 0, s>>>(long_rows, off, deg, adj, dplus, part, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_orient_copy(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
+                              const int32_t* dplus, const int32_t* part, const int32_t* medium_rows, int32_t nmedium,
+                              const int32_t* long_rows, int32_t nlong, const int64_t* doff, int32_t* dcol,
+                              const int64_t* dinoff, int32_t* dincol, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_orient_copy_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, dplus, part,
+                                                                                  doff, dcol, dinoff, dincol);
+  if (nmedium > 0)
+    k_orient_copy_listed<kWave><<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(
+        medium_rows, nmedium, off, deg, dplus, part, doff, dcol, dinoff, dincol);
   if (nlong > 0)
-    k_orient_long<<<nlong, 256, 0, s>>>(pass, long_rows, off, deg, adj, dplus, doff, dcol, stats, dinoff, dincol);
+    k_orient_copy_listed<256><<<grid_for((int64_t)nlong * 256, 256, 1u << 14), 256, 0, s>>>(
+        long_rows, nlong, off, deg, dplus, part, doff, dcol, dinoff, dincol);
   return hipGetLastError();
 }
 

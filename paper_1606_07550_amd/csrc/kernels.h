@@ -74,16 +74,21 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
                              int32_t* adj, int32_t* deg, hipStream_t s);
 
 // ---- Degree-order orientation --------------------------------------------
-// pass 0: dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|, stats[0] = max d,
-// stats[1] = max d+; pass 1: writes N+(v) (ascending id) at dcol[doff[v]..].
-// Rows of raw length > 64 must be listed: medium_rows (a wavefront each) and
-// long_rows (a block each) together.
-// With dincol != NULL, pass 1 also writes the in-list N-(v) = {w in N(v):
-// (d(w),w) < (d(v),v)} (ascending id) at dincol[dinoff[v]..].
-hipError_t launch_orient(int pass, int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
-                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
-                         int32_t nlong, int32_t* dplus, const int64_t* doff, int32_t* dcol, int32_t* stats,
-                         const int64_t* dinoff, int32_t* dincol, hipStream_t s);
+// One pass over every row: dplus[v] = |{w in N(v): (d(v),v) < (d(w),w)}|,
+// stats[0] = max d, stats[1] = max d+, and row v partitioned into
+// part[off[v] .. off[v] + d(v)): N+(v) ascending from the front, N-(v) from
+// the back in reverse. Rows of raw length > 64 must be listed: medium_rows
+// (a wavefront each) and long_rows (a block each) together.
+hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
+                         const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
+                         int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s);
+// After doff / dinoff are the scans of d+ / d-: N+(v) to dcol[doff[v]..] and
+// (dincol != NULL) N-(v) to dincol[dinoff[v]..], both ascending.
+hipError_t launch_orient_copy(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
+                              const int32_t* dplus, const int32_t* part, const int32_t* medium_rows, int32_t nmedium,
+                              const int32_t* long_rows, int32_t nlong, const int64_t* doff, int32_t* dcol,
+                              const int64_t* dinoff, int32_t* dincol, hipStream_t s);
+
 // din = deg - dplus; *deg2 (zeroed) += nodes with deg >= 2
 hipError_t launch_indeg(int32_t n, const int32_t* deg, const int32_t* dplus, int32_t* din, int32_t* deg2,
                         hipStream_t s);
