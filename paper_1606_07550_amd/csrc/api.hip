@@ -42,7 +42,6 @@ enum : int {
   kHdrErr = 0,
   kHdrStats = 4,      // [0] max d, [1] max d+
   kHdrDeg2 = 6,       // nodes with d >= 2
-  kHdrRowCnt = 8,     // [kNumRowClasses]
   kHdrBinCnt = 16,    // [kNumBins]
   kHdrLimits = 24,    // [kNumBins - 1]
   kHdrListElems = 32, // u64 at byte 128
@@ -399,15 +398,16 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
     if (cnt[kRowLarge] > 0)
       if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
   }
-  // a4: orientation (rows longer than 64 raw entries: class kRowLds4k is
-  // medium, the classes above it are long)
+  // a4: orientation (rows longer than 64 raw entries: classes kRow128 ..
+  // kRowLds4k are medium, the classes above them are long; the row lists
+  // are class-major, so each range is contiguous)
   int32_t* dplus = g->at<int32_t>(L.dplus);
   int64_t* doff = g->at<int64_t>(L.doff);
   int32_t* dcol = g->at<int32_t>(L.dcol);
-  const int32_t* med_rows = rowlist + cls_off[kRowLds4k];
-  const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRowLds4k]);
-  const int32_t* long_rows = rowlist + cls_off[kRowLds32k];
-  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds32k]);
+  const int32_t* med_rows = rowlist + cls_off[kRow128];
+  const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRow128]);
+  const int32_t* long_rows = rowlist + cls_off[kRowLds8k];
+  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds8k]);
   // one pass partitions every row into tmp (free again after a3), then
   // the scans place the out- and in-lists
   int32_t* part = g->at<int32_t>(L.tmp);

@@ -390,7 +390,12 @@ __device__ __forceinline__ int row_class(int32_t len) {
   if (len <= 16) return kRow16;
   if (len <= 32) return kRow32;
   if (len <= 64) return kRow64;
+  if (len <= 128) return kRow128;
+  if (len <= 256) return kRow256;
+  if (len <= 512) return kRow512;
+  if (len <= 1024) return kRow1024;
   if (len <= 4096) return kRowLds4k;
+  if (len <= 8192) return kRowLds8k;
   if (len <= kLargeChunk) return kRowLds32k;
   return kRowLarge;
 }
@@ -613,6 +618,72 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ row
   if (threadIdx.x == 0) deg[v] = carry;
 }
 
+// Rows of up to 64 * E raw entries: one wavefront per row (grid-stride), the
+// row in registers (id i in lane i % 64, register i / 64), a bitonic network
+// whose strides >= 64 swap registers inside a lane and whose smaller strides
+// exchange with the lane i ^ j by a shuffle, so no LDS and no barrier.
+// Then an in-order dedup and a compacted, coalesced write to the row start.
+template <int E>
+__global__ __launch_bounds__(256) void k_sort_wave(const int32_t* __restrict__ rows, int32_t nrows,
+                                                   const int64_t* __restrict__ off, const int32_t* __restrict__ len,
+                                                   int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  constexpr int P = kWave * E;
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (256 / kWave);
+  for (int64_t r = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; r < nrows; r += nw) {
+    const int32_t v = rows[r];
+    const int64_t beg = off[v];
+    const int32_t L = len[v];
+    int32_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t i = e * kWave + lane;
+      x[e] = i < L ? adj[beg + i] : kPad;
+    }
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= kWave) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int pe = e ^ (j / kWave);
+            if (pe > e) {
+              const bool up = ((e * kWave) & k) == 0;  // k > 64: the lane bits do not matter
+              const int32_t a = x[e], b = x[pe];
+              x[e] = up ? min(a, b) : max(a, b);
+              x[pe] = up ? max(a, b) : min(a, b);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int32_t y = __shfl_xor(x[e], j, kWave);
+            const bool up = ((e * kWave + lane) & k) == 0;
+            const bool lo = (lane & j) == 0;
+            x[e] = (lo == up) ? min(x[e], y) : max(x[e], y);
+          }
+        }
+      }
+    }
+    int32_t base = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t i = e * kWave + lane;
+      int32_t prev = __shfl_up(x[e], 1, kWave);
+      if (e > 0) {
+        const int32_t last = __builtin_amdgcn_readlane(x[e > 0 ? e - 1 : 0], kWave - 1);
+        if (lane == 0) prev = last;
+      }
+      const bool u = i < L && (i == 0 || x[e] != prev);
+      const uint64_t m = __ballot(u);
+      if (u) adj[beg + base + mask_below(m)] = x[e];
+      base += (int32_t)__popcll(m);
+    }
+    if (lane == 0) deg[v] = base;
+  }
+}
+
 hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const int64_t* off,
                             const int32_t* len, int32_t* adj, int32_t* deg, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
@@ -621,7 +692,12 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
     case kRow16: k_sort_small<16><<<grid_for((int64_t)nrows * 16, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRow32: k_sort_small<32><<<grid_for((int64_t)nrows * 32, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRow64: k_sort_small<64><<<grid_for((int64_t)nrows * 64, 256, 1u << 30), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow128: k_sort_wave<2><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow256: k_sort_wave<4><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow512: k_sort_wave<8><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
+    case kRow1024: k_sort_wave<16><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRowLds4k: k_sort_lds<4096, 256, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds8k: k_sort_lds<8192, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     case kRowLds32k: k_sort_lds<kLargeChunk, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     default: return hipErrorInvalidValue;
   }
