@@ -283,6 +283,99 @@ __global__ __launch_bounds__(kPartNT) void k_part_place(const int32_t* __restric
   }
 }
 
+// Pass B with coalesced stores, for at most kStagedParts partitions: a tile
+// of kStagedPairs pairs is ranked per partition (LDS atomics), scanned, and
+// staged in LDS in partition order; each partition's run then goes to its
+// reserved range with consecutive lanes on consecutive addresses, instead
+// of one cache line per lane.
+constexpr int kStagedParts = 1024;
+constexpr int kStagedNT = 1024;
+constexpr int kStagedPairs = 8192;
+constexpr int kStagedPer = kStagedPairs / kStagedNT;
+
+__global__ __launch_bounds__(kStagedNT) void k_part_place_staged(const int32_t* __restrict__ src,
+                                                                 const int32_t* __restrict__ dst, int64_t m_raw,
+                                                                 int pbits, int32_t P,
+                                                                 const int64_t* __restrict__ pstart,
+                                                                 uint32_t* __restrict__ pcur, int32_t* __restrict__ pv,
+                                                                 uint16_t* __restrict__ pu) {
+  __shared__ uint32_t cnt[kStagedParts];   // entries of each partition in the tile
+  __shared__ uint32_t lst[kStagedParts];   // their exclusive prefix (run start in the stage)
+  __shared__ int64_t hoff[kStagedParts];   // global start of the run
+  __shared__ int32_t sv[2 * kStagedPairs];  // staged other endpoint
+  __shared__ int32_t ss[2 * kStagedPairs];  // staged row endpoint
+  __shared__ uint32_t red[kStagedNT / kWave + 1];
+  const int64_t ntiles = (m_raw + kStagedPairs - 1) / kStagedPairs;
+  const int32_t lmask = (1 << pbits) - 1;
+  constexpr int BPT = kStagedParts / kStagedNT;  // bins per thread in the scan
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int b = threadIdx.x; b < P; b += kStagedNT) cnt[b] = 0;
+    __syncthreads();
+    int32_t a[kStagedPer], c[kStagedPer];
+    uint32_t ra[kStagedPer], rc[kStagedPer];
+    const int64_t base = tile * kStagedPairs + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kStagedPer; ++k) {
+      const int64_t e = base + (int64_t)k * kStagedNT;
+      a[k] = -1;
+      c[k] = -1;
+      if (e < m_raw) {
+        a[k] = src[e];
+        c[k] = dst[e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kStagedPer; ++k) {
+      if (a[k] == c[k]) a[k] = -1;  // self loop or past the end
+      if (a[k] >= 0) {
+        ra[k] = atomicAdd(&cnt[a[k] >> pbits], 1u);
+        rc[k] = atomicAdd(&cnt[c[k] >> pbits], 1u);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of cnt over the partitions (BPT consecutive bins per thread)
+    uint32_t loc[BPT > 0 ? BPT : 1];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = threadIdx.x * BPT + q;
+      loc[q] = b < P ? cnt[b] : 0u;
+      sum += loc[q];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<uint32_t, kStagedNT>(sum, red, &tot);
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = threadIdx.x * BPT + q;
+      if (b < P) {
+        lst[b] = run;
+        if (loc[q]) hoff[b] = pstart[b] + atomicAdd(&pcur[b], loc[q]);
+      }
+      run += loc[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kStagedPer; ++k) {
+      if (a[k] < 0) continue;
+      const uint32_t i = lst[a[k] >> pbits] + ra[k];
+      sv[i] = c[k];
+      ss[i] = a[k];
+      const uint32_t j = lst[c[k] >> pbits] + rc[k];
+      sv[j] = a[k];
+      ss[j] = c[k];
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < tot; t += kStagedNT) {
+      const int32_t r = ss[t];
+      const int32_t p = r >> pbits;
+      const int64_t pos = hoff[p] + (t - lst[p]);
+      pv[pos] = sv[t];
+      pu[pos] = (uint16_t)(r & lmask);
+    }
+    __syncthreads();  // the stage and the tables are reused by the next tile
+  }
+}
+
 // Passes C (pass 0) and D (pass 1). Block c takes chunk c; blocks past the
 // last chunk exit. A partition held by one chunk writes its rows directly;
 // one spread over several chunks combines them with global atomics (len for
@@ -368,6 +461,11 @@ hipError_t launch_part_scan(const uint32_t* ptotal, int32_t P, int64_t* pstart, 
 hipError_t launch_part_place(const int32_t* src, const int32_t* dst, int64_t m_raw, int pbits, int32_t P,
                              const int64_t* pstart, uint32_t* pcur, int32_t* pv, uint16_t* pu, hipStream_t s) {
   if (m_raw == 0) return hipSuccess;
+  if (P <= kStagedParts) {
+    k_part_place_staged<<<grid_for(m_raw, kStagedPairs, 4096), kStagedNT, 0, s>>>(src, dst, m_raw, pbits, P, pstart,
+                                                                                 pcur, pv, pu);
+    return hipGetLastError();
+  }
   k_part_place<<<grid_for(m_raw, (int)kPartTile, 4096), kPartNT, 0, s>>>(src, dst, m_raw, pbits, P, pstart, pcur,
                                                                          pv, pu);
   return hipGetLastError();
