@@ -171,7 +171,7 @@ constexpr int kPartNT = 1024;
 constexpr int kPartPairs = 16;  // pairs per thread per tile in pass B
 constexpr int64_t kPartTile = (int64_t)kPartNT * kPartPairs;
 constexpr int kRowsNT = 1024;
-constexpr int kRowsUnroll = 4;
+constexpr int kRowsUnroll = 2;  // groups of 8 entries per thread per step
 constexpr int64_t kRowsChunk = int64_t(1) << 18;  // entries per block in C and D
 
 int part_bits(int64_t n) {
@@ -406,13 +406,28 @@ __global__ __launch_bounds__(kRowsNT) void k_part_rows(int pass, int pbits, int3
   const int32_t W = min(1 << pbits, n - v0);
   for (int j = threadIdx.x; j < W; j += kRowsNT) cnt[j] = 0;
   __syncthreads();
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kRowsNT * kRowsUnroll) {
-    uint16_t r[kRowsUnroll];
+  // aligned groups of 8 entries, one 16-byte load of local rows each (the
+  // group start rounds down inside the array; the last group may read up
+  // to 7 entries past the end, inside the staging area's padding); entries
+  // outside [i0, i1) are masked
+  const int64_t g0 = i0 & ~int64_t(7);
+  for (int64_t gs = g0 + 8 * (int64_t)threadIdx.x; gs < i1; gs += 8 * kRowsNT * kRowsUnroll) {
+    uint4 w[kRowsUnroll];
 #pragma unroll
-    for (int k = 0; k < kRowsUnroll; ++k) r[k] = i + k * kRowsNT < i1 ? pu[i + k * kRowsNT] : 0xffff;
+    for (int k = 0; k < kRowsUnroll; ++k) {
+      const int64_t at = gs + (int64_t)k * 8 * kRowsNT;
+      w[k] = at < i1 ? *reinterpret_cast<const uint4*>(pu + at) : make_uint4(0, 0, 0, 0);
+    }
 #pragma unroll
-    for (int k = 0; k < kRowsUnroll; ++k)
-      if (r[k] != 0xffff) atomicAdd(&cnt[r[k]], 1u);
+    for (int k = 0; k < kRowsUnroll; ++k) {
+      const int64_t at = gs + (int64_t)k * 8 * kRowsNT;
+      const uint32_t ws[4] = {w[k].x, w[k].y, w[k].z, w[k].w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t i = at + q;
+        if (i >= i0 && i < i1) atomicAdd(&cnt[(ws[q >> 1] >> (16 * (q & 1))) & 0xffffu], 1u);
+      }
+    }
   }
   __syncthreads();
   if (pass == 0) {
@@ -431,18 +446,28 @@ __global__ __launch_bounds__(kRowsNT) void k_part_rows(int pass, int pbits, int3
     cnt[j] = (uint32_t)(raw_off[v0 + j] - pb) + (uint32_t)at;
   }
   __syncthreads();
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kRowsNT * kRowsUnroll) {
-    uint16_t r[kRowsUnroll];
-    int32_t x[kRowsUnroll];
+  for (int64_t gs = g0 + 8 * (int64_t)threadIdx.x; gs < i1; gs += 8 * kRowsNT * kRowsUnroll) {
+    uint4 w[kRowsUnroll];
+    int4 xa[kRowsUnroll], xb[kRowsUnroll];
 #pragma unroll
     for (int k = 0; k < kRowsUnroll; ++k) {
-      const bool ok = i + k * kRowsNT < i1;
-      r[k] = ok ? pu[i + k * kRowsNT] : 0xffff;
-      x[k] = ok ? pv[i + k * kRowsNT] : 0;
+      const int64_t at = gs + (int64_t)k * 8 * kRowsNT;
+      const bool ok = at < i1;
+      w[k] = ok ? *reinterpret_cast<const uint4*>(pu + at) : make_uint4(0, 0, 0, 0);
+      xa[k] = ok ? *reinterpret_cast<const int4*>(pv + at) : make_int4(0, 0, 0, 0);
+      xb[k] = ok ? *reinterpret_cast<const int4*>(pv + at + 4) : make_int4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int k = 0; k < kRowsUnroll; ++k)
-      if (r[k] != 0xffff) adj[pb + atomicAdd(&cnt[r[k]], 1u)] = x[k];
+    for (int k = 0; k < kRowsUnroll; ++k) {
+      const int64_t at = gs + (int64_t)k * 8 * kRowsNT;
+      const uint32_t ws[4] = {w[k].x, w[k].y, w[k].z, w[k].w};
+      const int32_t xs[8] = {xa[k].x, xa[k].y, xa[k].z, xa[k].w, xb[k].x, xb[k].y, xb[k].z, xb[k].w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t i = at + q;
+        if (i >= i0 && i < i1) adj[pb + atomicAdd(&cnt[(ws[q >> 1] >> (16 * (q & 1))) & 0xffffu], 1u)] = xs[q];
+      }
+    }
   }
 }
 
