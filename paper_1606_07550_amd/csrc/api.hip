@@ -57,7 +57,7 @@ constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, total;
+      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, hubmap, total;
   int64_t cls_nblk;
   int64_t max_jobs;
 };
@@ -93,6 +93,7 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.inch = take(sizeof(int32_t) * n);
   L.incoff = take(sizeof(int64_t) * (n + 1));
   L.part = take(2 * sizeof(uint32_t) * kPartMaxParts + 2 * sizeof(int64_t) * (kPartMaxParts + 1));
+  L.hubmap = take(sizeof(uint32_t) * (size_t)hub_map_words(n) * (size_t)hub_map_slots(n));
   L.total = p;
   return L;
 }
@@ -340,6 +341,8 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
   int32_t* adj = g->at<int32_t>(L.adj);
   int rc;
 
+  // the hub variant expects zeroed bitmaps and leaves them zeroed
+  HIPCHK(hipMemsetAsync(g->ws + L.hubmap, 0, sizeof(uint32_t) * (size_t)hub_map_words(n) * hub_map_slots(n), s));
   if (!presorted) HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
   if (!presorted) HIPCHK(hipMemsetAsync(len, 0, sizeof(int32_t) * (size_t)n, s));
   const int pbits = m_raw > 0 && !presorted ? part_bits(n) : -1;
@@ -438,7 +441,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
   static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 36};
+  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 37};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;
@@ -638,6 +641,9 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
     bl.dinoff = g->at<int64_t>(L.dinoff);
     bl.dincol = g->at<int32_t>(L.dincol);
   }
+  bl.hubmap = g->at<uint32_t>(L.hubmap);
+  bl.hub_slots = hub_map_slots(g->n);
+  bl.map_words = hub_map_words(g->n);
   HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
                           reinterpret_cast<unsigned long long*>(d_node_tri), static_cast<hipStream_t>(stream)));
   return TRICC_OK;

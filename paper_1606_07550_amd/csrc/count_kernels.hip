@@ -751,6 +751,76 @@ __global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict_
   node_count_global(list[blockIdx.x], red, doff, dcol, T);
 }
 
+// Hub variant: N+(u) as a bitmap over all node ids, one private bitmap per
+// block in global memory (2 MB at 16.7M ids, L2-resident). The block sets
+// u's bits, makes them visible (device fence, so that no stale L1 line
+// survives), streams every N+(w) with its wavefronts (buffer loads, then one
+// 4-byte bitmap load per id), credits x with a global atomic per hit and w
+// once per list, and finally clears exactly the words it set, so the map is
+// all zero again for the next node or launch. The grid never exceeds the
+// number of bitmaps.
+constexpr int kHubNT = 1024;
+
+template <int U>
+__global__ __launch_bounds__(kHubNT) void k_count_bitmap(const int32_t* __restrict__ list, int32_t nlist,
+                                                         uint32_t* __restrict__ hubmap, int64_t map_words,
+                                                         const int64_t* __restrict__ doff,
+                                                         const int32_t* __restrict__ dcol,
+                                                         unsigned long long* __restrict__ T) {
+  static_assert(U * kWave * 4 <= 4096, "per-load offsets must fit the 12-bit immediate field");
+  constexpr int WPB = kHubNT / kWave;
+  __shared__ unsigned long long red[WPB];
+  uint32_t* map = hubmap + (int64_t)blockIdx.x * map_words;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  for (int32_t idx = blockIdx.x; idx < nlist; idx += gridDim.x) {
+    const int32_t u = list[idx];
+    const int64_t ub = doff[u];
+    const int32_t nu = (int32_t)(doff[u + 1] - ub);
+    for (int32_t i = threadIdx.x; i < nu; i += kHubNT) {
+      const int32_t x = dcol[ub + i];
+      atomicOr(&map[x >> 5], 1u << (x & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned long long tu = 0;
+    for (int32_t i = __builtin_amdgcn_readfirstlane(wv); i < nu; i += WPB) {
+      const int32_t w = __builtin_amdgcn_readfirstlane(dcol[ub + i]);
+      const int64_t wb = doff[w];  // w is uniform, so are its bounds
+      const int32_t wn = (int32_t)(doff[w + 1] - wb);
+      uint32_t cw = 0;
+      for (int32_t p = 0; p < wn; p += U * kWave) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(dcol + wb + p), (short)0, (wn - p) * 4,
+                                              kRawBufferWord3);
+        int32_t x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) x[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4 + k * kWave * 4, 0, 0);
+        uint32_t mw[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) mw[k] = p + k * kWave + lane < wn ? map[x[k] >> 5] : 0u;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const bool hit = (mw[k] >> (x[k] & 31)) & 1u;
+          cw += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+          if (hit) atomicAdd(&T[x[k]], 1ull);
+        }
+      }
+      if (lane == 0) {
+        if (cw) atomicAdd(&T[w], (unsigned long long)cw);
+        tu += cw;  // cw is wave-uniform: counted once per wave for the block sum
+      }
+    }
+    const unsigned long long t = block_sum<unsigned long long, kHubNT>(tu, red);
+    if (threadIdx.x == 0 && t) atomicAdd(&T[u], t);
+    __syncthreads();  // every probe of this node is done
+    for (int32_t i = threadIdx.x; i < nu; i += kHubNT) map[dcol[ub + i] >> 5] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Several short-list nodes per wavefront: GS lanes per node (d+(u) <= GS),
 // 64 / GS nodes per wave. Lane j of a node's lanes owns the out-edge to the
@@ -1076,10 +1146,12 @@ static constexpr VariantInfo kVariants[] = {
     {512, 512, 64, 2048, 1024},   // 33: d+ <= 1024, denser table
     {512, 512, 64, 4096, 2048},   // 34: d+ <= 2048
     {256, 256, 64, 512, 256},     // 35: d+ <= 256, denser table
-    {256, 256, 64, 0},       // 36: global fallback, any d+
+    {256, 256, 64, 0},       // 36: global fallback (binary search), any d+
+    {1024, 1024, 64, 0},     // 37: hub bitmap in global memory, any d+
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr int kVariantGlobal = kNumVariants - 1;
+constexpr int kVariantGlobal = 36;
+constexpr int kVariantBitmap = 37;
 
 int count_variant_valid(int v) { return v >= 0 && v < kNumVariants; }
 int count_variant_capacity(int v) {
@@ -1127,6 +1199,14 @@ static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dc
 
 int count_variant_min_side(int v) { return v >= 28 && v <= 35; }
 
+// Hub bitmaps: one bit per node id, as many bitmaps as fit 256 MB (8 to 256,
+// one per block of the hub variant's grid).
+int64_t hub_map_words(int64_t n) { return (n + 31) / 32 > 0 ? (n + 31) / 32 : 1; }
+int32_t hub_map_slots(int64_t n) {
+  const int64_t fit = (int64_t(256) << 20) / (4 * hub_map_words(n));
+  return (int32_t)(fit < 8 ? 8 : fit > 256 ? 256 : fit);
+}
+
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s) {
   if (b.count <= 0 && b.in_items <= 0) return hipSuccess;
@@ -1169,6 +1249,11 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 35: launch_ms<256, 256, 512, 256>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
+      break;
+    case kVariantBitmap:
+      if (!b.hubmap || b.hub_slots < 1) return hipErrorInvalidValue;
+      k_count_bitmap<8><<<(unsigned)min(b.count, b.hub_slots), kHubNT, 0, s>>>(b.list, b.count, b.hubmap, b.map_words,
+                                                                             doff, dcol, T);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -138,7 +138,14 @@ struct BinLaunch {
   int32_t w_max = 0;
   const int64_t* dinoff = nullptr;
   const int32_t* dincol = nullptr;
+  // hub bitmap variant only: hub_slots zeroed bitmaps of map_words words
+  uint32_t* hubmap = nullptr;
+  int32_t hub_slots = 0;
+  int64_t map_words = 0;
 };
+// Bitmaps for the hub variant: words per bitmap and how many fit the region.
+int64_t hub_map_words(int64_t n);
+int32_t hub_map_slots(int64_t n);
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
                             unsigned long long* T, hipStream_t s);
 int count_variant_capacity(int variant);  // max d+(u) a variant accepts

@@ -217,7 +217,7 @@ def test_min_side_split(ti):
         ref = oracle.count(n, s, d, order=1)
         g = P.Graph(n, to_dev(s), to_dev(d))
         mo = g.info["max_outdeg"]
-        if mo > tun["bin_limit"][4] and tun["bin_variant"][5] != P.variant_count() - 1:
+        if P.variant_capacity(tun["bin_variant"][5]) < mo:
             continue
         g.retune(tun)
         if tun["min_side"] and n > 1000:
@@ -255,6 +255,29 @@ def test_each_variant_owns_every_node(variant):
         r = gpu_count(n, s, d, tuning=_tuning_all_to(variant))
         assert sum(r["info"]["bin_count"]) == r["info"]["bin_count"][N.NUM_BINS - 1]
         check_against(r, ref, n)
+
+
+def test_hubs_above_every_table():
+    """K_4200: nodes 0..102 have d+ above the largest LDS table (4096), so the
+    default tuning sends them to the hub variant (a bitmap of N+(u) over all
+    ids); then the same with the binary-search fallback. Closed form:
+    T(v) = C(n-1, 2), CC = 1."""
+    n = 4200
+    iu = np.triu_indices(n, 1)
+    s, d = iu[0].astype(np.int32), iu[1].astype(np.int32)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    assert g.info["max_outdeg"] == n - 1 and g.info["bin_count"][N.NUM_BINS - 1] == n - 1 - 4096
+    for var in (P.default_tuning().bin_variant[N.NUM_BINS - 1], 36):
+        t = P.default_tuning()
+        t.bin_variant[N.NUM_BINS - 1] = var
+        g.retune(t)
+        for _ in range(2):  # the hub bitmaps are left clean for the next launch
+            o = g.count()
+            torch.cuda.synchronize()
+            T = o["T"].cpu().numpy().view(np.uint64)
+            assert np.all(T == (n - 1) * (n - 2) // 2), var
+            assert int(o["total"].cpu().numpy().view(np.uint64)[0]) == n * (n - 1) * (n - 2) // 6
+            assert np.all(o["cc"].cpu().numpy() == 1.0)
 
 
 def test_retune_matches():
