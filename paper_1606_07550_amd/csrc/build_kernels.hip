@@ -821,7 +821,7 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
     case kRow1024: k_sort_wave<16><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRowLds4k: k_sort_lds<4096, 256, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     case kRowLds8k: k_sort_lds<8192, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
-    case kRowLds32k: k_sort_lds<kLargeChunk, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds32k: k_sort_lds<kLargeChunk, 1024, true><<<nrows, 1024, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -830,7 +830,7 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
 hipError_t launch_sort_chunks(const int64_t* chunk_beg, const int32_t* chunk_len, int32_t nchunks,
                               int32_t* buf, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
-  k_sort_lds<kLargeChunk, 512, false><<<nchunks, 512, 0, s>>>(nullptr, chunk_beg, chunk_len, nullptr, nullptr, buf, nullptr);
+  k_sort_lds<kLargeChunk, 1024, false><<<nchunks, 1024, 0, s>>>(nullptr, chunk_beg, chunk_len, nullptr, nullptr, buf, nullptr);
   return hipGetLastError();
 }
 
@@ -880,26 +880,41 @@ hipError_t launch_merge_pass(const int64_t* a_beg, const int32_t* la, const int3
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_dedup_rows(const int32_t* __restrict__ rows,
-                                                    const int64_t* __restrict__ seg_beg,
-                                                    const int32_t* __restrict__ len,
-                                                    const int32_t* __restrict__ sorted,
-                                                    const int64_t* __restrict__ off,
-                                                    int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
-  __shared__ int32_t lds_scan[256 / kWave + 1];
+constexpr int kDedupNT = 1024;
+constexpr int kDedupPer = 4;  // consecutive entries per thread per step
+
+__global__ __launch_bounds__(kDedupNT) void k_dedup_rows(const int32_t* __restrict__ rows,
+                                                         const int64_t* __restrict__ seg_beg,
+                                                         const int32_t* __restrict__ len,
+                                                         const int32_t* __restrict__ sorted,
+                                                         const int64_t* __restrict__ off,
+                                                         int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  __shared__ int32_t lds_scan[kDedupNT / kWave + 1];
   const int32_t v = rows[blockIdx.x];
   const int32_t L = len[v];
   const int32_t* S = sorted + seg_beg[blockIdx.x];
   int32_t* D = adj + off[v];
   int32_t carry = 0;
-  for (int base = 0; base < L; base += 256) {
-    const int i = base + threadIdx.x;
-    const int32_t x = i < L ? S[i] : kPad;
-    const bool u = i < L && (i == 0 || x != S[i - 1]);
-    __syncthreads();  // all reads of this chunk precede writes (S may alias D)
+  for (int base = 0; base < L; base += kDedupNT * kDedupPer) {
+    const int i0 = base + threadIdx.x * kDedupPer;
+    int32_t x[kDedupPer];
+    bool u[kDedupPer];
+    int32_t c = 0;
+    int32_t prev = i0 > 0 && i0 - 1 < L ? S[i0 - 1] : kPad;
+#pragma unroll
+    for (int q = 0; q < kDedupPer; ++q) {
+      const int i = i0 + q;
+      x[q] = i < L ? S[i] : kPad;
+      u[q] = i < L && (i == 0 || x[q] != prev);
+      prev = x[q];
+      c += u[q];
+    }
+    __syncthreads();  // every read of this step precedes the writes (S may alias D)
     int32_t tot;
-    const int32_t ex = block_excl_scan<int32_t, 256>(u ? 1 : 0, lds_scan, &tot);
-    if (u) D[carry + ex] = x;
+    int32_t at = carry + block_excl_scan<int32_t, kDedupNT>(c, lds_scan, &tot);
+#pragma unroll
+    for (int q = 0; q < kDedupPer; ++q)
+      if (u[q]) D[at++] = x[q];
     carry += tot;
     __syncthreads();
   }
@@ -910,7 +925,7 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
                              const int32_t* len, const int32_t* sorted, const int64_t* off,
                              int32_t* adj, int32_t* deg, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  k_dedup_rows<<<nrows, 256, 0, s>>>(rows, seg_beg, len, sorted, off, adj, deg);
+  k_dedup_rows<<<nrows, kDedupNT, 0, s>>>(rows, seg_beg, len, sorted, off, adj, deg);
   return hipGetLastError();
 }
 

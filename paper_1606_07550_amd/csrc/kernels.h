@@ -13,7 +13,7 @@ enum RowClass : int {
   kRow128, kRow256, kRow512, kRow1024,  // register bitonic sort by a wavefront
   kRowLds4k,   // <= 4096, LDS bitonic sort, 256 threads
   kRowLds8k,   // <= 8192, LDS bitonic sort, 512 threads
-  kRowLds32k,  // <= 32768, LDS bitonic sort, 512 threads
+  kRowLds32k,  // <= 32768, LDS bitonic sort, 1024 threads
   kRowLarge,   // > 32768: chunk sort + merge passes
   kNumRowClasses
 };
