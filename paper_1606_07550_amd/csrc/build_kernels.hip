@@ -998,31 +998,44 @@ __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* 
   }
 }
 
-__global__ __launch_bounds__(256) void k_orient_long(const int32_t* __restrict__ rows,
-                                                     const int64_t* __restrict__ off,
-                                                     const int32_t* __restrict__ deg,
-                                                     const int32_t* __restrict__ adj,
-                                                     int32_t* __restrict__ dplus, int32_t* __restrict__ part,
-                                                     int32_t* __restrict__ stats) {
-  __shared__ int32_t lds[256 / kWave + 1];
+constexpr int kOrientLongNT = 1024;
+constexpr int kOrientLongPer = 4;  // consecutive entries per thread per step
+
+__global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __restrict__ rows,
+                                                               const int64_t* __restrict__ off,
+                                                               const int32_t* __restrict__ deg,
+                                                               const int32_t* __restrict__ adj,
+                                                               int32_t* __restrict__ dplus,
+                                                               int32_t* __restrict__ part,
+                                                               int32_t* __restrict__ stats) {
+  __shared__ int32_t lds[kOrientLongNT / kWave + 1];
   const int32_t v = rows[blockIdx.x];
   const int32_t dv = deg[v];
   const int64_t rb = off[v];
   const int32_t* row = adj + rb;
   int32_t* prow = part + rb;
   int32_t c = 0;
-  for (int32_t b = 0; b < dv; b += 256) {
-    const int32_t i = b + threadIdx.x;
-    bool f = false;
-    int32_t w = 0;
-    if (i < dv) {
-      w = row[i];
-      f = rank_below(dv, v, deg[w], w);
+  for (int32_t b = 0; b < dv; b += kOrientLongNT * kOrientLongPer) {
+    const int32_t i0 = b + threadIdx.x * kOrientLongPer;
+    int32_t w[kOrientLongPer];
+    bool f[kOrientLongPer];
+    int32_t k = 0;
+#pragma unroll
+    for (int q = 0; q < kOrientLongPer; ++q) w[q] = i0 + q < dv ? row[i0 + q] : 0;
+#pragma unroll
+    for (int q = 0; q < kOrientLongPer; ++q) {
+      f[q] = i0 + q < dv && rank_below(dv, v, deg[w[q]], w[q]);
+      k += f[q];
     }
     int32_t tot;
-    const int32_t ex = block_excl_scan<int32_t, 256>(f ? 1 : 0, lds, &tot);
-    if (f) prow[c + ex] = w;
-    else if (i < dv) prow[dv - 1 - (i - (c + ex))] = w;
+    int32_t o = c + block_excl_scan<int32_t, kOrientLongNT>(k, lds, &tot);  // out-entries before i0
+#pragma unroll
+    for (int q = 0; q < kOrientLongPer; ++q) {
+      const int32_t i = i0 + q;
+      if (i >= dv) break;
+      if (f[q]) prow[o++] = w[q];
+      else prow[dv - 1 - (i - o)] = w[q];
+    }
     c += tot;
   }
   if (threadIdx.x == 0) {
@@ -1138,7 +1151,7 @@ hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, cons
   if (nmedium > 0)
     k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(medium_rows, nmedium, off, deg,
                                                                                    adj, dplus, part, stats);
-  if (nlong > 0) k_orient_long<<<nlong, 256, 0, s>>>(long_rows, off, deg, adj, dplus, part, stats);
+  if (nlong > 0) k_orient_long<<<nlong, kOrientLongNT, 0, s>>>(long_rows, off, deg, adj, dplus, part, stats);
   return hipGetLastError();
 }
 
