@@ -30,6 +30,9 @@ LIMIT_SETS = [
     [32, 64, 256, 1024, 2048],
     [16, 64, 256, 512, 2048],
     [16, 32, 128, 1024, 4096],
+    [64, 256, 512, 1024, 2048],
+    [64, 256, 512, 1024, 4096],
+    [32, 128, 256, 512, 1024],
 ]
 
 
