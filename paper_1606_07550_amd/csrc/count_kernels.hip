@@ -217,6 +217,89 @@ __device__ __forceinline__ void credit(uint32_t* C, int off) {
   atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(C) + off), 1u);
 }
 
+// Two-choice cuckoo table of SLOTS int32 keys (-1 = empty), one key per
+// slot (Pagh and Rodler 2001; built in parallel with atomic exchanges as in
+// Alcantara et al. 2009): key x sits in slot a(x) or b(x), so a lookup is two
+// 4-byte LDS reads and two compares, with no probe loop. Ids share a slot
+// pair when their low 24 bits agree.
+template <int SLOTS>
+__device__ __forceinline__ void cuckoo_pos(int32_t x, uint32_t* a, uint32_t* b) {
+  constexpr int bits = __builtin_ctz(SLOTS);
+  const uint32_t lo = (uint32_t)x & 0xFFFFFFu;
+  *a = (lo * 0x9E3779u) >> (32 - bits);
+  *b = (lo * 0x3C6EF3u) >> (32 - bits);
+}
+
+// The same two slots as byte offsets (4 x slot).
+template <int SLOTS>
+__device__ __forceinline__ void cuckoo_off(int32_t x, uint32_t* a, uint32_t* b) {
+  cuckoo_pos<SLOTS>(x, a, b);
+  *a <<= 2;
+  *b <<= 2;
+}
+
+// Eviction chains longer than this give up: the caller then rebuilds the
+// node's table in the bucket layout.
+constexpr int kCuckooMaxChain = 48;
+
+// Inserts x (absent from the table; keys are distinct). Each thread holds
+// exactly one key outside the table at any time, so concurrent inserts lose
+// nothing while they succeed. False: the chain gave up and the key it held
+// is not in the table.
+template <int SLOTS>
+__device__ __forceinline__ bool cuckoo_insert(int32_t* K, int32_t x) {
+  uint32_t a, b;
+  cuckoo_pos<SLOTS>(x, &a, &b);
+  if (atomicCAS(&K[a], -1, x) == -1 || atomicCAS(&K[b], -1, x) == -1) return true;
+  uint32_t pos = a;
+#pragma unroll 1
+  for (int it = 0; it < kCuckooMaxChain; ++it) {
+    x = atomicExch(&K[pos], x);
+    if (x == -1) return true;
+    cuckoo_pos<SLOTS>(x, &a, &b);  // the evicted key moves to its other slot
+    pos = pos == a ? b : a;
+  }
+  return false;
+}
+
+// Slot of x in a complete cuckoo table, or -1.
+template <int SLOTS>
+__device__ __forceinline__ int cuckoo_find(const int32_t* K, int32_t x) {
+  uint32_t a, b;
+  cuckoo_pos<SLOTS>(x, &a, &b);
+  return K[a] == x ? (int)a : K[b] == x ? (int)b : -1;
+}
+
+// Probes of the streaming loops: true when the lane is valid and x is in the
+// table, with *off the byte offset of x's counter in C (4 x slot); *hits
+// grows by the wave's number of such lanes.
+template <int NB>
+struct BucketProbe {
+  const int4* Kb;
+  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off, uint32_t* hits) const {
+    const bool hit = bucket_credit<NB>(Kb, x, valid, off);
+    *hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+    return hit;
+  }
+};
+
+template <int SLOTS>
+struct CuckooProbe {
+  const int32_t* K;
+  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off, uint32_t* hits) const {
+    x = valid ? x : -2;  // in no table
+    uint32_t a, b;
+    cuckoo_off<SLOTS>(x, &a, &b);
+    const char* Kc = reinterpret_cast<const char*>(K);
+    const bool ea = *reinterpret_cast<const int32_t*>(Kc + a) == x;
+    const bool eb = *reinterpret_cast<const int32_t*>(Kc + b) == x;
+    *off = (int)(ea ? a : b);
+    // the compare masks are counted as they are (a == b makes them equal)
+    *hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ea) | __builtin_amdgcn_ballot_w64(eb));
+    return ea | eb;
+  }
+};
+
 // LDS of one node group of the wave-stream kernel.
 template <int SLOTS, int CAP>
 struct WaveGroupLds {
@@ -228,6 +311,7 @@ struct WaveGroupLds {
   uint32_t Wc[CAP];      // hits per streamed list (packed phase)
   int32_t Wl[CAP];       // indices of the lists streamed one by one
   int32_t nlong;         // number of such lists
+  int32_t fail;          // a cuckoo insert gave up
 };
 
 // Lists shorter than this are streamed packed: a wavefront covers several
@@ -244,9 +328,9 @@ constexpr int kSmallGS = 16;
 // prefix of lengths); each step gives every lane one id of the window's
 // concatenation, found by a shuffle binary search over the prefixes. A hit
 // credits its table slot and its list's counter Wc. Returns the wave's hits.
-template <int NB>
+template <typename Probe>
 __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const int32_t* Wb, const int32_t* Wn,
-                                                  uint32_t* Wc, const int32_t* __restrict__ dcol, const int4* Kb,
+                                                  uint32_t* Wc, const int32_t* __restrict__ dcol, Probe probe,
                                                   uint32_t* C) {
   const int lane = lane_id();
   uint32_t hits = 0;
@@ -283,8 +367,7 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
       for (int r = 0; r < kPackUnroll; ++r) {
         if (t0 + r * kWave >= total) break;
         int off;
-        const bool hit = bucket_credit<NB>(Kb, x[r], t0 + r * kWave + lane < total, &off);
-        hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+        const bool hit = probe(x[r], t0 + r * kWave + lane < total, &off, &hits);
         if (hit) {
           credit(C, off);
           atomicAdd(&Wc[base + kk[r]], 1u);
@@ -315,10 +398,10 @@ __device__ __forceinline__ void load_chunk(int32_t (&x)[U], const int32_t* L, in
 // the current chunk is probed. Base and length of a list are wave-uniform
 // (scalar registers). Each hit credits its table slot; done(i, hits)
 // receives list i's hit count (wave-uniform). Returns the wave's hits.
-template <int NB, int U, typename Done>
+template <int U, typename Probe, typename Done>
 __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_t nl, const int32_t* Wl,
                                                 const int32_t* Wb, const int32_t* Wn,
-                                                const int32_t* __restrict__ dcol, const int4* Kb, uint32_t* C,
+                                                const int32_t* __restrict__ dcol, Probe probe, uint32_t* C,
                                                 Done done) {
   // j0 is the wave's index inside its group: uniform, but not provably so
   int32_t j = __builtin_amdgcn_readfirstlane(j0);
@@ -349,8 +432,7 @@ __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_
     for (int k = 0; k < U; ++k) {
       if (p + k * kWave >= n) break;
       int off;
-      const bool hit = bucket_credit<NB>(Kb, cur[k], lane < n - p - k * kWave, &off);
-      cw += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+      const bool hit = probe(cur[k], lane < n - p - k * kWave, &off, &cw);
       if (hit) credit(C, off);
     }
     if (np == 0) {
@@ -373,11 +455,30 @@ __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_
   return total;
 }
 
+// Builds the cuckoo table of the keys src[0..len) for a group of G lanes
+// (g = lane in group). If an insert gives up, the table is rebuilt in the
+// bucket layout instead. Returns true for a cuckoo table (group-uniform).
+template <int G, int SLOTS, int CAP>
+__device__ __forceinline__ bool build_cuckoo(WaveGroupLds<SLOTS, CAP>& S, const int32_t* __restrict__ src,
+                                             int32_t len, int g) {
+  int32_t* K = reinterpret_cast<int32_t*>(S.K);
+  for (int i = g; i < len; i += G)
+    if (!cuckoo_insert<SLOTS>(K, src[i])) S.fail = 1;
+  group_sync<G>();
+  if (__builtin_amdgcn_readfirstlane(S.fail) == 0) return true;
+  for (int s = g; s < SLOTS; s += G) K[s] = -1;
+  group_sync<G>();
+  for (int i = g; i < len; i += G) bucket_insert<SLOTS / 4>(K, src[i]);
+  group_sync<G>();
+  return false;
+}
+
 // One node u (u < 0: inactive group) counted by a group of G lanes (G a
 // multiple of 64; when G > 64 the group is the whole block).
 // w_max > 0 (min-side mode): edges u->w with d+(u) < d+(w) <= w_max are left
 // to w's in-list pass (node_count_inw), which then streams the shorter list.
-template <int G, int SLOTS, int CAP, int U>
+// CK: N+(u) goes into a cuckoo table (bucket table if its build gives up).
+template <int G, int SLOTS, int CAP, int U, bool CK = false>
 __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, CAP>& S,
                                                 unsigned long long* red, const int64_t* __restrict__ doff,
                                                 const int32_t* __restrict__ dcol,
@@ -397,11 +498,14 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
     len = (int32_t)(doff[u + 1] - beg);
   }
   for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
-  if (g == 0) S.nlong = 0;
+  if (g == 0) { S.nlong = 0; S.fail = 0; }
   group_sync<G>();
+  bool ck = false;
+  if constexpr (CK) ck = build_cuckoo<G>(S, dcol + beg, len, g);
   for (int i = g; i < len; i += G) {
     const int32_t w = dcol[beg + i];
-    S.Ws[i] = bucket_insert<NB>(K, w);
+    if constexpr (CK) S.Ws[i] = ck ? cuckoo_find<SLOTS>(K, w) : table_find<SLOTS>(K, w);
+    else S.Ws[i] = bucket_insert<NB>(K, w);
     const int64_t b = doff[w];
     int32_t wn = (int32_t)(doff[w + 1] - b);
     // edges u->w with d+(u) < d+(w) <= w_max are counted from w's in-list
@@ -413,10 +517,20 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
   }
   group_sync<G>();
   const int32_t nl = __builtin_amdgcn_readfirstlane(S.nlong);
-  uint32_t tu = stream_long<NB, U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, S.K, S.C, [&](int32_t i, uint32_t cw) {
+  auto done = [&](int32_t i, uint32_t cw) {
     if (cw && lane == 0) atomicAdd(&S.C[S.Ws[i]], cw);
-  });  // wave-uniform
-  tu += stream_packed<NB>(wv * len / WPG, (wv + 1) * len / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
+  };
+  const int32_t p0 = wv * len / WPG, p1 = (wv + 1) * len / WPG;
+  uint32_t tu;  // wave-uniform
+  if (ck) {
+    const CuckooProbe<SLOTS> probe{K};
+    tu = stream_long<U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, probe, S.C, done);
+    tu += stream_packed(p0, p1, S.Wb, S.Wn, S.Wc, dcol, probe, S.C);
+  } else {
+    const BucketProbe<NB> probe{S.K};
+    tu = stream_long<U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, probe, S.C, done);
+    tu += stream_packed(p0, p1, S.Wb, S.Wn, S.Wc, dcol, probe, S.C);
+  }
   group_sync<G>();
   for (int i = g; i < len; i += G)
     if (S.Wc[i]) atomicAdd(&S.C[S.Ws[i]], S.Wc[i]);
@@ -459,7 +573,7 @@ __global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ l
 // table; for every in-neighbour with 2 <= d+(u) < d+(w) one wavefront
 // streams N+(u) against it. A hit x is the triangle u < w < x: x is credited
 // in the table, w in the group total, u with one global atomic per in-edge.
-template <int G, int SLOTS, int CAP, int U>
+template <int G, int SLOTS, int CAP, int U, bool CK = false>
 __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGroupLds<SLOTS, CAP>& S,
                                                unsigned long long* red, const int64_t* __restrict__ doff,
                                                const int32_t* __restrict__ dcol,
@@ -482,9 +596,11 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
     nin = (int32_t)min((int64_t)CAP, dinoff[w + 1] - ib);
   }
   for (int s = g; s < SLOTS; s += G) { K[s] = -1; S.C[s] = 0; }
-  if (g == 0) S.nlong = 0;
+  if (g == 0) { S.nlong = 0; S.fail = 0; }
   group_sync<G>();
-  for (int i = g; i < len; i += G) bucket_insert<NB>(K, dcol[beg + i]);
+  bool ck = false;
+  if constexpr (CK) ck = build_cuckoo<G>(S, dcol + beg, len, g);
+  else for (int i = g; i < len; i += G) bucket_insert<NB>(K, dcol[beg + i]);
   for (int i = g; i < nin; i += G) {
     const int32_t u = dincol[ib + i];
     const int64_t b = doff[u];
@@ -498,10 +614,20 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
   }
   group_sync<G>();
   const int32_t nl = __builtin_amdgcn_readfirstlane(S.nlong);
-  uint32_t tw = stream_long<NB, U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, S.K, S.C, [&](int32_t i, uint32_t cu) {
+  auto done = [&](int32_t i, uint32_t cu) {
     if (cu && lane == 0) atomicAdd(&T[S.Ws[i]], (unsigned long long)cu);
-  });  // wave-uniform
-  tw += stream_packed<NB>(wv * nin / WPG, (wv + 1) * nin / WPG, S.Wb, S.Wn, S.Wc, dcol, S.K, S.C);
+  };
+  const int32_t p0 = wv * nin / WPG, p1 = (wv + 1) * nin / WPG;
+  uint32_t tw;  // wave-uniform
+  if (ck) {
+    const CuckooProbe<SLOTS> probe{K};
+    tw = stream_long<U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, probe, S.C, done);
+    tw += stream_packed(p0, p1, S.Wb, S.Wn, S.Wc, dcol, probe, S.C);
+  } else {
+    const BucketProbe<NB> probe{S.K};
+    tw = stream_long<U>(wv, WPG, nl, S.Wl, S.Wb, S.Wn, dcol, probe, S.C, done);
+    tw += stream_packed(p0, p1, S.Wb, S.Wn, S.Wc, dcol, probe, S.C);
+  }
   group_sync<G>();
   for (int i = g; i < nin; i += G)
     if (S.Wc[i]) atomicAdd(&T[S.Ws[i]], (unsigned long long)S.Wc[i]);
@@ -535,7 +661,7 @@ struct InItems {
   int64_t items;
 };
 
-template <int NT, int G, int SLOTS, int CAP, int U>
+template <int NT, int G, int SLOTS, int CAP, int U, bool CK>
 __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ list, int32_t nlist, InItems in,
                                                  int32_t w_max, const int64_t* __restrict__ doff,
                                                  const int32_t* __restrict__ dcol,
@@ -550,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
   const int64_t nbu = ((int64_t)nlist + GPB - 1) / GPB;
   if ((int64_t)blockIdx.x < nbu) {
     const int64_t idx = (int64_t)blockIdx.x * GPB + gi;
-    node_count_wave<G, SLOTS, CAP, U>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, w_max);
+    node_count_wave<G, SLOTS, CAP, U, CK>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, w_max);
     return;
   }
   const int64_t j = ((int64_t)blockIdx.x - nbu) * GPB + gi;
@@ -566,7 +692,7 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
     w = in.list[lo];
     chunk = gc - in.coff[lo];
   }
-  node_count_inw<G, SLOTS, CAP, U>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T);
+  node_count_inw<G, SLOTS, CAP, U, CK>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T);
 }
 
 // Merge variant for short lists: a group of G lanes owns node u and each
@@ -1148,6 +1274,15 @@ static constexpr VariantInfo kVariants[] = {
     {256, 256, 64, 512, 256},     // 35: d+ <= 256, denser table
     {256, 256, 64, 0},       // 36: global fallback (binary search), any d+
     {1024, 1024, 64, 0},     // 37: hub bitmap in global memory, any d+
+    // as 28..35 with cuckoo tables (bucket tables where a build gives up)
+    {256, 64, 64, 128, 16},       // 38: d+ <= 16
+    {256, 64, 64, 256, 64},       // 39: d+ <= 64
+    {256, 256, 64, 1024, 256},    // 40: d+ <= 256
+    {512, 512, 64, 4096, 1024},   // 41: d+ <= 1024
+    {1024, 1024, 64, 8192, 4096}, // 42: d+ <= 4096
+    {512, 512, 64, 2048, 1024},   // 43: d+ <= 1024, denser table
+    {512, 512, 64, 4096, 2048},   // 44: d+ <= 2048
+    {256, 256, 64, 512, 256},     // 45: d+ <= 256, denser table
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = 36;
@@ -1185,7 +1320,7 @@ static void launch_plain(const BinLaunch& b, const int64_t* doff, const int32_t*
   k_count_plain<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
 }
 
-template <int NT, int G, int SLOTS, int CAP, int U = 8>
+template <int NT, int G, int SLOTS, int CAP, bool CK = false, int U = 8>
 static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
                       hipStream_t s) {
   constexpr int GPB = NT / G;
@@ -1193,11 +1328,11 @@ static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dc
   const int64_t nbw = (b.in_items + GPB - 1) / GPB;
   if (nbu + nbw == 0) return;
   InItems in{b.in_list, b.in_coff, b.in_nodes, b.in_items};
-  k_count_ms<NT, G, SLOTS, CAP, U><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
+  k_count_ms<NT, G, SLOTS, CAP, U, CK><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
                                                                         b.dinoff, b.dincol, T);
 }
 
-int count_variant_min_side(int v) { return v >= 28 && v <= 35; }
+int count_variant_min_side(int v) { return (v >= 28 && v <= 35) || (v >= 38 && v <= 45); }
 
 // Hub bitmaps: one bit per node id, as many bitmaps as fit 256 MB (8 to 256,
 // one per block of the hub variant's grid).
@@ -1247,6 +1382,14 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 33: launch_ms<512, 512, 2048, 1024>(b, doff, dcol, T, s); break;
     case 34: launch_ms<512, 512, 4096, 2048>(b, doff, dcol, T, s); break;
     case 35: launch_ms<256, 256, 512, 256>(b, doff, dcol, T, s); break;
+    case 38: launch_ms<256, 64, 128, 16, true>(b, doff, dcol, T, s); break;
+    case 39: launch_ms<256, 64, 256, 64, true>(b, doff, dcol, T, s); break;
+    case 40: launch_ms<256, 256, 1024, 256, true>(b, doff, dcol, T, s); break;
+    case 41: launch_ms<512, 512, 4096, 1024, true>(b, doff, dcol, T, s); break;
+    case 42: launch_ms<1024, 1024, 8192, 4096, true>(b, doff, dcol, T, s); break;
+    case 43: launch_ms<512, 512, 2048, 1024, true>(b, doff, dcol, T, s); break;
+    case 44: launch_ms<512, 512, 4096, 2048, true>(b, doff, dcol, T, s); break;
+    case 45: launch_ms<256, 256, 512, 256, true>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;

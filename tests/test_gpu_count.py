@@ -201,6 +201,10 @@ MIN_SIDE_TUNINGS = [
     {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [28, 28, 28, 28, 29, 36], "min_side": 1},
     {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 0},
     {"bin_limit": [32, 64, 256, 1024, 2048], "bin_variant": [29, 29, 35, 33, 34, 36], "min_side": 1},
+    # cuckoo tables
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [38, 39, 40, 41, 42, 37], "min_side": 1},
+    {"bin_limit": [64, 256, 512, 1024, 2048], "bin_variant": [39, 45, 43, 41, 44, 36], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [38, 38, 39, 40, 41, 36], "min_side": 1},
 ]
 
 
@@ -278,6 +282,38 @@ def test_hubs_above_every_table():
             assert np.all(T == (n - 1) * (n - 2) // 2), var
             assert int(o["total"].cpu().numpy().view(np.uint64)[0]) == n * (n - 1) * (n - 2) // 6
             assert np.all(o["cc"].cpu().numpy() == 1.0)
+
+
+def test_cuckoo_tables_fall_back_to_buckets():
+    """Cuckoo-table variants rebuild a node's table in the bucket layout when
+    an insert gives up. Forced two ways: (1) K_5 on ids whose low 24 bits
+    agree, so four keys share one slot pair; (2) K_4097 on the d+ <= 4096
+    variant, whose largest tables are half full. Closed forms: T(v) =
+    C(d(v), 2) on complete graphs, 0 elsewhere."""
+    hub = [0, 1, 1 + (1 << 24), 1 + (1 << 25), 1 + 3 * (1 << 24)]
+    n = hub[-1] + 1
+    s = np.array([a for i, a in enumerate(hub) for b in hub[i + 1:]], dtype=np.int32)
+    d = np.array([b for i, a in enumerate(hub) for b in hub[i + 1:]], dtype=np.int32)
+    g = P.Graph(n, to_dev(s), to_dev(d))
+    for var in (38, 39, 40, 41):
+        g.retune(_tuning_all_to(var))
+        o = g.count()
+        torch.cuda.synchronize()
+        T = o["T"].cpu().numpy().view(np.uint64)
+        assert np.all(T[hub] == 6) and int(T.sum()) == 30, var
+    k = 4097
+    iu = np.triu_indices(k, 1)
+    s, d = iu[0].astype(np.int32), iu[1].astype(np.int32)
+    g = P.Graph(k, to_dev(s), to_dev(d))
+    assert g.info["max_outdeg"] == k - 1
+    for tun in (_tuning_all_to(42),
+                {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [38, 39, 40, 41, 42, 37], "min_side": 1}):
+        g.retune(tun)
+        o = g.count()
+        torch.cuda.synchronize()
+        T = o["T"].cpu().numpy().view(np.uint64)
+        assert np.all(T == (k - 1) * (k - 2) // 2)
+        assert int(o["total"].cpu().numpy().view(np.uint64)[0]) == k * (k - 1) * (k - 2) // 6
 
 
 def test_retune_matches():
