@@ -215,11 +215,12 @@ typedef struct tricc_batch tricc_batch;
 
 typedef struct tricc_batch_tuning {
   int32_t merge_limit;     /* nodes with d+ <= merge_limit take the short-list path (0..wave_limit;
-                              at most 16 with variants 2 and 3) */
+                              at most 16 with variants 2, 3, 6, 7, 32 with 4, 8 with 5) */
   int32_t wave_limit;      /* other nodes with d+ <= wave_limit: one wavefront each (2..64) */
-  int32_t persist_variant; /* block nodes up to d+ 256 (0, 2) or 1024 (1, 3); short-list path:
-                              8-lane two-pointer merge (0, 1) or four nodes per wavefront with
-                              LDS tables and packed streaming (2, 3) */
+  int32_t persist_variant; /* block nodes up to d+ 256 (0, 2, 4, 5, 6) or 1024 (1, 3, 7);
+                              short-list path: 8-lane two-pointer merge (0, 1) or several nodes
+                              per wavefront with LDS tables and packed streaming (2..7);
+                              wave and block nodes in cuckoo tables (6, 7) or bucket tables */
   int32_t blocks_per_cu;   /* persistent grid = compute units x this; 0 = occupancy limit */
 } tricc_batch_tuning;
 

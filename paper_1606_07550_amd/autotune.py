@@ -25,14 +25,11 @@ from .graph import default_tuning, variant_capacity, variant_count
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 LIMIT_SETS = [
-    [16, 64, 256, 1024, 4096],
-    [32, 64, 256, 1024, 4096],
-    [32, 64, 256, 1024, 2048],
-    [16, 64, 256, 512, 2048],
-    [16, 32, 128, 1024, 4096],
+    [64, 256, 1024, 2048, 4096],
     [64, 256, 512, 1024, 2048],
     [64, 256, 512, 1024, 4096],
-    [32, 128, 256, 512, 1024],
+    [32, 64, 256, 1024, 4096],
+    [64, 128, 512, 1024, 2048],
 ]
 
 
@@ -84,9 +81,10 @@ def _bin_ms(graph, T, b, reps):
     return _time(run, reps)
 
 
-def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
+def tune_single(graph, reps=3, key=None, log=None, min_side=(1,)):
     """Tunes a built :class:`Graph` in place; returns (tuning dict, ms).
-    With min_side on, bins 0..4 only take min-side variants."""
+    With min_side on, bins 0..4 only take min-side variants (min_side=(1, 0)
+    also searches the variants that count every edge from its tail)."""
     T = torch.zeros(max(graph.n, 1), dtype=torch.int64, device=graph.device)
     best_total, best = None, None
     max_outdeg = graph.info["max_outdeg"]
@@ -131,7 +129,7 @@ def tune_single(graph, reps=3, key=None, log=None, min_side=(1, 0)):
 
 
 # largest merge_limit of each persistent variant's short-list path
-MERGE_CAP = {0: 64, 1: 64, 2: 16, 3: 16, 4: 32, 5: 8}
+MERGE_CAP = {0: 64, 1: 64, 2: 16, 3: 16, 4: 32, 5: 8, 6: 16, 7: 16}
 BATCH_SPACE = [(ml, wl, pv, bpc) for pv in sorted(MERGE_CAP) for wl in (32, 64) for ml in (0, 8, 16, 32, 64)
                for bpc in (0, 4) if ml <= wl and ml <= MERGE_CAP[pv]]
 

@@ -440,8 +440,8 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
 
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
-  static const int32_t lim[kNumBins - 1] = {16, 64, 256, 1024, 4096};
-  static const int32_t var[kNumBins] = {28, 29, 30, 31, 32, 37};
+  static const int32_t lim[kNumBins - 1] = {64, 256, 1024, 2048, 4096};
+  static const int32_t var[kNumBins] = {29, 40, 43, 44, 42, 37};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;
@@ -765,8 +765,8 @@ int check_batch_tuning(const tricc_batch_tuning* t) {
 // global fallback), run in the persistent kernel; bins 3 (up to 1024) and 4
 // (up to 4096) run before it with the large-table kernel variants. The
 // single-graph variants are set so that tricc_count also works on the union.
-constexpr int kBatchVarBin3 = 24;  // 512 threads, table for d+ <= 1024
-constexpr int kBatchVarBin4 = 21;  // 1024 threads, table for d+ <= 4096
+constexpr int kBatchVarBin3 = 43;  // 512 threads, cuckoo table for d+ <= 1024
+constexpr int kBatchVarBin4 = 42;  // 1024 threads, cuckoo table for d+ <= 4096
 void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
   const int32_t cb = persist_block_cap(bt.persist_variant);
   const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, std::max(cb, 1024), 4096};

@@ -1053,7 +1053,7 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
 // loads. Each wave owns a private LDS region in phase 2.
 constexpr int kPersistGrab = 8;
 
-template <int SW, int CW, int SB, int CB, int SMALL = 0>
+template <int SW, int CW, int SB, int CB, int SMALL = 0, bool CK = false>
 __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict__ glist, int32_t ng,
                                                        const int32_t* __restrict__ blist, int32_t nbk,
                                                        const int32_t* __restrict__ wlist, int32_t nw,
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
     __syncthreads();
     if (c >= n1) break;
     if (c < ng) node_count_global(glist[c], red, doff, dcol, T);
-    else node_count_wave<256, SB, CB, 4>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
+    else node_count_wave<256, SB, CB, 4, CK>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
     __syncthreads();
   }
   constexpr int NPW = SMALL ? kWave / kGS : kWave / 8;  // short-list nodes per wave item
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
     const int32_t end = min(cur + kPersistGrab, n2);
     for (int32_t it = cur; it < end; ++it) {
       if (it < nw) {
-        node_count_wave<kWave, SW, CW, 4>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T);
+        node_count_wave<kWave, SW, CW, 4, CK>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T);
       } else if constexpr (SMALL != 0) {
         nodes_count_small<kGS>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol, T);
       } else {
@@ -1108,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
   }
 }
 
-struct PersistShape { int sw, cw, sb, cb, small; };
+struct PersistShape { int sw, cw, sb, cb, small, ck = 0; };
 static constexpr PersistShape kPersist[] = {
     {256, 64, 1024, 256, 0},   // 0: block nodes up to d+ 256, 8-lane merge
     {256, 64, 4096, 1024, 0},  // 1: block nodes up to d+ 1024, 8-lane merge
@@ -1116,6 +1116,8 @@ static constexpr PersistShape kPersist[] = {
     {256, 64, 4096, 1024, 16}, // 3: as 1, short lists on the packed small-node path
     {256, 64, 1024, 256, 32},  // 4: as 2 with 32 lanes per node (d+ <= 32)
     {256, 64, 1024, 256, 8},   // 5: as 2 with 8 lanes per node (d+ <= 8)
+    {256, 64, 1024, 256, 16, 1},   // 6: as 2 with cuckoo tables for wave and block nodes
+    {256, 64, 4096, 1024, 16, 1},  // 7: as 3 with cuckoo tables for wave and block nodes
 };
 int persist_variant_count() { return (int)(sizeof(kPersist) / sizeof(kPersist[0])); }
 int persist_wave_cap(int v) { return kPersist[v].cw; }
@@ -1130,6 +1132,8 @@ const void* persist_kernel(int v) {
     case 3: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024, 16>);
     case 4: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 32>);
     case 5: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 8>);
+    case 6: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 1024, 256, 16, true>);
+    case 7: return reinterpret_cast<const void*>(&k_count_persist<256, 64, 4096, 1024, 16, true>);
     default: return nullptr;
   }
 }
@@ -1162,6 +1166,14 @@ hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int3
     case 5:
       k_count_persist<256, 64, 1024, 256, 8><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
                                                                   doff, dcol, T);
+      break;
+    case 6:
+      k_count_persist<256, 64, 1024, 256, 16, true><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
+                                                                         queue, doff, dcol, T);
+      break;
+    case 7:
+      k_count_persist<256, 64, 4096, 1024, 16, true><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
+                                                                          queue, doff, dcol, T);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -114,6 +114,8 @@ def test_graph_replays_match_eager(mixed):
     {"merge_limit": 3, "wave_limit": 8, "persist_variant": 2, "blocks_per_cu": 1},
     {"merge_limit": 32, "wave_limit": 64, "persist_variant": 4, "blocks_per_cu": 0},
     {"merge_limit": 8, "wave_limit": 64, "persist_variant": 5, "blocks_per_cu": 0},
+    {"merge_limit": 16, "wave_limit": 64, "persist_variant": 6, "blocks_per_cu": 0},
+    {"merge_limit": 5, "wave_limit": 24, "persist_variant": 7, "blocks_per_cu": 1},
 ])
 def test_tunings_agree(mixed, tun):
     graphs, (node_off, edge_off, src, dst) = mixed

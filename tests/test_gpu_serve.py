@@ -135,6 +135,7 @@ def test_bad_queries_rejected(resident):
     {"merge_limit": 4, "wave_limit": 32, "persist_variant": 3, "blocks_per_cu": 1},
     {"merge_limit": 32, "wave_limit": 64, "persist_variant": 1, "blocks_per_cu": 0},
     {"merge_limit": 0, "wave_limit": 64, "persist_variant": 0, "blocks_per_cu": 0},
+    {"merge_limit": 16, "wave_limit": 64, "persist_variant": 6, "blocks_per_cu": 0},
 ])
 def test_every_batch_variant_serves(resident, tun):
     n, s, d, g, queries = resident
