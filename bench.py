@@ -95,16 +95,18 @@ def probe_bandwidth(torch, N, nbytes=2 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def measured_traffic(workload, variant):
+def measured_traffic(workload, variant, bin):
     """HBM traffic per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on this workload and variant
-    with the current intersection-kernel source; else None."""
+    rocprofv3 counter summary, if it was taken on this workload, variant and
+    bin with the current intersection-kernel source; else None."""
     from paper_1606_07550_amd import profiling
     rec = profiling.read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                               f"traffic_{workload}.md"))
     if not rec:
         return None
     if rec.get("count_kernels_sha256") != profiling.count_source_sha256() or int(rec.get("variant", -1)) != variant:
+        return None
+    if "bin" in rec and int(rec["bin"]) != bin:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -397,7 +399,7 @@ def main():
     a6_ms = sum(avg_bin_ms)
     tuning_used = (tuning or P.default_tuning()).as_dict()
     variant = tuning_used["bin_variant"][dom]
-    traffic = measured_traffic(cfg["workload"], variant)
+    traffic = measured_traffic(cfg["workload"], variant, dom)
     bw, _ = probe_bandwidth(torch, N)
     line = {
         "metric": METRIC,

@@ -29,16 +29,27 @@ def count_source_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _per_kernel(db, counter):
+def _per_kernel(db, counter, every=1, offset=0):
+    """{kernel: (dispatches, mean value)}; with every > 1 only the dispatches
+    at positions offset, offset + every, ... (in dispatch order) of each
+    kernel count, e.g. one bin's launches when several bins of one count run
+    the same kernel."""
     c = sqlite3.connect(db)
-    return {k: (n, v) for k, n, v in c.execute(
-        "select kernel_name, count(*), avg(value) from counters_collection where counter_name=? "
-        "group by kernel_name", (counter,))}
+    vals = {}
+    for k, v in c.execute("select kernel_name, value from counters_collection where counter_name=? "
+                          "order by dispatch_id", (counter,)):
+        vals.setdefault(k, []).append(v)
+    out = {}
+    for k, vs in vals.items():
+        pick = vs[offset::every] if "k_probe_copy" not in k else vs
+        if pick:
+            out[k] = (len(pick), sum(pick) / len(pick))
+    return out
 
 
-def traffic_summary(fetch_db, write_db, kernel, variant, workload, command):
-    f = _per_kernel(fetch_db, "FETCH_SIZE")
-    w = _per_kernel(write_db, "WRITE_SIZE")
+def traffic_summary(fetch_db, write_db, kernel, variant, workload, command, bin=None, every=1, offset=0):
+    f = _per_kernel(fetch_db, "FETCH_SIZE", every, offset)
+    w = _per_kernel(write_db, "WRITE_SIZE", every, offset)
     probe = [k for k in f if "k_probe_copy" in k][0]
     fscale = PROBE_BYTES / (f[probe][1] * 1024.0)
     wscale = PROBE_BYTES / (w[probe][1] * 1024.0)
@@ -48,6 +59,8 @@ def traffic_summary(fetch_db, write_db, kernel, variant, workload, command):
     k = ks[0]
     fb = f[k][1] * 1024.0 * fscale
     wb = w[k][1] * 1024.0 * wscale
+    sel = (f"Dispatches {offset}, {offset} + {every}, ... of this kernel (bin {bin}'s launches; "
+           f"{every} bins of one count run it).") if every > 1 else ""
     lines = [
         f"# Memory traffic of {k.split('(')[0].replace('void ', '')} — {workload}",
         "",
@@ -55,6 +68,7 @@ def traffic_summary(fetch_db, write_db, kernel, variant, workload, command):
         "each scaled by the ratio of the true bytes of the library's streaming copy kernel (k_probe_copy,",
         f"{PROBE_BYTES} bytes read and written per launch, run inside the same benchmark) to what the same",
         f"counter reads for it: FETCH x{fscale:.3f}, WRITE x{wscale:.3f}.",
+        *([sel] if sel else []),
         "",
         "Commands (from /tmp, repository at /root/repo):",
         f"    {command.replace('PMC', 'FETCH_SIZE')}",
@@ -62,6 +76,7 @@ def traffic_summary(fetch_db, write_db, kernel, variant, workload, command):
         "",
         f"kernel: {k.split('(')[0].replace('void ', '')}",
         f"variant: {variant}",
+        *([f"bin: {bin}"] if bin is not None else []),
         f"workload: {workload}",
         f"dispatches: {f[k][0]}",
         f"fetch_bytes_per_launch: {fb:.0f}",
@@ -122,13 +137,17 @@ def main():
     ap.add_argument("--variant", type=int)
     ap.add_argument("--workload")
     ap.add_argument("--command", default="")
+    ap.add_argument("--bin", type=int, default=None, help="the bin whose launches are summarised")
+    ap.add_argument("--every", type=int, default=1, help="launches of the kernel per count")
+    ap.add_argument("--offset", type=int, default=0, help="position of the bin's launch among them")
     a = ap.parse_args()
     if a.what == "kernels":
         print(kernel_stats(a.db, a.top))
     elif a.what == "counters":
         print(counter_stats(a.db, a.kernel))
     else:
-        print(traffic_summary(a.fetch, a.write, a.kernel, a.variant, a.workload, a.command))
+        print(traffic_summary(a.fetch, a.write, a.kernel, a.variant, a.workload, a.command, a.bin, a.every,
+                              a.offset))
 
 
 if __name__ == "__main__":
