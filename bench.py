@@ -426,8 +426,13 @@ def main():
             "kernel": f"intersection bin {dom} (variant {variant})",
             "kernel_ms": avg_bin_ms[dom],
             "alg_bytes_per_launch": dom_bytes,
+            # algorithmic bytes count list reads that caches serve (frac > 1 is
+            # cache reuse); the measured DRAM traffic gives the HBM-side rate
+            "traffic_GBps": traffic / (avg_bin_ms[dom] * 1e-3) / 1e9 if traffic else None,
+            "traffic_frac": traffic / (avg_bin_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBPS if traffic else None,
         },
         "stage_a6": {"ms": a6_ms, "alg_bytes": stage_bytes,
+                     "compulsory_bytes": 4 * m + 8 * (n + 1) + 12 * n,
                      "achieved_GBps": stage_bytes / (a6_ms * 1e-3) / 1e9 if a6_ms else 0.0,
                      "frac": stage_bytes / (a6_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if a6_ms else 0.0,
                      "bin_ms": avg_bin_ms, "bin_count": info["bin_count"]},

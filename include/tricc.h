@@ -220,7 +220,7 @@ typedef struct tricc_batch_tuning {
   int32_t persist_variant; /* block nodes up to d+ 256 (0, 2, 4, 5, 6) or 1024 (1, 3, 7);
                               short-list path: 8-lane two-pointer merge (0, 1) or several nodes
                               per wavefront with LDS tables and packed streaming (2..7);
-                              wave and block nodes in cuckoo tables (6, 7) or bucket tables */
+                              cuckoo tables (6, 7) or bucket tables */
   int32_t blocks_per_cu;   /* persistent grid = compute units x this; 0 = occupancy limit */
 } tricc_batch_tuning;
 

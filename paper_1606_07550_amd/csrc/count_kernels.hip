@@ -963,7 +963,53 @@ struct SmallLds {
   uint32_t Wc[kWave];              // hits per lane's list
 };
 
-template <int GS>
+// The packed stream of the small-node path: the 64 lanes' lists (begin wb,
+// inclusive prefix incl of their lengths, total) against the lanes' node
+// tables; a hit credits its table slot and its list's counter Wc.
+template <int GS, bool CK>
+__device__ __forceinline__ void small_stream(SmallLds<GS>& S, int32_t incl, int32_t total, int32_t excl, int32_t wb,
+                                             const int32_t* __restrict__ dcol, int lane) {
+  for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
+    // kPackUnroll independent gathers in flight before the probes
+    int32_t x[kPackUnroll];
+    int kk[kPackUnroll];
+#pragma unroll
+    for (int r = 0; r < kPackUnroll; ++r) {
+      const int32_t t = t0 + r * kWave + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1) {
+        const int32_t v = __shfl(incl, k + step - 1, kWave);
+        if (v <= t) k += step;
+      }
+      const int32_t kb = __shfl(wb, k, kWave);
+      const int32_t ke = __shfl(excl, k, kWave);
+      x[r] = t < total ? dcol[kb + (t - ke)] : -1;
+      kk[r] = k;
+    }
+#pragma unroll
+    for (int r = 0; r < kPackUnroll; ++r) {
+      if (t0 + r * kWave >= total) break;
+      int off;
+      uint32_t unused = 0;
+      bool hit;
+      if constexpr (CK) {
+        hit = CuckooProbe<4 * GS>{reinterpret_cast<const int32_t*>(S.K[kk[r] / GS])}(
+            x[r], t0 + r * kWave + lane < total, &off, &unused);
+      } else {
+        hit = bucket_credit<GS>(S.K[kk[r] / GS], x[r], t0 + r * kWave + lane < total, &off);
+      }
+      if (hit) {
+        credit(S.C[kk[r] / GS], off);
+        atomicAdd(&S.Wc[kk[r]], 1u);
+      }
+    }
+  }
+}
+
+// CK: the node tables are cuckoo tables (all of the wave's tables are
+// rebuilt in the bucket layout if one insert gives up).
+template <int GS, bool CK = false>
 __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ list, int64_t first, int64_t nlist,
                                                   SmallLds<GS>& S, const int64_t* __restrict__ doff,
                                                   const int32_t* __restrict__ dcol,
@@ -988,45 +1034,31 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
     nu = (int32_t)(doff[u + 1] - ub);
   }
   wave_sync();
+  bool gave_up = false;
   if (j < nu) {
     w = dcol[ub + j];
-    bucket_insert<NB>(K, w);
+    if constexpr (CK) gave_up = !cuckoo_insert<4 * GS>(K, w);
+    else bucket_insert<NB>(K, w);
     const int64_t b = doff[w];
     wb = (int32_t)b;
     wn = (int32_t)(doff[w + 1] - b);
   }
   wave_sync();
+  bool ck = false;
+  if constexpr (CK) {
+    ck = __builtin_amdgcn_ballot_w64(gave_up) == 0;
+    if (!ck) {
+      for (int s = j; s < 4 * GS; s += GS) K[s] = -1;
+      wave_sync();
+      if (j < nu) bucket_insert<NB>(K, w);
+      wave_sync();
+    }
+  }
   const int32_t incl = wave_incl_scan(wn);
   const int32_t total = __shfl(incl, kWave - 1, kWave);
   const int32_t excl = incl - wn;
-  for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
-    // kPackUnroll independent gathers in flight before the probes
-    int32_t x[kPackUnroll];
-    int kk[kPackUnroll];
-#pragma unroll
-    for (int r = 0; r < kPackUnroll; ++r) {
-      const int32_t t = t0 + r * kWave + lane;
-      int k = 0;
-#pragma unroll
-      for (int step = kWave / 2; step > 0; step >>= 1) {
-        const int32_t v = __shfl(incl, k + step - 1, kWave);
-        if (v <= t) k += step;
-      }
-      const int32_t kb = __shfl(wb, k, kWave);
-      const int32_t ke = __shfl(excl, k, kWave);
-      x[r] = t < total ? dcol[kb + (t - ke)] : -1;
-      kk[r] = k;
-    }
-#pragma unroll
-    for (int r = 0; r < kPackUnroll; ++r) {
-      if (t0 + r * kWave >= total) break;
-      int off;
-      if (bucket_credit<NB>(S.K[kk[r] / GS], x[r], t0 + r * kWave + lane < total, &off)) {
-        credit(S.C[kk[r] / GS], off);
-        atomicAdd(&S.Wc[kk[r]], 1u);
-      }
-    }
-  }
+  if (ck) small_stream<GS, true>(S, incl, total, excl, wb, dcol, lane);
+  else small_stream<GS, false>(S, incl, total, excl, wb, dcol, lane);
   wave_sync();
   const uint32_t c = S.Wc[lane];
   if (c) atomicAdd(&T[w], (unsigned long long)c);
@@ -1098,7 +1130,8 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
       if (it < nw) {
         node_count_wave<kWave, SW, CW, 4, CK>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T);
       } else if constexpr (SMALL != 0) {
-        nodes_count_small<kGS>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol, T);
+        nodes_count_small<kGS, CK>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol,
+                                   T);
       } else {
         const int64_t k = (int64_t)(it - nw) * NPW + lane / 8;
         node_count_merge<8>(k < nm ? mlist[k] : -1, doff, dcol, T);
@@ -1116,8 +1149,8 @@ static constexpr PersistShape kPersist[] = {
     {256, 64, 4096, 1024, 16}, // 3: as 1, short lists on the packed small-node path
     {256, 64, 1024, 256, 32},  // 4: as 2 with 32 lanes per node (d+ <= 32)
     {256, 64, 1024, 256, 8},   // 5: as 2 with 8 lanes per node (d+ <= 8)
-    {256, 64, 1024, 256, 16, 1},   // 6: as 2 with cuckoo tables for wave and block nodes
-    {256, 64, 4096, 1024, 16, 1},  // 7: as 3 with cuckoo tables for wave and block nodes
+    {256, 64, 1024, 256, 16, 1},   // 6: as 2 with cuckoo tables (bucket tables where a build gives up)
+    {256, 64, 4096, 1024, 16, 1},  // 7: as 3 with cuckoo tables
 };
 int persist_variant_count() { return (int)(sizeof(kPersist) / sizeof(kPersist[0])); }
 int persist_wave_cap(int v) { return kPersist[v].cw; }

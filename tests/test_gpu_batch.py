@@ -159,6 +159,30 @@ def test_batched_equals_single_graph(mixed):
         assert abs(o["avg"].item() - r["graph_avg"][gi]) <= 1e-12 * max(1e-300, abs(r["graph_avg"][gi]))
 
 
+def test_cuckoo_small_tables_fall_back_to_buckets():
+    """A member with K_5 on local ids whose low 24 bits agree: four keys of
+    one short-list node share a cuckoo slot pair, so that wave's tables are
+    rebuilt in the bucket layout. Closed form: T = 6 on the K_5, 0 elsewhere;
+    the other members against the oracle."""
+    hub = [0, 1, 1 + (1 << 24), 1 + (1 << 25), 1 + 3 * (1 << 24)]
+    pairs = [(a, b) for i, a in enumerate(hub) for b in hub[i + 1:]]
+    big = (hub[-1] + 1, np.array([p[0] for p in pairs], np.int32), np.array([p[1] for p in pairs], np.int32))
+    small = [F.complete(12), F.wheel(15), F.windmill(4)]
+    graphs = small + [big]
+    node_off, edge_off, src, dst = pack(graphs)
+    for pv in (6, 7, 2):
+        b = P.Batch(node_off, edge_off, dev(src), dev(dst),
+                    tuning={"merge_limit": 16, "wave_limit": 64, "persist_variant": pv, "blocks_per_cu": 0})
+        b.plan()
+        b.run()
+        torch.cuda.synchronize()
+        r = to_host(b.out)
+        check_batch(r, small, node_off)
+        T = r["T"][node_off[3]:node_off[4]]
+        assert np.all(T[hub] == 6) and int(T.sum()) == 30, pv
+        assert r["graph_tri"][3] == 10, pv
+
+
 def test_bad_local_id_is_rejected():
     graphs = [F.complete(5), (4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))]
     node_off, edge_off, src, dst = pack(graphs)
