@@ -414,7 +414,10 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
   // one pass partitions every row into tmp (free again after a3), then
   // the scans place the out- and in-lists
   int32_t* part = g->at<int32_t>(L.tmp);
-  HIPCHK(launch_orient(n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, dplus, part, hdr + kHdrStats, s));
+  // the degree-class words (n / 4 bytes) sit in binlist, free until the binning
+  uint32_t* cls = reinterpret_cast<uint32_t*>(g->at<int32_t>(L.binlist));
+  HIPCHK(launch_orient(n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, cls, dplus, part,
+                       hdr + kHdrStats, s));
   HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
   int32_t* din = g->at<int32_t>(L.din);
   int64_t* dinoff = g->at<int64_t>(L.dinoff);

@@ -938,8 +938,42 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 // a group of kOrientG lanes per row, grid-stride; medium rows: a wavefront
 // each; long rows: a block each (both listed contiguously by the row
 // classes).
+// Degree classes for the rank test: class(d) = 0 below 64, 1 below 512, 2
+// below 4096, else 3, two bits per node (16 nodes per word, 4 MB for 2^24
+// nodes, small enough to stay in L2). A class order agrees with the degree
+// order, so w ranks above v whenever class(w) > class(v), and below it
+// whenever class(w) < class(v); only nodes of one class need d(w) itself.
+// At R-MAT 24 about 3 in 4 edges join nodes of different classes, which
+// saves that many random gathers of d(w).
+__device__ __forceinline__ uint32_t deg_class(int32_t d) {
+  return (uint32_t)(d >= 64) + (uint32_t)(d >= 512) + (uint32_t)(d >= 4096);
+}
+
+// True when w ranks above v (rank = (d, id)); dv, cv = d(v), class(d(v)).
+__device__ __forceinline__ bool ranks_above(int32_t dv, uint32_t cv, int32_t v, int32_t w,
+                                            const int32_t* __restrict__ deg, const uint32_t* __restrict__ cls) {
+  const uint32_t cw = (cls[w >> 4] >> (2 * (w & 15))) & 3u;
+  if (cw != cv) return cw > cv;
+  return rank_below(dv, v, deg[w], w);
+}
+
+__global__ __launch_bounds__(256) void k_deg_class(int32_t n, const int32_t* __restrict__ deg,
+                                                   uint32_t* __restrict__ cls) {
+  const int64_t words = ((int64_t)n + 15) / 16;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t word = 0;
+    for (int j = 0; j < 16; ++j) {
+      const int64_t v = k * 16 + j;
+      if (v < n) word |= deg_class(deg[v]) << (2 * j);
+    }
+    cls[k] = word;
+  }
+}
+
 constexpr int kOrientG = 8;
 constexpr int32_t kOrientShort = 64;
+constexpr int kOrientShortUnroll = 4;  // steps of G entries issued together (short rows)
+constexpr int kOrientMedUnroll = 4;    // chunks of 64 entries issued together (medium rows)
 
 template <typename T>
 __device__ __forceinline__ T block_max(T x, T* lds) {
@@ -957,6 +991,7 @@ __device__ __forceinline__ T block_max(T x, T* lds) {
 __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* __restrict__ off,
                                                       const int32_t* __restrict__ len,
                                                       const int32_t* __restrict__ deg,
+                                                      const uint32_t* __restrict__ cls,
                                                       const int32_t* __restrict__ adj,
                                                       int32_t* __restrict__ dplus, int32_t* __restrict__ part,
                                                       int32_t* __restrict__ stats) {
@@ -969,22 +1004,33 @@ __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* 
   for (int64_t v = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; v < n; v += ngroups) {
     if (len[v] > kOrientShort) continue;
     const int32_t dv = deg[v];
+    const uint32_t cv = deg_class(dv);
     const int64_t rb = off[v];
     const int32_t* row = adj + rb;
     int32_t* prow = part + rb;
     int32_t c = 0;
-    for (int32_t b = 0; b < dv; b += G) {
-      bool f = false;
-      int32_t w = 0;
-      if (b + g < dv) {
-        w = row[b + g];
-        f = rank_below(dv, (int32_t)v, deg[w], w);
+    for (int32_t b = 0; b < dv; b += G * kOrientShortUnroll) {
+      int32_t w[kOrientShortUnroll];
+      bool f[kOrientShortUnroll];
+#pragma unroll
+      for (int q = 0; q < kOrientShortUnroll; ++q) {
+        const int32_t i = b + q * G + g;
+        w[q] = i < dv ? row[i] : 0;
       }
-      const uint32_t mask = (uint32_t)(__ballot(f) >> shift) & ((1u << G) - 1);
-      const int32_t below = __popc(mask & ((1u << g) - 1));
-      if (f) prow[c + below] = w;
-      else if (b + g < dv) prow[dv - 1 - ((b + g) - (c + below))] = w;
-      c += __popc(mask);
+#pragma unroll
+      for (int q = 0; q < kOrientShortUnroll; ++q) {
+        const int32_t i = b + q * G + g;
+        f[q] = i < dv && ranks_above(dv, cv, (int32_t)v, w[q], deg, cls);
+      }
+#pragma unroll
+      for (int q = 0; q < kOrientShortUnroll; ++q) {
+        const int32_t i = b + q * G + g;
+        const uint32_t mask = (uint32_t)(__ballot(f[q]) >> shift) & ((1u << G) - 1);
+        const int32_t below = __popc(mask & ((1u << g) - 1));
+        if (f[q]) prow[c + below] = w[q];
+        else if (i < dv) prow[dv - 1 - (i - (c + below))] = w[q];
+        c += __popc(mask);
+      }
     }
     if (g == 0) dplus[v] = c;
     mx_d = max(mx_d, dv);
@@ -1004,6 +1050,7 @@ constexpr int kOrientLongPer = 4;  // consecutive entries per thread per step
 __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __restrict__ rows,
                                                                const int64_t* __restrict__ off,
                                                                const int32_t* __restrict__ deg,
+                                                               const uint32_t* __restrict__ cls,
                                                                const int32_t* __restrict__ adj,
                                                                int32_t* __restrict__ dplus,
                                                                int32_t* __restrict__ part,
@@ -1011,6 +1058,7 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
   __shared__ int32_t lds[kOrientLongNT / kWave + 1];
   const int32_t v = rows[blockIdx.x];
   const int32_t dv = deg[v];
+  const uint32_t cv = deg_class(dv);
   const int64_t rb = off[v];
   const int32_t* row = adj + rb;
   int32_t* prow = part + rb;
@@ -1024,7 +1072,7 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
     for (int q = 0; q < kOrientLongPer; ++q) w[q] = i0 + q < dv ? row[i0 + q] : 0;
 #pragma unroll
     for (int q = 0; q < kOrientLongPer; ++q) {
-      f[q] = i0 + q < dv && rank_below(dv, v, deg[w[q]], w[q]);
+      f[q] = i0 + q < dv && ranks_above(dv, cv, v, w[q], deg, cls);
       k += f[q];
     }
     int32_t tot;
@@ -1050,6 +1098,7 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
 __global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict__ rows, int32_t nrows,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ deg,
+                                                       const uint32_t* __restrict__ cls,
                                                        const int32_t* __restrict__ adj,
                                                        int32_t* __restrict__ dplus, int32_t* __restrict__ part,
                                                        int32_t* __restrict__ stats) {
@@ -1060,22 +1109,35 @@ __global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict
   for (int64_t r = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; r < nrows; r += nwaves) {
     const int32_t v = rows[r];
     const int32_t dv = deg[v];
+    const uint32_t cv = deg_class(dv);
     const int64_t rb = off[v];
     const int32_t* row = adj + rb;
     int32_t* prow = part + rb;
     int32_t c = 0;
-    for (int32_t b = 0; b < dv; b += kWave) {
-      bool f = false;
-      int32_t w = 0;
-      if (b + l < dv) {
-        w = row[b + l];
-        f = rank_below(dv, v, deg[w], w);
+    // kOrientMedUnroll chunks of 64 entries per step: their row loads, then
+    // their degree gathers, are issued together
+    for (int32_t b = 0; b < dv; b += kWave * kOrientMedUnroll) {
+      int32_t w[kOrientMedUnroll];
+      bool f[kOrientMedUnroll];
+#pragma unroll
+      for (int q = 0; q < kOrientMedUnroll; ++q) {
+        const int32_t i = b + q * kWave + l;
+        w[q] = i < dv ? row[i] : 0;
       }
-      const uint64_t m = __ballot(f);
-      const int32_t below = mask_below(m);
-      if (f) prow[c + below] = w;
-      else if (b + l < dv) prow[dv - 1 - ((b + l) - (c + below))] = w;
-      c += (int32_t)__popcll(m);
+#pragma unroll
+      for (int q = 0; q < kOrientMedUnroll; ++q) {
+        const int32_t i = b + q * kWave + l;
+        f[q] = i < dv && ranks_above(dv, cv, v, w[q], deg, cls);
+      }
+#pragma unroll
+      for (int q = 0; q < kOrientMedUnroll; ++q) {
+        const int32_t i = b + q * kWave + l;
+        const uint64_t m = __ballot(f[q]);
+        const int32_t below = mask_below(m);
+        if (f[q]) prow[c + below] = w[q];
+        else if (i < dv) prow[dv - 1 - (i - (c + below))] = w[q];
+        c += (int32_t)__popcll(m);
+      }
     }
     if (l == 0) dplus[v] = c;
     mx_d = max(mx_d, dv);
@@ -1144,14 +1206,15 @@ __global__ __launch_bounds__(256) void k_orient_copy_listed(const int32_t* __res
 
 hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
                          const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
-                         int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s) {
+                         uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, adj, dplus, part,
-                                                                             stats);
+  k_deg_class<<<grid_for(((int64_t)n + 15) / 16, 256, 4096), 256, 0, s>>>(n, deg, cls);
+  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, cls, adj, dplus,
+                                                                             part, stats);
   if (nmedium > 0)
     k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(medium_rows, nmedium, off, deg,
-                                                                                   adj, dplus, part, stats);
-  if (nlong > 0) k_orient_long<<<nlong, kOrientLongNT, 0, s>>>(long_rows, off, deg, adj, dplus, part, stats);
+                                                                                   cls, adj, dplus, part, stats);
+  if (nlong > 0) k_orient_long<<<nlong, kOrientLongNT, 0, s>>>(long_rows, off, deg, cls, adj, dplus, part, stats);
   return hipGetLastError();
 }
 

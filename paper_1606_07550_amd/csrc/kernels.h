@@ -80,10 +80,11 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 // stats[0] = max d, stats[1] = max d+, and row v partitioned into
 // part[off[v] .. off[v] + d(v)): N+(v) ascending from the front, N-(v) from
 // the back in reverse. Rows of raw length > 64 must be listed: medium_rows
-// (a wavefront each) and long_rows (a block each) together.
+// (a wavefront each) and long_rows (a block each) together. cls: scratch of
+// ceil(n / 16) words for the degree classes of the rank test.
 hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
                          const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
-                         int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s);
+                         uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s);
 // After doff / dinoff are the scans of d+ / d-: N+(v) to dcol[doff[v]..] and
 // (dincol != NULL) N-(v) to dincol[dinoff[v]..], both ascending.
 hipError_t launch_orient_copy(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
