@@ -807,6 +807,121 @@ __global__ __launch_bounds__(256) void k_sort_wave(const int32_t* __restrict__ r
   }
 }
 
+// Rows (or chunks) of up to 64 * E * W ids: one block of W wavefronts holds
+// the row in registers (id i in wavefront i / (64 E), register (i / 64) % E,
+// lane i % 64) and runs a bitonic network on it: strides below 64 exchange
+// by shuffles, strides below 64 E swap registers inside a lane, and only the
+// strides of 64 E and up go through LDS (write, barrier, read of the partner,
+// barrier). The stages run in a loop over k with the strides unrolled, which
+// keeps the code small. DEDUP: the unique ids, compacted to the row start,
+// and deg[v]; otherwise the sorted chunk back in place.
+template <int E, int W, bool DEDUP>
+__global__ __launch_bounds__(kWave * W) void k_sort_block(const int32_t* __restrict__ rows,
+                                                          const int64_t* __restrict__ seg_beg,
+                                                          const int32_t* __restrict__ seg_len,
+                                                          const int64_t* __restrict__ off,
+                                                          const int32_t* __restrict__ len,
+                                                          int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+  constexpr int PW = kWave * E;  // ids per wavefront
+  constexpr int P = PW * W;
+  __shared__ int32_t s[P];
+  __shared__ int32_t wsum[W + 1];
+  __shared__ int32_t wlast[W];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  const int32_t i0 = wv * PW + lane;  // index of x[0]; x[e] is i0 + 64 e
+  int32_t v = -1;
+  int64_t beg;
+  int32_t L;
+  if (DEDUP) {
+    v = rows[blockIdx.x];
+    beg = off[v];
+    L = len[v];
+  } else {
+    beg = seg_beg[blockIdx.x];
+    L = seg_len[blockIdx.x];
+  }
+  int32_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t i = i0 + e * kWave;
+    x[e] = i < L ? adj[beg + i] : kPad;
+  }
+  for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+    for (int j = P / 2; j > 0; j >>= 1) {
+      if (j >= k) continue;  // block-uniform: the strides of stage k are k / 2 .. 1
+      if (j >= PW) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) s[i0 + e * kWave] = x[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int32_t i = i0 + e * kWave;
+          const int32_t y = s[i ^ j];
+          const bool up = (i & k) == 0;
+          const bool lo = (i & j) == 0;
+          x[e] = (lo == up) ? min(x[e], y) : max(x[e], y);
+        }
+        __syncthreads();
+      } else if (j >= kWave) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int pe = e ^ (j / kWave);
+          if (pe > e) {
+            const bool up = ((wv * PW + e * kWave) & k) == 0;  // k > 64: the lane bits do not matter
+            const int32_t a = x[e], b = x[pe];
+            x[e] = up ? min(a, b) : max(a, b);
+            x[pe] = up ? max(a, b) : min(a, b);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int32_t y = __shfl_xor(x[e], j, kWave);
+          const bool up = ((i0 + e * kWave) & k) == 0;
+          const bool lo = (lane & j) == 0;
+          x[e] = (lo == up) ? min(x[e], y) : max(x[e], y);
+        }
+      }
+    }
+  }
+  if (!DEDUP) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t i = i0 + e * kWave;
+      if (i < L) adj[beg + i] = x[e];
+    }
+    return;
+  }
+  // in-order dedup: the id before x[0] of lane 0 is the previous wavefront's
+  // last; the unique flags are formed twice (count, then write) rather than
+  // kept in registers
+  if (lane == kWave - 1) wlast[wv] = x[E - 1];
+  __syncthreads();
+  const int32_t before = wv > 0 ? wlast[wv > 0 ? wv - 1 : 0] : 0;
+  auto unique = [&](int e) -> uint64_t {
+    const int32_t i = i0 + e * kWave;
+    int32_t prev = __shfl_up(x[e], 1, kWave);
+    if (lane == 0) prev = e > 0 ? __builtin_amdgcn_readlane(x[e > 0 ? e - 1 : 0], kWave - 1) : before;
+    return __ballot(i < L && (i == 0 || x[e] != prev));
+  };
+  int32_t cnt = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) cnt += (int32_t)__popcll(unique(e));
+  if (lane == 0) wsum[wv] = cnt;
+  __syncthreads();
+  int32_t base = 0;
+  for (int q = 0; q < wv; ++q) base += wsum[q];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t um = unique(e);
+    if ((um >> lane) & 1) adj[beg + base + mask_below(um)] = x[e];
+    base += (int32_t)__popcll(um);
+  }
+  if (wv == W - 1 && lane == 0) deg[v] = base;
+}
+
 hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const int64_t* off,
                             const int32_t* len, int32_t* adj, int32_t* deg, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
@@ -819,7 +934,7 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
     case kRow256: k_sort_wave<4><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRow512: k_sort_wave<8><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRow1024: k_sort_wave<16><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
-    case kRowLds4k: k_sort_lds<4096, 256, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds4k: k_sort_block<16, 4, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     case kRowLds8k: k_sort_lds<8192, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     case kRowLds32k: k_sort_lds<kLargeChunk, 1024, true><<<nrows, 1024, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
     default: return hipErrorInvalidValue;

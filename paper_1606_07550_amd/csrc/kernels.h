@@ -11,7 +11,7 @@ enum RowClass : int {
   kRowTrivial = 0,  // len <= 1
   kRow8, kRow16, kRow32, kRow64,  // register bitonic sort by a lane group
   kRow128, kRow256, kRow512, kRow1024,  // register bitonic sort by a wavefront
-  kRowLds4k,   // <= 4096, LDS bitonic sort, 256 threads
+  kRowLds4k,   // <= 4096, register bitonic sort by a block of 4 wavefronts
   kRowLds8k,   // <= 8192, LDS bitonic sort, 512 threads
   kRowLds32k,  // <= 32768, LDS bitonic sort, 1024 threads
   kRowLarge,   // > 32768: chunk sort + merge passes
