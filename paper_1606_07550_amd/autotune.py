@@ -26,10 +26,10 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.j
 
 LIMIT_SETS = [
     [64, 256, 1024, 2048, 4096],
-    [64, 256, 512, 1024, 2048],
     [64, 256, 512, 1024, 4096],
-    [32, 64, 256, 1024, 4096],
-    [64, 128, 512, 1024, 2048],
+    [32, 128, 512, 1024, 4096],
+    [64, 128, 512, 1024, 4096],
+    [32, 128, 256, 1024, 4096],
 ]
 
 

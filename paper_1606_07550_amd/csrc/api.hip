@@ -444,7 +444,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
   static const int32_t lim[kNumBins - 1] = {64, 256, 1024, 2048, 4096};
-  static const int32_t var[kNumBins] = {29, 40, 43, 44, 42, 37};
+  static const int32_t var[kNumBins] = {29, 47, 43, 44, 42, 37};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;

@@ -1328,6 +1328,8 @@ static constexpr VariantInfo kVariants[] = {
     {512, 512, 64, 2048, 1024},   // 43: d+ <= 1024, denser table
     {512, 512, 64, 4096, 2048},   // 44: d+ <= 2048
     {256, 256, 64, 512, 256},     // 45: d+ <= 256, denser table
+    {128, 128, 64, 512, 128},     // 46: d+ <= 128, two wavefronts per node
+    {128, 128, 64, 1024, 256},    // 47: d+ <= 256, two wavefronts per node
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = 36;
@@ -1377,7 +1379,7 @@ static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dc
                                                                         b.dinoff, b.dincol, T);
 }
 
-int count_variant_min_side(int v) { return (v >= 28 && v <= 35) || (v >= 38 && v <= 45); }
+int count_variant_min_side(int v) { return (v >= 28 && v <= 35) || (v >= 38 && v <= 47); }
 
 // Hub bitmaps: one bit per node id, as many bitmaps as fit 256 MB (8 to 256,
 // one per block of the hub variant's grid).
@@ -1435,6 +1437,8 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 43: launch_ms<512, 512, 2048, 1024, true>(b, doff, dcol, T, s); break;
     case 44: launch_ms<512, 512, 4096, 2048, true>(b, doff, dcol, T, s); break;
     case 45: launch_ms<256, 256, 512, 256, true>(b, doff, dcol, T, s); break;
+    case 46: launch_ms<128, 128, 512, 128, true>(b, doff, dcol, T, s); break;
+    case 47: launch_ms<128, 128, 1024, 256, true>(b, doff, dcol, T, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
       break;
