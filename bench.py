@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-graphs leg")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="skip the batched leg's per-graph-launch baseline (for profiling runs)")
     ap.add_argument("--autotune", action="store_true", help="search the batched tuning first (cached per arch)")
     ap.add_argument("--autotune-single", action="store_true",
                     help="search the single-graph bin tuning first (cached per arch/workload)")
@@ -155,6 +157,18 @@ def batched_leg(args, torch, P, N):
     n_tot = int(bt["node_off"][-1])
     alg = 4 * gi.list_elems + 4 * gi.m + 8 * (n_tot + G) + 12 * n_tot
     tri = int(b.out["graph_tri"].sum().item())
+    out = {
+        "workload": f"batched-{G}", "graphs": G, "nodes": n_tot, "pairs": int(bt["edge_off"][-1]), "m": int(gi.m),
+        "triangles": tri,
+        "graphs_per_s": G / (launch_ms * 1e-3), "launch_ms": launch_ms, "edges_per_s": gi.m / (launch_ms * 1e-3),
+        "alg_bytes": alg, "achieved_GBps": alg / (launch_ms * 1e-3) / 1e9,
+        "frac": alg / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "build_ms": build_ms, "tuning": tuning, "grid": info["grid"],
+        "lists": {"merge": info["merge_nodes"], "wave": info["wave_nodes"], "block": info["block_nodes"],
+                  "hub": info["hub_nodes"]},
+    }
+    if args.no_per_graph:
+        return out
     # per-graph launches of the single-graph path on the same graphs
     log("building per-graph handles for the baseline ...")
     graphs = []
@@ -175,18 +189,10 @@ def batched_leg(args, torch, P, N):
     per_graph_ms = 1e3 * (time.perf_counter() - t0)
     tri_pg = sum(int(o["total"].item()) for o in outs)
     del graphs, outs
-    return {
-        "workload": f"batched-{G}", "graphs": G, "nodes": n_tot, "pairs": int(bt["edge_off"][-1]), "m": int(gi.m),
-        "triangles": tri, "triangles_match_per_graph": tri == tri_pg,
-        "graphs_per_s": G / (launch_ms * 1e-3), "launch_ms": launch_ms, "edges_per_s": gi.m / (launch_ms * 1e-3),
-        "alg_bytes": alg, "achieved_GBps": alg / (launch_ms * 1e-3) / 1e9,
-        "frac": alg / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-        "per_graph_launches": {"graphs_per_s": G / (per_graph_ms * 1e-3), "ms": per_graph_ms},
-        "speedup_vs_per_graph": per_graph_ms / launch_ms,
-        "build_ms": build_ms, "tuning": tuning, "grid": info["grid"],
-        "lists": {"merge": info["merge_nodes"], "wave": info["wave_nodes"], "block": info["block_nodes"],
-                  "hub": info["hub_nodes"]},
-    }
+    out["triangles_match_per_graph"] = tri == tri_pg
+    out["per_graph_launches"] = {"graphs_per_s": G / (per_graph_ms * 1e-3), "ms": per_graph_ms}
+    out["speedup_vs_per_graph"] = per_graph_ms / launch_ms
+    return out
 
 
 def run_trace(P, N, g, queries, arrivals, slots, max_batch, budget, tuning=None):
