@@ -1,10 +1,11 @@
-"""CPU oracle: exact triangle counts and clustering coefficients.
+"""CPU oracle: exact triangle counts, clustering coefficients, edge tests.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
 shares no code with the GPU path: the arithmetic lives in the plain C file
 ``tricc_oracle.c`` (node iterator over sorted adjacency lists, FP64 clustering
-coefficients), built by ``build.py`` into ``liboracle.so``.
+coefficients; the edge-existence test as a search in the sorted edge set),
+built by ``build.py`` into ``liboracle.so``.
 
 The definitions it follows are stated at the top of ``tricc_oracle.c``: the
 paper names node clustering coefficient and triangle counting among SNAP's
@@ -35,6 +36,8 @@ def lib():
         L.oracle_induced.restype = ctypes.c_int
         L.oracle_sampled.argtypes = [i64, i64, P, P, i64, P, P, P]
         L.oracle_sampled.restype = ctypes.c_int
+        L.oracle_has_edges.argtypes = [i64, i64, P, P, i64, P, P, P]
+        L.oracle_has_edges.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -97,6 +100,18 @@ def sampled(n, src, dst, samples):
     if rc:
         raise OracleError(f"oracle_sampled failed ({rc})")
     return dict(T=T, deg=deg)
+
+
+def has_edges(n, src, dst, qu, qv):
+    """uint8 per query pair: 1 edge, 0 no edge (self pairs included), 0xFF an
+    id outside [0, n)."""
+    src, dst, qu, qv = _i32(src), _i32(dst), _i32(qu), _i32(qv)
+    assert qu.shape == qv.shape
+    out = np.zeros(qu.size, np.uint8)
+    rc = lib().oracle_has_edges(n, src.size, _ptr(src), _ptr(dst), qu.size, _ptr(qu), _ptr(qv), _ptr(out))
+    if rc:
+        raise OracleError(f"oracle_has_edges failed ({rc})")
+    return out
 
 
 def wtime():

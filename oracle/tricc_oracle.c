@@ -1,5 +1,6 @@
 /*
- * CPU oracle for exact triangle counting and clustering coefficients.
+ * CPU oracle for exact triangle counting, clustering coefficients and
+ * edge-existence tests.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
  * calls this file; only the tests, the smoke check and the benchmark's CPU
@@ -56,11 +57,10 @@ static void og_free(og_graph* g) {
   g->adj = NULL;
 }
 
-/* Symmetrise, drop self loops and duplicate pairs. Returns 0, -1 on an id
- * outside [0,n), -2 on allocation failure. */
-static int og_build(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, og_graph* g) {
-  memset(g, 0, sizeof(*g));
-  g->n = n;
+/* The edge set E as sorted unique keys min << 32 | max (symmetrised, self
+ * loops and duplicate pairs dropped). Returns |E|, -1 on an id outside
+ * [0,n), -2 on allocation failure; *out receives the array (caller frees). */
+static int64_t og_keys(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, uint64_t** out) {
   uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m_raw > 0 ? m_raw : 1));
   if (!key) return -2;
   int64_t k = 0;
@@ -75,6 +75,18 @@ static int og_build(int64_t n, int64_t m_raw, const int32_t* src, const int32_t*
   int64_t m = 0;
   for (int64_t i = 0; i < k; ++i)
     if (i == 0 || key[i] != key[i - 1]) key[m++] = key[i];
+  *out = key;
+  return m;
+}
+
+/* Symmetrise, drop self loops and duplicate pairs. Returns 0, -1 on an id
+ * outside [0,n), -2 on allocation failure. */
+static int og_build(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, og_graph* g) {
+  memset(g, 0, sizeof(*g));
+  g->n = n;
+  uint64_t* key = NULL;
+  const int64_t m = og_keys(n, m_raw, src, dst, &key);
+  if (m < 0) return (int)m;
   g->m = m;
   g->off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   g->adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m > 0 ? 2 * m : 1));
@@ -337,6 +349,39 @@ done:
   free(poff);
   free(pairs);
   return rc;
+}
+
+/*
+ * Edge-existence tests (IsEdge, among the graph methods of Section 4; the
+ * paper tests an edge by searching a node's sorted neighbour vector,
+ * Section 5.1, at O(log deg_max) in its complexity table, and times random
+ * tests in Section 6.2). Written as the definition: out[i] = 1 when
+ * {qu[i], qv[i]} is in E, 0 when it is not (a pair (v, v) never is, E has
+ * no self loops), 0xFF when qu[i] or qv[i] lies outside [0,n); E's sorted
+ * keys are searched with the C library's bsearch. Returns 0, -1 if an input
+ * pair holds an id outside [0,n), -2 on allocation failure.
+ */
+int oracle_has_edges(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst,
+                     int64_t q, const int32_t* qu, const int32_t* qv, uint8_t* out) {
+  uint64_t* key = NULL;
+  const int64_t m = og_keys(n, m_raw, src, dst, &key);
+  if (m < 0) return (int)m;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < q; ++i) {
+    const int64_t u = qu[i], v = qv[i];
+    if (u < 0 || v < 0 || u >= n || v >= n) {
+      out[i] = 0xFF;
+      continue;
+    }
+    if (u == v) {
+      out[i] = 0;
+      continue;
+    }
+    const uint64_t k = ((uint64_t)(u < v ? u : v) << 32) | (uint64_t)(u < v ? v : u);
+    out[i] = bsearch(&k, key, (size_t)m, sizeof(uint64_t), cmp_u64) != NULL;
+  }
+  free(key);
+  return 0;
 }
 
 /* Wall-clock seconds (monotonic), for timing the oracle in the benchmark. */

@@ -361,3 +361,130 @@ def test_unmutated_oracle_passes_battery(tmp_path):
     lib = tmp_path / "liborig.so"
     subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
     assert _pins_pass(str(lib))
+
+
+# ---------------------------------------------------------------------------
+# edge-existence tests (IsEdge): pinned to the dense adjacency matrix built
+# from the raw pairs, to networkx, and to relabelling / noisy-input invariance
+
+def _all_pairs(n, extra=True):
+    """Every ordered pair of ids, plus ids just outside [0, n)."""
+    qu, qv = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    qu, qv = qu.ravel(), qv.ravel()
+    if extra:
+        bad_u = np.array([-1, n, 0, n + 5, -7, 2**31 - 1], np.int64)
+        bad_v = np.array([0, 0, n, 1, -1, 0], np.int64)
+        qu, qv = np.concatenate([qu, bad_u]), np.concatenate([qv, bad_v])
+    return qu.astype(np.int32), qv.astype(np.int32)
+
+
+def _edge_expect(n, s, d, qu, qv):
+    A = adjacency(n, s, d)
+    ok = (qu >= 0) & (qu < n) & (qv >= 0) & (qv < n)
+    out = np.full(qu.size, 0xFF, np.uint8)
+    out[ok] = A[qu[ok], qv[ok]].astype(np.uint8)
+    return out
+
+
+EDGE_CASES = [
+    ("messy_K8", lambda: F.messy(*F.complete(8), seed=3)),
+    ("wheel", lambda: F.wheel(17)),
+    ("star", lambda: F.star(25)),
+    ("rmat6", lambda: I.rmat(6, 8, seed=4)),
+    ("er", lambda: (60, *I.er(60, 400, 5))),
+    ("loops_only", lambda: (5, np.array([0, 1, 2], np.int32), np.array([0, 1, 2], np.int32))),
+    ("no_edges", lambda: (7, np.zeros(0, np.int32), np.zeros(0, np.int32))),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in EDGE_CASES])
+def test_has_edges_against_dense_matrix(name):
+    n, s, d = dict(EDGE_CASES)[name]()
+    qu, qv = _all_pairs(n)
+    out = oracle.has_edges(n, s, d, qu, qv)
+    np.testing.assert_array_equal(out, _edge_expect(n, s, d, qu, qv))
+    # symmetric, never a self pair
+    sq = qu.size - 6
+    M = out[:sq].reshape(n, n)
+    assert np.array_equal(M, M.T) and not M.diagonal().any()
+
+
+def test_has_edges_against_networkx():
+    s, d = I.ba(800, 5, 11)
+    G = nx.Graph()
+    G.add_nodes_from(range(800))
+    G.add_edges_from(zip(s.tolist(), d.tolist()))
+    G.remove_edges_from(nx.selfloop_edges(G))
+    rng = np.random.default_rng(12)
+    qu = rng.integers(0, 800, 20000).astype(np.int32)
+    qv = rng.integers(0, 800, 20000).astype(np.int32)
+    # half of the queries are input pairs, in either direction
+    k = rng.integers(0, s.size, 10000)
+    flip = rng.integers(0, 2, 10000).astype(bool)
+    qu[:10000] = np.where(flip, d[k], s[k])
+    qv[:10000] = np.where(flip, s[k], d[k])
+    out = oracle.has_edges(800, s, d, qu, qv)
+    ref = np.array([G.has_edge(int(a), int(b)) for a, b in zip(qu, qv)], np.uint8)
+    np.testing.assert_array_equal(out, ref)
+    assert out[:10000].all()
+
+
+def test_has_edges_invariant_under_noise_and_relabelling():
+    n, s, d = I.rmat(9, 8, seed=21)
+    rng = np.random.default_rng(22)
+    qu = rng.integers(0, n, 5000).astype(np.int32)
+    qv = rng.integers(0, n, 5000).astype(np.int32)
+    base = oracle.has_edges(n, s, d, qu, qv)
+    n2, s2, d2 = F.messy(n, s, d, seed=23)
+    np.testing.assert_array_equal(oracle.has_edges(n2, s2, d2, qu, qv), base)
+    n3, s3, d3, perm = F.relabel(n, s, d, seed=24)
+    np.testing.assert_array_equal(oracle.has_edges(n3, s3, d3, perm[qu], perm[qv]), base)
+
+
+EDGE_MUTANTS = {
+    "edge_key_not_ordered": ("const uint64_t k = ((uint64_t)(u < v ? u : v) << 32) | (uint64_t)(u < v ? v : u);",
+                             "const uint64_t k = ((uint64_t)u << 32) | (uint64_t)v;"),
+    "edge_range_off_by_one": ("if (u < 0 || v < 0 || u >= n || v >= n) {\n      out[i] = 0xFF;",
+                              "if (u < 0 || v < 0 || u > n || v > n) {\n      out[i] = 0xFF;"),
+    "edge_found_inverted": ("sizeof(uint64_t), cmp_u64) != NULL;", "sizeof(uint64_t), cmp_u64) == NULL;"),
+}
+
+
+def _edge_pins_pass(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.c_void_p
+    L.oracle_has_edges.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int64, P, P, P]
+    for name, make in EDGE_CASES:
+        n, s, d = make()
+        s = np.ascontiguousarray(s, np.int32)
+        d = np.ascontiguousarray(d, np.int32)
+        qu, qv = _all_pairs(n)
+        out = np.zeros(qu.size, np.uint8)
+        if L.oracle_has_edges(n, s.size, s.ctypes.data, d.ctypes.data, qu.size, qu.ctypes.data, qv.ctypes.data,
+                              out.ctypes.data):
+            return False
+        if not np.array_equal(out, _edge_expect(n, s, d, qu, qv)):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", sorted(EDGE_MUTANTS))
+def test_planted_edge_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = EDGE_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    assert not _edge_pins_pass(str(lib)), f"mutant {mutant} passed the pins"
+
+
+def test_unmutated_oracle_passes_edge_battery(tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    lib = tmp_path / "liborig.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
+    assert _edge_pins_pass(str(lib))
