@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="search the batched tuning first (cached per arch)")
     ap.add_argument("--autotune-single", action="store_true",
                     help="search the single-graph bin tuning first (cached per arch/workload)")
+    ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
+    ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
+    ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
     ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
     ap.add_argument("--serve-queries", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=3)
@@ -234,6 +237,71 @@ def run_trace(P, N, g, queries, arrivals, slots, max_batch, budget, tuning=None)
         "edges": int(sum(r["m"] for r in results.values())),
         "edges_per_s": sum(r["m"] for r in results.values()) / (t_end - t_first),
     }
+
+
+def edge_query_leg(args, torch, P, N):
+    """Edge-existence tests as the paper times them (Section 6.2): an ER graph
+    G(n, m) and m tests of random (source, destination) pairs, here the
+    paper's largest configuration (10M nodes, 100M edges). Timed with HIP
+    events around the query kernel on its stream, inputs resident in HBM.
+    Algorithmic bytes per query: the pair (8) and its result (1), both
+    degrees (8), the shorter row's start (8), and 4 bytes per step of the
+    binary search, ceil(log2(d_min + 1)) steps."""
+    from paper_1606_07550_amd import inputs as I
+    dev = torch.device("cuda:0")
+    n, m = args.edge_n, args.edge_m
+    t0 = time.perf_counter()
+    s, d = I.er(n, m, 2016)
+    log(f"edge-existence leg: G(n={n}, m={m}) generated in {time.perf_counter() - t0:.1f}s")
+    g = P.Graph(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2017)
+    qu = torch.randint(0, n, (m,), dtype=torch.int32, device=dev, generator=gen)
+    qv = torch.randint(0, n, (m,), dtype=torch.int32, device=dev, generator=gen)
+    out = torch.empty(m, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        g.has_edges(qu, qv, out=out, stream=stream)
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.has_edges(qu, qv, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    deg = g.arrays()["deg"]
+    dmin = torch.minimum(deg[qu.long()], deg[qv.long()]).double()
+    steps = torch.ceil(torch.log2(dmin + 1.0))
+    alg = float((8 + 1 + 8 + 8) * m + 4.0 * steps.sum().item())
+    positives = int((out == 1).sum().item())
+    # every input pair must test positive (a property that holds at any size)
+    k = min(m, 1 << 22)
+    pos = g.has_edges(torch.from_numpy(s[:k]).to(dev), torch.from_numpy(d[:k]).to(dev))
+    line = {
+        "workload": f"er-n{n}-m{m}", "n": n, "m": int(g.info["m"]), "queries": m, "ms": ms,
+        "queries_per_s": m / (ms * 1e-3), "positives": positives, "input_pairs_all_positive": bool(pos.all().item()),
+        "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, "alg_bytes_per_launch": alg,
+                     "kernel": "k_has_edges", "kernel_ms": ms},
+    }
+    del g, qu, qv, out, deg, dmin, steps, pos
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        import oracle
+        n1, m1 = 1_000_000, 10_000_000
+        s1, d1 = I.er(n1, m1, 2018)
+        rng = np.random.default_rng(2019)
+        q1u = rng.integers(0, n1, m1).astype(np.int32)
+        q1v = rng.integers(0, n1, m1).astype(np.int32)
+        t0 = oracle.wtime()
+        oracle.has_edges(n1, s1, d1, q1u, q1v)
+        sec = oracle.wtime() - t0
+        line["cpu_oracle"] = {"value": m1 / sec, "unit": "queries/s", "kind": "oracle",
+                              "cores": int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0)),
+                              "sample": f"G(n={n1}, m={m1}), {m1} random queries; edge-key sort + searches "
+                                        f"{sec:.2f} s"}
+    return line
 
 
 def serving_leg(args, torch, P, N):
@@ -451,6 +519,9 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         line["batched"] = batched_leg(args, torch, P, N)
+    if not args.no_edge_queries:
+        log("edge-existence leg ...")
+        line["edge_queries"] = edge_query_leg(args, torch, P, N)
     if args.serving:
         log("serving leg ...")
         line["serving"] = serving_leg(args, torch, P, N)

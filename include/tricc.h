@@ -199,6 +199,25 @@ int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream)
 int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_t** d_deg,
                        const int32_t** d_adj, const int64_t** d_doff, const int32_t** d_dcol);
 
+/*
+ * Edge-existence tests on a built graph (IsEdge, among the graph methods of
+ * the paper's Section 4; Section 5.1 tests an edge by searching a node's
+ * sorted neighbour vector, O(log deg_max), and Section 6.2 times random
+ * tests). Query i asks whether {d_u[i], d_v[i]} is an edge of the simple
+ * graph (symmetrised, loops and duplicates dropped); the search runs in
+ * the shorter of the two sorted rows, one query per GPU thread.
+ *   q           number of queries (>= 0)
+ *   d_u, d_v    device int32[q], the caller's; only read
+ *   d_out       device uint8[q], the caller's: 1 = edge, 0 = no edge (a pair
+ *               (v, v) is never an edge), 0xFF = an id outside [0, n)
+ * Asynchronous on `stream`. Reads the graph's rows only, so it may overlap
+ * counts of the same graph. Errors: TRICC_EINVAL for a null handle, q < 0,
+ * or a null array with q > 0; TRICC_EHIP on a launch failure. An invalid id
+ * is reported per query, not as an error.
+ */
+int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, const int32_t* d_v,
+                          uint8_t* d_out, void* stream);
+
 void tricc_graph_free(tricc_graph* g);
 
 /* ---------------------------------------------------------------------------

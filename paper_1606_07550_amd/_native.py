@@ -117,6 +117,7 @@ _SIGS = {
     "tricc_graph_retune": (ctypes.c_int, [_P, ctypes.POINTER(Tuning), _P]),
     "tricc_graph_stats": (ctypes.c_int, [_P, _P]),
     "tricc_count": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_graph_has_edges": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P]),
     "tricc_count_begin": (ctypes.c_int, [_P, _P, _P]),
     "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "tricc_count_finish": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),

@@ -697,6 +697,18 @@ int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_
   return TRICC_OK;
 }
 
+int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, const int32_t* d_v,
+                          uint8_t* d_out, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (q < 0) return fail(TRICC_EINVAL, "negative query count");
+  if (q == 0) return TRICC_OK;
+  if (!d_u || !d_v || !d_out) return fail(TRICC_EINVAL, "null query or output array");
+  const Layout& L = g->L;
+  HIPCHK(launch_has_edges(q, d_u, d_v, g->n, g->at<int64_t>(L.raw_off), g->at<int32_t>(L.deg),
+                          g->at<int32_t>(L.adj), d_out, static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
 void tricc_graph_free(tricc_graph* g) { delete g; }
 
 }  // extern "C"

@@ -183,4 +183,12 @@ hipError_t launch_batch_relabel(int32_t num_graphs, const int64_t* node_off, con
                                 const int32_t* src, const int32_t* dst, int64_t m_raw, int32_t* gsrc,
                                 int32_t* gdst, int32_t* err, hipStream_t s);
 
+// ---- Edge-existence tests ---------------------------------------------------
+// out[i] = 1 if {qu[i], qv[i]} is an edge of the simple graph whose row v is
+// adj[off[v] .. off[v] + deg[v]) ascending, 0 if not (qu[i] == qv[i]
+// included), kEdgeQueryBadId if an id lies outside [0, n).
+constexpr uint8_t kEdgeQueryBadId = 0xFF;
+hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int32_t n, const int64_t* off,
+                            const int32_t* deg, const int32_t* adj, uint8_t* out, hipStream_t s);
+
 }  // namespace tricc

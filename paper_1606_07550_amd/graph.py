@@ -148,6 +148,19 @@ class Graph:
         N.check(rc, "tricc_count")
         return out
 
+    def has_edges(self, u, v, out=None, stream=None):
+        """Edge-existence tests: u, v int32 device tensors of one shape;
+        returns uint8 (1 edge, 0 no edge, 0xFF an id outside [0, n))."""
+        if u.dtype != torch.int32 or v.dtype != torch.int32 or u.shape != v.shape:
+            raise ValueError("u and v must be int32 tensors of one shape")
+        u, v = u.contiguous(), v.contiguous()
+        if out is None:
+            out = torch.empty(u.shape, dtype=torch.uint8, device=u.device)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_has_edges(self._h, u.numel(), _ptr(u), _ptr(v), _ptr(out), _stream_ptr(stream))
+        N.check(rc, "tricc_graph_has_edges")
+        return out
+
     def arrays(self):
         """Device views (slices of the workspace) of the simple graph and DAG:
         off[n+1] int64, deg[n] int32, adj int32, doff[n+1] int64, dcol[m] int32."""

@@ -8,7 +8,9 @@ benchmark times (its cached tuning, or the default):
 - the 4,096-graph batch: sampled graphs against the oracle, every graph's
   total against its per-node counts;
 - serving on R-MAT 22: sampled queries (the largest and random ones) of the
-  20,000-query trace against the oracle's induced-subgraph count.
+  20,000-query trace against the oracle's induced-subgraph count;
+- edge-existence tests on G(n=10M, m=100M): every input pair positive, 2M
+  sampled queries against the oracle.
 """
 import numpy as np
 import pytest
@@ -123,6 +125,27 @@ def test_batch_4096_sampled_graphs_and_totals():
         np.testing.assert_allclose(cc[a:e].astype(np.float64), ref["cc"], rtol=CC_RTOL, atol=0)
         assert abs(gavg[gi] - ref["avg"]) <= CC_RTOL * abs(ref["avg"]), gi
     say(f"batch: {picks.size} graphs against the oracle")
+
+
+def test_edge_queries_er_10m_100m_sampled():
+    """The benchmark's edge-existence configuration, G(n=10M, m=100M) with
+    random queries: every input pair tests positive, and 1M random queries
+    plus 1M input pairs (reversed) match the oracle."""
+    n, m = 10_000_000, 100_000_000
+    s, d = I.er(n, m, 2016)
+    say(f"edge queries: G(n={n}, m={m})")
+    g = P.Graph(n, dev(s), dev(d))
+    pos = g.has_edges(dev(s), dev(d))
+    assert bool(pos.all().item())
+    rng = np.random.default_rng(2020)
+    k = 1_000_000
+    e = rng.integers(0, m, k)
+    qu = np.concatenate([rng.integers(0, n, k), d[e]]).astype(np.int32)
+    qv = np.concatenate([rng.integers(0, n, k), s[e]]).astype(np.int32)
+    got = g.has_edges(dev(qu), dev(qv)).cpu().numpy()
+    say("edge queries: oracle on 2M queries ...")
+    np.testing.assert_array_equal(got, oracle.has_edges(n, s, d, qu, qv))
+    say("edge queries: done")
 
 
 def test_serving_rmat22_sampled_queries():
