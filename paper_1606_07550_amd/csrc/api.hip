@@ -57,7 +57,7 @@ constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, hubmap, total;
+      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, hubmap, rec, total;
   int64_t cls_nblk;
   int64_t max_jobs;
 };
@@ -94,6 +94,7 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.incoff = take(sizeof(int64_t) * (n + 1));
   L.part = take(2 * sizeof(uint32_t) * kPartMaxParts + 2 * sizeof(int64_t) * (kPartMaxParts + 1));
   L.hubmap = take(sizeof(uint32_t) * (size_t)hub_map_words(n) * (size_t)hub_map_slots(n));
+  L.rec = take(sizeof(int32_t) * 2 * n);  // edge-existence records (row start, degree)
   L.total = p;
   return L;
 }
@@ -425,6 +426,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
   HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
   HIPCHK(launch_orient_copy(n, raw_off, len, deg, dplus, part, med_rows, nmed, long_rows, nlong, doff, dcol, dinoff,
                             g->at<int32_t>(L.dincol), s));
+  HIPCHK(launch_edge_records(n, raw_off, deg, g->at<int32_t>(L.rec), s));
   int32_t stats[3];  // max d, max d+, nodes with d >= 2
   if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
   int64_t m = 0;
@@ -704,8 +706,8 @@ int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, c
   if (q == 0) return TRICC_OK;
   if (!d_u || !d_v || !d_out) return fail(TRICC_EINVAL, "null query or output array");
   const Layout& L = g->L;
-  HIPCHK(launch_has_edges(q, d_u, d_v, g->n, g->at<int64_t>(L.raw_off), g->at<int32_t>(L.deg),
-                          g->at<int32_t>(L.adj), d_out, static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_has_edges(q, d_u, d_v, g->n, g->at<int32_t>(L.rec), g->at<int32_t>(L.adj), d_out,
+                          static_cast<hipStream_t>(stream)));
   return TRICC_OK;
 }
 

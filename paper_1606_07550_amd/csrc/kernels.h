@@ -184,11 +184,14 @@ hipError_t launch_batch_relabel(int32_t num_graphs, const int64_t* node_off, con
                                 int32_t* gdst, int32_t* err, hipStream_t s);
 
 // ---- Edge-existence tests ---------------------------------------------------
-// out[i] = 1 if {qu[i], qv[i]} is an edge of the simple graph whose row v is
-// adj[off[v] .. off[v] + deg[v]) ascending, 0 if not (qu[i] == qv[i]
+// Records of the simple graph whose row v is adj[off[v] .. off[v] + deg[v])
+// ascending: rec[2v] = off[v] as uint32 (offsets stay below 2^32), rec[2v+1]
+// = deg[v]; 8-byte aligned, 2n int32.
+hipError_t launch_edge_records(int32_t n, const int64_t* off, const int32_t* deg, int32_t* rec, hipStream_t s);
+// out[i] = 1 if {qu[i], qv[i]} is an edge, 0 if not (qu[i] == qv[i]
 // included), kEdgeQueryBadId if an id lies outside [0, n).
 constexpr uint8_t kEdgeQueryBadId = 0xFF;
-hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int32_t n, const int64_t* off,
-                            const int32_t* deg, const int32_t* adj, uint8_t* out, hipStream_t s);
+hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int32_t n, const int32_t* rec,
+                            const int32_t* adj, uint8_t* out, hipStream_t s);
 
 }  // namespace tricc
