@@ -1,4 +1,5 @@
-"""CPU oracle: exact triangle counts, clustering coefficients, edge tests.
+"""CPU oracle: exact triangle counts, clustering coefficients, edge tests,
+core numbers.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
@@ -38,6 +39,8 @@ def lib():
         L.oracle_sampled.restype = ctypes.c_int
         L.oracle_has_edges.argtypes = [i64, i64, P, P, i64, P, P, P]
         L.oracle_has_edges.restype = ctypes.c_int
+        L.oracle_core.argtypes = [i64, i64, P, P, ctypes.c_int32, P]
+        L.oracle_core.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -111,6 +114,16 @@ def has_edges(n, src, dst, qu, qv):
     rc = lib().oracle_has_edges(n, src.size, _ptr(src), _ptr(dst), qu.size, _ptr(qu), _ptr(qv), _ptr(out))
     if rc:
         raise OracleError(f"oracle_has_edges failed ({rc})")
+    return out
+
+
+def core(n, src, dst, k_stop=-1):
+    """int32 core number of every node (k_stop >= 0: min(core, k_stop))."""
+    src, dst = _i32(src), _i32(dst)
+    out = np.zeros(n, np.int32)
+    rc = lib().oracle_core(n, src.size, _ptr(src), _ptr(dst), k_stop, _ptr(out))
+    if rc:
+        raise OracleError(f"oracle_core failed ({rc})")
     return out
 
 

@@ -1,6 +1,6 @@
 /*
- * CPU oracle for exact triangle counting, clustering coefficients and
- * edge-existence tests.
+ * CPU oracle for exact triangle counting, clustering coefficients,
+ * edge-existence tests and core numbers.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
  * calls this file; only the tests, the smoke check and the benchmark's CPU
@@ -382,6 +382,75 @@ int oracle_has_edges(int64_t n, int64_t m_raw, const int32_t* src, const int32_t
   }
   free(key);
   return 0;
+}
+
+/*
+ * Core numbers (k-core analysis, among the analytics methods of Section 4;
+ * Section 5 names the decomposition algorithm of Batagelj and Zaversnik
+ * and the operations it needs: visit the nodes, read a node's degree,
+ * delete it). The k-core is the largest subgraph whose nodes all have
+ * degree >= k; core[v] is the largest k whose k-core holds v.
+ * The bucket algorithm: nodes sorted by current degree; repeatedly take the
+ * node v of smallest current degree (its core number is that degree) and
+ * lower by one the current degree of every neighbour still above it,
+ * moving that neighbour one bucket down. O(n + m).
+ * k_stop >= 0: core[v] = min(core number, k_stop), so the k_stop-core is
+ * { v : core[v] == k_stop }. Returns 0, -1 on an id outside [0,n), -2 on
+ * allocation failure.
+ */
+int oracle_core(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, int32_t k_stop,
+                int32_t* core) {
+  og_graph g;
+  int rc = og_build(n, m_raw, src, dst, &g);
+  if (rc) return rc;
+  int64_t md = 0;
+  int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* vert = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  for (int64_t v = 0; v < n && d; ++v) {
+    d[v] = g.off[v + 1] - g.off[v];
+    if (d[v] > md) md = d[v];
+  }
+  int64_t* bin = (int64_t*)calloc((size_t)md + 2, sizeof(int64_t)); /* bin[x]: first position of degree x */
+  if (!d || !pos || !vert || !bin) { rc = -2; goto done; }
+  for (int64_t v = 0; v < n; ++v) bin[d[v] + 1]++;
+  for (int64_t x = 0; x <= md; ++x) bin[x + 1] += bin[x];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(md + 1));
+    if (!fill) { rc = -2; goto done; }
+    memcpy(fill, bin, sizeof(int64_t) * (size_t)(md + 1));
+    for (int64_t v = 0; v < n; ++v) {
+      pos[v] = fill[d[v]]++;
+      vert[pos[v]] = v;
+    }
+    free(fill);
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t v = vert[i];
+    for (int64_t p = g.off[v]; p < g.off[v + 1]; ++p) {
+      const int64_t u = g.adj[p];
+      if (d[u] > d[v]) {
+        /* swap u with the first node of its bucket, then shrink the bucket */
+        const int64_t du = d[u], pu = pos[u], pw = bin[du], w = vert[pw];
+        if (u != w) {
+          pos[u] = pw;
+          vert[pw] = u;
+          pos[w] = pu;
+          vert[pu] = w;
+        }
+        bin[du]++;
+        d[u]--;
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) core[v] = (int32_t)(k_stop >= 0 && d[v] > k_stop ? k_stop : d[v]);
+done:
+  free(d);
+  free(pos);
+  free(vert);
+  free(bin);
+  og_free(&g);
+  return rc;
 }
 
 /* Wall-clock seconds (monotonic), for timing the oracle in the benchmark. */

@@ -488,3 +488,131 @@ def test_unmutated_oracle_passes_edge_battery(tmp_path):
     lib = tmp_path / "liborig.so"
     subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
     assert _edge_pins_pass(str(lib))
+
+
+# ---------------------------------------------------------------------------
+# core numbers: pinned to naive repeated deletion per k, to networkx, to the
+# closed forms of regular families, to invariances and to planted mistakes
+
+def naive_core(n, s, d):
+    """core(v) = the largest k such that v survives repeated deletion of the
+    nodes of degree < k (the k-core, computed afresh for every k)."""
+    A = adjacency(n, s, d).astype(bool)
+    core = np.zeros(n, np.int64)
+    k = 0
+    while True:
+        k += 1
+        alive = np.ones(n, bool)
+        while True:
+            deg = (A & alive[None, :]).sum(1) * alive
+            drop = alive & (deg < k)
+            if not drop.any():
+                break
+            alive &= ~drop
+        if not alive.any():
+            return core
+        core[alive] = k
+
+
+CORE_CASES = [
+    ("messy_K9", lambda: F.messy(*F.complete(9), seed=5)),
+    ("wheel_union", lambda: F.disjoint_union(F.wheel(12), F.windmill(5), F.star(6), F.complete(5))),
+    ("rmat7", lambda: I.rmat(7, 8, seed=6)),
+    ("er", lambda: (70, *I.er(70, 500, 7))),
+    ("ba", lambda: (90, *I.ba(90, 4, 8))),
+    ("isolated", lambda: (6, np.array([1, 2], np.int32), np.array([2, 1], np.int32))),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in CORE_CASES])
+def test_core_against_naive_deletion(name):
+    n, s, d = dict(CORE_CASES)[name]()
+    ref = naive_core(n, s, d)
+    np.testing.assert_array_equal(oracle.core(n, s, d), ref)
+    for k in (0, 1, 2, 3, 5):
+        np.testing.assert_array_equal(oracle.core(n, s, d, k_stop=k), np.minimum(ref, k))
+
+
+def test_core_against_networkx():
+    n, s, d = I.rmat(12, 16, seed=9)
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from(zip(s.tolist(), d.tolist()))
+    G.remove_edges_from(nx.selfloop_edges(G))
+    ref = nx.core_number(G)
+    np.testing.assert_array_equal(oracle.core(n, s, d), np.array([ref[v] for v in range(n)]))
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("complete", lambda: (F.complete(11), 10)),
+    ("ring", lambda: (F.ring(30), 2)),
+    ("path", lambda: (F.path(20), 1)),
+    ("star", lambda: (F.star(15), 1)),
+    ("tree", lambda: (F.random_tree(40, 3), 1)),
+    ("grid", lambda: (F.grid(5, 7), 2)),
+    ("bipartite", lambda: (F.complete_bipartite(4, 9), 4)),
+    ("wheel", lambda: (F.wheel(10), 3)),
+    ("windmill", lambda: (F.windmill(6), 2)),
+    ("lattice", lambda: (F.ring_lattice(40, 6), 6)),
+])
+def test_core_closed_forms(case, expect):
+    (n, s, d), k = expect()
+    assert np.all(oracle.core(n, s, d) == k)
+
+
+def test_core_invariant_under_noise_and_relabelling():
+    n, s, d = I.rmat(10, 8, seed=10)
+    base = oracle.core(n, s, d)
+    n2, s2, d2 = F.messy(n, s, d, seed=11)
+    np.testing.assert_array_equal(oracle.core(n2, s2, d2), base)
+    n3, s3, d3, perm = F.relabel(n, s, d, seed=12)
+    got = oracle.core(n3, s3, d3)
+    np.testing.assert_array_equal(got[perm], base)
+
+
+CORE_MUTANTS = {
+    "core_ties_lowered": ("      if (d[u] > d[v]) {", "      if (d[u] >= d[v]) {"),
+    "core_bucket_not_moved": ("        bin[du]++;\n        d[u]--;", "        d[u]--;"),
+    "core_stop_ignored": ("core[v] = (int32_t)(k_stop >= 0 && d[v] > k_stop ? k_stop : d[v]);",
+                          "core[v] = (int32_t)d[v];"),
+}
+
+
+def _core_pins_pass(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.c_void_p
+    L.oracle_core.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int32, P]
+    for name, make in CORE_CASES:
+        n, s, d = make()
+        s = np.ascontiguousarray(s, np.int32)
+        d = np.ascontiguousarray(d, np.int32)
+        ref = naive_core(n, s, d)
+        for k in (-1, 2):
+            out = np.zeros(n, np.int32)
+            if L.oracle_core(n, s.size, s.ctypes.data, d.ctypes.data, k, out.ctypes.data):
+                return False
+            if not np.array_equal(out, ref if k < 0 else np.minimum(ref, k)):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", sorted(CORE_MUTANTS))
+def test_planted_core_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = CORE_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    assert not _core_pins_pass(str(lib)), f"mutant {mutant} passed the pins"
+
+
+def test_unmutated_oracle_passes_core_battery(tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    lib = tmp_path / "liborig.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
+    assert _core_pins_pass(str(lib))
