@@ -218,6 +218,28 @@ int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_
 int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, const int32_t* d_v,
                           uint8_t* d_out, void* stream);
 
+/*
+ * Core numbers (k-core analysis, among the analytics methods of the paper's
+ * Section 4; Section 5 names the Batagelj-Zaversnik decomposition, and
+ * Section 6.3 times the extraction of a 3-core). The k-core is the largest
+ * subgraph whose nodes all have degree >= k; the core number of v is the
+ * largest k whose k-core holds v. Computed on the GPU by level-synchronous
+ * peeling of the simple graph.
+ *   k_stop      < 0: every node's core number; >= 0: min(core number,
+ *               k_stop), so the k_stop-core is { v : d_core[v] == k_stop }
+ *               and the peeling stops at that level
+ *   d_core      device int32[n], the caller's (written)
+ *   d_ws        device scratch of tricc_core_workspace_size(n) bytes, the
+ *               caller's; contents on entry do not matter
+ *   h_max_core  host int32 (may be NULL): the largest value written
+ * Synchronises `stream` (the peeling loop reads the frontier sizes back).
+ * Errors: TRICC_EINVAL for a null handle or null arrays with n > 0,
+ * TRICC_ENOMEM for a short workspace, TRICC_EHIP on a runtime error.
+ */
+int tricc_core_workspace_size(int32_t n, size_t* bytes);
+int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void* d_ws, size_t ws_bytes,
+                     int32_t* h_max_core, void* stream);
+
 void tricc_graph_free(tricc_graph* g);
 
 /* ---------------------------------------------------------------------------

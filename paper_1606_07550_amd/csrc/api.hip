@@ -711,6 +711,69 @@ int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, c
   return TRICC_OK;
 }
 
+int tricc_core_workspace_size(int32_t n, size_t* bytes) {
+  if (n < 0 || !bytes) return fail(TRICC_EINVAL, "bad core workspace query");
+  *bytes = 3 * align_up(sizeof(int32_t) * (size_t)std::max(n, 1)) + 256;
+  return TRICC_OK;
+}
+
+int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void* d_ws, size_t ws_bytes,
+                     int32_t* h_max_core, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  const int32_t n = g->n;
+  size_t need = 0;
+  tricc_core_workspace_size(n, &need);
+  if (n > 0 && (!d_core || !d_ws)) return fail(TRICC_EINVAL, "null core output or workspace");
+  if (n > 0 && ws_bytes < need) return fail(TRICC_ENOMEM, "core workspace of %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t maxc = 0;
+  if (n > 0) {
+    char* w = static_cast<char*>(d_ws);
+    const size_t slice = align_up(sizeof(int32_t) * (size_t)n);
+    int32_t* cur = reinterpret_cast<int32_t*>(w);
+    int32_t* F = reinterpret_cast<int32_t*>(w + slice);
+    int32_t* G = reinterpret_cast<int32_t*>(w + 2 * slice);
+    int32_t* cnt = reinterpret_cast<int32_t*>(w + 3 * slice);
+    const Layout& L = g->L;
+    const int64_t* off = g->at<int64_t>(L.raw_off);
+    const int32_t* deg = g->at<int32_t>(L.deg);
+    const int32_t* adj = g->at<int32_t>(L.adj);
+    HIPCHK(launch_core_init(n, deg, cur, d_core, s));
+    int64_t left = n;
+    int32_t k = 0;
+    int rc;
+    while (left > 0 && (k_stop < 0 || k < k_stop)) {
+      HIPCHK(launch_core_reset(cnt, 0, s));
+      HIPCHK(launch_core_scan(n, k, cur, d_core, F, cnt, s));
+      int32_t c[3];
+      if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
+      if (c[0] == 0) {  // no node at this level: jump to the smallest current degree left
+        if (c[2] == 0x7fffffff) break;
+        k = c[2];
+        continue;
+      }
+      int32_t nf = c[0];
+      while (nf > 0) {
+        left -= nf;
+        HIPCHK(launch_core_reset(cnt, 1, s));
+        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, s));
+        if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
+        std::swap(F, G);
+        nf = c[1];
+      }
+      maxc = k;
+      ++k;
+    }
+    if (k_stop >= 0 && left > 0) {
+      HIPCHK(launch_core_fill(n, k_stop, d_core, s));
+      maxc = k_stop;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (h_max_core) *h_max_core = maxc;
+  return TRICC_OK;
+}
+
 void tricc_graph_free(tricc_graph* g) { delete g; }
 
 }  // extern "C"

@@ -1,0 +1,161 @@
+// Core numbers by parallel level-synchronous peeling (k-core analysis,
+// among the analytics methods of Section 4; Section 5 names the
+// Batagelj-Zaversnik decomposition, which removes nodes in order of their
+// current degree). Here every node whose current degree is at most k is
+// removed together (core number k), and the removals lower their
+// neighbours' current degrees with atomics; a neighbour that falls to k
+// joins the next frontier of the same level. Levels with no node are
+// skipped: a scan that finds no frontier reports the smallest current
+// degree left.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace tricc {
+
+namespace {
+
+constexpr int kCoreNT = 256;
+constexpr int kPeelG = 8;  // lanes per frontier node in the peel
+
+// Appends the items of the lanes with `take` to q[*cnt ..], one atomic per
+// wavefront. All lanes of the wavefront must call it.
+__device__ __forceinline__ void wave_push(bool take, int32_t item, int32_t* __restrict__ q, int32_t* __restrict__ cnt) {
+  const uint64_t m = __ballot(take);
+  if (!m) return;
+  const int leader = __builtin_ctzll(m);
+  int32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(cnt, (int32_t)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  if (take) q[base + mask_below(m)] = item;
+}
+
+__global__ __launch_bounds__(kCoreNT) void k_core_init(int32_t n, const int32_t* __restrict__ deg,
+                                                       int32_t* __restrict__ cur, int32_t* __restrict__ core) {
+  const int64_t stride = (int64_t)gridDim.x * kCoreNT;
+  for (int64_t v = (int64_t)blockIdx.x * kCoreNT + threadIdx.x; v < n; v += stride) {
+    cur[v] = deg[v];
+    core[v] = -1;
+  }
+}
+
+// cnt[0] = frontier size, cnt[1] = next frontier size, cnt[2] = smallest
+// current degree above k among the nodes left.
+__global__ void k_core_reset(int32_t* __restrict__ cnt, int which) {
+  if (threadIdx.x == 0) {
+    if (which == 0) {
+      cnt[0] = 0;
+      cnt[2] = 0x7fffffff;
+    } else {
+      cnt[1] = 0;
+    }
+  }
+}
+
+// Frontier of level k: the nodes left whose current degree is <= k.
+__global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t n, int32_t k, const int32_t* __restrict__ cur,
+                                                       int32_t* __restrict__ core, int32_t* __restrict__ F,
+                                                       int32_t* __restrict__ cnt) {
+  const int64_t stride = (int64_t)gridDim.x * kCoreNT;
+  int32_t mn = 0x7fffffff;
+  for (int64_t b = (int64_t)blockIdx.x * kCoreNT; b < n; b += stride) {  // uniform trip count
+    const int64_t v = b + threadIdx.x;
+    bool take = false;
+    if (v < n && core[v] < 0) {
+      const int32_t c = cur[v];
+      if (c <= k) {
+        core[v] = k;
+        take = true;
+      } else {
+        mn = min(mn, c);
+      }
+    }
+    wave_push(take, (int32_t)v, F, cnt);
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, kWave));
+  if (lane_id() == 0 && mn != 0x7fffffff) atomicMin(cnt + 2, mn);
+}
+
+// Removes the frontier F[0, nf) of level k: every neighbour w still left
+// loses one from its current degree; the one decrement that takes it from
+// k + 1 to k gives it core number k and puts it on the next frontier G.
+__global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict__ F, int32_t nf, int32_t k,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ deg,
+                                                       const int32_t* __restrict__ adj, int32_t* __restrict__ cur,
+                                                       int32_t* __restrict__ core, int32_t* __restrict__ G,
+                                                       int32_t* __restrict__ cnt) {
+  constexpr int GPB = kCoreNT / kPeelG;
+  const int g = threadIdx.x % kPeelG;
+  const int64_t step = (int64_t)gridDim.x * GPB;
+  for (int64_t b = (int64_t)blockIdx.x * GPB; b < nf; b += step) {  // uniform trip count
+    const int64_t fi = b + threadIdx.x / kPeelG;
+    int32_t dv = 0;
+    const int32_t* row = adj;
+    if (fi < nf) {
+      const int32_t v = F[fi];
+      dv = deg[v];
+      row = adj + off[v];
+    }
+    int32_t dmax = dv;  // the wavefront walks its longest row
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
+    for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG) {
+      const int32_t j = j0 + g;
+      bool take = false;
+      int32_t w = 0;
+      if (j < dv) {
+        w = row[j];
+        if (core[w] < 0 && atomicSub(&cur[w], 1) == k + 1) {
+          core[w] = k;
+          take = true;
+        }
+      }
+      wave_push(take, w, G, cnt + 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kCoreNT) void k_core_fill(int32_t n, int32_t k, int32_t* __restrict__ core) {
+  const int64_t stride = (int64_t)gridDim.x * kCoreNT;
+  for (int64_t v = (int64_t)blockIdx.x * kCoreNT + threadIdx.x; v < n; v += stride)
+    if (core[v] < 0) core[v] = k;
+}
+
+unsigned core_grid(int64_t work) {
+  int64_t b = (work + kCoreNT - 1) / kCoreNT;
+  return (unsigned)(b < 1 ? 1 : b > 8192 ? 8192 : b);
+}
+
+}  // namespace
+
+hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t* core, hipStream_t s) {
+  k_core_init<<<core_grid(n), kCoreNT, 0, s>>>(n, deg, cur, core);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s) {
+  k_core_reset<<<1, 64, 0, s>>>(cnt, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_scan(int32_t n, int32_t k, const int32_t* cur, int32_t* core, int32_t* F, int32_t* cnt,
+                            hipStream_t s) {
+  k_core_scan<<<core_grid(n), kCoreNT, 0, s>>>(n, k, cur, core, F, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
+                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt,
+                            hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, k, off, deg, adj, cur, core, G, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s) {
+  k_core_fill<<<core_grid(n), kCoreNT, 0, s>>>(n, k, core);
+  return hipGetLastError();
+}
+
+}  // namespace tricc

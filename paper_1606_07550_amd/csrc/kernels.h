@@ -194,4 +194,17 @@ constexpr uint8_t kEdgeQueryBadId = 0xFF;
 hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int32_t n, const int32_t* rec,
                             const int32_t* adj, uint8_t* out, hipStream_t s);
 
+// ---- Core numbers ------------------------------------------------------------
+// Level-synchronous peeling over the simple graph's rows (row v =
+// adj[off[v] .. off[v] + deg[v])). cur, F, G: int32[n] scratch; core: int32[n]
+// (-1 while a node is left); cnt: int32[3] counters (see core_kernels.hip).
+hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t* core, hipStream_t s);
+hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s);
+hipError_t launch_core_scan(int32_t n, int32_t k, const int32_t* cur, int32_t* core, int32_t* F, int32_t* cnt,
+                            hipStream_t s);
+hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
+                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt,
+                            hipStream_t s);
+hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
+
 }  // namespace tricc

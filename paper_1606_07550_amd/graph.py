@@ -161,6 +161,23 @@ class Graph:
         N.check(rc, "tricc_graph_has_edges")
         return out
 
+    def core(self, k_stop=-1, out=None, stream=None):
+        """Core numbers: (int32 tensor[n], largest value). k_stop >= 0 gives
+        min(core number, k_stop), so the k_stop-core is where it equals
+        k_stop. Synchronises the stream."""
+        n = self.n
+        need = ctypes.c_size_t()
+        N.check(N.lib().tricc_core_workspace_size(n, ctypes.byref(need)), "tricc_core_workspace_size")
+        ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty(max(n, 0), dtype=torch.int32, device=self.device)
+        mx = ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_core(self._h, int(k_stop), _ptr(out) if n > 0 else None, _ptr(ws),
+                                          need.value, ctypes.byref(mx), _stream_ptr(stream))
+        N.check(rc, "tricc_graph_core")
+        return out, int(mx.value)
+
     def arrays(self):
         """Device views (slices of the workspace) of the simple graph and DAG:
         off[n+1] int64, deg[n] int32, adj int32, doff[n+1] int64, dcol[m] int32."""
