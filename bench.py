@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--autotune-single", action="store_true",
                     help="search the single-graph bin tuning first (cached per arch/workload)")
     ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
+    ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
     ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
@@ -237,6 +238,24 @@ def run_trace(P, N, g, queries, arrivals, slots, max_batch, budget, tuning=None)
         "edges": int(sum(r["m"] for r in results.values())),
         "edges_per_s": sum(r["m"] for r in results.values()) / (t_end - t_first),
     }
+
+
+def core_leg(g, torch, m):
+    """Core numbers on the benchmark's graph: the 3-core (the paper times its
+    extraction, Section 6.3) and the full decomposition, each timed on the
+    host around the call (it synchronises: the peeling loop reads frontier
+    sizes back). Rate = undirected edges / time."""
+    out = {}
+    for name, k in (("three_core", 3), ("full", -1)):
+        g.core(k)  # warm-up
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c, mx = g.core(k)
+        sec = (time.perf_counter() - t0) / reps
+        out[name] = {"k_stop": k, "ms": 1e3 * sec, "edges_per_s": m / sec, "max_core": mx,
+                     "nodes_at_max": int((c == mx).sum().item())}
+    return out
 
 
 def edge_query_leg(args, torch, P, N):
@@ -514,6 +533,9 @@ def main():
         "build_ms": 1e3 * build_s / args.steps,
         "probe_copy_GBps": bw,
     }
+    if not args.no_core:
+        log("core-number leg ...")
+        line["core"] = core_leg(g, torch, m)
     del src, dst, ws, T, cc, g
     torch.cuda.empty_cache()
     if not args.no_batched:

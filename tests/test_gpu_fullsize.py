@@ -10,7 +10,8 @@ benchmark times (its cached tuning, or the default):
 - serving on R-MAT 22: sampled queries (the largest and random ones) of the
   20,000-query trace against the oracle's induced-subgraph count;
 - edge-existence tests on G(n=10M, m=100M): every input pair positive, 2M
-  sampled queries against the oracle.
+  sampled queries against the oracle;
+- core numbers on R-MAT 22, every node against the oracle.
 """
 import numpy as np
 import pytest
@@ -146,6 +147,23 @@ def test_edge_queries_er_10m_100m_sampled():
     say("edge queries: oracle on 2M queries ...")
     np.testing.assert_array_equal(got, oracle.has_edges(n, s, d, qu, qv))
     say("edge queries: done")
+
+
+def test_core_numbers_rmat22():
+    """Every node's core number on R-MAT 22 against the oracle's bucket
+    algorithm, and the 3-core (stop level 3)."""
+    n, s, d = I.rmat(22, 16, seed=22)
+    say(f"core numbers: rmat22 n={n}")
+    g = P.Graph(n, dev(s), dev(d))
+    c, mx = g.core()
+    c3, _ = g.core(3)
+    got, got3 = c.cpu().numpy(), c3.cpu().numpy()
+    say("core numbers: oracle ...")
+    ref = oracle.core(n, s, d)
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_array_equal(got3, np.minimum(ref, 3))
+    assert mx == ref.max()
+    say(f"core numbers: max core {mx}")
 
 
 def test_serving_rmat22_sampled_queries():
