@@ -713,7 +713,7 @@ int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, c
 
 int tricc_core_workspace_size(int32_t n, size_t* bytes) {
   if (n < 0 || !bytes) return fail(TRICC_EINVAL, "bad core workspace query");
-  *bytes = 3 * align_up(sizeof(int32_t) * (size_t)std::max(n, 1)) + 256;
+  *bytes = 5 * align_up(sizeof(int32_t) * (size_t)std::max(n, 1)) + 256;
   return TRICC_OK;
 }
 
@@ -733,7 +733,9 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
     int32_t* cur = reinterpret_cast<int32_t*>(w);
     int32_t* F = reinterpret_cast<int32_t*>(w + slice);
     int32_t* G = reinterpret_cast<int32_t*>(w + 2 * slice);
-    int32_t* cnt = reinterpret_cast<int32_t*>(w + 3 * slice);
+    int32_t* A = reinterpret_cast<int32_t*>(w + 3 * slice);  // nodes left, listed by the last scan
+    int32_t* S = reinterpret_cast<int32_t*>(w + 4 * slice);
+    int32_t* cnt = reinterpret_cast<int32_t*>(w + 5 * slice);
     const Layout& L = g->L;
     const int64_t* off = g->at<int64_t>(L.raw_off);
     const int32_t* deg = g->at<int32_t>(L.deg);
@@ -742,11 +744,21 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
     int64_t left = n;
     int32_t k = 0;
     int rc;
+    // scan candidates: all ids, until at most a quarter of the nodes are
+    // left; from then on each scan lists the survivors for the next one
+    const int32_t* cand = nullptr;
+    int32_t ncand = n;
     while (left > 0 && (k_stop < 0 || k < k_stop)) {
+      const bool listing = cand != nullptr || left <= n / 4;
       HIPCHK(launch_core_reset(cnt, 0, s));
-      HIPCHK(launch_core_scan(n, k, cur, d_core, F, cnt, s));
-      int32_t c[3];
+      HIPCHK(launch_core_scan(ncand, cand, k, cur, d_core, F, listing ? S : nullptr, cnt, s));
+      int32_t c[4];
       if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
+      if (listing) {
+        std::swap(A, S);
+        cand = A;
+        ncand = c[3];
+      }
       if (c[0] == 0) {  // no node at this level: jump to the smallest current degree left
         if (c[2] == 0x7fffffff) break;
         k = c[2];

@@ -39,37 +39,48 @@ __global__ __launch_bounds__(kCoreNT) void k_core_init(int32_t n, const int32_t*
 }
 
 // cnt[0] = frontier size, cnt[1] = next frontier size, cnt[2] = smallest
-// current degree above k among the nodes left.
+// current degree above k among the nodes left, cnt[3] = survivors listed.
 __global__ void k_core_reset(int32_t* __restrict__ cnt, int which) {
   if (threadIdx.x == 0) {
     if (which == 0) {
       cnt[0] = 0;
       cnt[2] = 0x7fffffff;
+      cnt[3] = 0;
     } else {
       cnt[1] = 0;
     }
   }
 }
 
-// Frontier of level k: the nodes left whose current degree is <= k.
-__global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t n, int32_t k, const int32_t* __restrict__ cur,
-                                                       int32_t* __restrict__ core, int32_t* __restrict__ F,
+// Frontier of level k: the nodes left whose current degree is <= k, among
+// the listed candidates A[0, na) (A == NULL: all ids 0 .. na-1). The other
+// nodes still left are listed in S (S == NULL: not listed), so later scans
+// only visit them.
+__global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t* __restrict__ A, int32_t k,
+                                                       const int32_t* __restrict__ cur, int32_t* __restrict__ core,
+                                                       int32_t* __restrict__ F, int32_t* __restrict__ S,
                                                        int32_t* __restrict__ cnt) {
   const int64_t stride = (int64_t)gridDim.x * kCoreNT;
   int32_t mn = 0x7fffffff;
-  for (int64_t b = (int64_t)blockIdx.x * kCoreNT; b < n; b += stride) {  // uniform trip count
-    const int64_t v = b + threadIdx.x;
-    bool take = false;
-    if (v < n && core[v] < 0) {
-      const int32_t c = cur[v];
-      if (c <= k) {
-        core[v] = k;
-        take = true;
-      } else {
-        mn = min(mn, c);
+  for (int64_t b = (int64_t)blockIdx.x * kCoreNT; b < na; b += stride) {  // uniform trip count
+    const int64_t i = b + threadIdx.x;
+    bool take = false, keep = false;
+    int32_t v = 0;
+    if (i < na) {
+      v = A ? A[i] : (int32_t)i;
+      if (core[v] < 0) {
+        const int32_t c = cur[v];
+        if (c <= k) {
+          core[v] = k;
+          take = true;
+        } else {
+          mn = min(mn, c);
+          keep = true;
+        }
       }
     }
-    wave_push(take, (int32_t)v, F, cnt);
+    wave_push(take, v, F, cnt);
+    if (S) wave_push(keep, v, S, cnt + 3);
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, kWave));
@@ -139,9 +150,10 @@ hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_core_scan(int32_t n, int32_t k, const int32_t* cur, int32_t* core, int32_t* F, int32_t* cnt,
-                            hipStream_t s) {
-  k_core_scan<<<core_grid(n), kCoreNT, 0, s>>>(n, k, cur, core, F, cnt);
+hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
+                            int32_t* S, int32_t* cnt, hipStream_t s) {
+  if (na <= 0) return hipSuccess;
+  k_core_scan<<<core_grid(na), kCoreNT, 0, s>>>(na, A, k, cur, core, F, S, cnt);
   return hipGetLastError();
 }
 

@@ -196,12 +196,14 @@ hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int
 
 // ---- Core numbers ------------------------------------------------------------
 // Level-synchronous peeling over the simple graph's rows (row v =
-// adj[off[v] .. off[v] + deg[v])). cur, F, G: int32[n] scratch; core: int32[n]
-// (-1 while a node is left); cnt: int32[3] counters (see core_kernels.hip).
+// adj[off[v] .. off[v] + deg[v])). cur, F, G, A, S: int32[n] scratch; core:
+// int32[n] (-1 while a node is left); cnt: int32[4] counters (see
+// core_kernels.hip). The scan visits the listed candidates A[0, na) (A ==
+// NULL: all ids) and lists the other nodes left in S (if not NULL).
 hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t* core, hipStream_t s);
 hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s);
-hipError_t launch_core_scan(int32_t n, int32_t k, const int32_t* cur, int32_t* core, int32_t* F, int32_t* cnt,
-                            hipStream_t s);
+hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
+                            int32_t* S, int32_t* cnt, hipStream_t s);
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
                             const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt,
                             hipStream_t s);
