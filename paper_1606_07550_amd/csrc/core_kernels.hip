@@ -87,6 +87,21 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
   if (lane_id() == 0 && mn != 0x7fffffff) atomicMin(cnt + 2, mn);
 }
 
+// Lowers the current degree of w (if still left) at level k; true for the
+// one decrement that takes it from k + 1 to k (w then has core number k).
+__device__ __forceinline__ bool core_drop(int32_t w, int32_t k, int32_t* __restrict__ cur,
+                                          int32_t* __restrict__ core) {
+  if (core[w] < 0 && atomicSub(&cur[w], 1) == k + 1) {
+    core[w] = k;
+    return true;
+  }
+  return false;
+}
+
+// Rows up to this length are walked by their node's 8-lane group; longer
+// ones by the whole wavefront, one node after the other.
+constexpr int32_t kPeelShort = 64;
+
 // Removes the frontier F[0, nf) of level k: every neighbour w still left
 // loses one from its current degree; the one decrement that takes it from
 // k + 1 to k gives it core number k and puts it on the next frontier G.
@@ -97,32 +112,51 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
                                                        int32_t* __restrict__ core, int32_t* __restrict__ G,
                                                        int32_t* __restrict__ cnt) {
   constexpr int GPB = kCoreNT / kPeelG;
+  const int lane = lane_id();
   const int g = threadIdx.x % kPeelG;
   const int64_t step = (int64_t)gridDim.x * GPB;
   for (int64_t b = (int64_t)blockIdx.x * GPB; b < nf; b += step) {  // uniform trip count
     const int64_t fi = b + threadIdx.x / kPeelG;
     int32_t dv = 0;
-    const int32_t* row = adj;
+    int64_t rb = 0;
     if (fi < nf) {
       const int32_t v = F[fi];
       dv = deg[v];
-      row = adj + off[v];
+      rb = off[v];
     }
-    int32_t dmax = dv;  // the wavefront walks its longest row
+    // short rows: each group walks its own, the wavefront its longest short one
+    const int32_t ds = dv <= kPeelShort ? dv : 0;
+    int32_t dmax = ds;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
     for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG) {
       const int32_t j = j0 + g;
       bool take = false;
       int32_t w = 0;
-      if (j < dv) {
-        w = row[j];
-        if (core[w] < 0 && atomicSub(&cur[w], 1) == k + 1) {
-          core[w] = k;
-          take = true;
-        }
+      if (j < ds) {
+        w = adj[rb + j];
+        take = core_drop(w, k, cur, core);
       }
       wave_push(take, w, G, cnt + 1);
+    }
+    // long rows: the whole wavefront on each in turn (group leaders' bits)
+    uint64_t longs = __ballot(g == 0 && dv > kPeelShort);
+    while (longs) {
+      const int src = __builtin_ctzll(longs);
+      longs &= longs - 1;
+      const int32_t d = __shfl(dv, src, kWave);
+      const int64_t r = ((int64_t)__shfl((int32_t)(rb >> 32), src, kWave) << 32) |
+                        (uint32_t)__shfl((int32_t)rb, src, kWave);
+      for (int32_t j0 = 0; j0 < d; j0 += kWave) {
+        const int32_t j = j0 + lane;
+        bool take = false;
+        int32_t w = 0;
+        if (j < d) {
+          w = adj[r + j];
+          take = core_drop(w, k, cur, core);
+        }
+        wave_push(take, w, G, cnt + 1);
+      }
     }
   }
 }
