@@ -1,5 +1,5 @@
 """CPU oracle: exact triangle counts, clustering coefficients, edge tests,
-core numbers.
+core numbers, 4-clique counts.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
@@ -41,6 +41,8 @@ def lib():
         L.oracle_has_edges.restype = ctypes.c_int
         L.oracle_core.argtypes = [i64, i64, P, P, ctypes.c_int32, P]
         L.oracle_core.restype = ctypes.c_int
+        L.oracle_k4.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, P]
+        L.oracle_k4.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -125,6 +127,16 @@ def core(n, src, dst, k_stop=-1):
     if rc:
         raise OracleError(f"oracle_core failed ({rc})")
     return out
+
+
+def k4(n, src, dst, order=0, threads=0):
+    """Number of 4-cliques of the simple graph."""
+    src, dst = _i32(src), _i32(dst)
+    total = ctypes.c_uint64()
+    rc = lib().oracle_k4(n, src.size, _ptr(src), _ptr(dst), order, threads, ctypes.byref(total))
+    if rc:
+        raise OracleError(f"oracle_k4 failed ({rc})")
+    return int(total.value)
 
 
 def wtime():

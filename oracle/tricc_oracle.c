@@ -1,6 +1,6 @@
 /*
  * CPU oracle for exact triangle counting, clustering coefficients,
- * edge-existence tests and core numbers.
+ * edge-existence tests, core numbers and 4-clique counts.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
  * calls this file; only the tests, the smoke check and the benchmark's CPU
@@ -451,6 +451,65 @@ done:
   free(bin);
   og_free(&g);
   return rc;
+}
+
+/*
+ * Number of 4-cliques (clique detection, among the graph-motif methods of
+ * Section 4; the same counting of small complete subgraphs as the
+ * triangles above, one size up). Each 4-clique {u, w, x, z} with
+ * rank(u) < rank(w) < rank(x) < rank(z) is met once, at u: w is a
+ * neighbour of u ranked above it, x a neighbour of w ranked above w and
+ * marked as a neighbour of u, z a neighbour of x ranked above x and marked
+ * as a common neighbour of u and w. order_mode as for oracle_count.
+ * Returns 0, -1 on an id outside [0,n), -2 on allocation failure.
+ */
+int oracle_k4(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, int order_mode, int nthreads,
+              uint64_t* total) {
+  og_graph g;
+  int rc = og_build(n, m_raw, src, dst, &g);
+  if (rc) return rc;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  uint64_t count = 0;
+  int failed = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : count)
+  {
+    int64_t* m1 = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t)); /* neighbour of u above it */
+    int64_t* m2 = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t)); /* common with w */
+    if (!m1 || !m2) {
+#pragma omp atomic write
+      failed = 1;
+    } else {
+      int64_t stamp = 0;
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t u = 0; u < n; ++u) {
+        for (int64_t p = g.off[u]; p < g.off[u + 1]; ++p)
+          if (og_below(&g, order_mode, u, g.adj[p])) m1[g.adj[p]] = u + 1;
+        for (int64_t p = g.off[u]; p < g.off[u + 1]; ++p) {
+          const int64_t w = g.adj[p];
+          if (!og_below(&g, order_mode, u, w)) continue;
+          ++stamp;
+          for (int64_t q = g.off[w]; q < g.off[w + 1]; ++q) {
+            const int64_t x = g.adj[q];
+            if (og_below(&g, order_mode, w, x) && m1[x] == u + 1) m2[x] = stamp;
+          }
+          for (int64_t q = g.off[w]; q < g.off[w + 1]; ++q) {
+            const int64_t x = g.adj[q];
+            if (m2[x] != stamp) continue;
+            for (int64_t r = g.off[x]; r < g.off[x + 1]; ++r) {
+              const int64_t z = g.adj[r];
+              if (og_below(&g, order_mode, x, z) && m2[z] == stamp) count += 1;
+            }
+          }
+        }
+      }
+    }
+    free(m1);
+    free(m2);
+  }
+  og_free(&g);
+  if (failed) return -2;
+  *total = count;
+  return 0;
 }
 
 /* Wall-clock seconds (monotonic), for timing the oracle in the benchmark. */

@@ -616,3 +616,110 @@ def test_unmutated_oracle_passes_core_battery(tmp_path):
     lib = tmp_path / "liborig.so"
     subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
     assert _core_pins_pass(str(lib))
+
+
+# ---------------------------------------------------------------------------
+# 4-clique counts: pinned to brute force over all 4-subsets, to networkx's
+# clique enumeration, to closed forms, invariances and planted mistakes
+
+def brute_k4(n, s, d):
+    A = adjacency(n, s, d).astype(bool)
+    return sum(1 for q in itertools.combinations(range(n), 4)
+               if all(A[a, b] for a, b in itertools.combinations(q, 2)))
+
+
+K4_CASES = [
+    ("messy_K9", lambda: F.messy(*F.complete(9), seed=5)),
+    ("rmat5", lambda: I.rmat(5, 8, seed=6)),
+    ("er", lambda: (24, *I.er(24, 150, 7))),
+    ("ba", lambda: (26, *I.ba(26, 5, 8))),
+    ("union", lambda: F.disjoint_union(F.complete(6), F.wheel(3), F.ring_lattice(12, 6), F.windmill(3))),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in K4_CASES])
+def test_k4_against_brute_force(name):
+    n, s, d = dict(K4_CASES)[name]()
+    ref = brute_k4(n, s, d)
+    assert oracle.k4(n, s, d, order=0) == ref
+    assert oracle.k4(n, s, d, order=1) == ref
+
+
+def test_k4_against_networkx():
+    for n, s, d in (I.rmat(9, 8, seed=13), (2000, *I.ba(2000, 5, 14))):
+        G = nx.Graph()
+        G.add_edges_from(zip(s.tolist(), d.tolist()))
+        G.remove_edges_from(nx.selfloop_edges(G))
+        ref = sum(1 for c in nx.enumerate_all_cliques(G) if len(c) == 4)
+        assert oracle.k4(n, s, d) == ref
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("complete", lambda: (F.complete(13), 715)),
+    ("k4_wheel", lambda: (F.wheel(3), 1)),
+    ("wheel", lambda: (F.wheel(9), 0)),
+    ("bipartite", lambda: (F.complete_bipartite(5, 6), 0)),
+    ("windmill", lambda: (F.windmill(7), 0)),
+    ("lattice4", lambda: (F.ring_lattice(40, 4), 0)),
+    ("lattice6", lambda: (F.ring_lattice(40, 6), 40)),
+])
+def test_k4_closed_forms(case, expect):
+    (n, s, d), k = expect()
+    assert oracle.k4(n, s, d) == k
+
+
+def test_k4_invariant_under_noise_and_relabelling():
+    n, s, d = I.rmat(9, 8, seed=15)
+    base = oracle.k4(n, s, d)
+    assert oracle.k4(*F.messy(n, s, d, seed=16)) == base
+    n3, s3, d3, _ = F.relabel(n, s, d, seed=17)
+    assert oracle.k4(n3, s3, d3) == base
+
+
+K4_MUTANTS = {
+    "k4_no_rank_on_x": ("if (og_below(&g, order_mode, w, x) && m1[x] == u + 1) m2[x] = stamp;",
+                        "if (m1[x] == u + 1) m2[x] = stamp;"),
+    "k4_last_mark_wrong": ("if (og_below(&g, order_mode, x, z) && m2[z] == stamp) count += 1;",
+                           "if (og_below(&g, order_mode, x, z) && m1[z] == u + 1) count += 1;"),
+    "k4_stamp_not_advanced": ("          ++stamp;\n", "\n"),
+}
+
+
+def _k4_pins_pass(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.c_void_p
+    L.oracle_k4.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_int, P]
+    for name, make in K4_CASES:
+        n, s, d = make()
+        s = np.ascontiguousarray(s, np.int32)
+        d = np.ascontiguousarray(d, np.int32)
+        ref = brute_k4(n, s, d)
+        for order in (0, 1):
+            tot = ctypes.c_uint64()
+            if L.oracle_k4(n, s.size, s.ctypes.data, d.ctypes.data, order, 1, ctypes.byref(tot)):
+                return False
+            if tot.value != ref:
+                return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", sorted(K4_MUTANTS))
+def test_planted_k4_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = K4_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    assert not _k4_pins_pass(str(lib)), f"mutant {mutant} passed the pins"
+
+
+def test_unmutated_oracle_passes_k4_battery(tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    lib = tmp_path / "liborig.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
+    assert _k4_pins_pass(str(lib))
