@@ -240,6 +240,18 @@ int tricc_core_workspace_size(int32_t n, size_t* bytes);
 int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void* d_ws, size_t ws_bytes,
                      int32_t* h_max_core, void* stream);
 
+/*
+ * Number of 4-cliques (clique detection, among the graph-motif methods of
+ * the paper's Section 4: the triangle count one size up). Counted on the
+ * degree-ordered DAG: a 4-clique u < w < x < z (by rank) is met once, at u,
+ * from C = N+(u) ∩ N+(w) and the edges x -> z inside C.
+ *   d_total   device uint64[1], the caller's (overwritten)
+ * Asynchronous on `stream`. Errors: TRICC_EINVAL for a null handle or
+ * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 2048 (the LDS
+ * capacity of one node's list).
+ */
+int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream);
+
 void tricc_graph_free(tricc_graph* g);
 
 /* ---------------------------------------------------------------------------

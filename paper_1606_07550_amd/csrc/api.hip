@@ -786,6 +786,18 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
   return TRICC_OK;
 }
 
+int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (!d_total) return fail(TRICC_EINVAL, "null output");
+  if (g->info.max_outdeg > kK4Cap)
+    return fail(TRICC_EOVERFLOW, "4-clique counting takes out-degrees up to %d (this graph: %lld)", kK4Cap,
+                (long long)g->info.max_outdeg);
+  const Layout& L = g->L;
+  HIPCHK(launch_count_k4(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
+                         reinterpret_cast<unsigned long long*>(d_total), static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
 void tricc_graph_free(tricc_graph* g) { delete g; }
 
 }  // extern "C"

@@ -178,6 +178,15 @@ class Graph:
         N.check(rc, "tricc_graph_core")
         return out, int(mx.value)
 
+    def count_k4(self, out=None, stream=None):
+        """Number of 4-cliques: uint64[1] (as an int64 tensor) on the device."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_count_k4(self._h, _ptr(out), _stream_ptr(stream))
+        N.check(rc, "tricc_graph_count_k4")
+        return out
+
     def arrays(self):
         """Device views (slices of the workspace) of the simple graph and DAG:
         off[n+1] int64, deg[n] int32, adj int32, doff[n+1] int64, dcol[m] int32."""
