@@ -54,6 +54,8 @@ def parse():
                     help="search the single-graph bin tuning first (cached per arch/workload)")
     ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
     ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
+    ap.add_argument("--no-k4", action="store_true", help="skip the 4-clique leg")
+    ap.add_argument("--k4-scale", type=int, default=20, help="4-clique leg: R-MAT scale")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
     ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
@@ -256,6 +258,45 @@ def core_leg(g, torch, m):
         out[name] = {"k_stop": k, "ms": 1e3 * sec, "edges_per_s": m / sec, "max_core": mx,
                      "nodes_at_max": int((c == mx).sum().item())}
     return out
+
+
+def k4_leg(args, torch, P, N):
+    """4-clique count on R-MAT (same generator parameters as the main
+    workload) at --k4-scale, timed with HIP events around the kernel on its
+    stream; rate = undirected edges / time. The CPU oracle's rate is taken
+    on R-MAT 16."""
+    from paper_1606_07550_amd import inputs as I
+    dev = torch.device("cuda:0")
+    sc = args.k4_scale
+    n, s, d = I.rmat(sc, 16, seed=sc)
+    g = P.Graph(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev))
+    m = int(g.info["m"])
+    out = torch.empty(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    g.count_k4(out=out, stream=stream)
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.count_k4(out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    line = {"workload": f"rmat{sc}", "n": n, "m": m, "max_outdeg": int(g.info["max_outdeg"]),
+            "cliques4": int(out.cpu().numpy().view(np.uint64)[0]), "ms": ms, "edges_per_s": m / (ms * 1e-3)}
+    del g, out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        n1, s1, d1 = I.rmat(16, 16, seed=16)
+        t0 = time.perf_counter()
+        c1 = oracle.k4(n1, s1, d1, order=1, threads=threads)
+        sec = time.perf_counter() - t0
+        m1 = oracle.count(n1, s1, d1)["m"]
+        line["cpu_oracle"] = {"value": m1 / sec, "unit": "edges/s", "kind": "oracle", "cores": threads,
+                              "sample": f"R-MAT scale 16 (m={m1}, {c1} 4-cliques), build + count {sec:.2f} s"}
+    return line
 
 
 def edge_query_leg(args, torch, P, N):
@@ -541,6 +582,9 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         line["batched"] = batched_leg(args, torch, P, N)
+    if not args.no_k4:
+        log("4-clique leg ...")
+        line["k4"] = k4_leg(args, torch, P, N)
     if not args.no_edge_queries:
         log("edge-existence leg ...")
         line["edge_queries"] = edge_query_leg(args, torch, P, N)
