@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
     ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
     ap.add_argument("--no-k4", action="store_true", help="skip the 4-clique leg")
+    ap.add_argument("--no-gen", action="store_true", help="skip the device R-MAT generator leg")
     ap.add_argument("--k4-scale", type=int, default=20, help="4-clique leg: R-MAT scale")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
@@ -258,6 +259,54 @@ def core_leg(g, torch, m):
         out[name] = {"k_stop": k, "ms": 1e3 * sec, "edges_per_s": m / sec, "max_core": mx,
                      "nodes_at_max": int((c == mx).sum().item())}
     return out
+
+
+def gen_leg(args, torch, P, N):
+    """Device R-MAT generator on the benchmark's own graph (R-MAT 24, edge
+    factor 16, relabelled), timed with HIP events around the kernel on its
+    stream, against the host input generator that the other legs use (same
+    edges, bit for bit) and the oracle's R-MAT on a 2M-edge sample."""
+    from paper_1606_07550_amd import inputs as I
+    from paper_1606_07550_amd.generators import rmat
+    dev = torch.device("cuda:0")
+    sc = 24
+    perm_h = I.rmat_perm(sc, sc)
+    perm = torch.from_numpy(perm_h).to(dev)
+    m = 16 << sc
+    out = (torch.empty(m, dtype=torch.int32, device=dev), torch.empty(m, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+    rmat(sc, seed=sc, perm=perm, out=out, stream=stream)
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        rmat(sc, seed=sc, perm=perm, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    _, hs, hd = I.rmat(sc, 16, seed=sc, threads=threads)
+    host_s = time.perf_counter() - t0
+    sample = np.random.default_rng(1).integers(0, m, 4096)
+    ti = torch.from_numpy(sample).to(dev)
+    same = bool(np.array_equal(out[0][ti].cpu().numpy(), hs[sample])
+                and np.array_equal(out[1][ti].cpu().numpy(), hd[sample]))
+    line = {"workload": f"rmat{sc}-ef16", "edges": m, "ms": ms, "edges_per_s": m / (ms * 1e-3),
+            "write_GBps": 8 * m / (ms * 1e-3) / 1e9, "host_generator": {"s": host_s, "threads": threads,
+                                                                        "edges_per_s": m / host_s},
+            "sampled_edges_equal_host": same}
+    del out, perm
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 2_000_000
+        t0 = time.perf_counter()
+        oracle.rmat(sc, k, seed=sc, perm=perm_h)
+        sec = time.perf_counter() - t0
+        line["cpu_oracle"] = {"value": k / sec, "unit": "edges/s", "kind": "oracle", "cores": 1,
+                              "sample": f"first {k} edges of R-MAT 24, relabelled, {sec:.2f} s"}
+    return line
 
 
 def k4_leg(args, torch, P, N):
@@ -582,6 +631,9 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         line["batched"] = batched_leg(args, torch, P, N)
+    if not args.no_gen:
+        log("generator leg ...")
+        line["generator"] = gen_leg(args, torch, P, N)
     if not args.no_k4:
         log("4-clique leg ...")
         line["k4"] = k4_leg(args, torch, P, N)

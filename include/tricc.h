@@ -192,6 +192,31 @@ int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node
  * bandwidth and for calibrating memory-traffic counters. Asynchronous. */
 int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
 
+/*
+ * R-MAT edge generator on the device (the paper's table of graph
+ * generators, Section 4; R-MAT of Chakrabarti, Zhan and Faloutsos, SDM
+ * 2004). Edge e (0 <= e < m) of a graph with n = 2^scale ids is `scale`
+ * quadrant choices, most significant bit first. At level l, with
+ * k = 2 (e * scale + l) and word(c) = SplitMix64 output of
+ * S + c * 0x9E3779B97F4A7C15, S = SplitMix64 output of
+ * seed + 12 * 0x9E3779B97F4A7C15:
+ *   p_q = w_q * (1 + noise * (2 h_q / 65535 - 1)), h_q = bits 16q..16q+15
+ *         of word(k + 1), (w_0..w_3) = (a, b, c, d)            (FP64)
+ *   x   = (word(k + 2) >> 11) * 2^-53 * (p_0 + p_1 + p_2 + p_3)
+ *   q   = first q with x < p_0 + .. + p_q (else 3); src bit q >> 1, dst bit q & 1
+ * every FP64 operation separately rounded, sums left to right, so the
+ * edges are exact bit patterns, independent of the launch. Self loops and
+ * duplicate pairs are kept (the graph build removes them).
+ *   d_perm   device int32[n] (may be NULL): relabelling, both ends
+ *            id -> d_perm[id]; must hold ids in [0, n) (not checked)
+ *   d_src, d_dst  device int32[m], the caller's (written)
+ * Asynchronous on `stream`. Errors: TRICC_EINVAL for scale outside [1, 30],
+ * m < 0, weights negative, not finite or summing to 0, noise outside
+ * [0, 1], null outputs with m > 0.
+ */
+int tricc_gen_rmat(int32_t scale, int64_t m, double a, double b, double c, double d, double noise, uint64_t seed,
+                   const int32_t* d_perm, int32_t* d_src, int32_t* d_dst, void* stream);
+
 /* Device views of the graph held in the workspace, for inspection:
  * row v of the simple graph is d_adj[d_off[v] .. d_off[v] + d_deg[v]) in
  * ascending id order; the DAG out-list of v is d_dcol[d_doff[v] ..

@@ -1,5 +1,5 @@
 """CPU oracle: exact triangle counts, clustering coefficients, edge tests,
-core numbers, 4-clique counts.
+core numbers, 4-clique counts, R-MAT edges.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
@@ -43,6 +43,11 @@ def lib():
         L.oracle_core.restype = ctypes.c_int
         L.oracle_k4.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, P]
         L.oracle_k4.restype = ctypes.c_int
+        L.oracle_splitmix64.argtypes = [ctypes.c_uint64, i64, P]
+        L.oracle_splitmix64.restype = ctypes.c_int
+        d = ctypes.c_double
+        L.oracle_rmat.argtypes = [ctypes.c_int, d, d, d, d, d, ctypes.c_uint64, i64, P, P, P, P]
+        L.oracle_rmat.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -137,6 +142,34 @@ def k4(n, src, dst, order=0, threads=0):
     if rc:
         raise OracleError(f"oracle_k4 failed ({rc})")
     return int(total.value)
+
+
+def splitmix64(state, count):
+    """The first ``count`` SplitMix64 outputs from ``state`` (uint64 array)."""
+    out = np.zeros(count, np.uint64)
+    lib().oracle_splitmix64(state, count, _ptr(out))
+    return out
+
+
+def rmat(scale, m=None, abcd=(0.57, 0.19, 0.19, 0.05), noise=0.1, seed=0, idx=None, perm=None):
+    """R-MAT edges (src, dst int32) of the GPU generator's definition: edges
+    0..m-1, or the edges numbered in ``idx``; ``perm`` relabels both ends."""
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        k = idx.size
+    else:
+        k = int(m)
+    if perm is not None:
+        perm = _i32(perm)
+        assert perm.size == 1 << scale
+    src = np.zeros(k, np.int32)
+    dst = np.zeros(k, np.int32)
+    a, b, c, d = abcd
+    rc = lib().oracle_rmat(scale, a, b, c, d, noise, seed, k, _ptr(idx) if idx is not None else None,
+                           _ptr(perm) if perm is not None else None, _ptr(src), _ptr(dst))
+    if rc:
+        raise OracleError(f"oracle_rmat failed ({rc})")
+    return src, dst
 
 
 def wtime():

@@ -1,6 +1,6 @@
 /*
  * CPU oracle for exact triangle counting, clustering coefficients,
- * edge-existence tests, core numbers and 4-clique counts.
+ * edge-existence tests, core numbers, 4-clique counts and R-MAT edges.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
  * calls this file; only the tests, the smoke check and the benchmark's CPU
@@ -509,6 +509,82 @@ int oracle_k4(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, 
   og_free(&g);
   if (failed) return -2;
   *total = count;
+  return 0;
+}
+
+/*
+ * SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the state advances by the 64-bit golden-ratio
+ * increment, and each output is the state passed through two xor-shift /
+ * multiply steps and a final xor-shift.
+ */
+static const uint64_t sm_gamma = 0x9E3779B97F4A7C15ULL;
+
+static uint64_t sm_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* The first `count` outputs of SplitMix64 started from state `state`. */
+int oracle_splitmix64(uint64_t state, int64_t count, uint64_t* out) {
+  for (int64_t i = 0; i < count; ++i) {
+    state += sm_gamma;
+    out[i] = sm_out(state);
+  }
+  return 0;
+}
+
+/*
+ * R-MAT edges (the paper's table of graph generators, Section 4, cites
+ * Chakrabarti, Zhan and Faloutsos, SDM 2004), with per-level noise on the
+ * quadrant probabilities, as defined for the GPU generator:
+ *
+ *   word(c)  = c-th output (c = 1, 2, ...) of SplitMix64 started from state
+ *              S = out(seed + gamma * 12), i.e. out(S + gamma * c)   (stream 11)
+ *   edge e   = `scale` quadrant choices, most significant bit first; at level
+ *              l, with k = 2 (e * scale + l):
+ *     h_q    = bits 16q .. 16q+15 of word(k + 1), q = 0..3
+ *     p_q    = base_q * (1 + noise * (2 h_q / 65535 - 1))          (FP64)
+ *     x      = (word(k + 2) >> 11) * 2^-53 * (p_0 + p_1 + p_2 + p_3)
+ *     q      = first q in 0..2 with x < p_0 + ... + p_q, else 3
+ *     src bit = q >> 1, dst bit = q & 1   (a = (0,0), b = (0,1), c = (1,0), d = (1,1))
+ *   perm     = optional relabelling: both ends id -> perm[id].
+ *
+ * Self loops and duplicate pairs are kept. The edges are the k indices in
+ * idx (all of 0..k-1 when idx is NULL). Every FP64 operation is a separately
+ * rounded IEEE operation in the order written above (sums left to right).
+ * Returns 0, -1 on a bad scale.
+ */
+int oracle_rmat(int scale, double a, double b, double c, double d, double noise, uint64_t seed, int64_t k,
+                const int64_t* idx, const int32_t* perm, int32_t* src, int32_t* dst) {
+  if (scale < 1 || scale > 30) return -1;
+  const double base[4] = {a, b, c, d};
+  const uint64_t S = sm_out(seed + sm_gamma * 12u);
+  for (int64_t i = 0; i < k; ++i) {
+    const uint64_t e = idx ? (uint64_t)idx[i] : (uint64_t)i;
+    uint32_t u = 0, v = 0;
+    for (int l = 0; l < scale; ++l) {
+      const uint64_t kk = 2u * (e * (uint64_t)scale + (uint64_t)l);
+      const uint64_t w1 = sm_out(S + sm_gamma * (kk + 1u));
+      const uint64_t w2 = sm_out(S + sm_gamma * (kk + 2u));
+      double p[4];
+      for (int q = 0; q < 4; ++q) {
+        const double h = (double)((w1 >> (16 * q)) & 0xFFFFu);
+        p[q] = base[q] * (1.0 + noise * (2.0 * h / 65535.0 - 1.0));
+      }
+      const double x = (double)(w2 >> 11) * 0x1.0p-53 * (((p[0] + p[1]) + p[2]) + p[3]);
+      int q;
+      if (x < p[0]) q = 0;
+      else if (x < p[0] + p[1]) q = 1;
+      else if (x < (p[0] + p[1]) + p[2]) q = 2;
+      else q = 3;
+      u = (u << 1) | (uint32_t)(q >> 1);
+      v = (v << 1) | (uint32_t)(q & 1);
+    }
+    src[i] = perm ? perm[u] : (int32_t)u;
+    dst[i] = perm ? perm[v] : (int32_t)v;
+  }
   return 0;
 }
 

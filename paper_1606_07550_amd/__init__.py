@@ -11,3 +11,4 @@ from .graph import Graph, count, default_tuning, variant_capacity, variant_count
 from ._native import TriccError  # noqa: F401
 from .batch import Batch, batch_workspace_size, default_batch_tuning  # noqa: F401
 from .serve import Server  # noqa: F401
+from . import generators  # noqa: F401

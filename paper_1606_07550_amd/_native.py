@@ -126,6 +126,8 @@ _SIGS = {
     "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "tricc_count_finish": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "tricc_probe_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "tricc_gen_rmat": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_double] * 5
+                       + [ctypes.c_uint64, _P, _P, _P, _P]),
     "tricc_graph_arrays": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                           ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "tricc_graph_free": (None, [_P]),

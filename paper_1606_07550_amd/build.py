@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libtricc.so")
 ARCH = os.environ.get("TRICC_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["api.hip", "build_kernels.hip", "clique_kernels.hip", "core_kernels.hip", "count_kernels.hip",
-               "query_kernels.hip", "serve_kernels.hip", "serve_api.hip"]
+               "gen_kernels.hip", "query_kernels.hip", "serve_kernels.hip", "serve_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

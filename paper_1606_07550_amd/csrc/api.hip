@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -685,6 +686,23 @@ int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream)
     return fail(TRICC_EINVAL, "probe copy needs 16-byte multiples and alignment");
   if (bytes && (!d_dst || !d_src)) return fail(TRICC_EINVAL, "null pointer");
   HIPCHK(launch_probe_copy(d_dst, d_src, bytes, static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
+int tricc_gen_rmat(int32_t scale, int64_t m, double a, double b, double c, double d, double noise, uint64_t seed,
+                   const int32_t* d_perm, int32_t* d_src, int32_t* d_dst, void* stream) {
+  if (scale < 1 || scale > 30) return fail(TRICC_EINVAL, "R-MAT scale must be in [1, 30]");
+  if (m < 0) return fail(TRICC_EINVAL, "negative edge count");
+  const double abcd[4] = {a, b, c, d};
+  double sum = 0.0;
+  for (double w : abcd) {
+    if (!std::isfinite(w) || w < 0.0) return fail(TRICC_EINVAL, "R-MAT weights must be finite and >= 0");
+    sum += w;
+  }
+  if (!(sum > 0.0)) return fail(TRICC_EINVAL, "R-MAT weights sum to zero");
+  if (!(noise >= 0.0 && noise <= 1.0)) return fail(TRICC_EINVAL, "R-MAT noise must be in [0, 1]");
+  if (m > 0 && (!d_src || !d_dst)) return fail(TRICC_EINVAL, "null pointer");
+  HIPCHK(launch_gen_rmat(m, scale, abcd, noise, seed, d_perm, d_src, d_dst, static_cast<hipStream_t>(stream)));
   return TRICC_OK;
 }
 

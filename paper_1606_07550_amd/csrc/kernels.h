@@ -216,4 +216,10 @@ constexpr int32_t kK4Cap = 2048;
 hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* total,
                            hipStream_t s);
 
+// R-MAT edges 0..m-1 with 2^scale nodes (a, b, c, d quadrant weights, noise
+// in [0, 1]), counter-based from seed; perm (2^scale ids, may be null)
+// relabels both ends.
+hipError_t launch_gen_rmat(int64_t m, int scale, const double abcd[4], double noise, uint64_t seed,
+                           const int32_t* perm, int32_t* src, int32_t* dst, hipStream_t s);
+
 }  // namespace tricc

@@ -39,6 +39,7 @@ def _lib():
         P, i64, u64, f64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
         L.gen_er.argtypes = [i64, i64, u64, P, P]
         L.gen_rmat.argtypes = [i32, i64, f64, f64, f64, f64, f64, u64, i32, i32, P, P]
+        L.gen_rmat_perm.argtypes = [i32, u64, P]
         L.gen_ba_edges.argtypes = [i64, i64]
         L.gen_ba_edges.restype = i64
         L.gen_ba.argtypes = [i64, i64, u64, P, P]
@@ -78,6 +79,14 @@ def rmat(scale, edge_factor=16, seed=0, abcd=RMAT_ABCD, noise=0.1, permute=True,
     _check(_lib().gen_rmat(scale, m, a, b, c, d, noise, seed, int(bool(permute)), threads, _p(src), _p(dst)),
            "gen_rmat")
     return n, src, dst
+
+
+def rmat_perm(scale, seed=0):
+    """The node relabelling rmat(..., permute=True) applies: int32 array,
+    perm[old id] = new id over the 2**scale ids."""
+    perm = np.empty(1 << scale, np.int32)
+    _check(_lib().gen_rmat_perm(scale, seed, _p(perm)), "gen_rmat_perm")
+    return perm
 
 
 def ba(n, k, seed):

@@ -162,6 +162,13 @@ BatchSpec batch_spec(uint64_t master, int64_t g, int64_t nmin, int64_t nmax) {
 
 }  // namespace
 
+// Seeded uniform random permutation of [0, n) (Fisher-Yates, sequential).
+void rmat_perm(int64_t n, uint64_t seed, int32_t* perm) {
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  SeqRng rng(draw(seed, kStreamPerm, 0));
+  for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[below(rng.next(), (uint64_t)i + 1)]);
+}
+
 extern "C" {
 
 // Erdos-Renyi G(n,m). Writes m edges (no loops, no duplicate pairs, random
@@ -213,15 +220,21 @@ int gen_rmat(int scale, int64_t m, double a, double b, double c, double d, doubl
   }
   if (permute) {
     std::vector<int32_t> perm(n);
-    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
-    SeqRng rng(draw(seed, kStreamPerm, 0));
-    for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[below(rng.next(), (uint64_t)i + 1)]);
+    rmat_perm(n, seed, perm.data());
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t e = 0; e < m; ++e) {
       src[e] = perm[src[e]];
       dst[e] = perm[dst[e]];
     }
   }
+  return 0;
+}
+
+// The node relabelling gen_rmat applies when `permute` is set: perm[old id]
+// = new id, for the 2^scale ids.
+int gen_rmat_perm(int scale, uint64_t seed, int32_t* perm) {
+  if (scale < 1 || scale > 30) return -1;
+  rmat_perm((int64_t)1 << scale, seed, perm);
   return 0;
 }
 

@@ -723,3 +723,119 @@ def test_unmutated_oracle_passes_k4_battery(tmp_path):
     lib = tmp_path / "liborig.so"
     subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
     assert _k4_pins_pass(str(lib))
+
+
+# ---------------------------------------------------------------------------
+# R-MAT edges (the device generator's definition): pinned to SplitMix64's
+# published test vector, to the host input generator (independent code),
+# to the one-quadrant closed forms, to the quadrant frequencies, and by
+# planted mistakes
+
+def test_splitmix64_published_vector():
+    g = json.load(open(os.path.join(HERE, "golden", "splitmix64.json")))
+    out = oracle.splitmix64(g["state"], len(g["outputs"]))
+    assert [int(x) for x in out] == [int(x) for x in g["outputs"]]
+
+
+RMAT_MATCH = [(1, 0, 0.1), (4, 3, 0.0), (9, 7, 0.1), (11, 2**64 - 1, 0.5), (12, 12, 1.0)]
+
+
+@pytest.mark.parametrize("scale,seed,noise", RMAT_MATCH)
+def test_rmat_equals_input_generator(scale, seed, noise):
+    n, s, d = I.rmat(scale, 8, seed=seed, noise=noise, permute=False)
+    s2, d2 = oracle.rmat(scale, 8 << scale, seed=seed, noise=noise)
+    assert np.array_equal(s, s2) and np.array_equal(d, d2)
+    _, s3, d3 = I.rmat(scale, 8, seed=seed, noise=noise, permute=True)
+    s4, d4 = oracle.rmat(scale, 8 << scale, seed=seed, noise=noise, perm=I.rmat_perm(scale, seed))
+    assert np.array_equal(s3, s4) and np.array_equal(d3, d4)
+
+
+@pytest.mark.parametrize("q,corner", [(0, (0, 0)), (1, (0, 1)), (2, (1, 0)), (3, (1, 1))])
+@pytest.mark.parametrize("noise", [0.0, 0.5])
+def test_rmat_one_quadrant_closed_forms(q, corner, noise):
+    # all weight on one quadrant: every level picks it, so every edge is
+    # the corner (0 or n-1, 0 or n-1)
+    scale = 7
+    abcd = [0.0] * 4
+    abcd[q] = 1.0
+    s, d = oracle.rmat(scale, 3000, abcd=abcd, noise=noise, seed=5)
+    n = 1 << scale
+    assert (s == corner[0] * (n - 1)).all() and (d == corner[1] * (n - 1)).all()
+
+
+def test_rmat_quadrant_frequencies():
+    # noise 0: at every level the quadrant is (a, b, c, d)-distributed,
+    # independently; checked per level within 5 sigma
+    scale, m = 6, 200_000
+    for abcd in ((0.25, 0.25, 0.25, 0.25), (0.57, 0.19, 0.19, 0.05)):
+        s, d = oracle.rmat(scale, m, abcd=abcd, noise=0.0, seed=11)
+        for lvl in range(scale):
+            bit = scale - 1 - lvl
+            q = ((s >> bit) & 1) * 2 + ((d >> bit) & 1)
+            freq = np.bincount(q, minlength=4) / m
+            for k in range(4):
+                sigma = (abcd[k] * (1 - abcd[k]) / m) ** 0.5
+                assert abs(freq[k] - abcd[k]) < 5 * sigma + 1e-12, (abcd, lvl, k, freq)
+
+
+def test_rmat_indexed_edges_equal_full_run():
+    s, d = oracle.rmat(10, 5000, seed=21)
+    idx = np.array([0, 1, 17, 2047, 4999, 3333, 17], np.int64)
+    s2, d2 = oracle.rmat(10, idx=idx, seed=21)
+    assert np.array_equal(s[idx], s2) and np.array_equal(d[idx], d2)
+
+
+RMAT_MUTANTS = {
+    "rmat_bits_swapped": ("u = (u << 1) | (uint32_t)(q >> 1);", "u = (u << 1) | (uint32_t)(q & 1);"),
+    "rmat_noise_sign": ("(1.0 + noise * (2.0 * h / 65535.0 - 1.0))", "(1.0 + noise * (1.0 - 2.0 * h / 65535.0))"),
+    "rmat_draw_offset": ("sm_out(S + sm_gamma * (kk + 2u))", "sm_out(S + sm_gamma * (kk + 3u))"),
+    "rmat_sum_drops_last": ("(((p[0] + p[1]) + p[2]) + p[3])", "((p[0] + p[1]) + p[2])"),
+}
+
+
+def _rmat_pins_pass(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P, dbl = ctypes.c_void_p, ctypes.c_double
+    L.oracle_rmat.argtypes = [ctypes.c_int, dbl, dbl, dbl, dbl, dbl, ctypes.c_uint64, ctypes.c_int64, P, P, P, P]
+
+    def run(scale, m, abcd, noise, seed):
+        s = np.zeros(m, np.int32)
+        d = np.zeros(m, np.int32)
+        if L.oracle_rmat(scale, *abcd, noise, seed, m, None, None, s.ctypes.data, d.ctypes.data):
+            return None
+        return s, d
+
+    for scale, seed, noise in RMAT_MATCH[:3]:
+        _, s, d = I.rmat(scale, 8, seed=seed, noise=noise, permute=False)
+        r = run(scale, 8 << scale, (0.57, 0.19, 0.19, 0.05), noise, seed)
+        if r is None or not (np.array_equal(r[0], s) and np.array_equal(r[1], d)):
+            return False
+    for q, corner in ((1, (0, 1)), (2, (1, 0))):
+        abcd = [0.0] * 4
+        abcd[q] = 1.0
+        r = run(5, 500, abcd, 0.0, 3)
+        if r is None or not ((r[0] == corner[0] * 31).all() and (r[1] == corner[1] * 31).all()):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", sorted(RMAT_MUTANTS))
+def test_planted_rmat_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = RMAT_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    assert not _rmat_pins_pass(str(lib)), f"mutant {mutant} passed the pins"
+
+
+def test_unmutated_oracle_passes_rmat_battery(tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    lib = tmp_path / "liborig.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
+    assert _rmat_pins_pass(str(lib))
