@@ -24,20 +24,17 @@ __device__ __forceinline__ int32_t lower_pos(const int32_t* L, int32_t d, int32_
 }
 
 // One block per node u (grid-stride over the ids); each wavefront takes the
-// out-neighbours w of u in turn: it marks C_w = N+(w) ∩ N+(u) as bits over
-// the positions of N+(u) (held sorted in LDS, found by binary search) and
-// lists them, then streams the out-lists of the x in C_w packed (a window of
-// up to 64 lists in the lanes, each step one id per lane) and counts the ids
-// z whose position bit is set.
+// out-neighbours w of u in turn: it lists C_w = N+(w) ∩ N+(u) in id order
+// (each id of N+(w) searched in N+(u), held sorted in LDS), then streams the
+// out-lists of the x in C_w packed (a window of up to 64 lists in the lanes,
+// each step one id per lane) and counts the ids z found in C_w. Exactly
+// 40 KB of LDS per block, so four blocks share a CU.
 template <int CAP>
 __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, const int64_t* __restrict__ doff,
                                                     const int32_t* __restrict__ dcol,
                                                     unsigned long long* __restrict__ total) {
-  __shared__ int32_t L[CAP];
-  __shared__ uint32_t M[kK4Waves][CAP / 32];
+  __shared__ __align__(16) int32_t L[CAP];
   __shared__ int32_t Cl[kK4Waves][CAP];
-  __shared__ int32_t Cn[kK4Waves];
-  __shared__ unsigned long long red[kK4Waves];
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   unsigned long long acc = 0;
@@ -52,33 +49,28 @@ __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, const int64_t* __
       const int32_t w = L[i];
       const int64_t wb = doff[w];
       const int32_t dw = (int32_t)(doff[w + 1] - wb);
-      for (int32_t q = lane; q < (d + 31) / 32; q += kWave) M[wv][q] = 0;
-      if (lane == 0) Cn[wv] = 0;
-      wave_sync();
+      int32_t nc = 0;  // wave-uniform
       for (int32_t t0 = 0; t0 < dw; t0 += kWave) {
         const int32_t t = t0 + lane;
         bool hit = false;
-        int32_t p = 0;
+        int32_t y = 0;
         if (t < dw) {
-          const int32_t y = dcol[wb + t];
-          p = lower_pos(L, d, y);
+          y = dcol[wb + t];
+          const int32_t p = lower_pos(L, d, y);
           hit = p < d && L[p] == y;
         }
         const uint64_t m = __ballot(hit);
-        if (hit) {
-          atomicOr(&M[wv][p >> 5], 1u << (p & 31));
-          Cl[wv][Cn[wv] + mask_below(m)] = p;
-        }
-        wave_sync();
-        if (lane == 0) Cn[wv] += (int32_t)__popcll(m);
-        wave_sync();
+        if (hit) Cl[wv][nc + mask_below(m)] = y;
+        nc += (int32_t)__popcll(m);
       }
-      const int32_t nc = Cn[wv];
-      // edges x -> z inside C_w, over the out-lists of the x in C_w
-      for (int32_t base = 0; base < nc; base += kWave) {
+      wave_sync();
+      const int32_t* C = Cl[wv];
+      // edges x -> z inside C_w, over the out-lists of the x in C_w (a
+      // clique needs two of them)
+      for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
         int32_t xn = 0, xb = 0;
         if (base + lane < nc) {
-          const int32_t x = L[Cl[wv][base + lane]];
+          const int32_t x = C[base + lane];
           const int64_t b = doff[x];
           xb = (int32_t)b;
           xn = (int32_t)(doff[x + 1] - b);
@@ -98,16 +90,18 @@ __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, const int64_t* __
           const int32_t ke = __shfl(excl, k, kWave);
           if (t < tot) {
             const int32_t z = dcol[kb + (t - ke)];
-            const int32_t p = lower_pos(L, d, z);
-            if (p < d && L[p] == z && ((M[wv][p >> 5] >> (p & 31)) & 1u)) ++acc;
+            const int32_t p = lower_pos(C, nc, z);
+            if (p < nc && C[p] == z) ++acc;
           }
         }
       }
-      wave_sync();  // the next w reuses M and Cl
+      wave_sync();  // the next w reuses Cl
     }
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  unsigned long long* red = reinterpret_cast<unsigned long long*>(L);  // L is free now
+  __syncthreads();
   if (lane == 0) red[wv] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
