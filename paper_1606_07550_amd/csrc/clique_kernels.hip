@@ -11,6 +11,11 @@ namespace {
 
 constexpr int kK4NT = 256;
 constexpr int kK4Waves = kK4NT / kWave;
+// Out-degrees up to kK4BitsMid take the bit-row kernel with 256 threads and
+// 38 KB of LDS; up to kK4BitsMax the one with 512 threads and 148 KB (one
+// block per CU); longer lists the list kernel.
+constexpr int kK4BitsMid = 512;
+constexpr int kK4BitsMax = 1024;
 
 // First position p in L[0, d) (ascending) with L[p] >= x.
 __device__ __forceinline__ int32_t lower_pos(const int32_t* L, int32_t d, int32_t x) {
@@ -23,11 +28,152 @@ __device__ __forceinline__ int32_t lower_pos(const int32_t* L, int32_t d, int32_
   return lo;
 }
 
-// One block per node u (grid-stride over the ids); each wavefront takes the
-// out-neighbours w of u in turn: it lists C_w = N+(w) ∩ N+(u) in id order
-// (each id of N+(w) searched in N+(u), held sorted in LDS), then streams the
-// out-lists of the x in C_w packed (a window of up to 64 lists in the lanes,
-// each step one id per lane) and counts the ids z found in C_w. Exactly
+// One (u, w) pair, one wavefront: lists C_w = N+(w) ∩ N+(u) into C in id
+// order (each id of N+(w) searched in N+(u) = L[0, d), sorted), then streams
+// the out-lists of the x in C_w packed (a window of up to 64 lists in the
+// lanes, each step one id per lane) and counts the ids z found in C_w: the
+// 4-cliques {u, w, x, z}. C holds up to d ids. Returns this lane's share.
+__device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int32_t d, int32_t w, int32_t* C,
+                                                           const int64_t* __restrict__ doff,
+                                                           const int32_t* __restrict__ dcol, int lane) {
+  const int64_t wb = doff[w];
+  const int32_t dw = (int32_t)(doff[w + 1] - wb);
+  if (dw < 2) return 0;  // a clique needs two ids of N+(w) in C_w
+  unsigned long long acc = 0;
+  int32_t nc = 0;  // wave-uniform
+  for (int32_t t0 = 0; t0 < dw; t0 += kWave) {
+    const int32_t t = t0 + lane;
+    bool hit = false;
+    int32_t y = 0;
+    if (t < dw) {
+      y = dcol[wb + t];
+      const int32_t p = lower_pos(L, d, y);
+      hit = p < d && L[p] == y;
+    }
+    const uint64_t m = __ballot(hit);
+    if (hit) C[nc + mask_below(m)] = y;
+    nc += (int32_t)__popcll(m);
+  }
+  wave_sync();
+  for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
+    int32_t xn = 0, xb = 0;
+    if (base + lane < nc) {
+      const int32_t x = C[base + lane];
+      const int64_t b = doff[x];
+      xb = (int32_t)b;
+      xn = (int32_t)(doff[x + 1] - b);
+    }
+    const int32_t incl = wave_incl_scan(xn);
+    const int32_t tot = __shfl(incl, kWave - 1, kWave);
+    const int32_t excl = incl - xn;
+    for (int32_t t0 = 0; t0 < tot; t0 += kWave) {
+      const int32_t t = t0 + lane;
+      int k = 0;
+#pragma unroll
+      for (int s = kWave / 2; s > 0; s >>= 1) {
+        const int32_t v = __shfl(incl, k + s - 1, kWave);
+        if (v <= t) k += s;
+      }
+      const int32_t kb = __shfl(xb, k, kWave);
+      const int32_t ke = __shfl(excl, k, kWave);
+      if (t < tot) {
+        const int32_t z = dcol[kb + (t - ke)];
+        const int32_t p = lower_pos(C, nc, z);
+        if (p < nc && C[p] == z) ++acc;
+      }
+    }
+  }
+  wave_sync();  // the next pair reuses C
+  return acc;
+}
+
+// Block-wide total of the per-lane counts, one 64-bit atomic per block.
+// `red` holds NW values (the block's wavefronts); contains __syncthreads().
+template <int NW>
+__device__ __forceinline__ void k4_block_total(unsigned long long acc, unsigned long long* red,
+                                               unsigned long long* total) {
+  const int wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  __syncthreads();
+  if (lane_id() == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < NW; ++q) t += red[q];
+    if (t) atomicAdd(total, t);
+  }
+}
+
+// Nodes with DMIN < d+(u) <= DMAX (and d+(u) >= 3): one block of NT threads
+// per node (grid-stride over the ids). The block builds the subgraph induced on N+(u) as bit rows in
+// LDS (row i: the positions in N+(u) of N+(L[i]) ∩ N+(u), each wavefront
+// building the rows of its w's by searching N+(w) in N+(u)); then every pair
+// (w, x) with x in row w adds popcount(row w & row x): the z that close the
+// 4-clique {u, w, x, z}. Rows take RS = 2^rs words (RS >= d / 32), and the
+// lanes of a wavefront cover 64 / RS rows x at once, one word each.
+template <int DMIN, int DMAX, int NT>
+__global__ __launch_bounds__(NT) void k_count_k4_bits(int32_t n, const int64_t* __restrict__ doff,
+                                                      const int32_t* __restrict__ dcol,
+                                                      unsigned long long* __restrict__ total) {
+  constexpr int NW = NT / kWave;
+  static_assert(DMAX % 32 == 0 && DMAX <= 65536, "positions are stored in 16 bits");
+  __shared__ int32_t L[DMAX];
+  __shared__ uint32_t B[DMAX * (DMAX / 32)];
+  __shared__ uint16_t Pl[NW][DMAX];
+  __shared__ unsigned long long red[NW];
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  unsigned long long acc = 0;
+  for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {  // block-uniform
+    const int64_t ub = doff[u];
+    const int32_t d = (int32_t)(doff[u + 1] - ub);
+    if (d < 3 || d <= DMIN || d > DMAX) continue;
+    const int rs = d <= 32 ? 0 : 32 - __builtin_clz((uint32_t)((d + 31) / 32 - 1));
+    const int RS = 1 << rs;
+    __syncthreads();  // L and B of the previous node are no longer read
+    for (int32_t i = threadIdx.x; i < d; i += NT) L[i] = dcol[ub + i];
+    for (int32_t q = threadIdx.x; q < d * RS; q += NT) B[q] = 0u;
+    __syncthreads();
+    for (int32_t i = wv; i < d; i += NW) {
+      const int32_t w = L[i];
+      const int64_t wb = doff[w];
+      const int32_t dw = (int32_t)(doff[w + 1] - wb);
+      for (int32_t t = lane; t < dw; t += kWave) {
+        const int32_t y = dcol[wb + t];
+        const int32_t p = lower_pos(L, d, y);
+        if (p < d && L[p] == y) atomicOr(&B[i * RS + (p >> 5)], 1u << (p & 31));
+      }
+    }
+    __syncthreads();
+    for (int32_t i = wv; i < d; i += NW) {
+      const uint32_t* Bi = B + i * RS;
+      int32_t np = 0;  // wave-uniform: the x of row i, listed
+      for (int32_t b0 = 0; b0 < d; b0 += kWave) {
+        const int32_t b = b0 + lane;
+        const bool bit = b < d && ((Bi[b >> 5] >> (b & 31)) & 1u);
+        const uint64_t m = __ballot(bit);
+        if (bit) Pl[wv][np + mask_below(m)] = (uint16_t)b;
+        np += (int32_t)__popcll(m);
+      }
+      wave_sync();
+      if (np >= 2) {  // a clique needs x and z in row i
+        const int32_t k = lane & (RS - 1);
+        const int32_t js = lane >> rs;
+        const uint32_t bik = Bi[k];
+        for (int32_t j0 = 0; j0 < np; j0 += (kWave >> rs)) {
+          const int32_t jj = j0 + js;
+          if (jj < np) acc += (unsigned long long)__popc(bik & B[(int32_t)Pl[wv][jj] * RS + k]);
+        }
+      }
+      wave_sync();  // the next row reuses Pl
+    }
+  }
+  k4_block_total<NW>(acc, red, total);
+}
+
+// Nodes with d+(u) > kK4BitsMax: one block per node (grid-stride over the ids),
+// N+(u) in LDS, the wavefronts taking its out-neighbours w in turn. Exactly
 // 40 KB of LDS per block, so four blocks share a CU.
 template <int CAP>
 __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, const int64_t* __restrict__ doff,
@@ -41,74 +187,13 @@ __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, const int64_t* __
   for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {  // block-uniform
     const int64_t ub = doff[u];
     const int32_t d = (int32_t)(doff[u + 1] - ub);
-    if (d < 3) continue;
+    if (d <= kK4BitsMax) continue;
     __syncthreads();  // L of the previous node is no longer read
     for (int32_t i = threadIdx.x; i < d; i += kK4NT) L[i] = dcol[ub + i];
     __syncthreads();
-    for (int32_t i = wv; i < d; i += kK4Waves) {  // w = L[i]
-      const int32_t w = L[i];
-      const int64_t wb = doff[w];
-      const int32_t dw = (int32_t)(doff[w + 1] - wb);
-      int32_t nc = 0;  // wave-uniform
-      for (int32_t t0 = 0; t0 < dw; t0 += kWave) {
-        const int32_t t = t0 + lane;
-        bool hit = false;
-        int32_t y = 0;
-        if (t < dw) {
-          y = dcol[wb + t];
-          const int32_t p = lower_pos(L, d, y);
-          hit = p < d && L[p] == y;
-        }
-        const uint64_t m = __ballot(hit);
-        if (hit) Cl[wv][nc + mask_below(m)] = y;
-        nc += (int32_t)__popcll(m);
-      }
-      wave_sync();
-      const int32_t* C = Cl[wv];
-      // edges x -> z inside C_w, over the out-lists of the x in C_w (a
-      // clique needs two of them)
-      for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
-        int32_t xn = 0, xb = 0;
-        if (base + lane < nc) {
-          const int32_t x = C[base + lane];
-          const int64_t b = doff[x];
-          xb = (int32_t)b;
-          xn = (int32_t)(doff[x + 1] - b);
-        }
-        const int32_t incl = wave_incl_scan(xn);
-        const int32_t tot = __shfl(incl, kWave - 1, kWave);
-        const int32_t excl = incl - xn;
-        for (int32_t t0 = 0; t0 < tot; t0 += kWave) {
-          const int32_t t = t0 + lane;
-          int k = 0;
-#pragma unroll
-          for (int s = kWave / 2; s > 0; s >>= 1) {
-            const int32_t v = __shfl(incl, k + s - 1, kWave);
-            if (v <= t) k += s;
-          }
-          const int32_t kb = __shfl(xb, k, kWave);
-          const int32_t ke = __shfl(excl, k, kWave);
-          if (t < tot) {
-            const int32_t z = dcol[kb + (t - ke)];
-            const int32_t p = lower_pos(C, nc, z);
-            if (p < nc && C[p] == z) ++acc;
-          }
-        }
-      }
-      wave_sync();  // the next w reuses Cl
-    }
+    for (int32_t i = wv; i < d; i += kK4Waves) acc += wave_k4_pair(L, d, L[i], Cl[wv], doff, dcol, lane);
   }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  unsigned long long* red = reinterpret_cast<unsigned long long*>(L);  // L is free now
-  __syncthreads();
-  if (lane == 0) red[wv] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int q = 0; q < kK4Waves; ++q) t += red[q];
-    if (t) atomicAdd(total, t);
-  }
+  k4_block_total<kK4Waves>(acc, reinterpret_cast<unsigned long long*>(L), total);  // L is free after the barrier
 }
 
 __global__ void k_zero_one(unsigned long long* p) {
@@ -122,6 +207,9 @@ hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, 
   k_zero_one<<<1, 64, 0, s>>>(total);
   if (n > 0) {
     const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
+    k_count_k4_bits<0, kK4BitsMid, kK4NT><<<grid, kK4NT, 0, s>>>(n, doff, dcol, total);
+    const unsigned grid_big = (unsigned)(n < 2048 ? n : 2048);
+    k_count_k4_bits<kK4BitsMid, kK4BitsMax, 512><<<grid_big, 512, 0, s>>>(n, doff, dcol, total);
     k_count_k4<kK4Cap><<<grid, kK4NT, 0, s>>>(n, doff, dcol, total);
   }
   return hipGetLastError();

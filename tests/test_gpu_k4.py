@@ -49,10 +49,20 @@ def test_against_oracle(name):
     assert gpu_k4(g) == ref  # repeat calls
 
 
-@pytest.mark.parametrize("k", [4, 5, 17, 33, 60])
+@pytest.mark.parametrize("k", [4, 5, 17, 33, 60, 65, 66, 67, 300, 513, 514, 600, 1025, 1026, 1100])
 def test_complete_graphs(k):
     n, s, d = F.complete(k)
     assert gpu_k4(P.Graph(n, dev(s), dev(d))) == comb(k, 4)
+
+
+def test_dense_random_graph_against_oracle():
+    # G(1100, 0.6): the lowest-ranked nodes keep out-degrees of 512-617,
+    # which take the 148 KB bit-row kernel
+    n = 1100
+    s, d = I.er(n, int(0.6 * n * (n - 1) / 2), 77)
+    g = P.Graph(n, dev(s), dev(d))
+    assert 512 < g.info["max_outdeg"] <= 1024
+    assert gpu_k4(g) == oracle.k4(n, s, d, order=1)
 
 
 def test_rmat17_and_from_csr():
