@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
     ap.add_argument("--no-k4", action="store_true", help="skip the 4-clique leg")
     ap.add_argument("--no-gen", action="store_true", help="skip the device R-MAT generator leg")
-    ap.add_argument("--k4-scale", type=int, default=20, help="4-clique leg: R-MAT scale")
+    ap.add_argument("--k4-scale", type=int, default=22, help="4-clique leg: R-MAT scale")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
     ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
