@@ -88,6 +88,27 @@ def test_build_rejects_bad_arguments_before_device_work():
     assert not h.value
 
 
+@pytest.mark.parametrize("args", [
+    (0, 10, 0.57, 0.19, 0.19, 0.05, 0.1),       # scale below 1
+    (31, 10, 0.57, 0.19, 0.19, 0.05, 0.1),      # scale above 30
+    (5, -1, 0.57, 0.19, 0.19, 0.05, 0.1),       # negative edge count
+    (5, 10, -0.1, 0.5, 0.3, 0.3, 0.1),          # negative weight
+    (5, 10, float("inf"), 0.5, 0.3, 0.3, 0.1),  # weight not finite
+    (5, 10, 0.0, 0.0, 0.0, 0.0, 0.1),           # weights sum to zero
+    (5, 10, 0.57, 0.19, 0.19, 0.05, 1.5),       # noise above 1
+    (5, 10, 0.57, 0.19, 0.19, 0.05, float("nan")),
+    (5, 10, 0.57, 0.19, 0.19, 0.05, 0.1),       # null outputs with m > 0
+])
+def test_generator_rejects_bad_arguments_before_device_work(args):
+    assert N.lib().tricc_gen_rmat(*args, 0, None, None, None, None) == N.TRICC_EINVAL
+    assert N.last_error()
+
+
+def test_k4_rejects_null_arguments():
+    L = N.lib()
+    assert L.tricc_graph_count_k4(None, ctypes.c_void_p(256), None) == N.TRICC_EINVAL
+
+
 def test_min_side_variants_and_tuning_check():
     from paper_1606_07550_amd import default_tuning, variant_count
     L = N.lib()
