@@ -28,6 +28,17 @@ __device__ __forceinline__ int32_t lower_pos(const int32_t* L, int32_t d, int32_
   return lo;
 }
 
+// Position of the first element >= x in L[0, P), P a power of two and L
+// ascending (padded past its length with kPad, above every id): fixed
+// halving steps, no data-dependent exit. Every element before the result is
+// below x, so x is in L iff L[result] == x.
+__device__ __forceinline__ int32_t pow2_lower_pos(const int32_t* L, int32_t P, int32_t x) {
+  int32_t p = 0;
+  for (int32_t s = P >> 1; s > 0; s >>= 1)
+    if (L[p + s - 1] < x) p += s;
+  return p;
+}
+
 // One (u, w) pair, one wavefront: lists C_w = N+(w) ∩ N+(u) into C in id
 // order (each id of N+(w) searched in N+(u) = L[0, d), sorted), then streams
 // the out-lists of the x in C_w packed (a window of up to 64 lists in the
@@ -150,8 +161,9 @@ __global__ __launch_bounds__(NT) void k_count_k4_bits(int32_t n, int32_t chunk, 
       const int32_t d = (int32_t)(doff[u + 1] - ub);
       const int rs = d <= 32 ? 0 : 32 - __builtin_clz((uint32_t)((d + 31) / 32 - 1));
       const int RS = 1 << rs;
+      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= DMAX
       __syncthreads();  // L and B of the previous node are no longer read
-      for (int32_t i = threadIdx.x; i < d; i += NT) L[i] = dcol[ub + i];
+      for (int32_t i = threadIdx.x; i < P; i += NT) L[i] = i < d ? dcol[ub + i] : kPad;
       for (int32_t q = threadIdx.x; q < d * RS; q += NT) B[q] = 0u;
       __syncthreads();
       for (int32_t i = wv; i < d; i += NW) {
@@ -160,8 +172,8 @@ __global__ __launch_bounds__(NT) void k_count_k4_bits(int32_t n, int32_t chunk, 
         const int32_t dw = (int32_t)(doff[w + 1] - wb);
         for (int32_t t = lane; t < dw; t += kWave) {
           const int32_t y = dcol[wb + t];
-          const int32_t p = lower_pos(L, d, y);
-          if (p < d && L[p] == y) atomicOr(&B[i * RS + (p >> 5)], 1u << (p & 31));
+          const int32_t p = pow2_lower_pos(L, P, y);
+          if (L[p] == y) atomicOr(&B[i * RS + (p >> 5)], 1u << (p & 31));
         }
       }
       __syncthreads();
