@@ -67,11 +67,12 @@ __device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int
   }
   wave_sync();
   for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
-    int32_t xn = 0, xb = 0;
+    int32_t xn = 0;
+    int64_t xb = 0;  // start of N+(x): DAG offsets pass 2^31 on large graphs
     if (base + lane < nc) {
       const int32_t x = C[base + lane];
       const int64_t b = doff[x];
-      xb = (int32_t)b;
+      xb = b;
       xn = (int32_t)(doff[x + 1] - b);
     }
     const int32_t incl = wave_incl_scan(xn);
@@ -85,7 +86,7 @@ __device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int
         const int32_t v = __shfl(incl, k + s - 1, kWave);
         if (v <= t) k += s;
       }
-      const int32_t kb = __shfl(xb, k, kWave);
+      const int64_t kb = __shfl(xb, k, kWave);
       const int32_t ke = __shfl(excl, k, kWave);
       if (t < tot) {
         const int32_t z = dcol[kb + (t - ke)];
