@@ -17,17 +17,6 @@ constexpr int kK4Waves = kK4NT / kWave;
 constexpr int kK4BitsMid = 512;
 constexpr int kK4BitsMax = 1024;
 
-// First position p in L[0, d) (ascending) with L[p] >= x.
-__device__ __forceinline__ int32_t lower_pos(const int32_t* L, int32_t d, int32_t x) {
-  int32_t lo = 0, hi = d;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (L[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // Position of the first element >= x in L[0, P), P a power of two and L
 // ascending (padded past its length with kPad, above every id): fixed
 // halving steps, no data-dependent exit. Every element before the result is
@@ -40,11 +29,12 @@ __device__ __forceinline__ int32_t pow2_lower_pos(const int32_t* L, int32_t P, i
 }
 
 // One (u, w) pair, one wavefront: lists C_w = N+(w) ∩ N+(u) into C in id
-// order (each id of N+(w) searched in N+(u) = L[0, d), sorted), then streams
-// the out-lists of the x in C_w packed (a window of up to 64 lists in the
-// lanes, each step one id per lane) and counts the ids z found in C_w: the
-// 4-cliques {u, w, x, z}. C holds up to d ids. Returns this lane's share.
-__device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int32_t d, int32_t w, int32_t* C,
+// order (each id of N+(w) searched in N+(u), held sorted in L and padded with
+// kPad to the power of two P), then streams the out-lists of the x in C_w
+// packed (a window of up to 64 lists in the lanes, each step one id per lane)
+// and counts the ids z found in C_w: the 4-cliques {u, w, x, z}. C holds up
+// to P ids. Returns this lane's share.
+__device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int32_t P, int32_t w, int32_t* C,
                                                            const int64_t* __restrict__ doff,
                                                            const int32_t* __restrict__ dcol, int lane) {
   const int64_t wb = doff[w];
@@ -58,13 +48,15 @@ __device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int
     int32_t y = 0;
     if (t < dw) {
       y = dcol[wb + t];
-      const int32_t p = lower_pos(L, d, y);
-      hit = p < d && L[p] == y;
+      hit = L[pow2_lower_pos(L, P, y)] == y;
     }
     const uint64_t m = __ballot(hit);
     if (hit) C[nc + mask_below(m)] = y;
     nc += (int32_t)__popcll(m);
   }
+  // pad C_w to a power of two for the fixed-step search (nc <= d <= the capacity of C)
+  const int32_t Pc = nc <= 1 ? 1 : 1 << (32 - __builtin_clz((uint32_t)(nc - 1)));
+  for (int32_t t = nc + lane; t < Pc; t += kWave) C[t] = kPad;
   wave_sync();
   for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
     int32_t xn = 0;
@@ -90,8 +82,7 @@ __device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int
       const int32_t ke = __shfl(excl, k, kWave);
       if (t < tot) {
         const int32_t z = dcol[kb + (t - ke)];
-        const int32_t p = lower_pos(C, nc, z);
-        if (p < nc && C[p] == z) ++acc;
+        if (C[pow2_lower_pos(C, Pc, z)] == z) ++acc;
       }
     }
   }
@@ -252,10 +243,11 @@ __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, int32_t chunk, co
       const int32_t u = Q[qi];
       const int64_t ub = doff[u];
       const int32_t d = (int32_t)(doff[u + 1] - ub);
+      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= CAP
       __syncthreads();  // L of the previous node is no longer read
-      for (int32_t i = threadIdx.x; i < d; i += kK4NT) L[i] = dcol[ub + i];
+      for (int32_t i = threadIdx.x; i < P; i += kK4NT) L[i] = i < d ? dcol[ub + i] : kPad;
       __syncthreads();
-      for (int32_t i = wv; i < d; i += kK4Waves) acc += wave_k4_pair(L, d, L[i], Cl[wv], doff, dcol, lane);
+      for (int32_t i = wv; i < d; i += kK4Waves) acc += wave_k4_pair(L, P, L[i], Cl[wv], doff, dcol, lane);
     }
   }
   k4_block_total<kK4Waves>(acc, reinterpret_cast<unsigned long long*>(L), total);  // L is free after the barrier
