@@ -10,10 +10,9 @@ namespace tricc {
 namespace {
 
 constexpr int kK4NT = 256;
-constexpr int kK4Waves = kK4NT / kWave;
 // Out-degrees up to kK4BitsMid take the bit-row kernel with 256 threads and
-// 38 KB of LDS; up to kK4BitsMax the one with 1,024 threads and 132 KB (one
-// block per CU); longer lists the list kernel.
+// 39 KB of LDS; up to kK4BitsMax the one with 1,024 threads and 136 KB (one
+// block per CU); up to kK4Cap the quarter-pass kernel (1,024 threads, 142 KB).
 constexpr int kK4BitsMid = 512;
 constexpr int kK4BitsMax = 1024;
 
@@ -26,68 +25,6 @@ __device__ __forceinline__ int32_t pow2_lower_pos(const int32_t* L, int32_t P, i
   for (int32_t s = P >> 1; s > 0; s >>= 1)
     if (L[p + s - 1] < x) p += s;
   return p;
-}
-
-// One (u, w) pair, one wavefront: lists C_w = N+(w) ∩ N+(u) into C in id
-// order (each id of N+(w) searched in N+(u), held sorted in L and padded with
-// kPad to the power of two P), then streams the out-lists of the x in C_w
-// packed (a window of up to 64 lists in the lanes, each step one id per lane)
-// and counts the ids z found in C_w: the 4-cliques {u, w, x, z}. C holds up
-// to P ids. Returns this lane's share.
-__device__ __forceinline__ unsigned long long wave_k4_pair(const int32_t* L, int32_t P, int32_t w, int32_t* C,
-                                                           const int64_t* __restrict__ doff,
-                                                           const int32_t* __restrict__ dcol, int lane) {
-  const int64_t wb = doff[w];
-  const int32_t dw = (int32_t)(doff[w + 1] - wb);
-  if (dw < 2) return 0;  // a clique needs two ids of N+(w) in C_w
-  unsigned long long acc = 0;
-  int32_t nc = 0;  // wave-uniform
-  for (int32_t t0 = 0; t0 < dw; t0 += kWave) {
-    const int32_t t = t0 + lane;
-    bool hit = false;
-    int32_t y = 0;
-    if (t < dw) {
-      y = dcol[wb + t];
-      hit = L[pow2_lower_pos(L, P, y)] == y;
-    }
-    const uint64_t m = __ballot(hit);
-    if (hit) C[nc + mask_below(m)] = y;
-    nc += (int32_t)__popcll(m);
-  }
-  // pad C_w to a power of two for the fixed-step search (nc <= d <= the capacity of C)
-  const int32_t Pc = nc <= 1 ? 1 : 1 << (32 - __builtin_clz((uint32_t)(nc - 1)));
-  for (int32_t t = nc + lane; t < Pc; t += kWave) C[t] = kPad;
-  wave_sync();
-  for (int32_t base = 0; nc >= 2 && base < nc; base += kWave) {
-    int32_t xn = 0;
-    int64_t xb = 0;  // start of N+(x): DAG offsets pass 2^31 on large graphs
-    if (base + lane < nc) {
-      const int32_t x = C[base + lane];
-      const int64_t b = doff[x];
-      xb = b;
-      xn = (int32_t)(doff[x + 1] - b);
-    }
-    const int32_t incl = wave_incl_scan(xn);
-    const int32_t tot = __shfl(incl, kWave - 1, kWave);
-    const int32_t excl = incl - xn;
-    for (int32_t t0 = 0; t0 < tot; t0 += kWave) {
-      const int32_t t = t0 + lane;
-      int k = 0;
-#pragma unroll
-      for (int s = kWave / 2; s > 0; s >>= 1) {
-        const int32_t v = __shfl(incl, k + s - 1, kWave);
-        if (v <= t) k += s;
-      }
-      const int64_t kb = __shfl(xb, k, kWave);
-      const int32_t ke = __shfl(excl, k, kWave);
-      if (t < tot) {
-        const int32_t z = dcol[kb + (t - ke)];
-        if (C[pow2_lower_pos(C, Pc, z)] == z) ++acc;
-      }
-    }
-  }
-  wave_sync();  // the next pair reuses C
-  return acc;
 }
 
 // Block-wide total of the per-lane counts, one 64-bit atomic per block.
@@ -217,16 +154,28 @@ __global__ __launch_bounds__(NT) void k_count_k4_bits(int32_t n, int32_t chunk, 
   k4_block_total<NW>(acc, red, total);
 }
 
-// Nodes with d+(u) > kK4BitsMax: one block per node (chunks of ids scanned
-// and queued as in the bit-row kernel), N+(u) in LDS, the wavefronts taking
-// its out-neighbours w in turn.
-template <int CAP>
-__global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, int32_t chunk, const int64_t* __restrict__ doff,
-                                                    const int32_t* __restrict__ dcol,
-                                                    unsigned long long* __restrict__ total) {
-  __shared__ __align__(16) int32_t L[CAP];
-  __shared__ int32_t Cl[kK4Waves][CAP];
-  __shared__ int32_t Q[kK4NT];
+// Nodes with kK4BitsMax < d+(u) <= kK4Cap: bit rows over quarters of the
+// positions. Full rows (up to 64 words for 2,048 rows) do not fit in LDS, so
+// the block of 1,024 threads makes one pass per 512 positions: it builds that
+// quarter of every row (16 words, 128 KB for 2,048 rows); then each wavefront
+// streams N+(w) again, places its ids in N+(u), and for every x found (the
+// hits of 64 ids, four x at a time) adds popcount(row w & row x) over the
+// quarter. Summed over the quarters this is the count the full rows give.
+// Nodes are queued from chunks of ids as in the bit-row kernel.
+constexpr int kK4QNT = 1024;
+constexpr int kK4QWaves = kK4QNT / kWave;
+constexpr int kK4QCols = 512;
+constexpr int kK4QWords = kK4QCols / 32;
+
+__global__ __launch_bounds__(kK4QNT) void k_count_k4_quarters(int32_t n, int32_t chunk,
+                                                              const int64_t* __restrict__ doff,
+                                                              const int32_t* __restrict__ dcol,
+                                                              unsigned long long* __restrict__ total) {
+  __shared__ int32_t L[kK4Cap];
+  __shared__ uint32_t B[kK4Cap * kK4QWords];
+  __shared__ uint16_t H[kK4QWaves][kWave];
+  __shared__ unsigned long long red[kK4QWaves];
+  __shared__ int32_t Q[kK4QNT];
   __shared__ int32_t Qn;
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
@@ -236,21 +185,66 @@ __global__ __launch_bounds__(kK4NT) void k_count_k4(int32_t n, int32_t chunk, co
     if (threadIdx.x == 0) Qn = 0;
     __syncthreads();
     const int64_t v = base + threadIdx.x;
-    if ((int)threadIdx.x < chunk && v < n && doff[v + 1] - doff[v] > kK4BitsMax) Q[atomicAdd(&Qn, 1)] = (int32_t)v;
+    if ((int)threadIdx.x < chunk && v < n) {
+      const int64_t dv = doff[v + 1] - doff[v];
+      if (dv > kK4BitsMax && dv <= kK4Cap) Q[atomicAdd(&Qn, 1)] = (int32_t)v;
+    }
     __syncthreads();
     const int32_t nq = Qn;
     for (int32_t qi = 0; qi < nq; ++qi) {  // block-uniform
       const int32_t u = Q[qi];
       const int64_t ub = doff[u];
       const int32_t d = (int32_t)(doff[u + 1] - ub);
-      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= CAP
-      __syncthreads();  // L of the previous node is no longer read
-      for (int32_t i = threadIdx.x; i < P; i += kK4NT) L[i] = i < d ? dcol[ub + i] : kPad;
-      __syncthreads();
-      for (int32_t i = wv; i < d; i += kK4Waves) acc += wave_k4_pair(L, P, L[i], Cl[wv], doff, dcol, lane);
+      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= kK4Cap
+      __syncthreads();  // L and B of the previous node are no longer read
+      for (int32_t i = threadIdx.x; i < P; i += kK4QNT) L[i] = i < d ? dcol[ub + i] : kPad;
+      for (int32_t q = 0; q * kK4QCols < d; ++q) {
+        __syncthreads();  // L written; the previous quarter's rows no longer read
+        for (int32_t e = threadIdx.x; e < d * kK4QWords; e += kK4QNT) B[e] = 0u;
+        __syncthreads();
+        for (int32_t i = wv; i < d; i += kK4QWaves) {  // quarter q of row i
+          const int32_t w = L[i];
+          const int64_t wb = doff[w];
+          const int32_t dw = (int32_t)(doff[w + 1] - wb);
+          for (int32_t t = lane; t < dw; t += kWave) {
+            const int32_t y = dcol[wb + t];
+            const int32_t p = pow2_lower_pos(L, P, y);
+            if (L[p] == y && p / kK4QCols == q)
+              atomicOr(&B[i * kK4QWords + (p % kK4QCols) / 32], 1u << (p & 31));
+          }
+        }
+        __syncthreads();
+        const int32_t k = lane & (kK4QWords - 1);
+        const int32_t j = lane / kK4QWords;
+        for (int32_t i = wv; i < d; i += kK4QWaves) {  // the x of row i, quarter q of the AND
+          const int32_t w = L[i];
+          const int64_t wb = doff[w];
+          const int32_t dw = (int32_t)(doff[w + 1] - wb);
+          const uint32_t bw = B[i * kK4QWords + k];
+          for (int32_t t0 = 0; t0 < dw; t0 += kWave) {
+            const int32_t t = t0 + lane;
+            bool hit = false;
+            int32_t p = 0;
+            if (t < dw) {
+              const int32_t y = dcol[wb + t];
+              p = pow2_lower_pos(L, P, y);
+              hit = L[p] == y;
+            }
+            const uint64_t m = __ballot(hit);
+            const int32_t nh = (int32_t)__popcll(m);
+            if (hit) H[wv][mask_below(m)] = (uint16_t)p;
+            wave_sync();
+            for (int32_t g = 0; g < nh; g += kWave / kK4QWords) {
+              const int32_t jj = g + j;
+              if (jj < nh) acc += (unsigned long long)__popc(bw & B[(int32_t)H[wv][jj] * kK4QWords + k]);
+            }
+            wave_sync();  // H is rewritten by the next 64 ids
+          }
+        }
+      }
     }
   }
-  k4_block_total<kK4Waves>(acc, reinterpret_cast<unsigned long long*>(L), total);  // L is free after the barrier
+  k4_block_total<kK4QWaves>(acc, red, total);
 }
 
 __global__ void k_zero_one(unsigned long long* p) {
@@ -280,7 +274,7 @@ hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, 
     const int32_t cb = k4_chunk(n, 1024, 1024);
     k_count_k4_bits<kK4BitsMid, kK4BitsMax, 1024, false><<<k4_grid(n, cb, 1024), 1024, 0, s>>>(n, cb, doff, dcol,
                                                                                                  total);
-    k_count_k4<kK4Cap><<<k4_grid(n, cm, 65536), kK4NT, 0, s>>>(n, cm, doff, dcol, total);
+    k_count_k4_quarters<<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
   }
   return hipGetLastError();
 }
