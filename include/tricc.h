@@ -272,8 +272,9 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
  * from C = N+(u) ∩ N+(w) and the edges x -> z inside C.
  *   d_total   device uint64[1], the caller's (overwritten)
  * Asynchronous on `stream`. Errors: TRICC_EINVAL for a null handle or
- * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 2048 (the LDS
- * capacity of one node's list).
+ * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 4096 (the
+ * positions one node's bit rows can index in LDS, one block of them per
+ * pass).
  */
 int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream);
 

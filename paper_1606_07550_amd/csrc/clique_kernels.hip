@@ -12,7 +12,9 @@ namespace {
 constexpr int kK4NT = 256;
 // Out-degrees up to kK4BitsMid take the bit-row kernel with 256 threads and
 // 39 KB of LDS; up to kK4BitsMax the one with 1,024 threads and 136 KB (one
-// block per CU); up to kK4Cap the quarter-pass kernel (1,024 threads, 142 KB).
+// block per CU); up to 2,048 the pass kernel over quarters of the positions
+// (1,024 threads, 142 KB); up to kK4Cap the pass kernel over sixteenths
+// (150 KB).
 constexpr int kK4BitsMid = 512;
 constexpr int kK4BitsMax = 1024;
 
@@ -154,25 +156,28 @@ __global__ __launch_bounds__(NT) void k_count_k4_bits(int32_t n, int32_t chunk, 
   k4_block_total<NW>(acc, red, total);
 }
 
-// Nodes with kK4BitsMax < d+(u) <= kK4Cap: bit rows over quarters of the
-// positions. Full rows (up to 64 words for 2,048 rows) do not fit in LDS, so
-// the block of 1,024 threads makes one pass per 512 positions: it builds that
-// quarter of every row (16 words, 128 KB for 2,048 rows); then each wavefront
-// streams N+(w) again, places its ids in N+(u), and for every x found (the
-// hits of 64 ids, four x at a time) adds popcount(row w & row x) over the
-// quarter. Summed over the quarters this is the count the full rows give.
-// Nodes are queued from chunks of ids as in the bit-row kernel.
+// Nodes with DMIN < d+(u) <= CAP: bit rows over blocks of PCOLS positions.
+// Full rows (up to CAP / 32 words for CAP rows) do not fit in LDS, so the
+// block of 1,024 threads makes one pass per PCOLS positions: it builds that
+// block of every row (PCOLS / 32 words per row, 128 KB for CAP rows); then
+// each wavefront streams N+(w) again, places its ids in N+(u), and for every
+// x found (the hits of 64 ids, 64 / (PCOLS / 32) x at a time) adds
+// popcount(row w & row x) over the block. Summed over the passes this is the
+// count the full rows give. Nodes are queued from chunks of ids as in the
+// bit-row kernel.
 constexpr int kK4QNT = 1024;
 constexpr int kK4QWaves = kK4QNT / kWave;
-constexpr int kK4QCols = 512;
-constexpr int kK4QWords = kK4QCols / 32;
 
-__global__ __launch_bounds__(kK4QNT) void k_count_k4_quarters(int32_t n, int32_t chunk,
-                                                              const int64_t* __restrict__ doff,
-                                                              const int32_t* __restrict__ dcol,
-                                                              unsigned long long* __restrict__ total) {
-  __shared__ int32_t L[kK4Cap];
-  __shared__ uint32_t B[kK4Cap * kK4QWords];
+template <int DMIN, int CAP, int PCOLS>
+__global__ __launch_bounds__(kK4QNT) void k_count_k4_passes(int32_t n, int32_t chunk,
+                                                            const int64_t* __restrict__ doff,
+                                                            const int32_t* __restrict__ dcol,
+                                                            unsigned long long* __restrict__ total) {
+  constexpr int kK4QCols = PCOLS;
+  constexpr int kK4QWords = PCOLS / 32;
+  static_assert(PCOLS % 32 == 0 && kK4QWords <= kWave && CAP <= 65536, "pass layout");
+  __shared__ int32_t L[CAP];
+  __shared__ uint32_t B[CAP * kK4QWords];
   __shared__ uint16_t H[kK4QWaves][kWave];
   __shared__ unsigned long long red[kK4QWaves];
   __shared__ int32_t Q[kK4QNT];
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(kK4QNT) void k_count_k4_quarters(int32_t n, int32_t
     const int64_t v = base + threadIdx.x;
     if ((int)threadIdx.x < chunk && v < n) {
       const int64_t dv = doff[v + 1] - doff[v];
-      if (dv > kK4BitsMax && dv <= kK4Cap) Q[atomicAdd(&Qn, 1)] = (int32_t)v;
+      if (dv > DMIN && dv <= CAP) Q[atomicAdd(&Qn, 1)] = (int32_t)v;
     }
     __syncthreads();
     const int32_t nq = Qn;
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(kK4QNT) void k_count_k4_quarters(int32_t n, int32_t
       const int32_t u = Q[qi];
       const int64_t ub = doff[u];
       const int32_t d = (int32_t)(doff[u + 1] - ub);
-      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= kK4Cap
+      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= CAP
       __syncthreads();  // L and B of the previous node are no longer read
       for (int32_t i = threadIdx.x; i < P; i += kK4QNT) L[i] = i < d ? dcol[ub + i] : kPad;
       for (int32_t q = 0; q * kK4QCols < d; ++q) {
@@ -274,7 +279,8 @@ hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, 
     const int32_t cb = k4_chunk(n, 1024, 1024);
     k_count_k4_bits<kK4BitsMid, kK4BitsMax, 1024, false><<<k4_grid(n, cb, 1024), 1024, 0, s>>>(n, cb, doff, dcol,
                                                                                                  total);
-    k_count_k4_quarters<<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
+    k_count_k4_passes<kK4BitsMax, 2048, 512><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
+    k_count_k4_passes<2048, kK4Cap, 256><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
   }
   return hipGetLastError();
 }

@@ -211,8 +211,9 @@ hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
 
 // ---- 4-clique counts ---------------------------------------------------------
 // *total = number of 4-cliques, over the DAG N+(v) = dcol[doff[v] ..
-// doff[v+1]) (ascending ids); every d+(v) must be <= kK4Cap.
-constexpr int32_t kK4Cap = 2048;
+// doff[v+1]) (ascending ids); every d+(v) must be <= kK4Cap (bit rows over
+// blocks of positions index at most this many).
+constexpr int32_t kK4Cap = 4096;
 hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* total,
                            hipStream_t s);
 

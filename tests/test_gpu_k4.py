@@ -49,7 +49,8 @@ def test_against_oracle(name):
     assert gpu_k4(g) == ref  # repeat calls
 
 
-@pytest.mark.parametrize("k", [4, 5, 17, 33, 60, 65, 66, 67, 300, 513, 514, 600, 1025, 1026, 1100])
+@pytest.mark.parametrize("k", [4, 5, 17, 33, 60, 65, 66, 67, 300, 513, 514, 600, 1025, 1026, 1100, 2049, 2050,
+                               2100])
 def test_complete_graphs(k):
     n, s, d = F.complete(k)
     assert gpu_k4(P.Graph(n, dev(s), dev(d))) == comb(k, 4)
@@ -85,9 +86,9 @@ def test_rmat17_and_from_csr():
 
 
 def test_out_degree_limit_is_enforced():
-    n, s, d = F.complete(2100)
+    n, s, d = F.complete(4200)
     g = P.Graph(n, dev(s), dev(d))
-    assert g.info["max_outdeg"] > 2048
+    assert g.info["max_outdeg"] > 4096
     with pytest.raises(N.TriccError) as ei:
         g.count_k4()
     assert ei.value.status == N.TRICC_EOVERFLOW
