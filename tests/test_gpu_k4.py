@@ -1,7 +1,10 @@
 """GPU parity of the 4-clique count (tricc_graph_count_k4) against the
 oracle's node iterator: small graphs and closed forms, R-MAT / BA / ER graphs,
 a graph built from a CSR, repeat calls, and the out-degree limit. Counts are
-integers, compared exactly."""
+integers, compared exactly. Complete graphs K_k reach every kernel: out-degrees
+up to 512 (K_513 and below), 513-1,024 (K_514 .. K_1025), the quarter passes
+(K_1026 .. K_2049) and the sixteenth passes (K_2050, K_2100); the dense
+G(1100, 0.6) case takes the 513-1,024 kernel against the oracle."""
 from math import comb
 
 import numpy as np
