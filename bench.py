@@ -479,7 +479,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (this path runs on a "
-              "single device; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "single device; several GPUs would each take a share of the binned work lists and sum "
+              "their per-node counts with one all-reduce)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1606_07550_amd as P
