@@ -179,7 +179,9 @@ class Graph:
         return out, int(mx.value)
 
     def count_k4(self, out=None, stream=None):
-        """Number of 4-cliques: uint64[1] (as an int64 tensor) on the device."""
+        """Number of 4-cliques: uint64[1] (as an int64 tensor) on the device.
+        Asynchronous. Raises TriccError (TRICC_EOVERFLOW) when some out-degree
+        of the degree-ordered DAG exceeds 4,096."""
         if out is None:
             out = torch.empty(1, dtype=torch.int64, device=self.device)
         with torch.cuda.device(self.device):
