@@ -10,8 +10,16 @@ before the timed region, and stays there.
 Prints one JSON line. ``value`` is m / step time, with m the number of
 undirected simple edges (edges/s). ``roofline`` describes the dominant
 intersection kernel (the bin whose kernel takes longest), timed with HIP
-events on the stream it runs on; ``cpu_baseline`` is the CPU oracle timed on
-a bounded sample on this host.
+events on the stream it runs on: its achieved rate is the bytes that kernel
+moves when nothing is reused between its work items (LDS-table lists, row
+bounds, the shorter list streamed per edge, in-list chunks, credits; counted
+exactly on the graph by tricc_graph_stats) over its launch time. The bytes a
+merge of both lists would read (the classic sorted-list measure) are printed
+beside it as a work measure, and the rocprofv3 counters of the same kernel
+(DRAM-side bytes, L2 hit rate) are read from the committed summary while the
+kernel source is unchanged. The other legs (batched graphs, serving, the
+neighbouring methods) each carry their own figures; ``cpu_baseline`` is the
+CPU oracle timed on a stated sample of the benchmarked graph on this host.
 """
 import argparse
 import ctypes
@@ -59,8 +67,11 @@ def parse():
     ap.add_argument("--k4-scale", type=int, default=22, help="4-clique leg: R-MAT scale")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
-    ap.add_argument("--serving", action="store_true", help="add the query-serving leg to the line")
-    ap.add_argument("--serve-queries", type=int, default=20000)
+    ap.add_argument("--no-serving", action="store_true", help="skip the query-serving leg")
+    ap.add_argument("--serve-queries", type=int, default=5000,
+                    help="queries of the serving trace (the first ones of the 20,000-query trace's generator)")
+    ap.add_argument("--serve-lambdas", default="0.5,0.8,0.95",
+                    help="Poisson rates as fractions of the measured saturation rate")
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-gb", type=float, default=24.0, help="server workspace (GB), also the admission budget")
     ap.add_argument("--serve-tune", action="store_true", help="pick the server's batch tuning on a sample first")
@@ -104,20 +115,26 @@ def probe_bandwidth(torch, N, nbytes=2 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def measured_traffic(workload, variant, bin):
-    """HBM traffic per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on this workload, variant and
-    bin with the current intersection-kernel source; else None."""
+def measured_counters(workload, variant, bin):
+    """rocprofv3 counters of the dominant kernel from the committed summary
+    (profiles/counters_<workload>.md): DRAM-side bytes, L2 hit rate and the
+    calibrated FETCH_SIZE + WRITE_SIZE traffic per launch, if they were taken
+    on this workload, variant and bin with the current intersection-kernel
+    source; else None."""
     from paper_1606_07550_amd import profiling
-    rec = profiling.read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                                              f"traffic_{workload}.md"))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"counters_{workload}.md")
+    rec = profiling.read_summary(path)
     if not rec:
         return None
     if rec.get("count_kernels_sha256") != profiling.count_source_sha256() or int(rec.get("variant", -1)) != variant:
         return None
     if "bin" in rec and int(rec["bin"]) != bin:
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    out = {"source": f"profiles/counters_{workload}.md"}
+    for k in ("traffic_bytes_per_launch", "dram_bytes_per_launch", "l2_hit_rate"):
+        if k in rec:
+            out[k] = float(rec[k])
+    return out
 
 
 def batched_leg(args, torch, P, N):
@@ -415,9 +432,13 @@ def edge_query_leg(args, torch, P, N):
 
 def serving_leg(args, torch, P, N):
     """Resident R-MAT scale 22 (edge factor 16, same a,b,c,d); BFS-ball
-    queries of log-uniform size in [16, 100000] (seed 2022). Saturation
-    throughput, then an open-loop Poisson trace at 0.8 x saturation, against
-    a FIFO server that runs one query per launch."""
+    queries of log-uniform size in [16, 100000] (seed 2022; the first
+    --serve-queries of the 20,000-query trace, whose queries are drawn per
+    index). The continuous-batching server's saturation throughput (all
+    queries submitted at once), then open-loop Poisson traces at the given
+    fractions of it; the baseline is a FIFO server with one query per launch,
+    measured the same way (saturation, and Poisson at 0.8 x its own
+    saturation). Latency = completion seen on the host - scheduled arrival."""
     from paper_1606_07550_amd import inputs as I
     dev = torch.device("cuda:0")
     n, s, d = I.rmat(22, 16, seed=22)
@@ -444,20 +465,32 @@ def serving_leg(args, torch, P, N):
         tuning = best[1]
     sat = run_trace(P, N, g, queries, None, args.serve_slots, 256, budget, tuning)
     log(f"saturation: {sat}")
-    lam = 0.8 * sat["qps"]
-    arr = I.poisson_arrivals(Q, lam, 4)
-    arr = arr - arr[0]
-    open_loop = run_trace(P, N, g, queries, arr, args.serve_slots, 256, budget, tuning)
-    log(f"poisson at {lam:.1f}/s: {open_loop}")
+    sweep = []
+    for frac in [float(x) for x in args.serve_lambdas.split(",") if x]:
+        lam = frac * sat["qps"]
+        arr = I.poisson_arrivals(Q, lam, 4)
+        arr = arr - arr[0]
+        r = run_trace(P, N, g, queries, arr, args.serve_slots, 256, budget, tuning)
+        r.update(lambda_frac=frac, lambda_qps=lam)
+        log(f"poisson at {lam:.1f}/s ({frac} x saturation): {r}")
+        sweep.append(r)
     fifo_sat = run_trace(P, N, g, queries, None, 1, 1, budget, tuning)
     log(f"fifo saturation: {fifo_sat}")
+    lam_f = 0.8 * fifo_sat["qps"]
+    arr = I.poisson_arrivals(Q, lam_f, 4)
+    fifo_pois = run_trace(P, N, g, queries, arr - arr[0], 1, 1, budget, tuning)
+    fifo_pois.update(lambda_frac=0.8, lambda_qps=lam_f)
+    log(f"fifo poisson at {lam_f:.1f}/s: {fifo_pois}")
+    main_pt = min(sweep, key=lambda r: abs(r["lambda_frac"] - 0.8)) if sweep else sat
     return {
         "workload": f"serving-rmat22-{Q}", "resident": {"n": n, "m": g.info["m"]},
         "queries": Q, "query_nodes": int(off[-1]), "slots": args.serve_slots, "budget_bytes": budget,
         "tuning": tuning,
-        "saturation": sat, "lambda_qps": lam, "poisson": open_loop,
-        "fifo_per_query": {"saturation": fifo_sat},
-        "p50_ms": open_loop["p50_ms"], "p99_ms": open_loop["p99_ms"], "qps": open_loop["qps"],
+        "qps": main_pt["qps"], "p50_ms": main_pt["p50_ms"], "p99_ms": main_pt["p99_ms"],
+        "lambda_qps": main_pt.get("lambda_qps"), "lambda_frac": main_pt.get("lambda_frac"),
+        "saturation": sat, "poisson_sweep": sweep,
+        "fifo_per_query": {"saturation": fifo_sat, "poisson": fifo_pois},
+        "speedup_vs_fifo_saturation": sat["qps"] / fifo_sat["qps"],
     }
 
 
@@ -577,13 +610,17 @@ def main():
     # dominant intersection kernel
     avg_bin_ms = [bin_ms[b] / bin_launches[b] if bin_launches[b] else 0.0 for b in range(nb)]
     dom = max(range(nb), key=lambda b: avg_bin_ms[b])
-    dom_bytes = 4 * info["bin_list_elems"][dom] + 4 * info["bin_edges"][dom]
-    achieved = dom_bytes / (avg_bin_ms[dom] * 1e-3) / 1e9 if avg_bin_ms[dom] > 0 else 0.0
+    dom_s = avg_bin_ms[dom] * 1e-3
+    dom_kbytes = info["bin_kernel_bytes"][dom]
+    dom_merge = 4 * info["bin_list_elems"][dom] + 4 * info["bin_edges"][dom]
+    achieved = dom_kbytes / dom_s / 1e9 if dom_s > 0 else 0.0
     stage_bytes = 4 * info["list_elems"] + 4 * m + 8 * (n + 1) + 12 * n
+    stage_kbytes = sum(info["bin_kernel_bytes"]) + 8 * (n + 1) + 12 * n
     a6_ms = sum(avg_bin_ms)
     tuning_used = (tuning or P.default_tuning()).as_dict()
     variant = tuning_used["bin_variant"][dom]
-    traffic = measured_traffic(cfg["workload"], variant, dom)
+    prof = measured_counters(cfg["workload"], variant, dom)
+    traffic = prof.get("traffic_bytes_per_launch") if prof else None
     bw, _ = probe_bandwidth(torch, N)
     line = {
         "metric": METRIC,
@@ -609,17 +646,29 @@ def main():
             "traffic": traffic,
             "kernel": f"intersection bin {dom} (variant {variant})",
             "kernel_ms": avg_bin_ms[dom],
-            "alg_bytes_per_launch": dom_bytes,
-            # algorithmic bytes count list reads that caches serve (frac > 1 is
-            # cache reuse); the measured DRAM traffic gives the HBM-side rate
-            "traffic_GBps": traffic / (avg_bin_ms[dom] * 1e-3) / 1e9 if traffic else None,
-            "traffic_frac": traffic / (avg_bin_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBPS if traffic else None,
+            # bytes the min-side kernel moves with no reuse between its work
+            # items (exact count on this graph); the merge measure (both lists
+            # read per edge) is a work measure, not a bandwidth
+            "alg_bytes_per_launch": dom_kbytes,
+            "merge_bytes_per_launch": dom_merge,
+            "merge_GBps": dom_merge / dom_s / 1e9 if dom_s > 0 else 0.0,
+            # rocprofv3 counters of this kernel (committed summary; null once
+            # the kernel source has changed since they were taken)
+            "traffic_GBps": traffic / dom_s / 1e9 if traffic else None,
+            "traffic_frac": traffic / dom_s / 1e9 / HBM_PEAK_GBPS if traffic else None,
+            "l2_hit_rate": prof.get("l2_hit_rate") if prof else None,
+            "dram_bytes_per_launch": prof.get("dram_bytes_per_launch") if prof else None,
+            "counters": prof.get("source") if prof else None,
         },
-        "stage_a6": {"ms": a6_ms, "alg_bytes": stage_bytes,
+        "stage_a6": {"ms": a6_ms, "kernel_bytes": stage_kbytes,
+                     "kernel_GBps": stage_kbytes / (a6_ms * 1e-3) / 1e9 if a6_ms else 0.0,
+                     "kernel_frac": stage_kbytes / (a6_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if a6_ms else 0.0,
+                     "merge_bytes": stage_bytes,
                      "compulsory_bytes": 4 * m + 8 * (n + 1) + 12 * n,
-                     "achieved_GBps": stage_bytes / (a6_ms * 1e-3) / 1e9 if a6_ms else 0.0,
-                     "frac": stage_bytes / (a6_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if a6_ms else 0.0,
-                     "bin_ms": avg_bin_ms, "bin_count": info["bin_count"]},
+                     "bin_ms": avg_bin_ms, "bin_count": info["bin_count"],
+                     "bin_kernel_bytes": info["bin_kernel_bytes"],
+                     "bin_kernel_GBps": [info["bin_kernel_bytes"][b] / (avg_bin_ms[b] * 1e-3) / 1e9
+                                         if avg_bin_ms[b] > 0 else 0.0 for b in range(nb)]},
         "count_only": {"ms": count_ms, "edges_per_s": m / (count_ms * 1e-3)},
         "build_ms": 1e3 * build_s / args.steps,
         "probe_copy_GBps": bw,
@@ -641,7 +690,7 @@ def main():
     if not args.no_edge_queries:
         log("edge-existence leg ...")
         line["edge_queries"] = edge_query_leg(args, torch, P, N)
-    if args.serving:
+    if not args.no_serving:
         log("serving leg ...")
         line["serving"] = serving_leg(args, torch, P, N)
     if not args.no_cpu_baseline:

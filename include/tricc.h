@@ -13,7 +13,7 @@
  *   N(v)  = neighbours of v, d(v) = |N(v)|  (Section 5.1: a sorted vector of
  *           adjacent nodes per node)
  *   T(v)  = number of triangles that contain v
- *   T     = number of triangles = sum_v T(v) / 3
+ *   T     = number of triangles (each counted once; sum_v T(v) = 3 T)
  *   CC(v) = 2 T(v) / (d(v) (d(v) - 1)) if d(v) >= 2, else 0   (FP32)
  *   avg   = (1/n) sum over all n node ids of CC(v)             (FP64)
  *
@@ -84,6 +84,9 @@ typedef struct tricc_graph_info {
   int64_t bin_in_items[TRICC_NUM_BINS];    /* in-list work items of each bin (min-side) */
   int64_t n_deg2;              /* nodes with d(v) >= 2; the average CC over these nodes alone is
                                   avg * n / n_deg2 (every other node has CC 0) */
+  uint64_t bin_kernel_bytes[TRICC_NUM_BINS]; /* bytes each bin's min-side kernel reads and writes when
+                                  nothing is reused between its work items: out-list tables, row
+                                  bounds, streamed (shorter) lists, in-list chunks, credits (*) */
   /* (*) zero until tricc_graph_stats has run */
 } tricc_graph_info;
 
@@ -99,9 +102,17 @@ int tricc_version(void);
 int tricc_default_tuning(tricc_tuning* out);
 /* Largest d+ a kernel variant accepts; -1 if the variant does not exist. */
 int tricc_variant_capacity(int variant);
-/* Number of kernel variants (valid ids are 0 .. count-1). */
+/* Number of kernel variants (valid ids are 0 .. count-1):
+ *   0..7    LDS bucket tables (capacities 16, 64, 256, 1024, 4096, 1024,
+ *           2048, 256), one node per group of 64..1024 lanes
+ *   8       N+(u) binary-searched in HBM (any d+)
+ *   9       N+(u) as a bitmap over all ids in HBM (any d+; the default for
+ *           nodes above every LDS table)
+ *   10..17  as 0..7 with two-choice cuckoo tables
+ *   18, 19  cuckoo tables for d+ <= 128 and <= 256, two wavefronts per node */
 int tricc_variant_count(void);
-/* 1 if the variant implements both sides of the min-side split. */
+/* 1 if the variant implements both sides of the min-side split (every
+ * variant but 8 and 9). */
 int tricc_variant_min_side(int variant);
 
 /* Bytes of device workspace tricc_graph_build needs for (n, m_raw). */
@@ -168,9 +179,15 @@ int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream)
  * and the average. Asynchronous on `stream`.
  *   d_node_tri  device uint64[n] (overwritten)
  *   d_node_cc   device float[n]
- *   d_total     device uint64[1]
+ *   d_total     device uint64[1]: the number of triangles as the
+ *               intersection kernels found them (each triangle is found by
+ *               one node group, which adds it to the total), accumulated
+ *               apart from d_node_tri; sum_v T(v) = 3 * total holds when
+ *               both are right (tricc_count_check)
  *   d_avg_cc    device double[1]; the FP64 sum is taken in a fixed order,
  *               so repeated calls give bit-identical results.
+ * Counts of one graph must not overlap in time (they share the graph's
+ * workspace counters and hub bitmaps).
  */
 int tricc_count(tricc_graph* g, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
                 double* d_avg_cc, void* stream);
@@ -186,6 +203,11 @@ int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream);
 int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream);
 int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
                        double* d_avg_cc, void* stream);
+
+/* After a count of g: its total and the sum of its per-node counts, as the
+ * device computed them (the sum is taken by the epilogue, the total by the
+ * intersection kernels). Synchronises `stream`. */
+int tricc_count_check(const tricc_graph* g, uint64_t* h_total, uint64_t* h_sum_T, void* stream);
 
 /* Streaming copy of `bytes` (a multiple of 16, both pointers 16-byte
  * aligned) from d_src to d_dst: the reference kernel for achievable HBM
@@ -334,14 +356,18 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
  *   d_graph_tri device uint64[G]   triangles of each graph
  *   d_graph_avg device double[G]   average CC of each graph over its n_g
  *               nodes, summed in a fixed order that depends only on the graph
+ *   d_batch_tri device uint64[1] or NULL: triangles of the whole batch as the
+ *               intersection kernels found them, accumulated apart from the
+ *               per-node counts (it equals the sum of d_graph_tri when both
+ *               are right)
  * The buffers must stay valid while the plan is used. Synchronises. */
 int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
-                     double* d_graph_avg, void* stream);
+                     double* d_graph_avg, uint64_t* d_batch_tri, void* stream);
 
 /* Binds the outputs without capturing a graph (for tricc_batch_run_eager
  * only; a later tricc_batch_plan rebinds). Same buffers as tricc_batch_plan. */
 int tricc_batch_bind(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
-                     double* d_graph_avg);
+                     double* d_graph_avg, uint64_t* d_batch_tri);
 
 /* One hipGraphLaunch of the planned count. Asynchronous. Calls on one
  * batch must not overlap (they share the accumulators). */

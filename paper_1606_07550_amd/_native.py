@@ -52,14 +52,15 @@ class GraphInfo(ctypes.Structure):
                 ("bin_count", ctypes.c_int64 * NUM_BINS), ("list_elems", ctypes.c_uint64),
                 ("large_rows", ctypes.c_int64), ("bin_list_elems", ctypes.c_uint64 * NUM_BINS),
                 ("bin_edges", ctypes.c_int64 * NUM_BINS), ("bin_in_items", ctypes.c_int64 * NUM_BINS),
-                ("n_deg2", ctypes.c_int64)]
+                ("n_deg2", ctypes.c_int64), ("bin_kernel_bytes", ctypes.c_uint64 * NUM_BINS)]
 
     def as_dict(self):
         return {"n": self.n, "m_raw": self.m_raw, "m": self.m, "max_deg": self.max_deg,
                 "max_outdeg": self.max_outdeg, "bin_count": list(self.bin_count),
                 "list_elems": int(self.list_elems), "large_rows": self.large_rows,
                 "bin_list_elems": [int(x) for x in self.bin_list_elems], "bin_edges": list(self.bin_edges),
-                "bin_in_items": list(self.bin_in_items), "n_deg2": self.n_deg2}
+                "bin_in_items": list(self.bin_in_items), "n_deg2": self.n_deg2,
+                "bin_kernel_bytes": list(self.bin_kernel_bytes)}
 
 
 class BatchTuning(ctypes.Structure):
@@ -125,6 +126,7 @@ _SIGS = {
     "tricc_count_begin": (ctypes.c_int, [_P, _P, _P]),
     "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "tricc_count_finish": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tricc_count_check": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), _P]),
     "tricc_probe_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "tricc_gen_rmat": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_double] * 5
                        + [ctypes.c_uint64, _P, _P, _P, _P]),
@@ -136,8 +138,8 @@ _SIGS = {
                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "tricc_batch_build": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                          ctypes.POINTER(BatchTuning), _P, ctypes.POINTER(_P)]),
-    "tricc_batch_plan": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
-    "tricc_batch_bind": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "tricc_batch_plan": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "tricc_batch_bind": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "tricc_batch_run": (ctypes.c_int, [_P, _P]),
     "tricc_batch_run_eager": (ctypes.c_int, [_P, _P]),
     "tricc_batch_retune": (ctypes.c_int, [_P, ctypes.POINTER(BatchTuning), _P]),

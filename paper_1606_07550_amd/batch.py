@@ -75,13 +75,30 @@ class Batch:
             "cc": torch.empty(max(self.n_total, 0), dtype=torch.float32, device=dev),
             "graph_tri": torch.empty(max(self.G, 0), dtype=torch.int64, device=dev),
             "graph_avg": torch.empty(max(self.G, 0), dtype=torch.float64, device=dev),
+            "batch_tri": torch.zeros(1, dtype=torch.int64, device=dev),
         }
         o = self.out
         with torch.cuda.device(dev):
             rc = N.lib().tricc_batch_plan(self._h, _ptr(o["T"]), _ptr(o["cc"]), _ptr(o["graph_tri"]),
-                                          _ptr(o["graph_avg"]), _stream_ptr(stream))
+                                          _ptr(o["graph_avg"]), _ptr(o["batch_tri"]), _stream_ptr(stream))
         N.check(rc, "tricc_batch_plan")
         return o
+
+    def graph_arrays(self):
+        """Device views (slices of the workspace) of the union graph: deg
+        int32[total nodes] (degrees in each member's simple graph) and doff
+        int64[total nodes + 1] (its DAG offsets)."""
+        h = N.lib().tricc_batch_graph(self._h)
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        N.check(N.lib().tricc_graph_arrays(h, *[ctypes.byref(p) for p in ptrs]), "tricc_graph_arrays")
+        base = self.ws.data_ptr()
+
+        def view(p, dtype, count):
+            off = p.value - base
+            esz = torch.empty((), dtype=dtype).element_size()
+            return self.ws[off:off + count * esz].view(dtype)
+
+        return {"deg": view(ptrs[1], torch.int32, self.n_total), "doff": view(ptrs[3], torch.int64, self.n_total + 1)}
 
     def run(self, stream=None):
         N.check(N.lib().tricc_batch_run(self._h, _stream_ptr(stream)), "tricc_batch_run")

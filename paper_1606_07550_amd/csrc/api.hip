@@ -53,12 +53,15 @@ enum : int {
   kHdrInOff = 160,    // int64[kNumBins + 1] at byte 640: in-list bin boundaries
   kHdrInCap = 176,    // int32[kNumBins] at byte 704: chunk size of each bin
   kHdrInItems = 184,  // int64[kNumBins + 1] at byte 736: chunk prefix at the boundaries
+  kHdrCheck = 200,    // u64[2] at byte 800: the last count's total and sum of T(v)
+  kHdrBinKBytes = 208, // u64[kNumBins] at byte 832: modelled kernel bytes per bin
 };
 constexpr size_t kHdrBytes = 1024;
 
 struct Layout {
   size_t hdr, raw_off, len, deg, dplus, doff, scan_tmp, rowlist, binlist, adj, tmp, dcol, part_cc,
-      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, hubmap, rec, total;
+      part_T, meta, cls_hist, cls_off, din, dinoff, dincol, inlist, inch, incoff, part, hubmap, rec, tot,
+      total;
   int64_t cls_nblk;
   int64_t max_jobs;
 };
@@ -96,6 +99,7 @@ Layout make_layout(int64_t n, int64_t m_raw) {
   L.part = take(2 * sizeof(uint32_t) * kPartMaxParts + 2 * sizeof(int64_t) * (kPartMaxParts + 1));
   L.hubmap = take(sizeof(uint32_t) * (size_t)hub_map_words(n) * (size_t)hub_map_slots(n));
   L.rec = take(sizeof(int32_t) * 2 * n);  // edge-existence records (row start, degree)
+  L.tot = take(sizeof(unsigned long long) * kTotSlots);  // triangle-total counters
   L.total = p;
   return L;
 }
@@ -268,6 +272,7 @@ int bin_nodes(tricc_graph* g) {
     g->info.bin_count[b] = cnt;
     g->info.bin_list_elems[b] = 0;
     g->info.bin_edges[b] = 0;
+    g->info.bin_kernel_bytes[b] = 0;
     if (!cnt) continue;
     int64_t bound = g->info.max_outdeg;
     if (b < kNumBins - 1) bound = std::min<int64_t>(bound, g->tuning.bin_limit[b]);
@@ -309,19 +314,24 @@ int graph_stats(tricc_graph* g) {
   unsigned long long* d_elems = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinElems * 4);
   unsigned long long* d_edges = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinEdges * 4);
   unsigned long long* d_all = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrListElems * 4);
+  unsigned long long* d_kb = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrBinKBytes * 4);
   HIPCHK(hipMemsetAsync(d_elems, 0, sizeof(unsigned long long) * 2 * kNumBins, s));
+  HIPCHK(hipMemsetAsync(d_kb, 0, sizeof(unsigned long long) * kNumBins, s));
   HIPCHK(hipMemsetAsync(d_all, 0, sizeof(unsigned long long), s));
-  HIPCHK(launch_bin_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), g->hdr32() + kHdrLimits,
-                          g->tuning.min_side ? g->tuning.bin_limit[kNumBins - 2] : 0, d_elems, d_edges, s));
+  HIPCHK(launch_bin_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), g->at<int32_t>(L.din),
+                          g->hdr32() + kHdrLimits, g->hdr32() + kHdrInCap,
+                          g->tuning.min_side ? g->tuning.bin_limit[kNumBins - 2] : 0, d_elems, d_edges, d_kb, s));
   HIPCHK(launch_list_elems(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), d_all, s));
   unsigned long long be[2 * kNumBins];
   int rc = sync_copy(be, d_elems, sizeof(be), s);
   if (rc) return rc;
-  unsigned long long all = 0;
+  unsigned long long all = 0, kb[kNumBins];
   if ((rc = sync_copy(&all, d_all, sizeof(all), s))) return rc;
+  if ((rc = sync_copy(kb, d_kb, sizeof(kb), s))) return rc;
   for (int b = 0; b < kNumBins; ++b) {
     g->info.bin_list_elems[b] = be[b];
     g->info.bin_edges[b] = (int64_t)be[kNumBins + b];
+    g->info.bin_kernel_bytes[b] = kb[b];
   }
   g->info.list_elems = all;
   return TRICC_OK;
@@ -447,7 +457,7 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
   static const int32_t lim[kNumBins - 1] = {64, 256, 1024, 2048, 4096};
-  static const int32_t var[kNumBins] = {29, 47, 43, 44, 42, 37};
+  static const int32_t var[kNumBins] = {1, 19, 15, 16, 14, 9};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;
@@ -626,7 +636,8 @@ int tricc_graph_retune(tricc_graph* g, const tricc_tuning* tuning, void* stream)
 int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream) {
   if (!g) return fail(TRICC_EINVAL, "null graph");
   if (g->n > 0 && !d_node_tri) return fail(TRICC_EINVAL, "null output");
-  HIPCHK(launch_zero_u64(reinterpret_cast<unsigned long long*>(d_node_tri), g->n, static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_zero_counts(reinterpret_cast<unsigned long long*>(d_node_tri), g->n,
+                            g->at<unsigned long long>(g->L.tot), static_cast<hipStream_t>(stream)));
   return TRICC_OK;
 }
 
@@ -651,7 +662,8 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
   bl.hub_slots = hub_map_slots(g->n);
   bl.map_words = hub_map_words(g->n);
   HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
-                          reinterpret_cast<unsigned long long*>(d_node_tri), static_cast<hipStream_t>(stream)));
+                          reinterpret_cast<unsigned long long*>(d_node_tri), g->at<unsigned long long>(L.tot),
+                          static_cast<hipStream_t>(stream)));
   return TRICC_OK;
 }
 
@@ -665,8 +677,20 @@ int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node
   unsigned long long* part_T = g->at<unsigned long long>(L.part_T);
   const unsigned long long* T = reinterpret_cast<const unsigned long long*>(d_node_tri);
   HIPCHK(launch_epilogue(g->n, T, g->at<int32_t>(L.deg), d_node_cc, part_cc, part_T, s));
-  HIPCHK(launch_finish(epilogue_blocks(g->n), g->n, part_cc, part_T,
-                       reinterpret_cast<unsigned long long*>(d_total), d_avg_cc, s));
+  unsigned long long* check = reinterpret_cast<unsigned long long*>(g->ws + L.hdr + kHdrCheck * 4);
+  HIPCHK(launch_finish(epilogue_blocks(g->n), g->n, part_cc, part_T, g->at<unsigned long long>(L.tot),
+                       reinterpret_cast<unsigned long long*>(d_total), d_avg_cc, check + 1, s));
+  HIPCHK(hipMemcpyAsync(check, d_total, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+  return TRICC_OK;
+}
+
+int tricc_count_check(const tricc_graph* g, uint64_t* h_total, uint64_t* h_sum_T, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  unsigned long long v[2];
+  int rc = sync_copy(v, g->ws + g->L.hdr + kHdrCheck * 4, sizeof(v), static_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  if (h_total) *h_total = v[0];
+  if (h_sum_T) *h_sum_T = v[1];
   return TRICC_OK;
 }
 
@@ -843,6 +867,7 @@ struct tricc_batch {
   float* cc = nullptr;
   unsigned long long* graph_tri = nullptr;
   double* graph_avg = nullptr;
+  unsigned long long* batch_tri = nullptr;
   bool bound = false;
 };
 
@@ -887,12 +912,19 @@ int check_batch_tuning(const tricc_batch_tuning* t) {
 // global fallback), run in the persistent kernel; bins 3 (up to 1024) and 4
 // (up to 4096) run before it with the large-table kernel variants. The
 // single-graph variants are set so that tricc_count also works on the union.
-constexpr int kBatchVarBin3 = 43;  // 512 threads, cuckoo table for d+ <= 1024
-constexpr int kBatchVarBin4 = 42;  // 1024 threads, cuckoo table for d+ <= 4096
+constexpr int kBatchVarBin3 = 15;  // 512 threads, cuckoo table for d+ <= 1024
+constexpr int kBatchVarBin4 = 14;  // 1024 threads, cuckoo table for d+ <= 4096
+// variants for bins 0..2 and 5 when tricc_count runs on the union graph
+// (min_side 0: every edge counted from its tail)
+constexpr int kBatchVarWave = 11;       // one wavefront per node, d+ <= 64
+constexpr int kBatchVarBlock256 = 12;   // d+ <= 256
+constexpr int kBatchVarBlock1024 = 13;  // d+ <= 1024
+constexpr int kBatchVarGlobal = 8;
 void batch_graph_tuning(const tricc_batch_tuning& bt, tricc_tuning* t) {
   const int32_t cb = persist_block_cap(bt.persist_variant);
   const int32_t lim[kNumBins - 1] = {bt.merge_limit, bt.wave_limit, cb, std::max(cb, 1024), 4096};
-  const int32_t var[kNumBins] = {26, 22, cb <= 256 ? 23 : 24, kBatchVarBin3, kBatchVarBin4, 36};
+  const int32_t var[kNumBins] = {kBatchVarWave, kBatchVarWave, cb <= 256 ? kBatchVarBlock256 : kBatchVarBlock1024,
+                                 kBatchVarBin3, kBatchVarBin4, kBatchVarGlobal};
   std::memcpy(t->bin_limit, lim, sizeof(lim));
   std::memcpy(t->bin_variant, var, sizeof(var));
   t->min_side = 0;
@@ -916,11 +948,12 @@ int batch_launch(tricc_batch* b, hipStream_t s) {
   tricc_graph* g = &b->g;
   const Layout& L = g->L;
   const int32_t* binlist = g->at<int32_t>(L.binlist);
-  HIPCHK(launch_batch_zero(b->T, b->n_total, b->d_queue, s));
+  unsigned long long* tot = g->at<unsigned long long>(L.tot);
+  HIPCHK(launch_batch_zero(b->T, b->n_total, tot, b->d_queue, s));
   // the heaviest nodes first, with the large LDS tables
   for (int bin = 4; bin >= 3; --bin) {
     BinLaunch bl{g->tuning.bin_variant[bin], binlist + g->bin_off[bin], (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin])};
-    HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, s));
+    HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, tot, s));
   }
   const int32_t nm = (int32_t)(g->bin_off[1] - g->bin_off[0]);
   const int32_t nw = (int32_t)(g->bin_off[2] - g->bin_off[1]);
@@ -928,9 +961,9 @@ int batch_launch(tricc_batch* b, hipStream_t s) {
   const int32_t ng = (int32_t)(g->bin_off[kNumBins] - g->bin_off[kNumBins - 1]);
   HIPCHK(launch_count_persist(b->tuning.persist_variant, b->grid, binlist + g->bin_off[kNumBins - 1], ng,
                               binlist + g->bin_off[2], nbk, binlist + g->bin_off[1], nw, binlist + g->bin_off[0], nm,
-                              b->d_queue, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, s));
+                              b->d_queue, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, tot, s));
   HIPCHK(launch_graph_epilogue(b->G, b->d_node_off, b->T, g->at<int32_t>(L.deg), b->cc, b->graph_tri, b->graph_avg,
-                               s));
+                               tot, b->batch_tri, s));
   return TRICC_OK;
 }
 
@@ -1032,7 +1065,7 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
 }
 
 int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri, double* d_graph_avg,
-                     void* stream) {
+                     uint64_t* d_batch_tri, void* stream) {
   if (!b) return fail(TRICC_EINVAL, "null batch");
   if ((b->n_total > 0 && (!d_node_tri || !d_node_cc)) || (b->G > 0 && (!d_graph_tri || !d_graph_avg)))
     return fail(TRICC_EINVAL, "null output");
@@ -1041,6 +1074,7 @@ int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uin
   b->cc = d_node_cc;
   b->graph_tri = reinterpret_cast<unsigned long long*>(d_graph_tri);
   b->graph_avg = d_graph_avg;
+  b->batch_tri = reinterpret_cast<unsigned long long*>(d_batch_tri);
   b->bound = true;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipStreamSynchronize(s));
@@ -1069,7 +1103,7 @@ int tricc_batch_plan(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uin
 }
 
 int tricc_batch_bind(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_graph_tri,
-                     double* d_graph_avg) {
+                     double* d_graph_avg, uint64_t* d_batch_tri) {
   if (!b) return fail(TRICC_EINVAL, "null batch");
   if ((b->n_total > 0 && (!d_node_tri || !d_node_cc)) || (b->G > 0 && (!d_graph_tri || !d_graph_avg)))
     return fail(TRICC_EINVAL, "null output");
@@ -1078,6 +1112,7 @@ int tricc_batch_bind(tricc_batch* b, uint64_t* d_node_tri, float* d_node_cc, uin
   b->cc = d_node_cc;
   b->graph_tri = reinterpret_cast<unsigned long long*>(d_graph_tri);
   b->graph_avg = d_graph_avg;
+  b->batch_tri = reinterpret_cast<unsigned long long*>(d_batch_tri);
   b->bound = true;
   return TRICC_OK;
 }

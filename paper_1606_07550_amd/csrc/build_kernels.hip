@@ -1504,44 +1504,79 @@ __device__ __forceinline__ int bin_of(int32_t d, const int32_t* lim) {
   return b;
 }
 
+// Per bin b, over the DAG edges u->w that bin b's kernel counts (min-side
+// ownership with w_max; w_max = 0 counts every edge from its tail):
+//   elems[b]  sum of d+(u) + d+(w) (what a merge of both lists reads)
+//   edges[b]  number of such edges
+//   kbytes[b] bytes the min-side kernel moves for the bin when nothing is
+//             reused between its work items: per out-list item u, its row
+//             bounds (16), N+(u) for the table (4 d+(u)), the row bounds of
+//             every w (16 d+(u)) and the T credits (8 (d+(u) + 1)); per
+//             streamed list its ids (4 per id); per in-list chunk of w (din
+//             in-neighbours, chunks of cap[b]), its bounds (32), N+(w) for
+//             the table and the credits (12 d+(w) + 8); per in-neighbour its
+//             entry and row bounds (20) and, if its list is streamed, its
+//             credit (8).
 __global__ __launch_bounds__(256) void k_bin_elems(int32_t n, const int64_t* __restrict__ doff,
                                                    const int32_t* __restrict__ dcol,
-                                                   const int32_t* __restrict__ limit, int32_t w_max,
+                                                   const int32_t* __restrict__ din,
+                                                   const int32_t* __restrict__ limit,
+                                                   const int32_t* __restrict__ cap, int32_t w_max,
                                                    unsigned long long* __restrict__ elems,
-                                                   unsigned long long* __restrict__ edges) {
+                                                   unsigned long long* __restrict__ edges,
+                                                   unsigned long long* __restrict__ kbytes) {
   int32_t lim[kNumBins - 1];
 #pragma unroll
   for (int q = 0; q < kNumBins - 1; ++q) lim[q] = limit[q];
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int l = lane_id();
-  unsigned long long acc[kNumBins] = {}, eacc[kNumBins] = {};
+  unsigned long long acc[kNumBins] = {}, eacc[kNumBins] = {}, kacc[kNumBins] = {};
   for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < n; u += nwaves) {
     const int64_t beg = doff[u], end = doff[u + 1];
     const int32_t du = (int32_t)(end - beg);
-    if (du < 2) continue;
     const int bu = bin_of(du, lim);
+    if (l == 0) {
+      unsigned long long kb = 0;
+      if (du >= 2) kb += 16ull + 28ull * (unsigned long long)du + 8ull;
+      const int32_t di = din ? din[u] : 0;
+      if (w_max > 0 && du >= 3 && du <= w_max && di >= 1) {
+        const int32_t c = max(1, cap[bu]);
+        const unsigned long long chunks = (unsigned long long)((di + c - 1) / c);
+        kb += chunks * (40ull + 12ull * (unsigned long long)du) + 20ull * (unsigned long long)di;
+      }
+#pragma unroll
+      for (int q = 0; q < kNumBins; ++q)
+        if (q == bu) kacc[q] += kb;
+    }
+    if (du < 2) continue;
     for (int64_t p = beg + l; p < end; p += kWave) {
       const int32_t w = dcol[p];
       const int32_t dw = (int32_t)(doff[w + 1] - doff[w]);
-      const int b = (du < dw && dw <= w_max) ? bin_of(dw, lim) : bu;
+      const bool in_side = du < dw && dw <= w_max;
+      const int b = in_side ? bin_of(dw, lim) : bu;
+      const unsigned long long kb = in_side ? 4ull * (unsigned long long)du + 8ull : 4ull * (unsigned long long)dw;
 #pragma unroll
       for (int q = 0; q < kNumBins; ++q)
-        if (q == b) { acc[q] += (unsigned long long)(du + dw); eacc[q] += 1; }
+        if (q == b) { acc[q] += (unsigned long long)(du + dw); eacc[q] += 1; kacc[q] += kb; }
     }
   }
 #pragma unroll
   for (int q = 0; q < kNumBins; ++q) {
     const unsigned long long a = group_sum<unsigned long long, kWave>(acc[q]);
     const unsigned long long e = group_sum<unsigned long long, kWave>(eacc[q]);
+    const unsigned long long k = group_sum<unsigned long long, kWave>(kacc[q]);
     if (l == 0 && a) atomicAdd(&elems[q], a);
     if (l == 0 && e) atomicAdd(&edges[q], e);
+    if (l == 0 && k) atomicAdd(&kbytes[q], k);
   }
 }
 
-hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* limit,
-                            int32_t w_max, unsigned long long* elems, unsigned long long* edges, hipStream_t s) {
+hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* din,
+                            const int32_t* limit, const int32_t* cap, int32_t w_max, unsigned long long* elems,
+                            unsigned long long* edges, unsigned long long* kbytes, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_bin_elems<<<grid_for((int64_t)n * kWave, 256, 1u << 14), 256, 0, s>>>(n, doff, dcol, limit, w_max, elems, edges);
+  k_bin_elems<<<grid_for((int64_t)n * kWave, 256, 1u << 14), 256, 0, s>>>(n, doff, dcol, din, limit, cap, w_max,
+                                                                         elems, edges, kbytes);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@
 // Nodes are binned by d+(u); a bin's variant fixes the lane-group size G
 // that owns one node, the sub-group size SG that streams one N+(w), and the
 // table size SLOTS (at most half full).
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -28,6 +30,14 @@ template <int G>
 __device__ __forceinline__ void group_sync() {
   if constexpr (G > kWave) __syncthreads();
   else wave_sync();
+}
+
+// The triangle total is accumulated apart from the per-node counts T: each
+// triangle is found by exactly one node group (at its DAG edge u->w, as a
+// common x), and that group adds the number it found to one of kTotSlots
+// counters, chosen by block so that no single address takes every atomic.
+__device__ __forceinline__ void credit_total(unsigned long long* tot, unsigned long long t) {
+  if (t) atomicAdd(&tot[blockIdx.x & (kTotSlots - 1)], t);
 }
 
 // Open-addressing table of NB buckets of 4 int32 keys (-1 = empty), probed
@@ -67,124 +77,6 @@ __device__ __forceinline__ int table_find(const int32_t* K, int32_t x) {
 
 }  // namespace
 
-// NT threads per block; groups of G lanes (G divides NT, or G == NT) each own
-// one node u; sub-groups of SG lanes stream one N+(w) each, in 16-byte chunks,
-// with the next chunk (possibly of the next w) loaded before the current one
-// is probed. The row bounds of every w in N+(u) and w's table slot are staged
-// in LDS up front.
-template <int NT, int G, int SG, int SLOTS>
-__global__ __launch_bounds__(NT) void k_count_hash(const int32_t* __restrict__ list, int32_t nlist,
-                                                   const int64_t* __restrict__ doff,
-                                                   const int32_t* __restrict__ dcol,
-                                                   unsigned long long* __restrict__ T) {
-  static_assert(NT % G == 0 && G % SG == 0 && SG <= kWave && SLOTS % 4 == 0, "shape");
-  constexpr int GPB = NT / G;
-  constexpr int NSUB = G / SG;
-  constexpr int CAP = SLOTS / 2;
-  constexpr int NB = SLOTS / 4;
-  __shared__ int4 Ks[GPB][NB];
-  __shared__ uint32_t Cs[GPB][SLOTS];
-  __shared__ int32_t Wb[GPB][CAP];  // N+(w) begins (offsets < 2^30)
-  __shared__ int32_t Wn[GPB][CAP];  // |N+(w)|
-  __shared__ int32_t Ws[GPB][CAP];  // slot of w
-  __shared__ unsigned long long red[NT / kWave];
-  const int gi = threadIdx.x / G;
-  const int g = threadIdx.x % G;
-  const int idx = blockIdx.x * GPB + gi;
-  const int4* Kb = Ks[gi];
-  int32_t* K = reinterpret_cast<int32_t*>(Ks[gi]);
-  uint32_t* C = Cs[gi];
-  const bool active = idx < nlist;
-  unsigned long long tu = 0;
-  int32_t u = 0;
-  int64_t beg = 0;
-  int32_t len = 0;  // an inactive group runs every phase with an empty list,
-  if (active) {     // so barriers are reached by all threads of the block
-    u = list[idx];
-    beg = doff[u];
-    len = (int32_t)(doff[u + 1] - beg);
-  }
-  {
-    for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
-    group_sync<G>();
-    for (int i = g; i < len; i += G) {
-      const int32_t w = dcol[beg + i];
-      Ws[gi][i] = bucket_insert<NB>(K, w);
-      const int64_t b = doff[w];
-      Wb[gi][i] = (int32_t)b;
-      Wn[gi][i] = (int32_t)(doff[w + 1] - b);
-    }
-    group_sync<G>();
-    const int sub = g / SG, sg = g % SG;
-    int i = sub;
-    int32_t wb = 0, we = 0, ws = 0, cb = 0;
-    if (i < len) { wb = Wb[gi][i]; we = wb + Wn[gi][i]; ws = Ws[gi][i]; cb = wb & ~3; }
-    int4 cur = make_int4(-1, -1, -1, -1);
-    if (i < len && cb + 4 * sg < we) cur = *reinterpret_cast<const int4*>(dcol + cb + 4 * sg);
-    uint32_t cw = 0;
-    while (i < len) {
-      // next chunk: same w, or the first chunk of the sub-group's next w
-      const bool last = cb + 4 * SG >= we;  // uniform over the sub-group
-      int ni = i, nwb = wb, nwe = we, nws = ws, ncb = cb + 4 * SG;
-      if (last) {
-        ni = i + NSUB;
-        if (ni < len) { nwb = Wb[gi][ni]; nwe = nwb + Wn[gi][ni]; nws = Ws[gi][ni]; ncb = nwb & ~3; }
-      }
-      int4 nxt = make_int4(-1, -1, -1, -1);
-      if (ni < len && ncb + 4 * sg < nwe) nxt = *reinterpret_cast<const int4*>(dcol + ncb + 4 * sg);
-      // probe the four ids of this lane's chunk: issue the bucket reads together
-      const int32_t a = cb + 4 * sg;
-      const int32_t xs[4] = {cur.x, cur.y, cur.z, cur.w};
-      uint32_t hb[4];
-      int4 q[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        hb[k] = hash_slot(xs[k], __builtin_ctz(NB));
-        if (a + k >= wb && a + k < we) q[k] = Kb[hb[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (a + k < wb || a + k >= we) continue;
-        const int s = bucket_match<NB>(Kb, xs[k], hb[k], q[k]);
-        if (s >= 0) { atomicAdd(&C[s], 1u); ++cw; }
-      }
-      if (last) {
-        if (cw) atomicAdd(&C[ws], cw);
-        tu += cw;
-        cw = 0;
-      }
-      i = ni; wb = nwb; we = nwe; ws = nws; cb = ncb; cur = nxt;
-    }
-    group_sync<G>();
-    for (int s = g; s < SLOTS; s += G) {
-      const int32_t k = K[s];
-      const uint32_t c = C[s];
-      if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
-    }
-  }
-  if constexpr (G <= kWave) {
-    tu = group_sum<unsigned long long, G>(tu);
-    if (active && g == 0 && tu) atomicAdd(&T[u], tu);
-  } else {
-    // per-group sum of the wave partials (a block may hold several groups)
-    constexpr int WPG = G / kWave;
-    tu = group_sum<unsigned long long, kWave>(tu);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = tu;
-    __syncthreads();
-    if (active && g == 0) {
-      unsigned long long t = 0;
-      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
-      if (t) atomicAdd(&T[u], t);
-    }
-  }
-}
-
-// Wave-stream variant: every out-neighbour list N+(w) is streamed by one
-// full wavefront with wave-uniform loop bounds (held in scalar registers), so
-// the loop needs no divergence bookkeeping. The table is sparse (SLOTS >= 4x
-// the list), so a probe is one 16-byte LDS read and a few compares; the
-// overflow walk to the next bucket is rare. Hits are counted with a ballot
-// and a popcount into a wave-uniform total.
 // Looks x up in the bucket table: true when the lane is valid and x is in
 // the table, with *off the byte offset inside the counter array C of x's
 // slot (slot j of bucket b is counter 4b + j, at byte 16b + 4j). One 16-byte
@@ -482,7 +374,8 @@ template <int G, int SLOTS, int CAP, int U, bool CK = false>
 __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, CAP>& S,
                                                 unsigned long long* red, const int64_t* __restrict__ doff,
                                                 const int32_t* __restrict__ dcol,
-                                                unsigned long long* __restrict__ T, int32_t w_max = 0) {
+                                                unsigned long long* __restrict__ T,
+                                                unsigned long long* __restrict__ tot, int32_t w_max = 0) {
   static_assert(G % kWave == 0 && SLOTS % 4 == 0 && SLOTS >= 2 * CAP, "shape");
   constexpr int WPG = G / kWave;
   constexpr int NB = SLOTS / 4;
@@ -541,7 +434,10 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
     if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
   }
   if constexpr (WPG == 1) {
-    if (active && lane == 0 && tu) atomicAdd(&T[u], (unsigned long long)tu);
+    if (active && lane == 0 && tu) {
+      atomicAdd(&T[u], (unsigned long long)tu);
+      credit_total(tot, tu);
+    }
   } else {
     if (lane == 0) red[wv] = tu;
     __syncthreads();
@@ -549,23 +445,10 @@ __device__ __forceinline__ void node_count_wave(int32_t u, WaveGroupLds<SLOTS, C
       unsigned long long t = 0;
       for (int k = 0; k < WPG; ++k) t += red[k];
       if (t) atomicAdd(&T[u], t);
+      credit_total(tot, t);
     }
     __syncthreads();  // red and the table may be reused by the caller
   }
-}
-
-template <int NT, int G, int SLOTS, int CAP, int U>
-__global__ __launch_bounds__(NT) void k_count_wave(const int32_t* __restrict__ list, int32_t nlist,
-                                                   const int64_t* __restrict__ doff,
-                                                   const int32_t* __restrict__ dcol,
-                                                   unsigned long long* __restrict__ T) {
-  static_assert(NT % G == 0 && (G == kWave || G == NT), "groups are single waves or whole blocks");
-  constexpr int GPB = NT / G;
-  __shared__ WaveGroupLds<SLOTS, CAP> lds[GPB];
-  __shared__ unsigned long long red[NT / kWave];
-  const int gi = threadIdx.x / G;
-  const int idx = blockIdx.x * GPB + gi;
-  node_count_wave<G, SLOTS, CAP, U>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T);
 }
 
 // In-list side of the min-side split: a group owns node w and one chunk of
@@ -579,7 +462,8 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
                                                const int32_t* __restrict__ dcol,
                                                const int64_t* __restrict__ dinoff,
                                                const int32_t* __restrict__ dincol,
-                                               unsigned long long* __restrict__ T) {
+                                               unsigned long long* __restrict__ T,
+                                               unsigned long long* __restrict__ tot) {
   constexpr int WPG = G / kWave;
   constexpr int NB = SLOTS / 4;
   const int g = threadIdx.x % G;
@@ -637,7 +521,10 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
     if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
   }
   if constexpr (WPG == 1) {
-    if (active && lane == 0 && tw) atomicAdd(&T[w], (unsigned long long)tw);
+    if (active && lane == 0 && tw) {
+      atomicAdd(&T[w], (unsigned long long)tw);
+      credit_total(tot, tw);
+    }
   } else {
     if (lane == 0) red[wv] = tw;
     __syncthreads();
@@ -645,6 +532,7 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
       unsigned long long t = 0;
       for (int k = 0; k < WPG; ++k) t += red[k];
       if (t) atomicAdd(&T[w], t);
+      credit_total(tot, t);
     }
     __syncthreads();
   }
@@ -667,7 +555,8 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
                                                  const int32_t* __restrict__ dcol,
                                                  const int64_t* __restrict__ dinoff,
                                                  const int32_t* __restrict__ dincol,
-                                                 unsigned long long* __restrict__ T) {
+                                                 unsigned long long* __restrict__ T,
+                                                 unsigned long long* __restrict__ tot) {
   static_assert(NT % G == 0 && (G == kWave || G == NT), "groups are single waves or whole blocks");
   constexpr int GPB = NT / G;
   __shared__ WaveGroupLds<SLOTS, CAP> lds[GPB];
@@ -676,7 +565,7 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
   const int64_t nbu = ((int64_t)nlist + GPB - 1) / GPB;
   if ((int64_t)blockIdx.x < nbu) {
     const int64_t idx = (int64_t)blockIdx.x * GPB + gi;
-    node_count_wave<G, SLOTS, CAP, U, CK>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, w_max);
+    node_count_wave<G, SLOTS, CAP, U, CK>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, tot, w_max);
     return;
   }
   const int64_t j = ((int64_t)blockIdx.x - nbu) * GPB + gi;
@@ -692,7 +581,7 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
     w = in.list[lo];
     chunk = gc - in.coff[lo];
   }
-  node_count_inw<G, SLOTS, CAP, U, CK>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T);
+  node_count_inw<G, SLOTS, CAP, U, CK>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T, tot);
 }
 
 // Merge variant for short lists: a group of G lanes owns node u and each
@@ -703,7 +592,8 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
 template <int G>
 __device__ __forceinline__ void node_count_merge(int32_t u, const int64_t* __restrict__ doff,
                                                  const int32_t* __restrict__ dcol,
-                                                 unsigned long long* __restrict__ T) {
+                                                 unsigned long long* __restrict__ T,
+                                                 unsigned long long* __restrict__ tot) {
   const int g = threadIdx.x % G;
   unsigned long long tu = 0;
   if (u >= 0) {
@@ -739,98 +629,9 @@ __device__ __forceinline__ void node_count_merge(int32_t u, const int64_t* __res
     }
   }
   tu = group_sum<unsigned long long, G>(tu);
-  if (u >= 0 && g == 0 && tu) atomicAdd(&T[u], tu);
-}
-
-template <int NT, int G>
-__global__ __launch_bounds__(NT) void k_count_merge(const int32_t* __restrict__ list, int32_t nlist,
-                                                    const int64_t* __restrict__ doff,
-                                                    const int32_t* __restrict__ dcol,
-                                                    unsigned long long* __restrict__ T) {
-  const int idx = (blockIdx.x * NT + threadIdx.x) / G;
-  node_count_merge<G>(idx < nlist ? list[idx] : -1, doff, dcol, T);
-}
-
-// Plain variant: no staging, one id per lane per iteration, linear probing
-// over single slots. N+(w) bounds are read from HBM per w.
-template <int SLOTS>
-__device__ __forceinline__ int slot_find(const int32_t* K, int32_t x) {
-  uint32_t h = hash_slot(x, __builtin_ctz(SLOTS));
-  while (true) {
-    const int32_t k = K[h];
-    if (k == x) return (int)h;
-    if (k < 0) return -1;
-    h = (h + 1) & (SLOTS - 1);
-  }
-}
-
-template <int SLOTS>
-__device__ __forceinline__ void slot_insert(int32_t* K, int32_t x) {
-  uint32_t h = hash_slot(x, __builtin_ctz(SLOTS));
-  while (atomicCAS(&K[h], -1, x) != -1) h = (h + 1) & (SLOTS - 1);
-}
-
-template <int NT, int G, int SG, int SLOTS>
-__global__ __launch_bounds__(NT) void k_count_plain(const int32_t* __restrict__ list, int32_t nlist,
-                                                    const int64_t* __restrict__ doff,
-                                                    const int32_t* __restrict__ dcol,
-                                                    unsigned long long* __restrict__ T) {
-  static_assert(NT % G == 0 && G % SG == 0 && SG <= kWave, "shape");
-  constexpr int GPB = NT / G;
-  constexpr int NSUB = G / SG;
-  __shared__ int32_t Ks[GPB][SLOTS];
-  __shared__ uint32_t Cs[GPB][SLOTS];
-  __shared__ unsigned long long red[NT / kWave];
-  const int gi = threadIdx.x / G;
-  const int g = threadIdx.x % G;
-  const int idx = blockIdx.x * GPB + gi;
-  int32_t* K = Ks[gi];
-  uint32_t* C = Cs[gi];
-  const bool active = idx < nlist;
-  unsigned long long tu = 0;
-  int32_t u = 0;
-  int64_t beg = 0;
-  int32_t len = 0;
-  if (active) {
-    u = list[idx];
-    beg = doff[u];
-    len = (int32_t)(doff[u + 1] - beg);
-  }
-  for (int s = g; s < SLOTS; s += G) { K[s] = -1; C[s] = 0; }
-  group_sync<G>();
-  for (int i = g; i < len; i += G) slot_insert<SLOTS>(K, dcol[beg + i]);
-  group_sync<G>();
-  const int sub = g / SG, sg = g % SG;
-  for (int i = sub; i < len; i += NSUB) {
-    const int32_t w = dcol[beg + i];
-    const int64_t wb = doff[w], we = doff[w + 1];
-    uint32_t cw = 0;
-    for (int64_t p = wb + sg; p < we; p += SG) {
-      const int s = slot_find<SLOTS>(K, dcol[p]);
-      if (s >= 0) { atomicAdd(&C[s], 1u); ++cw; }
-    }
-    if (cw) atomicAdd(&C[slot_find<SLOTS>(K, w)], cw);
-    tu += cw;
-  }
-  group_sync<G>();
-  for (int s = g; s < SLOTS; s += G) {
-    const int32_t k = K[s];
-    const uint32_t c = C[s];
-    if (k >= 0 && c) atomicAdd(&T[k], (unsigned long long)c);
-  }
-  if constexpr (G <= kWave) {
-    tu = group_sum<unsigned long long, G>(tu);
-    if (active && g == 0 && tu) atomicAdd(&T[u], tu);
-  } else {
-    constexpr int WPG = G / kWave;
-    tu = group_sum<unsigned long long, kWave>(tu);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = tu;
-    __syncthreads();
-    if (active && g == 0) {
-      unsigned long long t = 0;
-      for (int k = 0; k < WPG; ++k) t += red[gi * WPG + k];
-      if (t) atomicAdd(&T[u], t);
-    }
+  if (u >= 0 && g == 0 && tu) {
+    atomicAdd(&T[u], tu);
+    credit_total(tot, tu);
   }
 }
 
@@ -840,7 +641,8 @@ __global__ __launch_bounds__(NT) void k_count_plain(const int32_t* __restrict__ 
 __device__ __forceinline__ void node_count_global(int32_t u, unsigned long long* red,
                                                   const int64_t* __restrict__ doff,
                                                   const int32_t* __restrict__ dcol,
-                                                  unsigned long long* __restrict__ T) {
+                                                  unsigned long long* __restrict__ T,
+                                                  unsigned long long* __restrict__ tot) {
   const int64_t beg = doff[u];
   const int32_t len = (int32_t)(doff[u + 1] - beg);
   const int32_t* U = dcol + beg;
@@ -866,15 +668,19 @@ __device__ __forceinline__ void node_count_global(int32_t u, unsigned long long*
     }
   }
   const unsigned long long t = block_sum<unsigned long long, 256>(tu, red);
-  if (threadIdx.x == 0 && t) atomicAdd(&T[u], t);
+  if (threadIdx.x == 0 && t) {
+    atomicAdd(&T[u], t);
+    credit_total(tot, t);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_count_global(const int32_t* __restrict__ list, int32_t nlist,
                                                       const int64_t* __restrict__ doff,
                                                       const int32_t* __restrict__ dcol,
-                                                      unsigned long long* __restrict__ T) {
+                                                      unsigned long long* __restrict__ T,
+                                                      unsigned long long* __restrict__ tot) {
   __shared__ unsigned long long red[256 / kWave];
-  node_count_global(list[blockIdx.x], red, doff, dcol, T);
+  node_count_global(list[blockIdx.x], red, doff, dcol, T, tot);
 }
 
 // Hub variant: N+(u) as a bitmap over all node ids, one private bitmap per
@@ -892,7 +698,8 @@ __global__ __launch_bounds__(kHubNT) void k_count_bitmap(const int32_t* __restri
                                                          uint32_t* __restrict__ hubmap, int64_t map_words,
                                                          const int64_t* __restrict__ doff,
                                                          const int32_t* __restrict__ dcol,
-                                                         unsigned long long* __restrict__ T) {
+                                                         unsigned long long* __restrict__ T,
+                                                         unsigned long long* __restrict__ tot) {
   static_assert(U * kWave * 4 <= 4096, "per-load offsets must fit the 12-bit immediate field");
   constexpr int WPB = kHubNT / kWave;
   __shared__ unsigned long long red[WPB];
@@ -939,7 +746,10 @@ __global__ __launch_bounds__(kHubNT) void k_count_bitmap(const int32_t* __restri
       }
     }
     const unsigned long long t = block_sum<unsigned long long, kHubNT>(tu, red);
-    if (threadIdx.x == 0 && t) atomicAdd(&T[u], t);
+    if (threadIdx.x == 0 && t) {
+      atomicAdd(&T[u], t);
+      credit_total(tot, t);
+    }
     __syncthreads();  // every probe of this node is done
     for (int32_t i = threadIdx.x; i < nu; i += kHubNT) map[dcol[ub + i] >> 5] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1013,7 +823,8 @@ template <int GS, bool CK = false>
 __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ list, int64_t first, int64_t nlist,
                                                   SmallLds<GS>& S, const int64_t* __restrict__ doff,
                                                   const int32_t* __restrict__ dcol,
-                                                  unsigned long long* __restrict__ T) {
+                                                  unsigned long long* __restrict__ T,
+                                                  unsigned long long* __restrict__ tot) {
   static_assert(kWave % GS == 0 && GS >= 4, "GS divides the wave");
   constexpr int NB = GS;
   const int lane = lane_id();
@@ -1064,6 +875,8 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
   if (c) atomicAdd(&T[w], (unsigned long long)c);
   const uint32_t tu = group_sum<uint32_t, GS>(c);
   if (j == 0 && tu) atomicAdd(&T[u], (unsigned long long)tu);
+  const uint32_t tw = group_sum<uint32_t, kWave>(c);  // the wave's nodes together
+  if (lane == 0) credit_total(tot, tw);
   for (int s = j; s < 4 * GS; s += GS) {
     const int32_t key = K[s];
     const uint32_t cs = C[s];
@@ -1093,7 +906,8 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
                                                        int32_t* __restrict__ queue,
                                                        const int64_t* __restrict__ doff,
                                                        const int32_t* __restrict__ dcol,
-                                                       unsigned long long* __restrict__ T) {
+                                                       unsigned long long* __restrict__ T,
+                                                       unsigned long long* __restrict__ tot) {
   using BL = WaveGroupLds<SB, CB>;
   using WL = WaveGroupLds<SW, CW>;
   constexpr int kGS = SMALL ? SMALL : kSmallGS;
@@ -1110,8 +924,8 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
     const int32_t c = chunk;
     __syncthreads();
     if (c >= n1) break;
-    if (c < ng) node_count_global(glist[c], red, doff, dcol, T);
-    else node_count_wave<256, SB, CB, 4, CK>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T);
+    if (c < ng) node_count_global(glist[c], red, doff, dcol, T, tot);
+    else node_count_wave<256, SB, CB, 4, CK>(blist[c - ng], *reinterpret_cast<BL*>(smem), red, doff, dcol, T, tot);
     __syncthreads();
   }
   constexpr int NPW = SMALL ? kWave / kGS : kWave / 8;  // short-list nodes per wave item
@@ -1128,13 +942,13 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
     const int32_t end = min(cur + kPersistGrab, n2);
     for (int32_t it = cur; it < end; ++it) {
       if (it < nw) {
-        node_count_wave<kWave, SW, CW, 4, CK>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T);
+        node_count_wave<kWave, SW, CW, 4, CK>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T, tot);
       } else if constexpr (SMALL != 0) {
         nodes_count_small<kGS, CK>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol,
-                                   T);
+                                   T, tot);
       } else {
         const int64_t k = (int64_t)(it - nw) * NPW + lane / 8;
-        node_count_merge<8>(k < nm ? mlist[k] : -1, doff, dcol, T);
+        node_count_merge<8>(k < nm ? mlist[k] : -1, doff, dcol, T, tot);
       }
     }
     cur = __builtin_amdgcn_readlane(nxt, 0);
@@ -1171,51 +985,39 @@ const void* persist_kernel(int v) {
   }
 }
 
+template <int SW, int CW, int SB, int CB, int SMALL = 0, bool CK = false>
+static void launch_persist(unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist, int32_t nbk,
+                           const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm, int32_t* queue,
+                           const int64_t* doff, const int32_t* dcol, unsigned long long* T, unsigned long long* tot,
+                           hipStream_t s) {
+  k_count_persist<SW, CW, SB, CB, SMALL, CK><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+                                                                   doff, dcol, T, tot);
+}
+
 hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
                                 int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
                                 int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
-                                hipStream_t s) {
+                                unsigned long long* tot, hipStream_t s) {
+#define TRICC_PERSIST_ARGS grid, glist, ng, blist, nbk, wlist, nw, mlist, nm, queue, doff, dcol, T, tot, s
   switch (v) {
-    case 0:
-      k_count_persist<256, 64, 1024, 256><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue, doff,
-                                                               dcol, T);
-      break;
-    case 1:
-      k_count_persist<256, 64, 4096, 1024><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
-                                                                doff, dcol, T);
-      break;
-    case 2:
-      k_count_persist<256, 64, 1024, 256, 16><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
-                                                                   doff, dcol, T);
-      break;
-    case 3:
-      k_count_persist<256, 64, 4096, 1024, 16><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
-                                                                    queue, doff, dcol, T);
-      break;
-    case 4:
-      k_count_persist<256, 64, 1024, 256, 32><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
-                                                                   doff, dcol, T);
-      break;
-    case 5:
-      k_count_persist<256, 64, 1024, 256, 8><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
-                                                                  doff, dcol, T);
-      break;
-    case 6:
-      k_count_persist<256, 64, 1024, 256, 16, true><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
-                                                                         queue, doff, dcol, T);
-      break;
-    case 7:
-      k_count_persist<256, 64, 4096, 1024, 16, true><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm,
-                                                                          queue, doff, dcol, T);
-      break;
+    case 0: launch_persist<256, 64, 1024, 256>(TRICC_PERSIST_ARGS); break;
+    case 1: launch_persist<256, 64, 4096, 1024>(TRICC_PERSIST_ARGS); break;
+    case 2: launch_persist<256, 64, 1024, 256, 16>(TRICC_PERSIST_ARGS); break;
+    case 3: launch_persist<256, 64, 4096, 1024, 16>(TRICC_PERSIST_ARGS); break;
+    case 4: launch_persist<256, 64, 1024, 256, 32>(TRICC_PERSIST_ARGS); break;
+    case 5: launch_persist<256, 64, 1024, 256, 8>(TRICC_PERSIST_ARGS); break;
+    case 6: launch_persist<256, 64, 1024, 256, 16, true>(TRICC_PERSIST_ARGS); break;
+    case 7: launch_persist<256, 64, 4096, 1024, 16, true>(TRICC_PERSIST_ARGS); break;
     default: return hipErrorInvalidValue;
   }
+#undef TRICC_PERSIST_ARGS
   return hipGetLastError();
 }
 
-// Clears T[n] and the two work-queue counters (a kernel, so that it can sit in a
-// captured graph).
+// Clears T[n], the kTotSlots total counters and the two work-queue counters
+// (a kernel, so that it can sit in a captured graph).
 __global__ __launch_bounds__(256) void k_batch_zero(unsigned long long* __restrict__ T, int64_t n,
+                                                    unsigned long long* __restrict__ tot,
                                                     int32_t* __restrict__ queue) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1223,26 +1025,39 @@ __global__ __launch_bounds__(256) void k_batch_zero(unsigned long long* __restri
     queue[0] = 0;
     queue[1] = 0;
   }
+  if (i0 < kTotSlots) tot[i0] = 0ull;
   for (int64_t i = i0; i < n; i += stride) T[i] = 0ull;
 }
 
-hipError_t launch_batch_zero(unsigned long long* T, int64_t n, int32_t* queue, hipStream_t s) {
-  int64_t g = (n + 255) / 256;
-  if (g < 1) g = 1;
+hipError_t launch_batch_zero(unsigned long long* T, int64_t n, unsigned long long* tot, int32_t* queue,
+                             hipStream_t s) {
+  int64_t g = (std::max<int64_t>(n, kTotSlots) + 255) / 256;
   if (g > 65536) g = 65536;
-  k_batch_zero<<<(unsigned)g, 256, 0, s>>>(T, n, queue);
+  k_batch_zero<<<(unsigned)g, 256, 0, s>>>(T, n, tot, queue);
   return hipGetLastError();
+}
+
+// Sum of the kTotSlots total counters by one block (fixed order).
+__device__ __forceinline__ unsigned long long sum_total(const unsigned long long* __restrict__ tot,
+                                                        unsigned long long* red) {
+  unsigned long long acc = 0;
+  for (int i = threadIdx.x; i < kTotSlots; i += 256) acc += tot[i];
+  return block_sum<unsigned long long, 256>(acc, red);
 }
 
 // Per-graph epilogue: one block per graph g owns nodes [node_off[g],
 // node_off[g+1]): CC(v) as in the single-graph epilogue, the graph's
 // triangle total (sum of T / 3) and its average CC over its n_g nodes, each
-// summed in a fixed order that depends only on the graph.
+// summed in a fixed order that depends only on the graph. Block 0 also
+// writes the batch's total from the counters the intersection kernels fed
+// (independent of T) to *batch_tri, if that is not null.
 __global__ __launch_bounds__(256) void k_graph_epilogue(const int64_t* __restrict__ node_off,
                                                         const unsigned long long* __restrict__ T,
                                                         const int32_t* __restrict__ deg, float* __restrict__ cc,
                                                         unsigned long long* __restrict__ graph_tri,
-                                                        double* __restrict__ graph_avg) {
+                                                        double* __restrict__ graph_avg,
+                                                        const unsigned long long* __restrict__ tot,
+                                                        unsigned long long* __restrict__ batch_tri) {
   __shared__ double red_d[256 / kWave];
   __shared__ unsigned long long red_t[256 / kWave];
   const int64_t nb = node_off[blockIdx.x], ne = node_off[blockIdx.x + 1];
@@ -1263,123 +1078,68 @@ __global__ __launch_bounds__(256) void k_graph_epilogue(const int64_t* __restric
     graph_tri[blockIdx.x] = st / 3ull;
     graph_avg[blockIdx.x] = ne > nb ? sd / (double)(ne - nb) : 0.0;
   }
+  if (blockIdx.x == 0 && batch_tri) {
+    const unsigned long long all = sum_total(tot, red_t);
+    if (threadIdx.x == 0) *batch_tri = all;
+  }
 }
 
 hipError_t launch_graph_epilogue(int32_t num_graphs, const int64_t* node_off, const unsigned long long* T,
                                  const int32_t* deg, float* cc, unsigned long long* graph_tri, double* graph_avg,
-                                 hipStream_t s) {
+                                 const unsigned long long* tot, unsigned long long* batch_tri, hipStream_t s) {
   if (num_graphs <= 0) return hipSuccess;
-  k_graph_epilogue<<<num_graphs, 256, 0, s>>>(node_off, T, deg, cc, graph_tri, graph_avg);
+  k_graph_epilogue<<<num_graphs, 256, 0, s>>>(node_off, T, deg, cc, graph_tri, graph_avg, tot, batch_tri);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Variant table. Capacity = SLOTS / 2 (table at most half full).
-struct VariantInfo { int nt, g, sg, slots, cap = 0; };
+// Variant table. Every table variant is a min-side kernel (out-list side and
+// in-list side of a bin); cap = the largest d+(u) its LDS table takes.
+struct VariantInfo { int nt, g, slots, cap; };
 static constexpr VariantInfo kVariants[] = {
-    {256, 16, 16, 32},       // 0: d+ <= 16
-    {256, 16, 8, 32},        // 1
-    {256, 64, 32, 128},      // 2: d+ <= 64
-    {256, 64, 16, 128},      // 3
-    {256, 128, 32, 512},     // 4: d+ <= 256
-    {256, 128, 16, 512},     // 5
-    {256, 256, 32, 512},     // 6
-    {512, 512, 32, 2048},    // 7: d+ <= 1024
-    {512, 512, 64, 2048},    // 8
-    {512, 512, 16, 2048},    // 9
-    {1024, 1024, 32, 8192},  // 10: d+ <= 4096
-    {1024, 1024, 64, 8192},  // 11
-    // plain kernel (no staging, single-slot probing)
-    {256, 16, 16, 32},       // 12: d+ <= 16
-    {256, 64, 32, 128},      // 13: d+ <= 64
-    {256, 64, 32, 512},      // 14: d+ <= 256
-    {256, 256, 32, 2048},    // 15: d+ <= 1024
-    {512, 512, 64, 8192},    // 16: d+ <= 4096
-    // wave-stream kernel (one wavefront per list, sparse bucket table)
-    {256, 64, 64, 128, 16},       // 17: d+ <= 16
-    {256, 64, 64, 512, 64},       // 18: d+ <= 64
-    {256, 256, 64, 2048, 256},    // 19: d+ <= 256
-    {512, 512, 64, 8192, 1024},   // 20: d+ <= 1024
-    {1024, 1024, 64, 8192, 4096}, // 21: d+ <= 4096
-    {256, 64, 64, 256, 64},       // 22: d+ <= 64, denser table
-    {256, 256, 64, 1024, 256},    // 23: d+ <= 256, denser table
-    {512, 512, 64, 4096, 1024},   // 24: d+ <= 1024, denser table
-    // merge kernel (lane group per node, two-pointer merge per out-edge)
-    {256, 4, 0, -1, 1 << 20},     // 25: any d+ (short lists)
-    {256, 8, 0, -1, 1 << 20},     // 26
-    {256, 16, 0, -1, 1 << 20},    // 27
-    // min-side wave-stream kernels (out-list side + in-list side per bin)
-    {256, 64, 64, 128, 16},       // 28: d+ <= 16
-    {256, 64, 64, 256, 64},       // 29: d+ <= 64
-    {256, 256, 64, 1024, 256},    // 30: d+ <= 256
-    {512, 512, 64, 4096, 1024},   // 31: d+ <= 1024
-    {1024, 1024, 64, 8192, 4096}, // 32: d+ <= 4096
-    {512, 512, 64, 2048, 1024},   // 33: d+ <= 1024, denser table
-    {512, 512, 64, 4096, 2048},   // 34: d+ <= 2048
-    {256, 256, 64, 512, 256},     // 35: d+ <= 256, denser table
-    {256, 256, 64, 0},       // 36: global fallback (binary search), any d+
-    {1024, 1024, 64, 0},     // 37: hub bitmap in global memory, any d+
-    // as 28..35 with cuckoo tables (bucket tables where a build gives up)
-    {256, 64, 64, 128, 16},       // 38: d+ <= 16
-    {256, 64, 64, 256, 64},       // 39: d+ <= 64
-    {256, 256, 64, 1024, 256},    // 40: d+ <= 256
-    {512, 512, 64, 4096, 1024},   // 41: d+ <= 1024
-    {1024, 1024, 64, 8192, 4096}, // 42: d+ <= 4096
-    {512, 512, 64, 2048, 1024},   // 43: d+ <= 1024, denser table
-    {512, 512, 64, 4096, 2048},   // 44: d+ <= 2048
-    {256, 256, 64, 512, 256},     // 45: d+ <= 256, denser table
-    {128, 128, 64, 512, 128},     // 46: d+ <= 128, two wavefronts per node
-    {128, 128, 64, 1024, 256},    // 47: d+ <= 256, two wavefronts per node
+    // bucket tables
+    {256, 64, 128, 16},       // 0: d+ <= 16
+    {256, 64, 256, 64},       // 1: d+ <= 64
+    {256, 256, 1024, 256},    // 2: d+ <= 256
+    {512, 512, 4096, 1024},   // 3: d+ <= 1024
+    {1024, 1024, 8192, 4096}, // 4: d+ <= 4096
+    {512, 512, 2048, 1024},   // 5: d+ <= 1024, denser table
+    {512, 512, 4096, 2048},   // 6: d+ <= 2048
+    {256, 256, 512, 256},     // 7: d+ <= 256, denser table
+    // table-free kernels for any d+
+    {256, 256, 0, 0x7fffffff},    // 8: global fallback (binary search of N+(u) in HBM)
+    {1024, 1024, 0, 0x7fffffff},  // 9: hub bitmap in global memory
+    // cuckoo tables (bucket tables where a build gives up)
+    {256, 64, 128, 16},       // 10: d+ <= 16
+    {256, 64, 256, 64},       // 11: d+ <= 64
+    {256, 256, 1024, 256},    // 12: d+ <= 256
+    {512, 512, 4096, 1024},   // 13: d+ <= 1024
+    {1024, 1024, 8192, 4096}, // 14: d+ <= 4096
+    {512, 512, 2048, 1024},   // 15: d+ <= 1024, denser table
+    {512, 512, 4096, 2048},   // 16: d+ <= 2048
+    {256, 256, 512, 256},     // 17: d+ <= 256, denser table
+    {128, 128, 512, 128},     // 18: d+ <= 128, two wavefronts per node
+    {128, 128, 1024, 256},    // 19: d+ <= 256, two wavefronts per node
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr int kVariantGlobal = 36;
-constexpr int kVariantBitmap = 37;
+constexpr int kVariantGlobal = 8;
+constexpr int kVariantBitmap = 9;
 
 int count_variant_valid(int v) { return v >= 0 && v < kNumVariants; }
-int count_variant_capacity(int v) {
-  if (!count_variant_valid(v)) return -1;
-  if (!kVariants[v].slots) return 0x7fffffff;
-  if (kVariants[v].slots < 0) return kVariants[v].cap;  // table-free kernels
-  return kVariants[v].cap ? kVariants[v].cap : kVariants[v].slots / 2;
-}
-
-template <int NT, int G, int SG, int SLOTS>
-static void launch_hash(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
-                        unsigned long long* T, hipStream_t s) {
-  constexpr int GPB = NT / G;
-  const unsigned grid = (unsigned)((b.count + GPB - 1) / GPB);
-  k_count_hash<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
-}
-
-template <int NT, int G, int SLOTS, int CAP, int U = 4>
-static void launch_wave(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
-                        unsigned long long* T, hipStream_t s) {
-  constexpr int GPB = NT / G;
-  const unsigned grid = (unsigned)((b.count + GPB - 1) / GPB);
-  k_count_wave<NT, G, SLOTS, CAP, U><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
-}
-
-template <int NT, int G, int SG, int SLOTS>
-static void launch_plain(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
-                         unsigned long long* T, hipStream_t s) {
-  constexpr int GPB = NT / G;
-  const unsigned grid = (unsigned)((b.count + GPB - 1) / GPB);
-  k_count_plain<NT, G, SG, SLOTS><<<grid, NT, 0, s>>>(b.list, b.count, doff, dcol, T);
-}
+int count_variant_capacity(int v) { return count_variant_valid(v) ? kVariants[v].cap : -1; }
+int count_variant_min_side(int v) { return count_variant_valid(v) && kVariants[v].slots > 0; }
 
 template <int NT, int G, int SLOTS, int CAP, bool CK = false, int U = 8>
 static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
-                      hipStream_t s) {
+                      unsigned long long* tot, hipStream_t s) {
   constexpr int GPB = NT / G;
   const int64_t nbu = ((int64_t)b.count + GPB - 1) / GPB;
   const int64_t nbw = (b.in_items + GPB - 1) / GPB;
   if (nbu + nbw == 0) return;
   InItems in{b.in_list, b.in_coff, b.in_nodes, b.in_items};
   k_count_ms<NT, G, SLOTS, CAP, U, CK><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
-                                                                        b.dinoff, b.dincol, T);
+                                                                        b.dinoff, b.dincol, T, tot);
 }
-
-int count_variant_min_side(int v) { return (v >= 28 && v <= 35) || (v >= 38 && v <= 47); }
 
 // Hub bitmaps: one bit per node id, as many bitmaps as fit 256 MB (8 to 256,
 // one per block of the hub variant's grid).
@@ -1390,62 +1150,34 @@ int32_t hub_map_slots(int64_t n) {
 }
 
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
-                            unsigned long long* T, hipStream_t s) {
+                            unsigned long long* T, unsigned long long* tot, hipStream_t s) {
   if (b.count <= 0 && b.in_items <= 0) return hipSuccess;
   switch (b.variant) {
-    case 0: launch_hash<256, 16, 16, 32>(b, doff, dcol, T, s); break;
-    case 1: launch_hash<256, 16, 8, 32>(b, doff, dcol, T, s); break;
-    case 2: launch_hash<256, 64, 32, 128>(b, doff, dcol, T, s); break;
-    case 3: launch_hash<256, 64, 16, 128>(b, doff, dcol, T, s); break;
-    case 4: launch_hash<256, 128, 32, 512>(b, doff, dcol, T, s); break;
-    case 5: launch_hash<256, 128, 16, 512>(b, doff, dcol, T, s); break;
-    case 6: launch_hash<256, 256, 32, 512>(b, doff, dcol, T, s); break;
-    case 7: launch_hash<512, 512, 32, 2048>(b, doff, dcol, T, s); break;
-    case 8: launch_hash<512, 512, 64, 2048>(b, doff, dcol, T, s); break;
-    case 9: launch_hash<512, 512, 16, 2048>(b, doff, dcol, T, s); break;
-    case 10: launch_hash<1024, 1024, 32, 8192>(b, doff, dcol, T, s); break;
-    case 11: launch_hash<1024, 1024, 64, 8192>(b, doff, dcol, T, s); break;
-    case 12: launch_plain<256, 16, 16, 32>(b, doff, dcol, T, s); break;
-    case 13: launch_plain<256, 64, 32, 128>(b, doff, dcol, T, s); break;
-    case 14: launch_plain<256, 64, 32, 512>(b, doff, dcol, T, s); break;
-    case 15: launch_plain<256, 256, 32, 2048>(b, doff, dcol, T, s); break;
-    case 16: launch_plain<512, 512, 64, 8192>(b, doff, dcol, T, s); break;
-    case 17: launch_wave<256, 64, 128, 16>(b, doff, dcol, T, s); break;
-    case 18: launch_wave<256, 64, 512, 64>(b, doff, dcol, T, s); break;
-    case 19: launch_wave<256, 256, 2048, 256>(b, doff, dcol, T, s); break;
-    case 20: launch_wave<512, 512, 8192, 1024>(b, doff, dcol, T, s); break;
-    case 21: launch_wave<1024, 1024, 8192, 4096>(b, doff, dcol, T, s); break;
-    case 22: launch_wave<256, 64, 256, 64>(b, doff, dcol, T, s); break;
-    case 23: launch_wave<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
-    case 24: launch_wave<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
-    case 25: k_count_merge<256, 4><<<(unsigned)(((int64_t)b.count * 4 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
-    case 26: k_count_merge<256, 8><<<(unsigned)(((int64_t)b.count * 8 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
-    case 27: k_count_merge<256, 16><<<(unsigned)(((int64_t)b.count * 16 + 255) / 256), 256, 0, s>>>(b.list, b.count, doff, dcol, T); break;
-    case 28: launch_ms<256, 64, 128, 16>(b, doff, dcol, T, s); break;
-    case 29: launch_ms<256, 64, 256, 64>(b, doff, dcol, T, s); break;
-    case 30: launch_ms<256, 256, 1024, 256>(b, doff, dcol, T, s); break;
-    case 31: launch_ms<512, 512, 4096, 1024>(b, doff, dcol, T, s); break;
-    case 32: launch_ms<1024, 1024, 8192, 4096>(b, doff, dcol, T, s); break;
-    case 33: launch_ms<512, 512, 2048, 1024>(b, doff, dcol, T, s); break;
-    case 34: launch_ms<512, 512, 4096, 2048>(b, doff, dcol, T, s); break;
-    case 35: launch_ms<256, 256, 512, 256>(b, doff, dcol, T, s); break;
-    case 38: launch_ms<256, 64, 128, 16, true>(b, doff, dcol, T, s); break;
-    case 39: launch_ms<256, 64, 256, 64, true>(b, doff, dcol, T, s); break;
-    case 40: launch_ms<256, 256, 1024, 256, true>(b, doff, dcol, T, s); break;
-    case 41: launch_ms<512, 512, 4096, 1024, true>(b, doff, dcol, T, s); break;
-    case 42: launch_ms<1024, 1024, 8192, 4096, true>(b, doff, dcol, T, s); break;
-    case 43: launch_ms<512, 512, 2048, 1024, true>(b, doff, dcol, T, s); break;
-    case 44: launch_ms<512, 512, 4096, 2048, true>(b, doff, dcol, T, s); break;
-    case 45: launch_ms<256, 256, 512, 256, true>(b, doff, dcol, T, s); break;
-    case 46: launch_ms<128, 128, 512, 128, true>(b, doff, dcol, T, s); break;
-    case 47: launch_ms<128, 128, 1024, 256, true>(b, doff, dcol, T, s); break;
+    case 0: launch_ms<256, 64, 128, 16>(b, doff, dcol, T, tot, s); break;
+    case 1: launch_ms<256, 64, 256, 64>(b, doff, dcol, T, tot, s); break;
+    case 2: launch_ms<256, 256, 1024, 256>(b, doff, dcol, T, tot, s); break;
+    case 3: launch_ms<512, 512, 4096, 1024>(b, doff, dcol, T, tot, s); break;
+    case 4: launch_ms<1024, 1024, 8192, 4096>(b, doff, dcol, T, tot, s); break;
+    case 5: launch_ms<512, 512, 2048, 1024>(b, doff, dcol, T, tot, s); break;
+    case 6: launch_ms<512, 512, 4096, 2048>(b, doff, dcol, T, tot, s); break;
+    case 7: launch_ms<256, 256, 512, 256>(b, doff, dcol, T, tot, s); break;
+    case 10: launch_ms<256, 64, 128, 16, true>(b, doff, dcol, T, tot, s); break;
+    case 11: launch_ms<256, 64, 256, 64, true>(b, doff, dcol, T, tot, s); break;
+    case 12: launch_ms<256, 256, 1024, 256, true>(b, doff, dcol, T, tot, s); break;
+    case 13: launch_ms<512, 512, 4096, 1024, true>(b, doff, dcol, T, tot, s); break;
+    case 14: launch_ms<1024, 1024, 8192, 4096, true>(b, doff, dcol, T, tot, s); break;
+    case 15: launch_ms<512, 512, 2048, 1024, true>(b, doff, dcol, T, tot, s); break;
+    case 16: launch_ms<512, 512, 4096, 2048, true>(b, doff, dcol, T, tot, s); break;
+    case 17: launch_ms<256, 256, 512, 256, true>(b, doff, dcol, T, tot, s); break;
+    case 18: launch_ms<128, 128, 512, 128, true>(b, doff, dcol, T, tot, s); break;
+    case 19: launch_ms<128, 128, 1024, 256, true>(b, doff, dcol, T, tot, s); break;
     case kVariantGlobal:
-      k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T);
+      k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T, tot);
       break;
     case kVariantBitmap:
       if (!b.hubmap || b.hub_slots < 1) return hipErrorInvalidValue;
       k_count_bitmap<8><<<(unsigned)min(b.count, b.hub_slots), kHubNT, 0, s>>>(b.list, b.count, b.hubmap, b.map_words,
-                                                                             doff, dcol, T);
+                                                                             doff, dcol, T, tot);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1453,16 +1185,19 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+// Clears T[n] and the kTotSlots total counters.
+__global__ __launch_bounds__(256) void k_zero_counts(unsigned long long* __restrict__ T, int64_t n,
+                                                     unsigned long long* __restrict__ tot) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 < kTotSlots) tot[i0] = 0ull;
+  for (int64_t i = i0; i < n; i += stride) T[i] = 0ull;
 }
 
-hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t g = (n + 255) / 256;
+hipError_t launch_zero_counts(unsigned long long* T, int64_t n, unsigned long long* tot, hipStream_t s) {
+  int64_t g = (std::max<int64_t>(n, kTotSlots) + 255) / 256;
   if (g > 65536) g = 65536;
-  k_zero_u64<<<(unsigned)g, 256, 0, s>>>(p, n);
+  k_zero_counts<<<(unsigned)g, 256, 0, s>>>(T, n, tot);
   return hipGetLastError();
 }
 
@@ -1500,9 +1235,14 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(int32_t n, const unsig
   if (threadIdx.x == 0) { part_cc[blockIdx.x] = s; part_T[blockIdx.x] = st; }
 }
 
+// The total from the intersection kernels' counters (not from T), the
+// average from the epilogue's FP64 partials in block order, and sum_T =
+// sum of the per-node counts (3x the total when both are right).
 __global__ __launch_bounds__(256) void k_finish(int64_t nb, int32_t n, const double* __restrict__ part_cc,
                                                 const unsigned long long* __restrict__ part_T,
-                                                unsigned long long* __restrict__ total, double* __restrict__ avg) {
+                                                const unsigned long long* __restrict__ tot,
+                                                unsigned long long* __restrict__ total, double* __restrict__ avg,
+                                                unsigned long long* __restrict__ sum_T) {
   __shared__ double red_d[256 / kWave];
   __shared__ unsigned long long red_t[256 / kWave];
   double acc = 0.0;
@@ -1510,9 +1250,11 @@ __global__ __launch_bounds__(256) void k_finish(int64_t nb, int32_t n, const dou
   for (int64_t i = threadIdx.x; i < nb; i += 256) { acc += part_cc[i]; tacc += part_T[i]; }
   const double s = block_sum<double, 256>(acc, red_d);
   const unsigned long long st = block_sum<unsigned long long, 256>(tacc, red_t);
+  const unsigned long long all = sum_total(tot, red_t);
   if (threadIdx.x == 0) {
-    *total = st / 3ull;
+    *total = all;
     *avg = n > 0 ? s / (double)n : 0.0;
+    *sum_T = st;
   }
 }
 
@@ -1525,8 +1267,9 @@ hipError_t launch_epilogue(int32_t n, const unsigned long long* T, const int32_t
 }
 
 hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const unsigned long long* part_T,
-                         unsigned long long* total, double* avg, hipStream_t s) {
-  k_finish<<<1, 256, 0, s>>>(nb, n, part_cc, part_T, total, avg);
+                         const unsigned long long* tot, unsigned long long* total, double* avg,
+                         unsigned long long* sum_T, hipStream_t s) {
+  k_finish<<<1, 256, 0, s>>>(nb, n, part_cc, part_T, tot, total, avg, sum_T);
   return hipGetLastError();
 }
 

@@ -120,10 +120,13 @@ constexpr int kNumBins = 6;
 // bin kNumBins-1 takes the rest.
 hipError_t launch_classify_bins(int pass, int32_t n, const int32_t* dplus, const int32_t* limit, int32_t* hist,
                                 const int64_t* off, int64_t nblk, int32_t* list, hipStream_t s);
-// per-bin sums of d+(u) + d+(w) and of edges over the DAG edges each bin's
-// kernel counts (min-side ownership with w_max; w_max = 0 disables it)
-hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* limit,
-                            int32_t w_max, unsigned long long* elems, unsigned long long* edges, hipStream_t s);
+// per-bin sums of d+(u) + d+(w), of edges over the DAG edges each bin's
+// kernel counts (min-side ownership with w_max; w_max = 0 disables it), and
+// of the bytes the min-side kernel moves (din / cap: in-degrees and in-list
+// chunk sizes; din may be null when w_max = 0)
+hipError_t launch_bin_elems(int32_t n, const int64_t* doff, const int32_t* dcol, const int32_t* din,
+                            const int32_t* limit, const int32_t* cap, int32_t w_max, unsigned long long* elems,
+                            unsigned long long* edges, unsigned long long* kbytes, hipStream_t s);
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // ---- Intersection and epilogue --------------------------------------------
@@ -147,18 +150,25 @@ struct BinLaunch {
 // Bitmaps for the hub variant: words per bitmap and how many fit the region.
 int64_t hub_map_words(int64_t n);
 int32_t hub_map_slots(int64_t n);
+// Counters of the triangle total, fed by the intersection kernels apart from
+// T (each node group adds the triangles it found to counter blockIdx % this).
+constexpr int kTotSlots = 512;
 hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32_t* dcol,
-                            unsigned long long* T, hipStream_t s);
+                            unsigned long long* T, unsigned long long* tot, hipStream_t s);
 int count_variant_capacity(int variant);  // max d+(u) a variant accepts
 int count_variant_valid(int variant);
 int count_variant_min_side(int variant);  // out-list + in-list kernel
-hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// Clears T[n] and tot[kTotSlots].
+hipError_t launch_zero_counts(unsigned long long* T, int64_t n, unsigned long long* tot, hipStream_t s);
 // cc[v] (fp32) from T and deg; block partials of the FP64 ratio sum and of T.
 int64_t epilogue_blocks(int64_t n);
 hipError_t launch_epilogue(int32_t n, const unsigned long long* T, const int32_t* deg, float* cc,
                            double* part_cc, unsigned long long* part_T, hipStream_t s);
+// *total = sum of tot (the intersection kernels' own count), *avg from the
+// FP64 partials, *sum_T = sum of the T partials.
 hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const unsigned long long* part_T,
-                         unsigned long long* total, double* avg, hipStream_t s);
+                         const unsigned long long* tot, unsigned long long* total, double* avg,
+                         unsigned long long* sum_T, hipStream_t s);
 
 // ---- Batched graphs ---------------------------------------------------------
 // Persistent intersection kernel over four node lists (hubs -> global
@@ -172,11 +182,13 @@ const void* persist_kernel(int v);
 hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
                                 int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
                                 int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
-                                hipStream_t s);
-hipError_t launch_batch_zero(unsigned long long* T, int64_t n, int32_t* queue, hipStream_t s);
+                                unsigned long long* tot, hipStream_t s);
+hipError_t launch_batch_zero(unsigned long long* T, int64_t n, unsigned long long* tot, int32_t* queue,
+                             hipStream_t s);
+// batch_tri (may be null): the batch's total from tot.
 hipError_t launch_graph_epilogue(int32_t num_graphs, const int64_t* node_off, const unsigned long long* T,
                                  const int32_t* deg, float* cc, unsigned long long* graph_tri, double* graph_avg,
-                                 hipStream_t s);
+                                 const unsigned long long* tot, unsigned long long* batch_tri, hipStream_t s);
 // Local -> global ids of a packed batch: edge e of graph g gets node_off[g]
 // added; err is set if a local id is outside [0, n_g).
 hipError_t launch_batch_relabel(int32_t num_graphs, const int64_t* node_off, const int64_t* edge_off,

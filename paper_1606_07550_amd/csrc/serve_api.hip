@@ -226,7 +226,7 @@ int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, 
   tricc_batch* b = nullptr;
   int rc = tricc_batch_build(G, qoff.data(), hq.data(), psrc, pdst, at(L.batch), S->slot_bytes - L.batch, &bt, st, &b);
   if (rc) return rc;
-  rc = tricc_batch_bind(b, T, cc, gtri, gavg);
+  rc = tricc_batch_bind(b, T, cc, gtri, gavg, nullptr);
   if (!rc) rc = tricc_batch_run_eager(b, st);
   std::vector<uint64_t> htri(G);
   std::vector<double> havg(G);

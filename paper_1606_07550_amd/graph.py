@@ -148,6 +148,15 @@ class Graph:
         N.check(rc, "tricc_count")
         return out
 
+    def count_check(self, stream=None):
+        """(total, sum of T(v)) of the last count, as the device computed them
+        (synchronises): the total comes from the intersection kernels' own
+        counters, the sum from the epilogue."""
+        t, s = ctypes.c_uint64(), ctypes.c_uint64()
+        N.check(N.lib().tricc_count_check(self._h, ctypes.byref(t), ctypes.byref(s), _stream_ptr(stream)),
+                "tricc_count_check")
+        return int(t.value), int(s.value)
+
     def has_edges(self, u, v, out=None, stream=None):
         """Edge-existence tests: u, v int32 device tensors of one shape;
         returns uint8 (1 edge, 0 no edge, 0xFF an id outside [0, n))."""

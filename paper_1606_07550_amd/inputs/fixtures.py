@@ -120,3 +120,32 @@ def relabel(n, src, dst, seed):
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n).astype(np.int64)
     return n, perm[src].astype(np.int32), perm[dst].astype(np.int32), perm
+
+
+def k4_core(core, centres, avg_deg, seed):
+    """Centres 0..centres-1, pairwise adjacent and joined to every node of a
+    core of `core` nodes that carries a seeded sparse random graph of average
+    degree `avg_deg`; each core node also gets core + centres + 1 private
+    leaves. Core nodes then outrank the centres in (degree, id) order, so a
+    centre's out-list holds the whole core (plus the centres above it): its
+    out-degree lands between `core` and `core + centres - 1`, in the range of
+    a chosen 4-clique kernel, while its rows stay sparse."""
+    rng = np.random.default_rng(seed)
+    c0 = centres
+    pairs = [(a, b) for a in range(centres) for b in range(a + 1, centres)]
+    ci = np.repeat(np.arange(centres), core)
+    cj = np.tile(np.arange(core), centres) + c0
+    m_in = int(core * avg_deg // 2)
+    ia = rng.integers(0, core, size=m_in) + c0
+    ib = rng.integers(0, core, size=m_in) + c0
+    L = core + centres + 1
+    la = np.repeat(np.arange(core), L) + c0
+    lb = np.arange(core * L) + c0 + core
+    s = np.concatenate([np.asarray([p[0] for p in pairs], np.int64), ci, ia, la])
+    d = np.concatenate([np.asarray([p[1] for p in pairs], np.int64), cj, ib, lb])
+    return c0 + core + core * L, s.astype(np.int32), d.astype(np.int32)
+
+
+# (core, centres, avg_deg, seed): the centres' out-degrees fall just above
+# 1,024, inside (1,024, 2,048] and inside (2,048, 4,096]
+K4_CORE_CASES = [(1030, 3, 240, 71), (1500, 4, 90, 72), (2100, 2, 60, 73), (3500, 3, 40, 74)]

@@ -4,6 +4,9 @@
     python -m paper_1606_07550_amd.profiling counters <results.db> [--kernel SUBSTR]
     python -m paper_1606_07550_amd.profiling traffic --fetch F.db --write W.db \
         --kernel SUBSTR --variant V --workload NAME --command "..."
+    python -m paper_1606_07550_amd.profiling summary --fetch F.db --write W.db \
+        --hitmiss H.db --dram D.db --kernel SUBSTR --variant V --bin B --workload NAME \
+        --command "..."
 
 ``kernels`` prints per-kernel call counts and durations (the same figures as
 ``rocprofv3 --stats``); ``counters`` prints the per-dispatch mean of every
@@ -12,7 +15,12 @@ FETCH_SIZE run and a WRITE_SIZE run into bytes per launch of one kernel,
 each scaled by what the same counter reads for the library's streaming copy
 kernel (k_probe_copy) of a known size, and prints a summary whose
 ``key: value`` lines the benchmark reads back (it uses them only while the
-intersection kernels' source hash still matches).
+intersection kernels' source hash still matches). ``summary`` adds the L2
+hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)) and the DRAM-side
+requests of L2 (TCC_EA0_RDREQ_DRAM_sum, TCC_EA0_WRREQ_DRAM_sum), turned into
+bytes by the same counters' reading for the streaming copy of known size: an
+upper bound on what reached HBM (the requests are counted before the
+Infinity Cache). Each counter set comes from its own rocprofv3 --pmc run.
 """
 import argparse
 import hashlib
@@ -87,6 +95,77 @@ def traffic_summary(fetch_db, write_db, kernel, variant, workload, command, bin=
     return "\n".join(lines)
 
 
+def _calib(db, counter, every, offset, kernel):
+    """(mean per launch of the kernel, mean per launch of the copy probe)."""
+    vals = _per_kernel(db, counter, every, offset)
+    probe = [k for k in vals if "k_probe_copy" in k]
+    ks = [k for k in vals if kernel in k]
+    if len(ks) != 1 or not probe:
+        raise SystemExit(f"{counter}: kernel substring {kernel!r} matches {len(ks)} kernels, probe {len(probe)}")
+    return vals[ks[0]][1], vals[probe[0]][1], vals[ks[0]][0], ks[0]
+
+
+def counters_summary(fetch_db, write_db, hitmiss_db, dram_db, kernel, variant, workload, command, bin=None,
+                     every=1, offset=0):
+    f_k, f_p, disp, kname = _calib(fetch_db, "FETCH_SIZE", every, offset, kernel)
+    w_k, w_p, _, _ = _calib(write_db, "WRITE_SIZE", every, offset, kernel)
+    h_k, h_p, _, _ = _calib(hitmiss_db, "TCC_HIT_sum", every, offset, kernel)
+    m_k, m_p, _, _ = _calib(hitmiss_db, "TCC_MISS_sum", every, offset, kernel)
+    r_k, r_p, _, _ = _calib(dram_db, "TCC_EA0_RDREQ_DRAM_sum", every, offset, kernel)
+    wr_k, wr_p, _, _ = _calib(dram_db, "TCC_EA0_WRREQ_DRAM_sum", every, offset, kernel)
+    fetch = f_k / f_p * PROBE_BYTES
+    write = w_k / w_p * PROBE_BYTES
+    dram_rd = r_k / r_p * PROBE_BYTES if r_p else 0.0
+    dram_wr = wr_k / wr_p * PROBE_BYTES if wr_p else 0.0
+    short = kname.split("(")[0].replace("void ", "")
+    sel = (f"Dispatches {offset}, {offset} + {every}, ... of this kernel (bin {bin}'s launches; "
+           f"{every} bins of one count run it).") if every > 1 else ""
+    lines = [
+        f"# rocprofv3 counters of {short} — {workload}",
+        "",
+        "Four rocprofv3 --pmc runs of the same command, one counter set each. Bytes are calibrated per",
+        "counter against the library's streaming copy kernel (k_probe_copy, run inside the same command),",
+        f"which reads and writes {PROBE_BYTES} bytes per launch: bytes = counter(kernel) / counter(copy) x",
+        f"{PROBE_BYTES}. FETCH_SIZE/WRITE_SIZE are L2-to-fabric traffic; TCC_EA0_RDREQ_DRAM/WRREQ_DRAM are",
+        "L2 requests addressed to DRAM, counted before the Infinity Cache: an upper bound on HBM bytes,",
+        "not HBM bytes. L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).",
+        *([sel] if sel else []),
+        "",
+        "Commands (from /tmp, repository at /root/repo; PMC is each counter set in turn):",
+        f"    {command}",
+        "    PMC = FETCH_SIZE | WRITE_SIZE | TCC_HIT_sum TCC_MISS_sum | TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum",
+        "",
+        "| counter | kernel, per launch | copy probe, per launch |",
+        "|---|---|---|",
+        f"| FETCH_SIZE (KiB) | {f_k:.0f} | {f_p:.0f} |",
+        f"| WRITE_SIZE (KiB) | {w_k:.0f} | {w_p:.0f} |",
+        f"| TCC_HIT_sum | {h_k:.0f} | {h_p:.0f} |",
+        f"| TCC_MISS_sum | {m_k:.0f} | {m_p:.0f} |",
+        f"| TCC_EA0_RDREQ_DRAM_sum | {r_k:.0f} | {r_p:.0f} |",
+        f"| TCC_EA0_WRREQ_DRAM_sum | {wr_k:.0f} | {wr_p:.0f} |",
+        "",
+        f"kernel: {short}",
+        f"variant: {variant}",
+        *([f"bin: {bin}"] if bin is not None else []),
+        f"workload: {workload}",
+        f"dispatches: {disp}",
+        f"fetch_bytes_per_launch: {fetch:.0f}",
+        f"write_bytes_per_launch: {write:.0f}",
+        f"traffic_bytes_per_launch: {fetch + write:.0f}",
+        f"dram_read_bytes_per_launch: {dram_rd:.0f}",
+        f"dram_write_bytes_per_launch: {dram_wr:.0f}",
+        f"dram_bytes_per_launch: {dram_rd + dram_wr:.0f}",
+        f"l2_hit_rate: {h_k / (h_k + m_k) if h_k + m_k else 0.0:.4f}",
+        f"count_kernels_sha256: {count_source_sha256()}",
+    ]
+    return "\n".join(lines)
+
+
+def read_summary(path):
+    """Parses the ``key: value`` lines of a summary; None if missing."""
+    return read_traffic(path)
+
+
 def read_traffic(path):
     """Parses a summary written by traffic_summary; None if missing."""
     if not os.path.exists(path):
@@ -128,12 +207,14 @@ def counter_stats(db, kernel=None):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["kernels", "counters", "traffic"])
+    ap.add_argument("what", choices=["kernels", "counters", "traffic", "summary"])
     ap.add_argument("db", nargs="?")
     ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--hitmiss")
+    ap.add_argument("--dram")
     ap.add_argument("--variant", type=int)
     ap.add_argument("--workload")
     ap.add_argument("--command", default="")
@@ -145,6 +226,9 @@ def main():
         print(kernel_stats(a.db, a.top))
     elif a.what == "counters":
         print(counter_stats(a.db, a.kernel))
+    elif a.what == "summary":
+        print(counters_summary(a.fetch, a.write, a.hitmiss, a.dram, a.kernel, a.variant, a.workload, a.command,
+                               a.bin, a.every, a.offset))
     else:
         print(traffic_summary(a.fetch, a.write, a.kernel, a.variant, a.workload, a.command, a.bin, a.every,
                               a.offset))

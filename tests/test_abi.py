@@ -113,14 +113,15 @@ def test_min_side_variants_and_tuning_check():
     from paper_1606_07550_amd import default_tuning, variant_count
     L = N.lib()
     ms = [v for v in range(variant_count()) if L.tricc_variant_min_side(v)]
-    assert ms == list(range(28, 36)) + list(range(38, 48))
+    assert ms == list(range(0, 8)) + list(range(10, 20))
     t = default_tuning()
     assert t.min_side == 1 and all(L.tricc_variant_min_side(t.bin_variant[b]) for b in range(N.NUM_BINS - 1))
     bad = default_tuning()
-    bad.bin_variant[1] = 17  # a wave-stream variant without the in-list side
+    bad.bin_variant[1] = 8  # the global fallback has no in-list side
     h = ctypes.c_void_p()
     assert L.tricc_graph_build(4, 0, None, None, ctypes.c_void_p(256), 1 << 30, ctypes.byref(bad), None,
                                ctypes.byref(h)) == N.TRICC_EINVAL
     assert "min_side" in N.last_error()
     bad.min_side = 0
     L.tricc_default_tuning(ctypes.byref(t))
+

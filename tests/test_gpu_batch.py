@@ -38,10 +38,14 @@ def to_host(out):
         "cc": out["cc"].cpu().numpy(),
         "graph_tri": out["graph_tri"].cpu().numpy().view(np.uint64),
         "graph_avg": out["graph_avg"].cpu().numpy(),
+        "batch_tri": int(out["batch_tri"].cpu().numpy().view(np.uint64)[0]),
     }
 
 
 def check_batch(r, graphs, node_off):
+    # the batch total comes from the intersection kernels' own counters, the
+    # per-graph totals from the per-node counts
+    assert r["batch_tri"] == int(r["graph_tri"].sum(dtype=np.uint64))
     for gi, (n, s, d) in enumerate(graphs):
         ref = oracle.count(n, s, d)
         a, b = node_off[gi], node_off[gi + 1]

@@ -37,6 +37,7 @@ def gpu_count(n, s, d, tuning=None):
         "avg": float(out["avg"].cpu().item()),
         "info": g.info,
         "graph": g,
+        "check": g.count_check(),
     }
     return r
 
@@ -44,6 +45,9 @@ def gpu_count(n, s, d, tuning=None):
 def check_against(r, ref, n):
     np.testing.assert_array_equal(r["T"], ref["T"])
     assert r["total"] == ref["total"]
+    # the total comes from the intersection kernels' own counters, not from T
+    assert r["check"] == (r["total"], int(r["T"].sum(dtype=np.uint64)))
+    assert int(r["T"].sum(dtype=np.uint64)) == 3 * r["total"]
     cc_ref = ref["cc"]
     np.testing.assert_allclose(r["cc"].astype(np.float64), cc_ref, rtol=CC_RTOL, atol=0)
     assert np.array_equal(r["cc"] == 0, cc_ref == 0)
@@ -196,15 +200,15 @@ def _tuning_all_to(variant, limit_bins=None):
 
 
 MIN_SIDE_TUNINGS = [
-    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 1},
-    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 1},
-    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [28, 28, 28, 28, 29, 36], "min_side": 1},
-    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [28, 29, 30, 31, 32, 36], "min_side": 0},
-    {"bin_limit": [32, 64, 256, 1024, 2048], "bin_variant": [29, 29, 35, 33, 34, 36], "min_side": 1},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [0, 1, 2, 3, 4, 8], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [0, 1, 2, 3, 4, 8], "min_side": 1},
+    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [0, 0, 0, 0, 1, 8], "min_side": 1},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [0, 1, 2, 3, 4, 8], "min_side": 0},
+    {"bin_limit": [32, 64, 256, 1024, 2048], "bin_variant": [1, 1, 7, 5, 6, 8], "min_side": 1},
     # cuckoo tables
-    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [38, 39, 40, 41, 42, 37], "min_side": 1},
-    {"bin_limit": [64, 256, 512, 1024, 2048], "bin_variant": [39, 45, 43, 41, 44, 36], "min_side": 1},
-    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [38, 38, 39, 40, 41, 36], "min_side": 1},
+    {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [10, 11, 12, 13, 14, 9], "min_side": 1},
+    {"bin_limit": [64, 256, 512, 1024, 2048], "bin_variant": [11, 17, 15, 13, 16, 8], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [10, 10, 11, 12, 13, 8], "min_side": 1},
 ]
 
 
@@ -271,7 +275,7 @@ def test_hubs_above_every_table():
     s, d = iu[0].astype(np.int32), iu[1].astype(np.int32)
     g = P.Graph(n, to_dev(s), to_dev(d))
     assert g.info["max_outdeg"] == n - 1 and g.info["bin_count"][N.NUM_BINS - 1] == n - 1 - 4096
-    for var in (P.default_tuning().bin_variant[N.NUM_BINS - 1], 36):
+    for var in (P.default_tuning().bin_variant[N.NUM_BINS - 1], 8):
         t = P.default_tuning()
         t.bin_variant[N.NUM_BINS - 1] = var
         g.retune(t)
@@ -295,7 +299,7 @@ def test_cuckoo_tables_fall_back_to_buckets():
     s = np.array([a for i, a in enumerate(hub) for b in hub[i + 1:]], dtype=np.int32)
     d = np.array([b for i, a in enumerate(hub) for b in hub[i + 1:]], dtype=np.int32)
     g = P.Graph(n, to_dev(s), to_dev(d))
-    for var in (38, 39, 40, 41):
+    for var in (10, 11, 12, 13):
         g.retune(_tuning_all_to(var))
         o = g.count()
         torch.cuda.synchronize()
@@ -306,8 +310,8 @@ def test_cuckoo_tables_fall_back_to_buckets():
     s, d = iu[0].astype(np.int32), iu[1].astype(np.int32)
     g = P.Graph(k, to_dev(s), to_dev(d))
     assert g.info["max_outdeg"] == k - 1
-    for tun in (_tuning_all_to(42),
-                {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [38, 39, 40, 41, 42, 37], "min_side": 1}):
+    for tun in (_tuning_all_to(14),
+                {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [10, 11, 12, 13, 14, 9], "min_side": 1}):
         g.retune(tun)
         o = g.count()
         torch.cuda.synchronize()
@@ -420,7 +424,8 @@ def test_from_csr_trusted_rows_match_pair_build():
     o = g.count()
     torch.cuda.synchronize()
     r = {"T": o["T"].cpu().numpy().view(np.uint64), "cc": o["cc"].cpu().numpy(),
-         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info}
+         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info,
+         "check": g.count_check()}
     check_against(r, ref, n)
     B = {k: v.cpu().numpy() for k, v in g.arrays().items()}
     np.testing.assert_array_equal(B["deg"], A["deg"])
@@ -439,7 +444,8 @@ def test_from_csr_general_rows_take_the_full_build():
     o = g.count()
     torch.cuda.synchronize()
     r = {"T": o["T"].cpu().numpy().view(np.uint64), "cc": o["cc"].cpu().numpy(),
-         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info}
+         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]), "avg": float(o["avg"].item()), "info": g.info,
+         "check": g.count_check()}
     check_against(r, ref, n)
     # empty graph and isolated ids
     g = P.Graph.from_csr(5, to_dev64(np.zeros(6, np.int64)), to_dev(np.zeros(0, np.int32)), True)

@@ -1,18 +1,23 @@
 """GPU parity at the benchmark's full sizes, in the launch configuration the
 benchmark times (its cached tuning, or the default):
 - R-MAT 20: every node against the oracle;
-- R-MAT 24: sampled nodes (high-degree and random ones) against the
-  oracle's per-node count from the raw edge list, plus identities that hold
-  at any size (sum of T(v) = 3T, T(v) <= C(d(v), 2), CC(v) from T(v) and
-  d(v) as the epilogue defines it, the average);
-- the 4,096-graph batch: sampled graphs against the oracle, every graph's
-  total against its per-node counts;
+- R-MAT 24 (the benchmark graph): every node against the oracle through the
+  stored oracle results (tests/golden/rmat24.json: edge count, total,
+  average, fingerprints of T(v) and d(v), and the 16 largest hubs' exact
+  T(v) and d(v)), the total from the kernels' own counters, plus identities
+  that hold at any size (T(v) <= C(d(v), 2), CC(v) from T(v) and d(v));
+- the 4,096-graph batch: every graph against the stored oracle results
+  (tests/golden/batch4096.json), and the batch total from the kernels' own
+  counters against the sum of the graph totals;
 - serving on R-MAT 22: sampled queries (the largest and random ones) of the
   20,000-query trace against the oracle's induced-subgraph count;
 - edge-existence tests on G(n=10M, m=100M): every input pair positive, 2M
   sampled queries against the oracle;
 - core numbers on R-MAT 22, every node against the oracle.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -25,6 +30,22 @@ from paper_1606_07550_amd import inputs as I
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 CC_RTOL = 1e-6
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def fingerprint(a):
+    """(sum a[v](v+1), sum a[v]^2 (2v+1)) mod 2^64, as tests/golden/make_golden.py
+    stores it for the oracle's arrays."""
+    a = np.ascontiguousarray(a).astype(np.uint64)
+    v = np.arange(a.size, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return [int((a * (v + np.uint64(1))).sum(dtype=np.uint64)),
+                int((a * a * (np.uint64(2) * v + np.uint64(1))).sum(dtype=np.uint64))]
 
 
 def say(msg):
@@ -50,12 +71,15 @@ def run_single(n, s, d, workload):
         "total": int(o["total"].cpu().numpy().view(np.uint64)[0]),
         "avg": float(o["avg"].item()),
         "deg": g.arrays()["deg"].cpu().numpy(),
+        "check": g.count_check(),
     }
 
 
 def check_identities(r):
     T, deg = r["T"], r["deg"].astype(np.int64)
-    assert int(T.sum()) == 3 * r["total"]
+    # the total comes from the intersection kernels' own counters, not from T
+    assert int(T.sum(dtype=np.uint64)) == 3 * r["total"]
+    assert r["check"] == (r["total"], int(T.sum(dtype=np.uint64)))
     assert np.all(T.astype(np.float64) <= deg * (deg - 1) / 2)
     dd = deg.astype(np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -77,30 +101,29 @@ def test_rmat20_every_node():
     check_identities(r)
 
 
-def test_rmat24_sampled_nodes_and_identities():
+def test_rmat24_every_node_against_stored_oracle():
+    ref = golden("rmat24.json")
     n, s, d = I.rmat(24, 16, seed=24)
+    assert (n, s.size) == (ref["n"], ref["m_raw"])
     say(f"rmat24 n={n} m_raw={s.size}")
     g, r = run_single(n, s, d, "rmat24")
     say(f"rmat24 total={r['total']} m={g.info['m']}")
+    assert g.info["m"] == ref["m"]
+    assert r["total"] == ref["total"]
+    assert fingerprint(r["deg"]) == ref["deg_fp"]
+    assert fingerprint(r["T"]) == ref["T_fp"]
+    assert abs(r["avg"] - float.fromhex(ref["avg_hex"])) <= CC_RTOL * float.fromhex(ref["avg_hex"])
+    for h in ref["hubs"]:  # the largest hubs, whose T(v) take the most atomics
+        assert (int(r["deg"][h["node"]]), int(r["T"][h["node"]])) == (h["deg"], h["T"]), h
     check_identities(r)
-    deg = r["deg"]
-    rng = np.random.default_rng(2424)
-    # high-degree nodes whose neighbour pairs the oracle can still list
-    # (the largest hubs are covered by the every-node check at R-MAT 20)
-    big = rng.choice(np.flatnonzero((deg >= 1000) & (deg <= 20000)), size=12, replace=False)
-    rest = rng.choice(np.flatnonzero(deg >= 1), size=200, replace=False)
-    samples = np.unique(np.concatenate([big, rest, [0, n - 1]])).astype(np.int32)
-    say(f"rmat24 oracle on {samples.size} sampled nodes (degrees up to {deg[samples].max()}) ...")
-    ref = oracle.sampled(n, s, d, samples)
-    say(f"rmat24 oracle on {samples.size} sampled nodes done")
-    np.testing.assert_array_equal(deg[samples], ref["deg"])
-    np.testing.assert_array_equal(r["T"][samples], ref["T"])
 
 
-def test_batch_4096_sampled_graphs_and_totals():
+def test_batch_4096_every_graph_against_stored_oracle():
     G = 4096
+    ref = golden("batch4096.json")["graphs"]
     bt = I.batch(G, 4096)
     node_off, edge_off = bt["node_off"], bt["edge_off"]
+    assert len(ref) == G and [x["n"] for x in ref] == np.diff(node_off).tolist()
     say(f"batch G={G} nodes={node_off[-1]} pairs={edge_off[-1]}")
     b = P.Batch(node_off, edge_off, dev(bt["src"]), dev(bt["dst"]),
                 tuning=autotune.default_or_cached_batch(f"batched-{G}"))
@@ -111,22 +134,23 @@ def test_batch_4096_sampled_graphs_and_totals():
     cc = b.out["cc"].cpu().numpy()
     gtri = b.out["graph_tri"].cpu().numpy().view(np.uint64)
     gavg = b.out["graph_avg"].cpu().numpy()
-    nonempty = np.flatnonzero(np.diff(node_off) > 0)
-    sums = np.add.reduceat(T.astype(np.uint64), node_off[nonempty].astype(np.int64))
-    np.testing.assert_array_equal(sums, 3 * gtri[nonempty])
-    rng = np.random.default_rng(4096)
-    sizes = np.diff(edge_off)
-    picks = np.unique(np.concatenate([np.argsort(sizes)[-6:], rng.choice(G, size=40, replace=False)]))
-    for gi in picks:
+    btri = int(b.out["batch_tri"].cpu().numpy().view(np.uint64)[0])
+    deg = b.graph_arrays()["deg"].cpu().numpy()
+    assert btri == int(gtri.sum(dtype=np.uint64)) == sum(x["total"] for x in ref)
+    for gi in range(G):
         a, e = int(node_off[gi]), int(node_off[gi + 1])
-        e0, e1 = int(edge_off[gi]), int(edge_off[gi + 1])
-        ref = oracle.count(e - a, bt["src"][e0:e1], bt["dst"][e0:e1])
-        np.testing.assert_array_equal(T[a:e], ref["T"], err_msg=f"graph {gi}")
-        assert gtri[gi] == ref["total"], gi
-        np.testing.assert_allclose(cc[a:e].astype(np.float64), ref["cc"], rtol=CC_RTOL, atol=0)
-        assert abs(gavg[gi] - ref["avg"]) <= CC_RTOL * abs(ref["avg"]), gi
-    say(f"batch: {picks.size} graphs against the oracle")
-
+        x = ref[gi]
+        assert int(gtri[gi]) == x["total"], gi
+        assert fingerprint(T[a:e]) == x["T_fp"], gi
+        assert fingerprint(deg[a:e]) == x["deg_fp"], gi
+        avg = float.fromhex(x["avg_hex"])
+        assert abs(gavg[gi] - avg) <= CC_RTOL * abs(avg), gi
+    # CC(v) from the (now verified) T(v) and d(v), rounded once from FP64
+    dd = deg.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(deg >= 2, 2.0 * T.astype(np.float64) / (dd * (dd - 1.0)), 0.0)
+    np.testing.assert_array_equal(cc, ratio.astype(np.float32))
+    say(f"batch: all {G} graphs against the stored oracle results")
 
 def test_edge_queries_er_10m_100m_sampled():
     """The benchmark's edge-existence configuration, G(n=10M, m=100M) with

@@ -4,7 +4,12 @@ a graph built from a CSR, repeat calls, and the out-degree limit. Counts are
 integers, compared exactly. Complete graphs K_k reach every kernel: out-degrees
 up to 512 (K_513 and below), 513-1,024 (K_514 .. K_1025), the quarter passes
 (K_1026 .. K_2049) and the sixteenth passes (K_2050, K_2100); the dense
-G(1100, 0.6) case takes the 513-1,024 kernel against the oracle."""
+G(1100, 0.6) case takes the 513-1,024 kernel against the oracle. The pass
+kernels also run on sparse rows: hub-and-core graphs whose centres have
+out-degrees just above 1,024, inside (1,024, 2,048] and inside
+(2,048, 4,096], against stored oracle counts (tests/golden/k4_pass.json)."""
+import json
+import os
 from math import comb
 
 import numpy as np
@@ -95,3 +100,22 @@ def test_out_degree_limit_is_enforced():
     with pytest.raises(N.TriccError) as ei:
         g.count_k4()
     assert ei.value.status == N.TRICC_EOVERFLOW
+
+
+def _k4_core_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "k4_pass.json")) as f:
+        return json.load(f)["graphs"]
+
+
+@pytest.mark.parametrize("case", _k4_core_cases(), ids=lambda c: f"core{c['core']}")
+def test_pass_kernels_on_sparse_rows(case):
+    """The centres' rows over N+(centre) (the core) are sparse with partial
+    last words, so the passes' position filter and hit lists matter."""
+    n, s, d = F.k4_core(case["core"], case["centres"], case["avg_deg"], case["seed"])
+    assert n == case["n"]
+    print(f"[k4] core={case['core']} centres={case['centres']} n={n}", flush=True)
+    g = P.Graph(n, dev(s), dev(d))
+    mo = g.info["max_outdeg"]
+    assert case["core"] <= mo <= case["core"] + case["centres"] - 1 and 1024 < mo <= 4096
+    assert gpu_k4(g) == case["k4"]
+    assert gpu_k4(g) == case["k4"]
