@@ -302,6 +302,29 @@ int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream);
 
 void tricc_graph_free(tricc_graph* g);
 
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation). The
+ * same result as tricc_graph_build with the default tuning followed by
+ * tricc_count, for a graph of at most TRICC_NOALLOC_MAX_NODES nodes and
+ * TRICC_NOALLOC_MAX_PAIRS input pairs, with the graph's workspace taken from
+ * a fixed device array of TRICC_NOALLOC_SCRATCH_BYTES inside the library
+ * (one per GPU, held until the process ends) instead of a caller buffer.
+ * No device or host memory is allocated; the outputs are the caller's, as
+ * in tricc_count. Synchronises `stream` (the build reads sizes back).
+ * Every call on one GPU uses that GPU's one array, so calls that overlap in
+ * time on one GPU (from several threads or streams) race and must not be
+ * made; each call clears what it needs before use.
+ * Errors: TRICC_EOVERFLOW above the size limits, TRICC_ERANGE for an id
+ * outside [0, n), TRICC_EINVAL for null arrays, TRICC_EHIP on a runtime
+ * error.
+ */
+#define TRICC_NOALLOC_MAX_NODES 65536
+#define TRICC_NOALLOC_MAX_PAIRS (1LL << 20)
+#define TRICC_NOALLOC_SCRATCH_BYTES (32u << 20)
+int tricc_count_noalloc(int32_t n, int64_t m_raw, const int32_t* d_src, const int32_t* d_dst, uint64_t* d_node_tri,
+                        float* d_node_cc, uint64_t* d_total, double* d_avg_cc, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched graphs: many independent graphs counted by one persistent launch.
  *

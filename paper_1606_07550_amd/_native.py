@@ -133,6 +133,7 @@ _SIGS = {
     "tricc_graph_arrays": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                           ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "tricc_graph_free": (None, [_P]),
+    "tricc_count_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P]),
     "tricc_batch_default_tuning": (ctypes.c_int, [ctypes.POINTER(BatchTuning)]),
     "tricc_batch_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                                   ctypes.POINTER(ctypes.c_size_t)]),

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -841,6 +842,70 @@ int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream) 
 }
 
 void tricc_graph_free(tricc_graph* g) { delete g; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Count without allocating: the graph workspace of a small graph lives in a
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code must not pass the array's name to a kernel (that is a host-side
+// stand-in): its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is used.
+namespace {
+
+constexpr size_t kNoAllocBytes = TRICC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TRICC_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % kAlign) return fail(TRICC_EHIP, "scratch symbol address unusable");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return TRICC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tricc_count_noalloc(int32_t n, int64_t m_raw, const int32_t* d_src, const int32_t* d_dst, uint64_t* d_node_tri,
+                        float* d_node_cc, uint64_t* d_total, double* d_avg_cc, void* stream) {
+  g_err[0] = 0;
+  if (n < 0 || m_raw < 0) return fail(TRICC_EINVAL, "negative size");
+  if (n > TRICC_NOALLOC_MAX_NODES || m_raw > TRICC_NOALLOC_MAX_PAIRS)
+    return fail(TRICC_EOVERFLOW, "tricc_count_noalloc takes n <= %d and m_raw <= %lld (got n = %d, m_raw = %lld)",
+                TRICC_NOALLOC_MAX_NODES, (long long)TRICC_NOALLOC_MAX_PAIRS, n, (long long)m_raw);
+  if (m_raw > 0 && (!d_src || !d_dst)) return fail(TRICC_EINVAL, "null edge arrays");
+  if ((n > 0 && (!d_node_tri || !d_node_cc)) || !d_total || !d_avg_cc) return fail(TRICC_EINVAL, "null output");
+  const Layout L = make_layout(n, m_raw);
+  if (L.total > kNoAllocBytes)
+    return fail(TRICC_EOVERFLOW, "graph needs %zu bytes of scratch, %zu available", L.total, kNoAllocBytes);
+  char* ws = nullptr;
+  int rc = scratch_for_current_device(&ws);
+  if (rc) return rc;
+  // the handle lives on this stack frame: no host or device allocation
+  tricc_graph g;
+  g.n = n;
+  g.m_raw = m_raw;
+  g.ws = ws;
+  g.L = L;
+  g.stream = static_cast<hipStream_t>(stream);
+  tricc_default_tuning_impl(&g.tuning);
+  std::memset(&g.info, 0, sizeof(g.info));
+  if ((rc = build_impl(&g, d_src, d_dst))) return rc;
+  return tricc_count(&g, d_node_tri, d_node_cc, d_total, d_avg_cc, stream);
+}
 
 }  // extern "C"
 

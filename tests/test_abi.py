@@ -125,3 +125,15 @@ def test_min_side_variants_and_tuning_check():
     bad.min_side = 0
     L.tricc_default_tuning(ctypes.byref(t))
 
+
+def test_noalloc_limits_are_checked_before_device_work():
+    L = N.lib()
+    P_ = ctypes.c_void_p(256)
+    assert L.tricc_count_noalloc(65537, 0, None, None, P_, P_, P_, P_, None) == N.TRICC_EOVERFLOW
+    assert L.tricc_count_noalloc(10, (1 << 20) + 1, P_, P_, P_, P_, P_, P_, None) == N.TRICC_EOVERFLOW
+    assert L.tricc_count_noalloc(-1, 0, None, None, P_, P_, P_, P_, None) == N.TRICC_EINVAL
+    assert L.tricc_count_noalloc(10, 5, None, None, P_, P_, P_, P_, None) == N.TRICC_EINVAL
+    assert L.tricc_count_noalloc(10, 0, None, None, None, P_, P_, P_, None) == N.TRICC_EINVAL
+    # the largest graph the fixed array takes fits it
+    from paper_1606_07550_amd.graph import workspace_size
+    assert workspace_size(65536, 1 << 20) <= 32 << 20
