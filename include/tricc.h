@@ -288,6 +288,42 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
                      int32_t* h_max_core, void* stream);
 
 /*
+ * Degeneracy ordering (the k-core row of the paper's Section 4 table of
+ * analytics methods, with the Batagelj-Zaversnik decomposition of
+ * Section 5). The full core decomposition of tricc_graph_core, which also
+ * records for every node the round in which the peeling removed it (every
+ * frontier is one round, counted across levels): d_order[v] = that round.
+ * A node removed in round r has at most core(v) neighbours removed in round
+ * r or later, so the orientation by (d_order[v], v) gives every node an
+ * out-degree of at most its core number, and the largest out-degree is at
+ * most the degeneracy (the largest core number), against sqrt(2m) for the
+ * degree order.
+ *   d_order, d_core  device int32[n], the caller's (written)
+ *   d_ws, ws_bytes   as for tricc_graph_core
+ *   h_degeneracy     host int32 (may be NULL): the largest core number
+ * Synchronises `stream`. Errors as tricc_graph_core.
+ */
+int tricc_graph_degeneracy(const tricc_graph* g, int32_t* d_order, int32_t* d_core, void* d_ws, size_t ws_bytes,
+                           int32_t* h_degeneracy, void* stream);
+
+/*
+ * Re-orients the graph's DAG by the rank (d_key[v], v) instead of (d(v), v)
+ * and re-bins its nodes (steps a4-a5 again on the built simple graph), so
+ * that the triangle and 4-clique counts run on that orientation; d_key =
+ * NULL restores the degree order. Any strict order gives the same counts;
+ * the order only moves work between nodes (with the degeneracy order of
+ * tricc_graph_degeneracy, out-degrees are bounded by core numbers).
+ *   d_key  device int32[n] of values >= 0 (not checked), or NULL; only read
+ *          during the call
+ * Clears the statistics of tricc_graph_stats. Synchronises `stream`.
+ * Errors: TRICC_EINVAL for a null handle, TRICC_EHIP on a runtime error;
+ * TRICC_EINVAL if the graph's tuning cannot hold the new out-degrees (the
+ * graph then keeps the new DAG with the old bins unusable: re-orient or
+ * retune before counting).
+ */
+int tricc_graph_reorient(tricc_graph* g, const int32_t* d_key, void* stream);
+
+/*
  * Number of 4-cliques (clique detection, among the graph-motif methods of
  * the paper's Section 4: the triangle count one size up). Counted on the
  * degree-ordered DAG: a 4-clique u < w < x < z (by rank) is met once, at u,
@@ -370,6 +406,26 @@ int tricc_batch_workspace_size(int32_t num_graphs, int64_t total_nodes, int64_t 
 int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64_t* h_edge_off,
                       const int32_t* d_src, const int32_t* d_dst, void* d_ws, size_t ws_bytes,
                       const tricc_batch_tuning* tuning, void* stream, tricc_batch** out);
+
+/* The same batch handed over as a packed CSR (the paper's sorted
+ * neighbour vectors, Section 5.1, for each graph, laid end to end): node v of
+ * graph g is row h_node_off[g] + v, its entries d_col[d_rowptr[r] ..
+ * d_rowptr[r+1]) hold local ids in [0, n_g).
+ *   h_node_off  host int64[G+1] as for tricc_batch_build
+ *   nnz         entries (d_rowptr[total nodes] must equal it; <= 2^30)
+ *   d_rowptr    device int64[total nodes + 1], from 0, non-decreasing
+ *   d_col       device int32[nnz]
+ *   assume_simple_sorted_symmetric  as for tricc_graph_from_csr: 1 skips the
+ *               sort (rows strictly ascending, no self loop, symmetric in
+ *               each graph; checked except symmetry), 0 takes every entry as
+ *               a pair through the full build
+ * Synchronises `stream`. Errors: TRICC_ERANGE for a local id outside its
+ * graph's range (or, with 1, outside [0, n)), TRICC_EINVAL for malformed
+ * offsets or rows, TRICC_ENOMEM for a short workspace
+ * (tricc_batch_workspace_size(G, total nodes, nnz)). */
+int tricc_batch_build_csr(int32_t num_graphs, const int64_t* h_node_off, int64_t nnz, const int64_t* d_rowptr,
+                          const int32_t* d_col, int assume_simple_sorted_symmetric, void* d_ws, size_t ws_bytes,
+                          const tricc_batch_tuning* tuning, void* stream, tricc_batch** out);
 
 /* Binds the outputs and captures the count into a hipGraph: clear (a
  * kernel), the persistent intersection kernel, the per-graph epilogue.

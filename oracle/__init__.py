@@ -48,6 +48,9 @@ def lib():
         d = ctypes.c_double
         L.oracle_rmat.argtypes = [ctypes.c_int, d, d, d, d, d, ctypes.c_uint64, i64, P, P, P, P]
         L.oracle_rmat.restype = ctypes.c_int
+        d_ = ctypes.c_double
+        L.oracle_count_timed.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, i64, i64, P, P, P, P]
+        L.oracle_count_timed.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -83,6 +86,19 @@ def count(n, src, dst, order=0, threads=0):
     if rc:
         raise OracleError(f"oracle_count failed ({rc})")
     return dict(T=T, cc=cc, deg=deg, total=int(total.value), avg=float(avg.value), m=int(m.value))
+
+
+def count_timed(n, src, dst, order=1, threads=0, stride=1, offset=0):
+    """Oracle timing on a node sample: dict(build_s, count_s, tri, m); tri
+    = triangles whose lowest-ranked vertex v has v % stride == offset."""
+    src, dst = _i32(src), _i32(dst)
+    tri, m = ctypes.c_uint64(), ctypes.c_int64()
+    b, c = ctypes.c_double(), ctypes.c_double()
+    rc = lib().oracle_count_timed(n, src.size, _ptr(src), _ptr(dst), order, threads, stride, offset,
+                                  ctypes.byref(tri), ctypes.byref(m), ctypes.byref(b), ctypes.byref(c))
+    if rc:
+        raise OracleError(f"oracle_count_timed failed ({rc})")
+    return dict(build_s=b.value, count_s=c.value, tri=int(tri.value), m=int(m.value))
 
 
 def induced(n, src, dst, nodes, threads=0):

@@ -118,16 +118,20 @@ static inline int og_below(const og_graph* g, int order_mode, int64_t a, int64_t
   return da < db || (da == db && a < b);
 }
 
-/* Node-iterator count over the whole graph; T must be zeroed. */
-static uint64_t og_count(const og_graph* g, int order_mode, int nthreads, uint64_t* T) {
+/* Node-iterator count from the lowest-ranked vertices v = offset, offset +
+ * stride, ... (stride 1, offset 0: the whole graph); T must be zeroed. */
+static uint64_t og_count_from(const og_graph* g, int order_mode, int nthreads, int64_t stride, int64_t offset,
+                              uint64_t* T) {
   const int64_t n = g->n;
   uint64_t total = 0;
   if (nthreads <= 0) nthreads = omp_get_max_threads();
+  const int64_t nv = offset < n ? (n - offset + stride - 1) / stride : 0;
 #pragma omp parallel num_threads(nthreads) reduction(+ : total)
   {
     int64_t* mark = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t v = 0; v < n; ++v) {
+    for (int64_t i = 0; i < nv; ++i) {
+      const int64_t v = offset + i * stride;
       for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) mark[g->adj[p]] = v + 1;
       for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) {
         const int64_t u = g->adj[p];
@@ -150,6 +154,10 @@ static uint64_t og_count(const og_graph* g, int order_mode, int nthreads, uint64
     free(mark);
   }
   return total;
+}
+
+static uint64_t og_count(const og_graph* g, int order_mode, int nthreads, uint64_t* T) {
+  return og_count_from(g, order_mode, nthreads, 1, 0, T);
 }
 
 static void og_cc(const og_graph* g, const uint64_t* T, double* cc, double* avg) {
@@ -185,6 +193,36 @@ int oracle_count(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* ds
     for (int64_t v = 0; v < n; ++v) deg[v] = g.off[v + 1] - g.off[v];
   if (m_out) *m_out = g.m;
   if (!T) free(t);
+  og_free(&g);
+  return 0;
+}
+
+/*
+ * Timing of the oracle on a node sample of a large graph: the graph build
+ * (symmetrise, dedup, sorted rows) over all pairs, timed on its own, then the
+ * node iterator from the lowest-ranked vertices v with v % stride == offset
+ * only, timed on its own. *tri receives the triangles whose lowest-ranked
+ * vertex is sampled (summed over offset = 0 .. stride-1 this is the total).
+ * Returns 0; -1 for an id outside [0,n); -2 on allocation failure; -3 for a
+ * bad stride or offset.
+ */
+int oracle_count_timed(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, int order_mode,
+                       int nthreads, int64_t stride, int64_t offset, uint64_t* tri, int64_t* m_out,
+                       double* build_s, double* count_s) {
+  if (stride < 1 || offset < 0 || offset >= stride) return -3;
+  og_graph g;
+  const double t0 = omp_get_wtime();
+  int rc = og_build(n, m_raw, src, dst, &g);
+  if (rc) return rc;
+  const double t1 = omp_get_wtime();
+  uint64_t* t = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+  if (!t) { og_free(&g); return -2; }
+  *tri = og_count_from(&g, order_mode, nthreads, stride, offset, t);
+  const double t2 = omp_get_wtime();
+  *build_s = t1 - t0;
+  *count_s = t2 - t1;
+  if (m_out) *m_out = g.m;
+  free(t);
   og_free(&g);
   return 0;
 }

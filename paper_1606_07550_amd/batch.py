@@ -62,6 +62,40 @@ class Batch:
         N.check(rc, "tricc_batch_build")
         self.out = None
 
+    @classmethod
+    def from_csr(cls, node_off, rowptr, col, assume_simple_sorted_symmetric=False, tuning=None, stream=None,
+                 workspace=None):
+        """A batch handed over as a packed CSR: ``node_off`` host int64[G+1];
+        ``rowptr`` device int64[total nodes + 1] over ``col`` (device int32,
+        local ids). Builds in the constructor (synchronises)."""
+        node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+        if node_off.ndim != 1 or node_off.size < 1:
+            raise ValueError("node_off must be a 1-D array of G+1 offsets")
+        if rowptr.dtype != torch.int64 or col.dtype != torch.int32 or not (rowptr.is_cuda and col.is_cuda):
+            raise TypeError("rowptr must be an int64 and col an int32 device tensor")
+        self = cls.__new__(cls)
+        self.G = node_off.size - 1
+        self.n_total = int(node_off[-1])
+        self.m_total = int(col.numel())
+        if rowptr.numel() != self.n_total + 1:
+            raise ValueError("rowptr must hold total nodes + 1 offsets")
+        self.device = col.device
+        self.node_off = node_off
+        self.edge_off = None
+        need = batch_workspace_size(self.G, self.n_total, self.m_total)
+        self.ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=self.device)
+        self._src, self._dst = rowptr.contiguous(), col.contiguous()
+        self._h = ctypes.c_void_p()
+        t = _as_batch_tuning(tuning)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_batch_build_csr(
+                self.G, node_off.ctypes.data_as(ctypes.c_void_p), self.m_total, _ptr(self._src), _ptr(self._dst),
+                int(bool(assume_simple_sorted_symmetric)), _ptr(self.ws), self.ws.numel(),
+                ctypes.byref(t) if t is not None else None, _stream_ptr(stream), ctypes.byref(self._h))
+        N.check(rc, "tricc_batch_build_csr")
+        self.out = None
+        return self
+
     @property
     def info(self):
         i = N.BatchInfo()

@@ -118,6 +118,8 @@ struct tricc_graph {
   int64_t bin_off[kNumBins + 1];
   int64_t in_off[kNumBins + 1];    // in-list nodes of each bin (min-side)
   int64_t in_items[kNumBins + 1];  // chunk prefix at the in-list bin boundaries
+  int64_t cls_off[kNumRowClasses + 1];  // row classes (by raw length) in the row list
+  int32_t oriented_by_key;         // 1 when the DAG follows a caller's key, not the degrees
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   int32_t* hdr32() const { return at<int32_t>(L.hdr); }
 };
@@ -338,6 +340,62 @@ int graph_stats(tricc_graph* g) {
   return TRICC_OK;
 }
 
+// a4-a5: orient every edge of the simple graph from the lower to the higher
+// rank (key(v), v), with key = the degrees when key is null, then bin the
+// DAG's nodes. The simple graph's rows (adj, raw_off, len, deg) and the row
+// lists by class are read; the DAG, in-lists, d+, d- and bins are rewritten.
+int orient_impl(tricc_graph* g, const int32_t* key) {
+  hipStream_t s = g->stream;
+  const Layout& L = g->L;
+  const int32_t n = g->n;
+  int32_t* hdr = g->hdr32();
+  int32_t* len = g->at<int32_t>(L.len);
+  int32_t* deg = g->at<int32_t>(L.deg);
+  int64_t* raw_off = g->at<int64_t>(L.raw_off);
+  int64_t* scan_tmp = g->at<int64_t>(L.scan_tmp);
+  int32_t* adj = g->at<int32_t>(L.adj);
+  int32_t* rowlist = g->at<int32_t>(L.rowlist);
+  const int64_t* cls_off = g->cls_off;
+  int rc;
+  HIPCHK(hipMemsetAsync(hdr + kHdrStats, 0, sizeof(int32_t) * 3, s));  // max d, max d+, nodes with d >= 2
+  // a4: orientation (rows longer than 64 raw entries: classes kRow128 ..
+  // kRowLds4k are medium, the classes above them are long; the row lists
+  // are class-major, so each range is contiguous)
+  int32_t* dplus = g->at<int32_t>(L.dplus);
+  int64_t* doff = g->at<int64_t>(L.doff);
+  int32_t* dcol = g->at<int32_t>(L.dcol);
+  const int32_t* med_rows = rowlist + cls_off[kRow128];
+  const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRow128]);
+  const int32_t* long_rows = rowlist + cls_off[kRowLds8k];
+  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds8k]);
+  // one pass partitions every row into tmp (free again after a3), then
+  // the scans place the out- and in-lists
+  int32_t* part = g->at<int32_t>(L.tmp);
+  // the degree-class words (n / 4 bytes) sit in binlist, free until the binning
+  uint32_t* cls = reinterpret_cast<uint32_t*>(g->at<int32_t>(L.binlist));
+  HIPCHK(launch_orient(n, raw_off, len, deg, key, adj, med_rows, nmed, long_rows, nlong, cls, dplus, part,
+                       hdr + kHdrStats, s));
+  HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
+  int32_t* din = g->at<int32_t>(L.din);
+  int64_t* dinoff = g->at<int64_t>(L.dinoff);
+  HIPCHK(launch_indeg(n, deg, dplus, din, hdr + kHdrDeg2, s));
+  HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
+  HIPCHK(launch_orient_copy(n, raw_off, len, deg, dplus, part, med_rows, nmed, long_rows, nlong, doff, dcol, dinoff,
+                            g->at<int32_t>(L.dincol), s));
+  HIPCHK(launch_edge_records(n, raw_off, deg, g->at<int32_t>(L.rec), s));
+  int32_t stats[3];  // max d, max d+, nodes with d >= 2
+  if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
+  int64_t m = 0;
+  if ((rc = sync_copy(&m, doff + n, sizeof(m), s))) return rc;
+  g->info.m = m;
+  g->info.max_deg = stats[0];
+  g->info.max_outdeg = stats[1];
+  g->info.n_deg2 = stats[2];
+  g->oriented_by_key = key != nullptr;
+  // a5: binning
+  return bin_nodes(g);
+}
+
 // Builds a1-a5. With presorted set, adj, raw_off, len and deg already hold
 // simple, sorted, symmetric rows (a caller CSR that was checked) and a1-a3
 // reduce to the row classification that the orientation needs.
@@ -414,43 +472,49 @@ int build_impl(tricc_graph* g, const int32_t* src, const int32_t* dst, bool pres
     if (cnt[kRowLarge] > 0)
       if ((rc = sort_large_rows(g, cnt[kRowLarge], rowlist + cls_off[kRowLarge]))) return rc;
   }
-  // a4: orientation (rows longer than 64 raw entries: classes kRow128 ..
-  // kRowLds4k are medium, the classes above them are long; the row lists
-  // are class-major, so each range is contiguous)
-  int32_t* dplus = g->at<int32_t>(L.dplus);
-  int64_t* doff = g->at<int64_t>(L.doff);
-  int32_t* dcol = g->at<int32_t>(L.dcol);
-  const int32_t* med_rows = rowlist + cls_off[kRow128];
-  const int32_t nmed = (int32_t)(cls_off[kRowLds4k + 1] - cls_off[kRow128]);
-  const int32_t* long_rows = rowlist + cls_off[kRowLds8k];
-  const int32_t nlong = (int32_t)(cls_off[kNumRowClasses] - cls_off[kRowLds8k]);
-  // one pass partitions every row into tmp (free again after a3), then
-  // the scans place the out- and in-lists
-  int32_t* part = g->at<int32_t>(L.tmp);
-  // the degree-class words (n / 4 bytes) sit in binlist, free until the binning
-  uint32_t* cls = reinterpret_cast<uint32_t*>(g->at<int32_t>(L.binlist));
-  HIPCHK(launch_orient(n, raw_off, len, deg, adj, med_rows, nmed, long_rows, nlong, cls, dplus, part,
-                       hdr + kHdrStats, s));
-  HIPCHK(launch_scan_i32(dplus, n, doff, scan_tmp, s));
-  int32_t* din = g->at<int32_t>(L.din);
-  int64_t* dinoff = g->at<int64_t>(L.dinoff);
-  HIPCHK(launch_indeg(n, deg, dplus, din, hdr + kHdrDeg2, s));
-  HIPCHK(launch_scan_i32(din, n, dinoff, scan_tmp, s));
-  HIPCHK(launch_orient_copy(n, raw_off, len, deg, dplus, part, med_rows, nmed, long_rows, nlong, doff, dcol, dinoff,
-                            g->at<int32_t>(L.dincol), s));
-  HIPCHK(launch_edge_records(n, raw_off, deg, g->at<int32_t>(L.rec), s));
-  int32_t stats[3];  // max d, max d+, nodes with d >= 2
-  if ((rc = sync_copy(stats, hdr + kHdrStats, sizeof(stats), s))) return rc;
-  int64_t m = 0;
-  if ((rc = sync_copy(&m, doff + n, sizeof(m), s))) return rc;
+  for (int c = 0; c <= kNumRowClasses; ++c) g->cls_off[c] = cls_off[c];
   g->info.n = n;
   g->info.m_raw = m_raw;
-  g->info.m = m;
-  g->info.max_deg = stats[0];
-  g->info.max_outdeg = stats[1];
-  g->info.n_deg2 = stats[2];
-  // a5: binning
-  return bin_nodes(g);
+  return orient_impl(g, nullptr);
+}
+
+
+}  // namespace
+
+namespace {
+// a1-a5 from a CSR (see tricc_graph_from_csr); g's size, layout, stream and
+// tuning are set. Reads the caller's arrays only.
+int csr_build(tricc_graph* g, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_col,
+              int assume_simple_sorted_symmetric) {
+  const int32_t n = g->n;
+  const Layout& L = g->L;
+  hipStream_t s = g->stream;
+  int32_t* hdr = g->hdr32();
+  int32_t err = 0;
+  int r;
+  HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
+  if (!assume_simple_sorted_symmetric) {
+    // rows as (v, w) pairs through the full build; the pair sources sit in
+    // the in-list area, which the build writes only after a3
+    HIPCHK(launch_csr_bounds(n, nnz, d_rowptr, nullptr, nullptr, hdr + kHdrErr, s));
+    if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+    if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
+    int32_t* src = g->at<int32_t>(L.dincol);
+    HIPCHK(launch_csr_expand(n, d_rowptr, src, s));
+    return build_impl(g, src, d_col);
+  }
+  int64_t* raw_off = g->at<int64_t>(L.raw_off);
+  int32_t* adj = g->at<int32_t>(L.adj);
+  HIPCHK(hipMemcpyAsync(raw_off, d_rowptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_csr_bounds(n, nnz, raw_off, g->at<int32_t>(L.len), g->at<int32_t>(L.deg), hdr + kHdrErr, s));
+  if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+  if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
+  if (nnz > 0) HIPCHK(hipMemcpyAsync(adj, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_csr_rows(n, raw_off, adj, hdr + kHdrErr, s));
+  if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
+  if (err & 1) return fail(TRICC_ERANGE, "CSR holds a node id outside [0, %d)", n);
+  if (err) return fail(TRICC_EINVAL, "CSR row not strictly ascending or holding its own id");
+  return build_impl(g, nullptr, nullptr, true);
 }
 
 }  // namespace
@@ -567,37 +631,7 @@ int tricc_graph_from_csr(int32_t n, int64_t nnz, const int64_t* d_rowptr, const 
   g->stream = static_cast<hipStream_t>(stream);
   g->tuning = t;
   std::memset(&g->info, 0, sizeof(g->info));
-  auto run = [&]() -> int {
-    const Layout& L = g->L;
-    hipStream_t s = g->stream;
-    int32_t* hdr = g->hdr32();
-    int32_t err = 0;
-    int r;
-    HIPCHK(hipMemsetAsync(hdr, 0, kHdrBytes, s));
-    if (!assume_simple_sorted_symmetric) {
-      // rows as (v, w) pairs through the full build; the pair sources sit in
-      // the in-list area, which the build writes only after a3
-      HIPCHK(launch_csr_bounds(n, nnz, d_rowptr, nullptr, nullptr, hdr + kHdrErr, s));
-      if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
-      if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
-      int32_t* src = g->at<int32_t>(L.dincol);
-      HIPCHK(launch_csr_expand(n, d_rowptr, src, s));
-      return build_impl(g, src, d_col);
-    }
-    int64_t* raw_off = g->at<int64_t>(L.raw_off);
-    int32_t* adj = g->at<int32_t>(L.adj);
-    HIPCHK(hipMemcpyAsync(raw_off, d_rowptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_csr_bounds(n, nnz, raw_off, g->at<int32_t>(L.len), g->at<int32_t>(L.deg), hdr + kHdrErr, s));
-    if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
-    if (err) return fail(TRICC_EINVAL, "CSR row offsets are not a non-decreasing sequence from 0 to nnz");
-    if (nnz > 0) HIPCHK(hipMemcpyAsync(adj, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_csr_rows(n, raw_off, adj, hdr + kHdrErr, s));
-    if ((r = sync_copy(&err, hdr + kHdrErr, sizeof(err), s))) return r;
-    if (err & 1) return fail(TRICC_ERANGE, "CSR holds a node id outside [0, %d)", n);
-    if (err) return fail(TRICC_EINVAL, "CSR row not strictly ascending or holding its own id");
-    return build_impl(g, nullptr, nullptr, true);
-  };
-  rc = run();
+  rc = csr_build(g, nnz, d_rowptr, d_col, assume_simple_sorted_symmetric);
   if (rc) {
     delete g;
     return rc;
@@ -760,8 +794,14 @@ int tricc_core_workspace_size(int32_t n, size_t* bytes) {
   return TRICC_OK;
 }
 
-int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void* d_ws, size_t ws_bytes,
-                     int32_t* h_max_core, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Peeling loop of the core decomposition; with d_order, every node's removal
+// round as well (frontiers counted across levels).
+int core_impl(const tricc_graph* g, int32_t k_stop, int32_t* d_core, int32_t* d_order, void* d_ws, size_t ws_bytes,
+              int32_t* h_max_core, int32_t* h_rounds, void* stream) {
   if (!g) return fail(TRICC_EINVAL, "null graph");
   const int32_t n = g->n;
   size_t need = 0;
@@ -769,7 +809,7 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
   if (n > 0 && (!d_core || !d_ws)) return fail(TRICC_EINVAL, "null core output or workspace");
   if (n > 0 && ws_bytes < need) return fail(TRICC_ENOMEM, "core workspace of %zu bytes, %zu needed", ws_bytes, need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int32_t maxc = 0;
+  int32_t maxc = 0, round = 0;
   if (n > 0) {
     char* w = static_cast<char*>(d_ws);
     const size_t slice = align_up(sizeof(int32_t) * (size_t)n);
@@ -794,7 +834,7 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
     while (left > 0 && (k_stop < 0 || k < k_stop)) {
       const bool listing = cand != nullptr || left <= n / 4;
       HIPCHK(launch_core_reset(cnt, 0, s));
-      HIPCHK(launch_core_scan(ncand, cand, k, cur, d_core, F, listing ? S : nullptr, cnt, s));
+      HIPCHK(launch_core_scan(ncand, cand, k, cur, d_core, F, listing ? S : nullptr, cnt, d_order, round, s));
       int32_t c[4];
       if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
       if (listing) {
@@ -811,7 +851,8 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
       while (nf > 0) {
         left -= nf;
         HIPCHK(launch_core_reset(cnt, 1, s));
-        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, s));
+        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, d_order, round, s));
+        ++round;
         if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
         std::swap(F, G);
         nf = c[1];
@@ -826,8 +867,35 @@ int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void
     HIPCHK(hipStreamSynchronize(s));
   }
   if (h_max_core) *h_max_core = maxc;
+  if (h_rounds) *h_rounds = round;
   return TRICC_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int tricc_graph_core(const tricc_graph* g, int32_t k_stop, int32_t* d_core, void* d_ws, size_t ws_bytes,
+                     int32_t* h_max_core, void* stream) {
+  return core_impl(g, k_stop, d_core, nullptr, d_ws, ws_bytes, h_max_core, nullptr, stream);
+}
+
+int tricc_graph_degeneracy(const tricc_graph* g, int32_t* d_order, int32_t* d_core, void* d_ws, size_t ws_bytes,
+                           int32_t* h_degeneracy, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (g->n > 0 && (!d_order || !d_core)) return fail(TRICC_EINVAL, "null order or core output");
+  return core_impl(g, -1, d_core, d_order, d_ws, ws_bytes, h_degeneracy, nullptr, stream);
+}
+
+int tricc_graph_reorient(tricc_graph* g, const int32_t* d_key, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  g->stream = static_cast<hipStream_t>(stream);
+  std::memset(g->info.bin_list_elems, 0, sizeof(g->info.bin_list_elems));
+  g->info.list_elems = 0;
+  return orient_impl(g, d_key);
+}
+
+
 
 int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream) {
   if (!g) return fail(TRICC_EINVAL, "null graph");
@@ -1124,6 +1192,79 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
   if ((rc = sync_copy(&err, b->d_err, sizeof(err), s))) return bail(rc);
   if (err) return bail(fail(TRICC_ERANGE, "a local node id is outside its graph's [0, n_g)"));
   if ((rc = build_impl(g, b->gsrc, b->gdst))) return bail(rc);
+  if ((rc = batch_bin(b))) return bail(rc);
+  *out = b;
+  return TRICC_OK;
+}
+
+int tricc_batch_build_csr(int32_t num_graphs, const int64_t* h_node_off, int64_t nnz, const int64_t* d_rowptr,
+                          const int32_t* d_col, int assume_simple_sorted_symmetric, void* d_ws, size_t ws_bytes,
+                          const tricc_batch_tuning* tuning, void* stream, tricc_batch** out) {
+  g_err[0] = 0;
+  if (!out) return fail(TRICC_EINVAL, "null out");
+  *out = nullptr;
+  if (num_graphs < 0 || (num_graphs > 0 && !h_node_off)) return fail(TRICC_EINVAL, "bad graph count or offsets");
+  if (nnz < 0) return fail(TRICC_EINVAL, "negative entry count");
+  const int64_t n_total = num_graphs ? h_node_off[num_graphs] : 0;
+  if (num_graphs && h_node_off[0] != 0) return fail(TRICC_EINVAL, "offsets must start at 0");
+  for (int32_t k = 0; k < num_graphs; ++k)
+    if (h_node_off[k + 1] < h_node_off[k]) return fail(TRICC_EINVAL, "offsets must be non-decreasing");
+  size_t need = 0;
+  int rc = tricc_batch_workspace_size(num_graphs, n_total, nnz, &need);
+  if (rc) return rc;
+  if (!d_rowptr || (nnz > 0 && !d_col)) return fail(TRICC_EINVAL, "null CSR arrays");
+  if (!d_ws) return fail(TRICC_EINVAL, "null workspace");
+  if (ws_bytes < need) return fail(TRICC_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(TRICC_EINVAL, "workspace not 256-byte aligned");
+  tricc_batch_tuning bt;
+  if (tuning) bt = *tuning; else tricc_batch_default_tuning(&bt);
+  if ((rc = check_batch_tuning(&bt))) return rc;
+
+  tricc_batch* b = new (std::nothrow) tricc_batch();
+  if (!b) return fail(TRICC_ENOMEM, "host allocation failed");
+  const BatchLayout BL = make_batch_layout(num_graphs, n_total, nnz);
+  char* ws = static_cast<char*>(d_ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  b->G = num_graphs;
+  b->n_total = n_total;
+  b->m_total = nnz;
+  b->ws = ws;
+  b->ws_bytes = ws_bytes;
+  b->d_queue = reinterpret_cast<int32_t*>(ws + BL.hdr);
+  b->d_err = reinterpret_cast<int32_t*>(ws + BL.hdr + 64);
+  b->d_node_off = reinterpret_cast<int64_t*>(ws + BL.node_off);
+  b->d_edge_off = reinterpret_cast<int64_t*>(ws + BL.edge_off);
+  b->gsrc = reinterpret_cast<int32_t*>(ws + BL.gsrc);
+  b->gdst = reinterpret_cast<int32_t*>(ws + BL.gdst);
+  b->tuning = bt;
+  tricc_graph* g = &b->g;
+  g->n = (int32_t)n_total;
+  g->m_raw = nnz;
+  g->ws = ws + BL.graph_ws;
+  g->L = make_layout(n_total, nnz);
+  g->stream = s;
+  std::memset(&g->info, 0, sizeof(g->info));
+  batch_graph_tuning(bt, &g->tuning);
+  auto bail = [&](int code) { delete b; return code; };
+  if (hipMemsetAsync(ws + BL.hdr, 0, 256, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
+  if ((rc = upload(b->d_node_off, h_node_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
+  // the graphs' entry ranges, rowptr at the node boundaries; the row offsets
+  // themselves are checked by the CSR build
+  int64_t last = 0;
+  if (num_graphs > 0) {
+    if (launch_gather_offsets(d_rowptr, b->d_node_off, num_graphs + 1, b->d_edge_off, s) != hipSuccess)
+      return bail(fail(TRICC_EHIP, "offset gather failed"));
+    if ((rc = sync_copy(&last, b->d_edge_off + num_graphs, sizeof(last), s))) return bail(rc);
+    if (last != nnz) return bail(fail(TRICC_EINVAL, "rowptr[total nodes] = %lld, expected nnz = %lld",
+                                      (long long)last, (long long)nnz));
+  }
+  if (launch_batch_relabel(num_graphs, b->d_node_off, b->d_edge_off, nullptr, d_col, nnz, nullptr, b->gdst, b->d_err,
+                           s) != hipSuccess)
+    return bail(fail(TRICC_EHIP, "relabel launch failed"));
+  int32_t err = 0;
+  if ((rc = sync_copy(&err, b->d_err, sizeof(err), s))) return bail(rc);
+  if (err) return bail(fail(TRICC_ERANGE, "a local node id is outside its graph's [0, n_g)"));
+  if ((rc = csr_build(g, nnz, d_rowptr, b->gdst, assume_simple_sorted_symmetric))) return bail(rc);
   if ((rc = batch_bin(b))) return bail(rc);
   *out = b;
   return TRICC_OK;

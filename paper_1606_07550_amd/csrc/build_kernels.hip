@@ -627,12 +627,12 @@ hipError_t launch_classify_inbins(int pass, int32_t n, const int32_t* dplus, con
 
 __global__ void k_gather_offsets(const int64_t* __restrict__ prefix, const int64_t* __restrict__ at, int k,
                                  int64_t* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i < k) out[i] = prefix[at[i]];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) out[i] = prefix[at[i]];
 }
 
 hipError_t launch_gather_offsets(const int64_t* prefix, const int64_t* at, int k, int64_t* out, hipStream_t s) {
-  k_gather_offsets<<<1, 64, 0, s>>>(prefix, at, k, out);
+  if (k <= 0) return hipSuccess;
+  k_gather_offsets<<<(unsigned)std::min(1024, (k + 255) / 256), 256, 0, s>>>(prefix, at, k, out);
   return hipGetLastError();
 }
 
@@ -1064,22 +1064,24 @@ __device__ __forceinline__ uint32_t deg_class(int32_t d) {
   return (uint32_t)(d >= 64) + (uint32_t)(d >= 512) + (uint32_t)(d >= 4096);
 }
 
-// True when w ranks above v (rank = (d, id)); dv, cv = d(v), class(d(v)).
-__device__ __forceinline__ bool ranks_above(int32_t dv, uint32_t cv, int32_t v, int32_t w,
-                                            const int32_t* __restrict__ deg, const uint32_t* __restrict__ cls) {
+// True when w ranks above v (rank = (key, id), key = d by default); kv, cv =
+// key(v), class(key(v)). The classes agree with any key order, so the same
+// test serves the degree order and a caller's order (e.g. degeneracy).
+__device__ __forceinline__ bool ranks_above(int32_t kv, uint32_t cv, int32_t v, int32_t w,
+                                            const int32_t* __restrict__ key, const uint32_t* __restrict__ cls) {
   const uint32_t cw = (cls[w >> 4] >> (2 * (w & 15))) & 3u;
   if (cw != cv) return cw > cv;
-  return rank_below(dv, v, deg[w], w);
+  return rank_below(kv, v, key[w], w);
 }
 
-__global__ __launch_bounds__(256) void k_deg_class(int32_t n, const int32_t* __restrict__ deg,
+__global__ __launch_bounds__(256) void k_deg_class(int32_t n, const int32_t* __restrict__ key,
                                                    uint32_t* __restrict__ cls) {
   const int64_t words = ((int64_t)n + 15) / 16;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (int64_t)gridDim.x * blockDim.x) {
     uint32_t word = 0;
     for (int j = 0; j < 16; ++j) {
       const int64_t v = k * 16 + j;
-      if (v < n) word |= deg_class(deg[v]) << (2 * j);
+      if (v < n) word |= deg_class(key[v]) << (2 * j);
     }
     cls[k] = word;
   }
@@ -1106,6 +1108,7 @@ __device__ __forceinline__ T block_max(T x, T* lds) {
 __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* __restrict__ off,
                                                       const int32_t* __restrict__ len,
                                                       const int32_t* __restrict__ deg,
+                                                      const int32_t* __restrict__ key,
                                                       const uint32_t* __restrict__ cls,
                                                       const int32_t* __restrict__ adj,
                                                       int32_t* __restrict__ dplus, int32_t* __restrict__ part,
@@ -1118,8 +1121,8 @@ __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* 
   int32_t mx_d = 0, mx_p = 0;
   for (int64_t v = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; v < n; v += ngroups) {
     if (len[v] > kOrientShort) continue;
-    const int32_t dv = deg[v];
-    const uint32_t cv = deg_class(dv);
+    const int32_t dv = deg[v], kv = key[v];
+    const uint32_t cv = deg_class(kv);
     const int64_t rb = off[v];
     const int32_t* row = adj + rb;
     int32_t* prow = part + rb;
@@ -1135,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_orient_short(int32_t n, const int64_t* 
 #pragma unroll
       for (int q = 0; q < kOrientShortUnroll; ++q) {
         const int32_t i = b + q * G + g;
-        f[q] = i < dv && ranks_above(dv, cv, (int32_t)v, w[q], deg, cls);
+        f[q] = i < dv && ranks_above(kv, cv, (int32_t)v, w[q], key, cls);
       }
 #pragma unroll
       for (int q = 0; q < kOrientShortUnroll; ++q) {
@@ -1165,6 +1168,7 @@ constexpr int kOrientLongPer = 4;  // consecutive entries per thread per step
 __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __restrict__ rows,
                                                                const int64_t* __restrict__ off,
                                                                const int32_t* __restrict__ deg,
+                                                               const int32_t* __restrict__ key,
                                                                const uint32_t* __restrict__ cls,
                                                                const int32_t* __restrict__ adj,
                                                                int32_t* __restrict__ dplus,
@@ -1172,8 +1176,8 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
                                                                int32_t* __restrict__ stats) {
   __shared__ int32_t lds[kOrientLongNT / kWave + 1];
   const int32_t v = rows[blockIdx.x];
-  const int32_t dv = deg[v];
-  const uint32_t cv = deg_class(dv);
+  const int32_t dv = deg[v], kv = key[v];
+  const uint32_t cv = deg_class(kv);
   const int64_t rb = off[v];
   const int32_t* row = adj + rb;
   int32_t* prow = part + rb;
@@ -1187,7 +1191,7 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
     for (int q = 0; q < kOrientLongPer; ++q) w[q] = i0 + q < dv ? row[i0 + q] : 0;
 #pragma unroll
     for (int q = 0; q < kOrientLongPer; ++q) {
-      f[q] = i0 + q < dv && ranks_above(dv, cv, v, w[q], deg, cls);
+      f[q] = i0 + q < dv && ranks_above(kv, cv, v, w[q], key, cls);
       k += f[q];
     }
     int32_t tot;
@@ -1213,6 +1217,7 @@ __global__ __launch_bounds__(kOrientLongNT) void k_orient_long(const int32_t* __
 __global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict__ rows, int32_t nrows,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ deg,
+                                                       const int32_t* __restrict__ key,
                                                        const uint32_t* __restrict__ cls,
                                                        const int32_t* __restrict__ adj,
                                                        int32_t* __restrict__ dplus, int32_t* __restrict__ part,
@@ -1223,8 +1228,8 @@ __global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict
   int32_t mx_d = 0, mx_p = 0;
   for (int64_t r = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; r < nrows; r += nwaves) {
     const int32_t v = rows[r];
-    const int32_t dv = deg[v];
-    const uint32_t cv = deg_class(dv);
+    const int32_t dv = deg[v], kv = key[v];
+    const uint32_t cv = deg_class(kv);
     const int64_t rb = off[v];
     const int32_t* row = adj + rb;
     int32_t* prow = part + rb;
@@ -1242,7 +1247,7 @@ __global__ __launch_bounds__(256) void k_orient_medium(const int32_t* __restrict
 #pragma unroll
       for (int q = 0; q < kOrientMedUnroll; ++q) {
         const int32_t i = b + q * kWave + l;
-        f[q] = i < dv && ranks_above(dv, cv, v, w[q], deg, cls);
+        f[q] = i < dv && ranks_above(kv, cv, v, w[q], key, cls);
       }
 #pragma unroll
       for (int q = 0; q < kOrientMedUnroll; ++q) {
@@ -1319,17 +1324,19 @@ __global__ __launch_bounds__(256) void k_orient_copy_listed(const int32_t* __res
     orient_copy_row<G>(rows[r], threadIdx.x % G, off, deg, dplus, part, doff, dcol, dinoff, dincol);
 }
 
-hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
-                         const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
-                         uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s) {
+hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* key,
+                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
+                         int32_t nlong, uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_deg_class<<<grid_for(((int64_t)n + 15) / 16, 256, 4096), 256, 0, s>>>(n, deg, cls);
-  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, cls, adj, dplus,
-                                                                             part, stats);
+  if (!key) key = deg;
+  k_deg_class<<<grid_for(((int64_t)n + 15) / 16, 256, 4096), 256, 0, s>>>(n, key, cls);
+  k_orient_short<<<grid_for((int64_t)n * kOrientG, 256, 1u << 16), 256, 0, s>>>(n, off, len, deg, key, cls, adj,
+                                                                             dplus, part, stats);
   if (nmedium > 0)
     k_orient_medium<<<grid_for((int64_t)nmedium * kWave, 256, 1u << 14), 256, 0, s>>>(medium_rows, nmedium, off, deg,
-                                                                                   cls, adj, dplus, part, stats);
-  if (nlong > 0) k_orient_long<<<nlong, kOrientLongNT, 0, s>>>(long_rows, off, deg, cls, adj, dplus, part, stats);
+                                                                                   key, cls, adj, dplus, part, stats);
+  if (nlong > 0)
+    k_orient_long<<<nlong, kOrientLongNT, 0, s>>>(long_rows, off, deg, key, cls, adj, dplus, part, stats);
   return hipGetLastError();
 }
 
@@ -1596,7 +1603,8 @@ hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream
 }
 
 // Packed batch -> disjoint union: the graph of edge e is found by binary
-// search over edge_off (G + 1 entries).
+// search over edge_off (G + 1 entries). With src null only dst is mapped (the
+// column array of a packed CSR, whose rows already sit at global positions).
 __global__ __launch_bounds__(256) void k_batch_relabel(int32_t G, const int64_t* __restrict__ node_off,
                                                        const int64_t* __restrict__ edge_off,
                                                        const int32_t* __restrict__ src,
@@ -1613,14 +1621,14 @@ __global__ __launch_bounds__(256) void k_batch_relabel(int32_t G, const int64_t*
     }
     const int64_t base = node_off[lo];
     const int64_t ng = node_off[lo + 1] - base;
-    const int32_t u = src[e], v = dst[e];
+    const int32_t u = src ? src[e] : 0, v = dst[e];
     if (u < 0 || v < 0 || u >= ng || v >= ng) {
       bad = true;
-      gsrc[e] = (int32_t)base;  // keeps the union well formed; the build is refused anyway
+      if (src) gsrc[e] = (int32_t)base;  // keeps the union well formed; the build is refused anyway
       gdst[e] = (int32_t)base;
       continue;
     }
-    gsrc[e] = (int32_t)(base + u);
+    if (src) gsrc[e] = (int32_t)(base + u);
     gdst[e] = (int32_t)(base + v);
   }
   if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1);

@@ -7,6 +7,13 @@
 // joins the next frontier of the same level. Levels with no node are
 // skipped: a scan that finds no frontier reports the smallest current
 // degree left.
+//
+// With `order` given, each node also records the round in which it was
+// removed (rounds count every frontier, across levels). A node removed in
+// round r had current degree <= k then, counting exactly its neighbours
+// removed in round r or later, so orienting every edge towards the later
+// (round, id) gives out-degrees at most the core number: the degeneracy
+// ordering.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -59,7 +66,8 @@ __global__ void k_core_reset(int32_t* __restrict__ cnt, int which) {
 __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t* __restrict__ A, int32_t k,
                                                        const int32_t* __restrict__ cur, int32_t* __restrict__ core,
                                                        int32_t* __restrict__ F, int32_t* __restrict__ S,
-                                                       int32_t* __restrict__ cnt) {
+                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ order,
+                                                       int32_t round) {
   const int64_t stride = (int64_t)gridDim.x * kCoreNT;
   int32_t mn = 0x7fffffff;
   for (int64_t b = (int64_t)blockIdx.x * kCoreNT; b < na; b += stride) {  // uniform trip count
@@ -72,6 +80,7 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
         const int32_t c = cur[v];
         if (c <= k) {
           core[v] = k;
+          if (order) order[v] = round;
           take = true;
         } else {
           mn = min(mn, c);
@@ -90,9 +99,11 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
 // Lowers the current degree of w (if still left) at level k; true for the
 // one decrement that takes it from k + 1 to k (w then has core number k).
 __device__ __forceinline__ bool core_drop(int32_t w, int32_t k, int32_t* __restrict__ cur,
-                                          int32_t* __restrict__ core) {
+                                          int32_t* __restrict__ core, int32_t* __restrict__ order,
+                                          int32_t next_round) {
   if (core[w] < 0 && atomicSub(&cur[w], 1) == k + 1) {
     core[w] = k;
+    if (order) order[w] = next_round;
     return true;
   }
   return false;
@@ -110,7 +121,8 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
                                                        const int32_t* __restrict__ deg,
                                                        const int32_t* __restrict__ adj, int32_t* __restrict__ cur,
                                                        int32_t* __restrict__ core, int32_t* __restrict__ G,
-                                                       int32_t* __restrict__ cnt) {
+                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ order,
+                                                       int32_t round) {
   constexpr int GPB = kCoreNT / kPeelG;
   const int lane = lane_id();
   const int g = threadIdx.x % kPeelG;
@@ -135,7 +147,7 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
       int32_t w = 0;
       if (j < ds) {
         w = adj[rb + j];
-        take = core_drop(w, k, cur, core);
+        take = core_drop(w, k, cur, core, order, round + 1);
       }
       wave_push(take, w, G, cnt + 1);
     }
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
         int32_t w = 0;
         if (j < d) {
           w = adj[r + j];
-          take = core_drop(w, k, cur, core);
+          take = core_drop(w, k, cur, core, order, round + 1);
         }
         wave_push(take, w, G, cnt + 1);
       }
@@ -185,17 +197,18 @@ hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s) {
 }
 
 hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
-                            int32_t* S, int32_t* cnt, hipStream_t s) {
+                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, hipStream_t s) {
   if (na <= 0) return hipSuccess;
-  k_core_scan<<<core_grid(na), kCoreNT, 0, s>>>(na, A, k, cur, core, F, S, cnt);
+  k_core_scan<<<core_grid(na), kCoreNT, 0, s>>>(na, A, k, cur, core, F, S, cnt, order, round);
   return hipGetLastError();
 }
 
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
-                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt,
-                            hipStream_t s) {
+                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
+                            int32_t round, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
-  k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, k, off, deg, adj, cur, core, G, cnt);
+  k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, k, off, deg, adj, cur, core, G, cnt, order,
+                                                                  round);
   return hipGetLastError();
 }
 

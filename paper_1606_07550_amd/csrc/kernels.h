@@ -81,10 +81,12 @@ hipError_t launch_dedup_rows(const int32_t* rows, const int64_t* seg_beg, int32_
 // part[off[v] .. off[v] + d(v)): N+(v) ascending from the front, N-(v) from
 // the back in reverse. Rows of raw length > 64 must be listed: medium_rows
 // (a wavefront each) and long_rows (a block each) together. cls: scratch of
-// ceil(n / 16) words for the degree classes of the rank test.
-hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* adj,
-                         const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows, int32_t nlong,
-                         uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s);
+// ceil(n / 16) words for the key classes of the rank test. key (may be
+// null: the degrees) replaces d in the rank (key(v), v); it must hold
+// non-negative values.
+hipError_t launch_orient(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg, const int32_t* key,
+                         const int32_t* adj, const int32_t* medium_rows, int32_t nmedium, const int32_t* long_rows,
+                         int32_t nlong, uint32_t* cls, int32_t* dplus, int32_t* part, int32_t* stats, hipStream_t s);
 // After doff / dinoff are the scans of d+ / d-: N+(v) to dcol[doff[v]..] and
 // (dincol != NULL) N-(v) to dincol[dinoff[v]..], both ascending.
 hipError_t launch_orient_copy(int32_t n, const int64_t* off, const int32_t* len, const int32_t* deg,
@@ -214,11 +216,13 @@ hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int
 // NULL: all ids) and lists the other nodes left in S (if not NULL).
 hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t* core, hipStream_t s);
 hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s);
+// order (may be null): removal round of each node taken, `round` for the
+// scan's frontier and round + 1 for the peel's next frontier.
 hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
-                            int32_t* S, int32_t* cnt, hipStream_t s);
+                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, hipStream_t s);
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
-                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt,
-                            hipStream_t s);
+                            const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
+                            int32_t round, hipStream_t s);
 hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
 
 // ---- 4-clique counts ---------------------------------------------------------

@@ -187,6 +187,42 @@ class Graph:
         N.check(rc, "tricc_graph_core")
         return out, int(mx.value)
 
+    def degeneracy(self, stream=None):
+        """Degeneracy ordering: (order int32[n], core int32[n], degeneracy),
+        order[v] = the peeling round that removed v. Synchronises."""
+        n = self.n
+        need = ctypes.c_size_t()
+        N.check(N.lib().tricc_core_workspace_size(n, ctypes.byref(need)), "tricc_core_workspace_size")
+        ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+        order = torch.empty(max(n, 0), dtype=torch.int32, device=self.device)
+        core = torch.empty(max(n, 0), dtype=torch.int32, device=self.device)
+        mx = ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_degeneracy(self._h, _ptr(order) if n > 0 else None,
+                                                _ptr(core) if n > 0 else None, _ptr(ws), need.value,
+                                                ctypes.byref(mx), _stream_ptr(stream))
+        N.check(rc, "tricc_graph_degeneracy")
+        return order, core, int(mx.value)
+
+    def reorient(self, key=None, stream=None):
+        """Orients the DAG by (key[v], v) (an int32 device tensor of n values
+        >= 0), or by degree when key is None, and re-bins. Synchronises."""
+        if key is not None:
+            if key.dtype != torch.int32 or not key.is_cuda or key.numel() != self.n:
+                raise TypeError("key must be an int32 device tensor of n values")
+            key = key.contiguous()
+        self._key = key  # kept alive for the call
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_reorient(self._h, _ptr(key) if key is not None and self.n > 0 else None,
+                                              _stream_ptr(stream))
+        N.check(rc, "tricc_graph_reorient")
+
+    def orient_degeneracy(self, stream=None):
+        """Re-orients by the degeneracy ordering; returns its degeneracy."""
+        order, _, dg = self.degeneracy(stream)
+        self.reorient(order, stream)
+        return dg
+
     def count_k4(self, out=None, stream=None):
         """Number of 4-cliques: uint64[1] (as an int64 tensor) on the device.
         Asynchronous. Raises TriccError (TRICC_EOVERFLOW) when some out-degree

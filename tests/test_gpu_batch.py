@@ -206,3 +206,60 @@ def test_empty_batch_members():
     r = to_host(b.out)
     assert list(r["graph_tri"]) == [0, 0, 4]
     assert r["graph_avg"][0] == 0.0 and r["graph_avg"][1] == 0.0 and r["graph_avg"][2] == 1.0
+
+
+def packed_csr(graphs, simple):
+    """Packed CSR of the graphs (local ids): simple=True gives each graph's
+    simple symmetric rows, ascending; False gives the raw pairs as rows
+    (row u holds v for every input pair (u, v))."""
+    rows, cols = [], []
+    n0 = 0
+    for n, s, d in graphs:
+        s = s.astype(np.int64)
+        d = d.astype(np.int64)
+        if simple:
+            a, b = np.minimum(s, d), np.maximum(s, d)
+            keep = a != b
+            key = np.unique(a[keep] * max(n, 1) + b[keep])
+            u, v = key // max(n, 1), key % max(n, 1)
+            r, c = np.concatenate([u, v]), np.concatenate([v, u])
+        else:
+            r, c = s, d
+        o = np.lexsort((c, r))
+        rows.append(r[o] + n0)
+        cols.append(c[o])
+        n0 += n
+    rows = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    cols = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    rowptr = np.zeros(n0 + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n0), out=rowptr[1:])
+    return rowptr, cols
+
+
+@pytest.mark.parametrize("simple", [True, False])
+def test_packed_csr_batch_matches_oracle(mixed, simple):
+    graphs, (node_off, edge_off, src, dst) = mixed
+    rowptr, col = packed_csr(graphs, simple)
+    print(f"[batch csr] simple={simple} G={len(graphs)} nnz={col.size}", flush=True)
+    b = P.Batch.from_csr(node_off, torch.from_numpy(rowptr).to(DEV), dev(col), assume_simple_sorted_symmetric=simple)
+    b.plan()
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(to_host(b.out), graphs, node_off)
+
+
+def test_packed_csr_batch_errors(mixed):
+    graphs = [F.complete(5), F.wheel(6)]
+    node_off, _, _, _ = pack(graphs)
+    rowptr, col = packed_csr(graphs, True)
+    bad = col.copy()
+    bad[-1] = 7  # the wheel has local ids 0..6: 7 is outside its range
+    for simple in (True, False):
+        with pytest.raises(N.TriccError) as ei:
+            P.Batch.from_csr(node_off, torch.from_numpy(rowptr).to(DEV), dev(bad), assume_simple_sorted_symmetric=simple)
+        assert ei.value.status == N.TRICC_ERANGE
+    rp = rowptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]  # not non-decreasing
+    with pytest.raises(N.TriccError) as ei:
+        P.Batch.from_csr(node_off, torch.from_numpy(rp).to(DEV), dev(col), assume_simple_sorted_symmetric=True)
+    assert ei.value.status in (N.TRICC_EINVAL, N.TRICC_ERANGE)

@@ -839,3 +839,19 @@ def test_unmutated_oracle_passes_rmat_battery(tmp_path):
     lib = tmp_path / "liborig.so"
     subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", src, "-o", str(lib)], check=True)
     assert _rmat_pins_pass(str(lib))
+
+
+def test_count_timed_sample_partitions_the_triangles():
+    """The node-sampled timing entry finds exactly the triangles whose
+    lowest-ranked vertex is sampled: over all offsets of one stride the
+    samples add up to the whole count (both rank orders), and stride 1 is the
+    whole count."""
+    from paper_1606_07550_amd import inputs as I
+    n, s, d = I.rmat(12, 16, seed=81)
+    for order in (0, 1):
+        full = oracle.count(n, s, d, order=order)["total"]
+        assert oracle.count_timed(n, s, d, order=order, stride=1)["tri"] == full
+        parts = [oracle.count_timed(n, s, d, order=order, stride=7, offset=o)["tri"] for o in range(7)]
+        assert sum(parts) == full and all(p < full for p in parts)
+    with pytest.raises(oracle.OracleError):
+        oracle.count_timed(n, s, d, stride=4, offset=4)
