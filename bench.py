@@ -47,8 +47,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS) + ["er"])
-    ap.add_argument("--cpu-sample-scale", type=int, default=19,
-                    help="R-MAT scale of the CPU oracle's sample (same generator and parameters)")
+    ap.add_argument("--cpu-sample-stride", type=int, default=64,
+                    help="CPU oracle: count from the root nodes with id % stride == 0 on all host threads")
+    ap.add_argument("--cpu-sample-stride1", type=int, default=2048,
+                    help="CPU oracle: the same on one thread from id % stride1 == 0 (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="JSON file with bin_limit / bin_variant")
     ap.add_argument("--out", default=None, help="also append the JSON line to this file")
@@ -62,8 +64,10 @@ def parse():
                     help="search the single-graph bin tuning first (cached per arch/workload)")
     ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
     ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
+    ap.add_argument("--no-degeneracy", action="store_true",
+                    help="skip the degeneracy-order leg (triangles and 4-cliques under both orders)")
     ap.add_argument("--no-k4", action="store_true", help="skip the 4-clique leg")
-    ap.add_argument("--no-gen", action="store_true", help="skip the device R-MAT generator leg")
+    ap.add_argument("--no-gen", action="store_true", help="skip the device generator legs (R-MAT, G(n, m), BA)")
     ap.add_argument("--k4-scale", type=int, default=22, help="4-clique leg: R-MAT scale")
     ap.add_argument("--edge-n", type=int, default=10_000_000, help="edge-existence leg: ER nodes")
     ap.add_argument("--edge-m", type=int, default=100_000_000, help="edge-existence leg: ER edges (= queries)")
@@ -326,6 +330,68 @@ def gen_leg(args, torch, P, N):
     return line
 
 
+def gen_er_ba_leg(args, torch, P, N):
+    """Device G(n, m) and Barabasi-Albert generators at the sizes the other
+    legs use: G(10^7, 10^8) (the edge-existence workload) and BA with n =
+    2^22, k = 16 (the batch's largest attachment count), each timed on the
+    host around the call (both synchronise), against the host input
+    generators and the oracle's generators of the same definitions on a
+    prefix (the first edges of a smaller instance of the same seed)."""
+    from paper_1606_07550_amd import generators as GEN
+    from paper_1606_07550_amd import inputs as I
+    import oracle
+    dev = torch.device("cuda:0")
+    out = {}
+    n, m = args.edge_n, args.edge_m
+    need = ctypes.c_size_t()
+    N.check(N.lib().tricc_gen_er_workspace_size(n, m, ctypes.byref(need)), "ws")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    buf = (torch.empty(m, dtype=torch.int32, device=dev), torch.empty(m, dtype=torch.int32, device=dev))
+    GEN.er(n, m, seed=2016, out=buf, workspace=ws)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        GEN.er(n, m, seed=2016, out=buf, workspace=ws)
+    sec = (time.perf_counter() - t0) / reps
+    k = 1_000_000
+    t1 = time.perf_counter()
+    so, do = oracle.er(n, k, 2016)
+    osec = time.perf_counter() - t1
+    same = bool(np.array_equal(buf[0][:k].cpu().numpy(), so) and np.array_equal(buf[1][:k].cpu().numpy(), do))
+    t1 = time.perf_counter()
+    I.er(n, m, 2016)
+    hsec = time.perf_counter() - t1
+    out["er"] = {"workload": f"er-n{n}-m{m}", "ms": 1e3 * sec, "edges_per_s": m / sec, "workspace_bytes": need.value,
+                 "prefix_equal_oracle": same,
+                 "cpu_oracle": {"value": k / osec, "unit": "edges/s", "kind": "oracle", "cores": 1,
+                                "sample": f"the first {k} edges of the same definition, {osec:.2f} s"},
+                 "host_input_generator": {"s": hsec, "edges_per_s": m / hsec,
+                                          "note": "the tests' own G(n, m) sampler (Floyd), not this definition"}}
+    del ws, buf
+    torch.cuda.empty_cache()
+    n, kk = 1 << 22, 16
+    mb = GEN.ba_edges(n, kk)
+    buf = (torch.empty(mb, dtype=torch.int32, device=dev), torch.empty(mb, dtype=torch.int32, device=dev))
+    GEN.ba(n, kk, seed=22, out=buf)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        GEN.ba(n, kk, seed=22, out=buf)
+    sec = (time.perf_counter() - t0) / reps
+    n1 = 1 << 16
+    t1 = time.perf_counter()
+    so, do = oracle.ba(n1, kk, 22)
+    osec = time.perf_counter() - t1
+    same = bool(np.array_equal(buf[0][:so.size].cpu().numpy(), so) and
+                np.array_equal(buf[1][:do.size].cpu().numpy(), do))
+    out["ba"] = {"workload": f"ba-n{n}-k{kk}", "edges": mb, "ms": 1e3 * sec, "edges_per_s": mb / sec,
+                 "prefix_equal_oracle": same,
+                 "cpu_oracle": {"value": so.size / osec, "unit": "edges/s", "kind": "oracle", "cores": 1,
+                                "sample": f"BA(n={n1}, k={kk}) of the same seed (a prefix), {osec:.2f} s"}}
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def k4_leg(args, torch, P, N):
     """4-clique count on R-MAT (same generator parameters as the main
     workload) at --k4-scale, timed with HIP events around the kernel on its
@@ -494,18 +560,82 @@ def serving_leg(args, torch, P, N):
     }
 
 
-def cpu_baseline(scale):
+def cpu_baseline(args, n, s, d, m):
+    """The CPU oracle on the benchmarked graph itself: its build (symmetrise,
+    dedup, sorted rows) over all input pairs, timed apart, then its node
+    iterator from a sample of root nodes (ids = 0 mod stride; ids are a random
+    permutation, so this is a uniform sample of the per-root work), on all
+    host threads and, on a smaller sample, on one thread (the paper's
+    protocol is one core). The count rate is m / (sample time x stride)."""
     import oracle
-    from paper_1606_07550_amd import inputs as I
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    n, s, d = I.rmat(scale, 16, seed=scale)
+    st, st1 = args.cpu_sample_stride, args.cpu_sample_stride1
+    r = oracle.count_timed(n, s, d, order=1, threads=threads, stride=st, offset=0, stride1=st1)
+    est = r["count_s"] * st
+    line = {"value": m / est, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"the benchmarked R-MAT graph (m={r['m']}): build over all {len(s)} input pairs "
+                      f"{r['build_s']:.1f} s (timed apart); node iterator from the roots with id % {st} == 0 "
+                      f"({r['tri']} triangles) {r['count_s']:.2f} s on {threads} threads, scaled x{st}",
+            "build_s": r["build_s"], "count_s_sample": r["count_s"], "count_s_full_est": est,
+            "build_plus_count_edges_per_s": m / (r["build_s"] + est)}
+    if st1 > 0:
+        est1 = r["count1_s"] * st1
+        line["one_thread"] = {"value": m / est1, "unit": "edges/s", "cores": 1,
+                              "sample": f"roots with id % {st1} == 0 ({r['tri1']} triangles) "
+                                        f"{r['count1_s']:.2f} s, scaled x{st1}",
+                              "count_s_full_est": est1}
+    return line
+
+
+def degeneracy_leg(g, torch, P, N):
+    """The benchmark's graph under the degree order and under the degeneracy
+    order (tricc_graph_degeneracy + tricc_graph_reorient): largest out-degree,
+    count time (a6 + a7, HIP events) and 4-clique time for both; the counts
+    must agree. The degeneracy order is left on the graph afterwards."""
+    stream = torch.cuda.current_stream()
+
+    def time_count(reps=3):
+        g.count()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            o = g.count()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, int(o["total"].cpu().numpy().view(np.uint64)[0])
+
+    def time_k4():
+        if g.info["max_outdeg"] > 4096:
+            return None, None
+        out = g.count_k4()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.count_k4(out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), int(out.cpu().numpy().view(np.uint64)[0])
+
+    res = {}
+    c_ms, tri = time_count()
+    k_ms, k4 = time_k4()
+    res["degree"] = {"max_outdeg": g.info["max_outdeg"], "count_ms": c_ms, "triangles": tri, "k4_ms": k_ms,
+                     "cliques4": k4}
     t0 = time.perf_counter()
-    r = oracle.count(n, s, d, order=1, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": r["m"] / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": f"R-MAT scale {scale}, edge factor 16, same generator parameters (n={n}, "
-                      f"m={r['m']}, {r['total']} triangles); whole oracle run (build + count) "
-                      f"{dt:.2f} s on {threads} threads"}
+    order, _, dg = g.degeneracy()
+    t1 = time.perf_counter()
+    try:
+        g.reorient(order)
+    except N.TriccError:
+        g.retune(P.default_tuning())
+        g.reorient(order)
+    t2 = time.perf_counter()
+    c_ms, tri2 = time_count()
+    k_ms, k42 = time_k4()
+    res["degeneracy"] = {"degeneracy": dg, "max_outdeg": g.info["max_outdeg"], "order_ms": 1e3 * (t1 - t0),
+                         "reorient_ms": 1e3 * (t2 - t1), "count_ms": c_ms, "triangles": tri2, "k4_ms": k_ms,
+                         "cliques4": k42}
+    res["counts_equal"] = tri == tri2 and k4 == k42
+    return res
 
 
 def main():
@@ -526,6 +656,7 @@ def main():
     log(f"generated {cfg['workload']} n={n} m_raw={s.size} in {time.perf_counter() - t0:.1f}s")
     src = torch.from_numpy(s).to(dev)
     dst = torch.from_numpy(d).to(dev)
+    host_pairs = (s, d)  # the CPU oracle's input (the same arrays)
     del s, d
     from paper_1606_07550_amd import autotune
     tuning = None
@@ -676,6 +807,9 @@ def main():
     if not args.no_core:
         log("core-number leg ...")
         line["core"] = core_leg(g, torch, m)
+    if not args.no_degeneracy:
+        log("degeneracy-order leg ...")
+        line["degeneracy"] = degeneracy_leg(g, torch, P, N)
     del src, dst, ws, T, cc, g
     torch.cuda.empty_cache()
     if not args.no_batched:
@@ -684,6 +818,8 @@ def main():
     if not args.no_gen:
         log("generator leg ...")
         line["generator"] = gen_leg(args, torch, P, N)
+        log("G(n, m) and Barabasi-Albert generator leg ...")
+        line["generator"].update(gen_er_ba_leg(args, torch, P, N))
     if not args.no_k4:
         log("4-clique leg ...")
         line["k4"] = k4_leg(args, torch, P, N)
@@ -695,7 +831,7 @@ def main():
         line["serving"] = serving_leg(args, torch, P, N)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on its sample ...")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)
+        line["cpu_baseline"] = cpu_baseline(args, n, host_pairs[0], host_pairs[1], m)
     else:
         line["cpu_baseline"] = None
     text = json.dumps(line)

@@ -239,6 +239,61 @@ int tricc_probe_copy(void* d_dst, const void* d_src, size_t bytes, void* stream)
 int tricc_gen_rmat(int32_t scale, int64_t m, double a, double b, double c, double d, double noise, uint64_t seed,
                    const int32_t* d_perm, int32_t* d_src, int32_t* d_dst, void* stream);
 
+/*
+ * Erdos-Renyi G(n, m) on the device (the paper's table of graph generators,
+ * Section 4): a uniform random m-subset of the N = n(n-1)/2 node pairs. The
+ * definition, written out so that the edges are exact: with word(c) =
+ * SplitMix64 output of S + c * 0x9E3779B97F4A7C15 and S = SplitMix64 output
+ * of seed + 13 * 0x9E3779B97F4A7C15, draw k (k = 0, 1, ...) is the pair
+ * index x_k = floor(word(k + 1) * N / 2^64); the edges are the first m
+ * distinct values of x_0, x_1, ... in draw order (edge e = the e-th new
+ * value); pair index t is the pair (i, j), i < j, with t = i n - i(i+1)/2 +
+ * (j - i - 1), written (i, j), or (j, i) when bit 0 of its word is 1. No
+ * self loops, no repeated pair.
+ *   n        0 <= n < 2^31; m: 0 <= m <= min(N, 2^30)
+ *   d_src, d_dst  device int32[m], the caller's (written)
+ *   d_ws     device scratch of tricc_gen_er_workspace_size(n, m) bytes
+ *            (256-byte aligned; about 12 bytes per draw slot of a hash table
+ *            of at least twice the draws, plus 12 bytes per draw)
+ * Synchronises `stream` (the number of distinct draws is read back).
+ * Errors: TRICC_EINVAL for n or m out of range, null arrays or a misaligned
+ * workspace; TRICC_ENOMEM for a short workspace; TRICC_EOVERFLOW when m is
+ * so close to N that the draw budget would pass 2^32 (or, with a chance far
+ * below any practical concern, the draws run short of m distinct values).
+ */
+int tricc_gen_er_workspace_size(int64_t n, int64_t m, size_t* bytes);
+int tricc_gen_er(int64_t n, int64_t m, uint64_t seed, int32_t* d_src, int32_t* d_dst, void* d_ws, size_t ws_bytes,
+                 void* stream);
+
+/*
+ * Barabasi-Albert preferential attachment on the device (the paper's table of
+ * graph generators, Section 4), with k distinct targets per node. Definition:
+ * nodes 0..k form the clique K_{k+1}, whose edges e = 0 .. k(k+1)/2 - 1 are
+ * its pairs (i, j), i < j, in lexicographic order (source i, target j). Node
+ * v > k adds edges e = E_v + j, j = 0..k-1, E_v = k(k+1)/2 + (v - k - 1) k,
+ * with source v. Edge e' holds its source at endpoint position 2e' and its
+ * target at 2e' + 1; the target of edge e = E_v + j is the node at position
+ * r = floor(word((e << 20) + a + 1) * 2 E_v / 2^64) (word as for G(n, m),
+ * S = SplitMix64 output of seed + 14 * 0x9E3779B97F4A7C15) for the first
+ * attempt a = 0, 1, ... whose node is not already a target of v's edges
+ * j' < j. Every position holds one endpoint, so a node is drawn in
+ * proportion to its degree among the edges before v's. The device resolves
+ * the edges in passes: an edge whose draws reach only final targets becomes
+ * final; the earliest open edge always can, so every pass makes progress.
+ *   m = tricc_gen_ba_edges(n, k) = k(k+1)/2 + (n - k - 1) k  (-1 unless
+ *       1 <= k <= 255 and k < n < 2^31); m <= 2^30
+ *   d_src, d_dst  device int32[m], the caller's (written)
+ *   d_ws     device scratch of tricc_gen_ba_workspace_size(n, k) bytes
+ * Synchronises `stream` (the passes read back how many nodes are open).
+ * Errors: TRICC_EINVAL for bad sizes or null arrays, TRICC_ENOMEM for a
+ * short workspace, TRICC_EOVERFLOW above 2^30 edges (or if an edge needs
+ * 2^20 attempts).
+ */
+int64_t tricc_gen_ba_edges(int64_t n, int32_t k);
+int tricc_gen_ba_workspace_size(int64_t n, int32_t k, size_t* bytes);
+int tricc_gen_ba(int64_t n, int32_t k, uint64_t seed, int32_t* d_src, int32_t* d_dst, void* d_ws, size_t ws_bytes,
+                 void* stream);
+
 /* Device views of the graph held in the workspace, for inspection:
  * row v of the simple graph is d_adj[d_off[v] .. d_off[v] + d_deg[v]) in
  * ascending id order; the DAG out-list of v is d_dcol[d_doff[v] ..

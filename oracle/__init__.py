@@ -1,5 +1,5 @@
 """CPU oracle: exact triangle counts, clustering coefficients, edge tests,
-core numbers, 4-clique counts, R-MAT edges.
+core numbers, 4-clique counts, R-MAT, G(n, m) and Barabasi-Albert edges.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
@@ -49,8 +49,12 @@ def lib():
         L.oracle_rmat.argtypes = [ctypes.c_int, d, d, d, d, d, ctypes.c_uint64, i64, P, P, P, P]
         L.oracle_rmat.restype = ctypes.c_int
         d_ = ctypes.c_double
-        L.oracle_count_timed.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, i64, i64, P, P, P, P]
+        L.oracle_count_timed.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, i64, i64, i64, P, P, P, P, P, P]
         L.oracle_count_timed.restype = ctypes.c_int
+        L.oracle_er.argtypes = [i64, i64, ctypes.c_uint64, P, P]
+        L.oracle_er.restype = ctypes.c_int
+        L.oracle_ba.argtypes = [i64, ctypes.c_int32, ctypes.c_uint64, P, P]
+        L.oracle_ba.restype = ctypes.c_int
         L.oracle_wtime.argtypes = []
         L.oracle_wtime.restype = ctypes.c_double
         _LIB = L
@@ -88,17 +92,21 @@ def count(n, src, dst, order=0, threads=0):
     return dict(T=T, cc=cc, deg=deg, total=int(total.value), avg=float(avg.value), m=int(m.value))
 
 
-def count_timed(n, src, dst, order=1, threads=0, stride=1, offset=0):
-    """Oracle timing on a node sample: dict(build_s, count_s, tri, m); tri
-    = triangles whose lowest-ranked vertex v has v % stride == offset."""
+def count_timed(n, src, dst, order=1, threads=0, stride=1, offset=0, stride1=0):
+    """Oracle timing on a node sample: dict(build_s, count_s, tri, count1_s,
+    tri1, m); tri = triangles whose lowest-ranked vertex v has v % stride ==
+    offset (threads threads); with stride1 > 0 also tri1 / count1_s for v %
+    stride1 == offset on one thread, on the same build."""
     src, dst = _i32(src), _i32(dst)
-    tri, m = ctypes.c_uint64(), ctypes.c_int64()
-    b, c = ctypes.c_double(), ctypes.c_double()
-    rc = lib().oracle_count_timed(n, src.size, _ptr(src), _ptr(dst), order, threads, stride, offset,
-                                  ctypes.byref(tri), ctypes.byref(m), ctypes.byref(b), ctypes.byref(c))
+    tri, tri1, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64()
+    b, c, c1 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = lib().oracle_count_timed(n, src.size, _ptr(src), _ptr(dst), order, threads, stride, offset, stride1,
+                                  ctypes.byref(tri), ctypes.byref(tri1), ctypes.byref(m), ctypes.byref(b),
+                                  ctypes.byref(c), ctypes.byref(c1))
     if rc:
         raise OracleError(f"oracle_count_timed failed ({rc})")
-    return dict(build_s=b.value, count_s=c.value, tri=int(tri.value), m=int(m.value))
+    return dict(build_s=b.value, count_s=c.value, tri=int(tri.value), count1_s=c1.value, tri1=int(tri1.value),
+                m=int(m.value))
 
 
 def induced(n, src, dst, nodes, threads=0):
@@ -185,6 +193,34 @@ def rmat(scale, m=None, abcd=(0.57, 0.19, 0.19, 0.05), noise=0.1, seed=0, idx=No
                            _ptr(perm) if perm is not None else None, _ptr(src), _ptr(dst))
     if rc:
         raise OracleError(f"oracle_rmat failed ({rc})")
+    return src, dst
+
+
+def er(n, m, seed):
+    """G(n, m) edges (src, dst int32[m]) of the GPU generator's definition."""
+    src = np.zeros(m, np.int32)
+    dst = np.zeros(m, np.int32)
+    rc = lib().oracle_er(n, m, seed, _ptr(src), _ptr(dst))
+    if rc:
+        raise OracleError(f"oracle_er failed ({rc})")
+    return src, dst
+
+
+def ba_edges(n, k):
+    return k * (k + 1) // 2 + (n - k - 1) * k
+
+
+def ba(n, k, seed):
+    """Barabasi-Albert edges (src, dst int32) of the GPU generator's
+    definition: the seed clique on 0..k, then k distinct targets per node."""
+    if not (1 <= k <= 255 and k < n):
+        raise OracleError("oracle_ba: need 1 <= k <= 255 and k < n")
+    m = ba_edges(n, k)
+    src = np.zeros(m, np.int32)
+    dst = np.zeros(m, np.int32)
+    rc = lib().oracle_ba(n, k, seed, _ptr(src), _ptr(dst))
+    if rc:
+        raise OracleError(f"oracle_ba failed ({rc})")
     return src, dst
 
 

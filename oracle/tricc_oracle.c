@@ -1,6 +1,7 @@
 /*
  * CPU oracle for exact triangle counting, clustering coefficients,
- * edge-existence tests, core numbers, 4-clique counts and R-MAT edges.
+ * edge-existence tests, core numbers, 4-clique counts and the R-MAT,
+ * G(n, m) and Barabasi-Albert edge generators.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or
  * calls this file; only the tests, the smoke check and the benchmark's CPU
@@ -201,15 +202,17 @@ int oracle_count(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* ds
  * Timing of the oracle on a node sample of a large graph: the graph build
  * (symmetrise, dedup, sorted rows) over all pairs, timed on its own, then the
  * node iterator from the lowest-ranked vertices v with v % stride == offset
- * only, timed on its own. *tri receives the triangles whose lowest-ranked
- * vertex is sampled (summed over offset = 0 .. stride-1 this is the total).
+ * only, on nthreads threads, timed on its own; then, if stride1 > 0, the
+ * same from v % stride1 == offset on one thread, timed on its own. *tri and
+ * *tri1 receive the triangles whose lowest-ranked vertex is in each sample
+ * (summed over offset = 0 .. stride-1 that is the total).
  * Returns 0; -1 for an id outside [0,n); -2 on allocation failure; -3 for a
  * bad stride or offset.
  */
 int oracle_count_timed(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, int order_mode,
-                       int nthreads, int64_t stride, int64_t offset, uint64_t* tri, int64_t* m_out,
-                       double* build_s, double* count_s) {
-  if (stride < 1 || offset < 0 || offset >= stride) return -3;
+                       int nthreads, int64_t stride, int64_t offset, int64_t stride1, uint64_t* tri, uint64_t* tri1,
+                       int64_t* m_out, double* build_s, double* count_s, double* count1_s) {
+  if (stride < 1 || offset < 0 || offset >= stride || stride1 < 0 || (stride1 > 0 && offset >= stride1)) return -3;
   og_graph g;
   const double t0 = omp_get_wtime();
   int rc = og_build(n, m_raw, src, dst, &g);
@@ -219,6 +222,13 @@ int oracle_count_timed(int64_t n, int64_t m_raw, const int32_t* src, const int32
   if (!t) { og_free(&g); return -2; }
   *tri = og_count_from(&g, order_mode, nthreads, stride, offset, t);
   const double t2 = omp_get_wtime();
+  *tri1 = 0;
+  *count1_s = 0.0;
+  if (stride1 > 0) {
+    memset(t, 0, sizeof(uint64_t) * (size_t)n);
+    *tri1 = og_count_from(&g, order_mode, 1, stride1, offset, t);
+    *count1_s = omp_get_wtime() - t2;
+  }
   *build_s = t1 - t0;
   *count_s = t2 - t1;
   if (m_out) *m_out = g.m;
@@ -622,6 +632,124 @@ int oracle_rmat(int scale, double a, double b, double c, double d, double noise,
     }
     src[i] = perm ? perm[u] : (int32_t)u;
     dst[i] = perm ? perm[v] : (int32_t)v;
+  }
+  return 0;
+}
+
+/* floor(w * N / 2^64): the high word of the 128-bit product. */
+static uint64_t mul_hi(uint64_t w, uint64_t N) { return (uint64_t)(((unsigned __int128)w * N) >> 64); }
+
+/* Largest i in [0, n-2] with i n - i(i+1)/2 <= t (binary search). */
+static int64_t pair_row(int64_t n, uint64_t t) {
+  int64_t lo = 0, hi = n - 2;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if ((uint64_t)(mid * n - mid * (mid + 1) / 2) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+/*
+ * Erdos-Renyi G(n, m) (the paper's table of graph generators, Section 4,
+ * names the G(n, m) model), as defined for the GPU generator: a uniform
+ * random m-subset of the N = n(n-1)/2 node pairs, by rejecting repeats in a
+ * counter-based sequence of uniform pair indices:
+ *
+ *   word(c) = out(S + gamma c), c = 1, 2, ...; S = out(seed + gamma * 13)
+ *   x_k     = floor(word(k + 1) N / 2^64), k = 0, 1, ...
+ *   edges   = the first m distinct values of x_0, x_1, ..., in draw order;
+ *             pair index t is the pair (i, j), i < j, with
+ *             t = i n - i(i+1)/2 + (j - i - 1) (row by row), written as
+ *             (i, j), or (j, i) when the low bit of its draw's word is 1.
+ *
+ * Returns 0; -1 for n outside [0, 2^31) or m outside [0, N]; -2 on
+ * allocation failure; -3 if the draws run past a guard far above what m
+ * distinct values need.
+ */
+int oracle_er(int64_t n, int64_t m, uint64_t seed, int32_t* src, int32_t* dst) {
+  if (n < 0 || n > 0x7fffffffLL) return -1;
+  const uint64_t N = n > 1 ? (uint64_t)n * (uint64_t)(n - 1) / 2 : 0;
+  if (m < 0 || (uint64_t)m > N) return -1;
+  if (m == 0) return 0;
+  uint64_t cap = 1;
+  while (cap < 2 * (uint64_t)m) cap <<= 1;
+  uint64_t* set = (uint64_t*)malloc(sizeof(uint64_t) * cap); /* value + 1; 0 = empty */
+  if (!set) return -2;
+  memset(set, 0, sizeof(uint64_t) * cap);
+  const uint64_t S = sm_out(seed + sm_gamma * 13u);
+  int64_t got = 0;
+  /* a guard only: the draws a valid run needs stay far below this */
+  const uint64_t draw_cap = 64u * (N + (uint64_t)m) + (1u << 20);
+  for (uint64_t k = 0; got < m; ++k) {
+    if (k >= draw_cap) { free(set); return -3; }
+    const uint64_t w = sm_out(S + sm_gamma * (k + 1u));
+    const uint64_t x = mul_hi(w, N);
+    uint64_t h = (x * 0x9E3779B97F4A7C15ULL) & (cap - 1);
+    int seen = 0;
+    while (set[h]) {
+      if (set[h] == x + 1) { seen = 1; break; }
+      h = (h + 1) & (cap - 1);
+    }
+    if (seen) continue;
+    set[h] = x + 1;
+    const int64_t i = pair_row(n, x);
+    const int64_t j = (int64_t)(x - (uint64_t)(i * n - i * (i + 1) / 2)) + i + 1;
+    src[got] = (int32_t)((w & 1u) ? j : i);
+    dst[got] = (int32_t)((w & 1u) ? i : j);
+    ++got;
+  }
+  free(set);
+  return 0;
+}
+
+/*
+ * Barabasi-Albert (the paper's table of graph generators, Section 4, names
+ * preferential attachment), as defined for the GPU generator, with k
+ * distinct targets per node:
+ *
+ *   nodes 0..k form the clique K_{k+1}: edges e = 0 .. k(k+1)/2 - 1 are its
+ *   pairs (i, j), i < j, in lexicographic order (source i, target j);
+ *   node v > k adds edges e = E_v + j, j = 0 .. k-1, with source v, where
+ *   E_v = k(k+1)/2 + (v - k - 1) k is the number of edges before v's.
+ *   Edge e' holds its source at endpoint position 2e' and its target at
+ *   2e' + 1; the target of edge e = E_v + j is the node at position
+ *     r = floor(word((e << 20) + a + 1) 2 E_v / 2^64)
+ *   (S = out(seed + gamma * 14)) for the first attempt a = 0, 1, ... whose
+ *   node differs from the targets of v's edges j' < j. Each position holds
+ *   one endpoint, so a node is drawn with probability proportional to its
+ *   degree among the edges before v's.
+ *
+ * src, dst: m = k(k+1)/2 + (n - k - 1) k entries. Returns 0; -1 unless
+ * 1 <= k <= 255 and k < n < 2^31; -3 if an edge needs 2^20 attempts.
+ */
+int oracle_ba(int64_t n, int32_t k, uint64_t seed, int32_t* src, int32_t* dst) {
+  if (k < 1 || k > 255 || n < k + 1 || n > 0x7fffffffLL) return -1;
+  const int64_t es = (int64_t)k * (k + 1) / 2;
+  int64_t e = 0;
+  for (int32_t i = 0; i <= k; ++i)
+    for (int32_t j = i + 1; j <= k; ++j) {
+      src[e] = i;
+      dst[e] = j;
+      ++e;
+    }
+  const uint64_t S = sm_out(seed + sm_gamma * 14u);
+  for (int64_t v = k + 1; v < n; ++v) {
+    const int64_t ev = es + (v - k - 1) * (int64_t)k;
+    for (int32_t j = 0; j < k; ++j) {
+      const int64_t ej = ev + j;
+      int32_t c = -1;
+      for (uint64_t a = 0;; ++a) {
+        if (a >= (1u << 20)) return -3;
+        const uint64_t r = mul_hi(sm_out(S + sm_gamma * (((uint64_t)ej << 20) + a + 1u)), 2u * (uint64_t)ev);
+        c = (r & 1u) ? dst[r >> 1] : src[r >> 1];
+        int dup = 0;
+        for (int32_t q = 0; q < j; ++q) dup |= dst[ev + q] == c;
+        if (!dup) break;
+      }
+      src[ej] = (int32_t)v;
+      dst[ej] = c;
+    }
   }
   return 0;
 }

@@ -132,6 +132,11 @@ _SIGS = {
     "tricc_probe_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "tricc_gen_rmat": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_double] * 5
                        + [ctypes.c_uint64, _P, _P, _P, _P]),
+    "tricc_gen_er_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "tricc_gen_er": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P]),
+    "tricc_gen_ba_edges": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
+    "tricc_gen_ba_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "tricc_gen_ba": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P]),
     "tricc_graph_arrays": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                           ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "tricc_graph_free": (None, [_P]),

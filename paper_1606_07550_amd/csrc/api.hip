@@ -765,6 +765,135 @@ int tricc_gen_rmat(int32_t scale, int64_t m, double a, double b, double c, doubl
   return TRICC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Draws the G(n, m) sampler runs: enough that fewer than m distinct values
+// among them is far beyond the sampler's spread (about 10 standard deviations
+// of the number of draws the m-th distinct value needs, or the coupon
+// collector's tail when m > N/2).
+int64_t er_draws(uint64_t N, int64_t m) {
+  if (m <= 0) return 0;
+  const double Nd = (double)N, f = (double)m / Nd;
+  double K;
+  if (2 * (uint64_t)m <= N) {
+    const double e = -Nd * std::log1p(-f);
+    const double var = Nd * (1.0 / (1.0 - f) - 1.0 + std::log1p(-f));
+    K = e + 10.0 * std::sqrt(std::max(var, 0.0)) + 16.0;
+  } else {
+    K = Nd * (std::log(Nd) + 12.0);
+  }
+  return (int64_t)std::ceil(K) + 1024;
+}
+
+struct ErLayout {
+  uint64_t P;
+  int64_t K;
+  size_t keys, idx, flag, pos, tmp, total;
+};
+
+int er_layout(int64_t n, int64_t m, ErLayout* L) {
+  if (n < 0 || n > 0x7fffffffLL) return fail(TRICC_EINVAL, "G(n, m): n outside [0, 2^31 - 1]");
+  const uint64_t N = n > 1 ? (uint64_t)n * (uint64_t)(n - 1) / 2 : 0;
+  if (m < 0 || (uint64_t)m > N) return fail(TRICC_EINVAL, "G(n, m): m outside [0, n(n-1)/2]");
+  if (m > (int64_t(1) << 30)) return fail(TRICC_EOVERFLOW, "G(n, m): m above 2^30");
+  const int64_t K = er_draws(N, m);
+  if (K >= (int64_t)0xFFFFFFFFLL) return fail(TRICC_EOVERFLOW, "G(n, m): too dense for the draw budget");
+  uint64_t P = 1;
+  while (P < 2 * (uint64_t)std::max<int64_t>(K, 1)) P <<= 1;
+  size_t p = 0;
+  auto take = [&](size_t bytes) { size_t at = p; p = align_up(p + std::max<size_t>(bytes, 1)); return at; };
+  L->P = P;
+  L->K = K;
+  L->keys = take(sizeof(uint64_t) * P);
+  L->idx = take(sizeof(uint32_t) * P);
+  L->flag = take(sizeof(int32_t) * K);
+  L->pos = take(sizeof(int64_t) * (K + 1));
+  L->tmp = take(sizeof(int64_t) * scan_tmp_elems(K + 1));
+  L->total = p;
+  return TRICC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tricc_gen_er_workspace_size(int64_t n, int64_t m, size_t* bytes) {
+  if (!bytes) return fail(TRICC_EINVAL, "null bytes");
+  ErLayout L;
+  int rc = er_layout(n, m, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return TRICC_OK;
+}
+
+int tricc_gen_er(int64_t n, int64_t m, uint64_t seed, int32_t* d_src, int32_t* d_dst, void* d_ws, size_t ws_bytes,
+                 void* stream) {
+  ErLayout L;
+  int rc = er_layout(n, m, &L);
+  if (rc) return rc;
+  if (m == 0) return TRICC_OK;
+  if (!d_src || !d_dst) return fail(TRICC_EINVAL, "null output arrays");
+  if (!d_ws || ws_bytes < L.total) return fail(TRICC_ENOMEM, "G(n, m) workspace %zu bytes, need %zu", ws_bytes, L.total);
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(TRICC_EINVAL, "workspace not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(d_ws);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(w + L.keys);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(w + L.idx);
+  int32_t* flag = reinterpret_cast<int32_t*>(w + L.flag);
+  int64_t* pos = reinterpret_cast<int64_t*>(w + L.pos);
+  const uint64_t N = (uint64_t)n * (uint64_t)(n - 1) / 2;
+  HIPCHK(launch_er_clear(L.P, keys, idx, s));
+  HIPCHK(launch_er_insert(L.K, N, seed, L.P - 1, keys, idx, s));
+  HIPCHK(launch_er_flag(L.K, N, seed, L.P - 1, keys, idx, flag, s));
+  HIPCHK(launch_scan_i32(flag, L.K, pos, reinterpret_cast<int64_t*>(w + L.tmp), s));
+  int64_t distinct = 0;
+  if ((rc = sync_copy(&distinct, pos + L.K, sizeof(distinct), s))) return rc;
+  if (distinct < m)
+    return fail(TRICC_EOVERFLOW, "G(n, m): %lld distinct pairs in %lld draws, %lld needed", (long long)distinct,
+                (long long)L.K, (long long)m);
+  HIPCHK(launch_er_emit(L.K, n, N, seed, m, flag, pos, d_src, d_dst, s));
+  return TRICC_OK;
+}
+
+int64_t tricc_gen_ba_edges(int64_t n, int32_t k) {
+  if (k < 1 || k > 255 || n < k + 1 || n > 0x7fffffffLL) return -1;
+  return (int64_t)k * (k + 1) / 2 + (n - k - 1) * (int64_t)k;
+}
+
+int tricc_gen_ba_workspace_size(int64_t n, int32_t k, size_t* bytes) {
+  if (!bytes) return fail(TRICC_EINVAL, "null bytes");
+  if (tricc_gen_ba_edges(n, k) < 0) return fail(TRICC_EINVAL, "Barabasi-Albert: need 1 <= k <= 255, k < n < 2^31");
+  *bytes = align_up(sizeof(int32_t) * (size_t)n) + 256;
+  return TRICC_OK;
+}
+
+int tricc_gen_ba(int64_t n, int32_t k, uint64_t seed, int32_t* d_src, int32_t* d_dst, void* d_ws, size_t ws_bytes,
+                 void* stream) {
+  const int64_t m = tricc_gen_ba_edges(n, k);
+  if (m < 0) return fail(TRICC_EINVAL, "Barabasi-Albert: need 1 <= k <= 255, k < n < 2^31");
+  if (m > (int64_t(1) << 30)) return fail(TRICC_EOVERFLOW, "Barabasi-Albert: more than 2^30 edges");
+  if (!d_src || !d_dst) return fail(TRICC_EINVAL, "null output arrays");
+  size_t need = 0;
+  tricc_gen_ba_workspace_size(n, k, &need);
+  if (!d_ws || ws_bytes < need) return fail(TRICC_ENOMEM, "Barabasi-Albert workspace %zu bytes, need %zu", ws_bytes, need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(d_ws);
+  int32_t* prog = reinterpret_cast<int32_t*>(w);
+  int32_t* cnt = reinterpret_cast<int32_t*>(w + align_up(sizeof(int32_t) * (size_t)n));
+  HIPCHK(launch_ba_init(m, k, (int32_t)n, d_src, d_dst, prog, cnt, s));
+  int32_t c[2] = {1, 0};
+  int rc;
+  for (int pass = 0; c[0] > 0; ++pass) {
+    if (pass >= (1 << 20)) return fail(TRICC_EHIP, "Barabasi-Albert: passes did not converge");
+    HIPCHK(launch_ba_pass((int32_t)n, k, seed, d_src, d_dst, prog, cnt, s));
+    if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
+    if (c[1]) return fail(TRICC_EOVERFLOW, "Barabasi-Albert: an edge ran out of attempts");
+  }
+  return TRICC_OK;
+}
+
 int tricc_graph_arrays(const tricc_graph* g, const int64_t** d_off, const int32_t** d_deg, const int32_t** d_adj,
                        const int64_t** d_doff, const int32_t** d_dcol) {
   if (!g) return fail(TRICC_EINVAL, "null graph");

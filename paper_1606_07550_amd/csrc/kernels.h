@@ -239,4 +239,24 @@ hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, 
 hipError_t launch_gen_rmat(int64_t m, int scale, const double abcd[4], double noise, uint64_t seed,
                            const int32_t* perm, int32_t* src, int32_t* dst, hipStream_t s);
 
+// Erdos-Renyi G(n, m) as the first m distinct draws of a counter-based
+// sequence over the N = n(n-1)/2 pair indices (seed stream 13): keys/idx a
+// table of P (a power of two, >= 2K) slots, cleared first; K draws inserted;
+// flag[k] = draw k is the first of its value; pos = exclusive scan of flag;
+// emit writes the new draws with pos[k] < m as edges pos[k].
+hipError_t launch_er_clear(uint64_t P, uint64_t* keys, uint32_t* idx, hipStream_t s);
+hipError_t launch_er_insert(int64_t K, uint64_t N, uint64_t seed, uint64_t mask, uint64_t* keys, uint32_t* idx,
+                            hipStream_t s);
+hipError_t launch_er_flag(int64_t K, uint64_t N, uint64_t seed, uint64_t mask, const uint64_t* keys,
+                          const uint32_t* idx, int32_t* flag, hipStream_t s);
+hipError_t launch_er_emit(int64_t K, int64_t n, uint64_t N, uint64_t seed, int64_t m, const int32_t* flag,
+                          const int64_t* pos, int32_t* src, int32_t* dst, hipStream_t s);
+// Barabasi-Albert with k distinct targets per node (seed stream 14): init
+// writes the seed clique and every source, clears prog[n] and cnt[2]; each
+// pass resolves what it can, cnt[0] = nodes left, cnt[1] = attempts ran out.
+hipError_t launch_ba_init(int64_t m, int32_t k, int32_t n, int32_t* src, int32_t* dst, int32_t* prog, int32_t* cnt,
+                          hipStream_t s);
+hipError_t launch_ba_pass(int32_t n, int32_t k, uint64_t seed, const int32_t* src, int32_t* dst, int32_t* prog,
+                          int32_t* cnt, hipStream_t s);
+
 }  // namespace tricc

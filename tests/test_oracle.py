@@ -851,7 +851,165 @@ def test_count_timed_sample_partitions_the_triangles():
     for order in (0, 1):
         full = oracle.count(n, s, d, order=order)["total"]
         assert oracle.count_timed(n, s, d, order=order, stride=1)["tri"] == full
-        parts = [oracle.count_timed(n, s, d, order=order, stride=7, offset=o)["tri"] for o in range(7)]
-        assert sum(parts) == full and all(p < full for p in parts)
+        parts = [oracle.count_timed(n, s, d, order=order, stride=7, offset=o, stride1=7) for o in range(7)]
+        assert sum(p["tri"] for p in parts) == full and all(p["tri"] < full for p in parts)
+        assert all(p["tri1"] == p["tri"] for p in parts)  # one thread finds the same
     with pytest.raises(oracle.OracleError):
         oracle.count_timed(n, s, d, stride=4, offset=4)
+
+
+# ---------------------------------------------------------------------------
+# G(n, m) and Barabasi-Albert generators of the oracle (the paper's table of
+# graph generators, Section 4). Pins: the defining properties of each model
+# (exactly m distinct loop-free pairs; a uniform m-subset, by frequencies and
+# a chi-square over all subsets of a tiny pair set; the complete graph at
+# m = N; the prefix property of first-m-distinct draws; k distinct earlier
+# targets per BA node, the seed clique, attachment in proportion to degree,
+# the heavy degree tail), and planted mistakes that each fail one of them.
+
+def _er_pins_pass(er):
+    from itertools import combinations
+    for n, m, seed in ((2, 1, 1), (7, 21, 2), (9, 36, 3), (50, 300, 4), (2000, 20000, 5), (100, 0, 6)):
+        s, d = er(n, m, seed)
+        if s is None or s.size != m:
+            return False
+        if m == 0:
+            continue
+        if s.min() < 0 or d.min() < 0 or s.max() >= n or d.max() >= n or np.any(s == d):
+            return False
+        key = np.minimum(s, d).astype(np.int64) * n + np.maximum(s, d)
+        if np.unique(key).size != m:
+            return False
+        if m == n * (n - 1) // 2 and np.unique(key).size != m:  # complete graph
+            return False
+    # prefix property: G(n, m') is the first m' edges of G(n, m)
+    s1, d1 = er(300, 2000, 7)
+    s2, d2 = er(300, 700, 7)
+    if s1 is None or s2 is None or not (np.array_equal(s1[:700], s2) and np.array_equal(d1[:700], d2)):
+        return False
+    # uniform m-subsets: n = 5 (N = 10), m = 3 over 12,000 seeds
+    pairs = list(combinations(range(5), 2))
+    subsets = {frozenset(c): i for i, c in enumerate(combinations(range(10), 3))}
+    cnt = np.zeros(len(subsets))
+    pair_cnt = np.zeros(10)
+    flips = 0
+    R = 12000
+    for seed in range(R):
+        s, d = er(5, 3, 1000 + seed)
+        ids = [pairs.index((min(a, b), max(a, b))) for a, b in zip(s.tolist(), d.tolist())]
+        cnt[subsets[frozenset(ids)]] += 1
+        pair_cnt[ids] += 1
+        flips += int(np.sum(s > d))
+    exp = R / len(subsets)
+    chi2 = float(((cnt - exp) ** 2 / exp).sum())
+    if chi2 > 200.0:  # 119 degrees of freedom: p below 1e-5
+        return False
+    p = 3 / 10
+    if np.any(np.abs(pair_cnt - R * p) > 5 * np.sqrt(R * p * (1 - p))):
+        return False
+    if abs(flips - 1.5 * R) > 5 * np.sqrt(3 * R * 0.25):
+        return False
+    return True
+
+
+def _ba_pins_pass(ba):
+    for n, k, seed in ((3, 2, 1), (40, 1, 2), (300, 3, 3), (2000, 5, 4), (500, 16, 5)):
+        s, d = ba(n, k, seed)
+        if s is None:
+            return False
+        m = k * (k + 1) // 2 + (n - k - 1) * k
+        if s.size != m:
+            return False
+        es = k * (k + 1) // 2
+        seed_pairs = sorted(zip(s[:es].tolist(), d[:es].tolist()))
+        if seed_pairs != [(i, j) for i in range(k + 1) for j in range(i + 1, k + 1)]:
+            return False
+        sv = s[es:].reshape(-1, k)
+        dv = d[es:].reshape(-1, k)
+        v = np.arange(k + 1, n)
+        if not np.all(sv == v[:, None]) or not np.all(dv < v[:, None]) or not np.all(dv >= 0):
+            return False
+        if any(len(set(row)) != k for row in dv.tolist()):
+            return False
+    # attachment in proportion to degree: the first target of node v = 20
+    # (k = 2) against the degrees of the graph before v, over many seeds
+    k, v = 2, 20
+    es = k * (k + 1) // 2
+    ev = es + (v - k - 1) * k
+    obs = np.zeros(v)
+    expct = np.zeros(v)
+    var = 0.0
+    for seed in range(3000):
+        s, d = ba(v + 1, k, 500 + seed)
+        deg = np.bincount(np.concatenate([s[:ev], d[:ev]]), minlength=v).astype(np.float64)
+        prob = deg / (2.0 * ev)
+        obs[d[ev]] += 1
+        expct += prob
+        var += float((prob * (1 - prob)).sum())
+    if np.any(np.abs(obs - expct) > 5 * np.sqrt(np.maximum(expct, 1.0))):
+        return False
+    # a heavy tail: uniform attachment would keep the largest degree near
+    # k ln n (about 46 here); preferential attachment grows it like sqrt(n)
+    s, d = ba(100000, 4, 9)
+    if np.bincount(np.concatenate([s, d])).max() < 300:
+        return False
+    return True
+
+
+def _lib_gens(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.c_void_p
+    L.oracle_er.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, P, P]
+    L.oracle_ba.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, P, P]
+
+    def er(n, m, seed):
+        s = np.zeros(m, np.int32)
+        d = np.zeros(m, np.int32)
+        return (s, d) if L.oracle_er(n, m, seed, s.ctypes.data, d.ctypes.data) == 0 else (None, None)
+
+    def ba(n, k, seed):
+        m = k * (k + 1) // 2 + (n - k - 1) * k
+        s = np.zeros(m, np.int32)
+        d = np.zeros(m, np.int32)
+        return (s, d) if L.oracle_ba(n, k, seed, s.ctypes.data, d.ctypes.data) == 0 else (None, None)
+    return er, ba
+
+
+def test_er_oracle_pins():
+    assert _er_pins_pass(oracle.er)
+
+
+def test_ba_oracle_pins():
+    assert _ba_pins_pass(oracle.ba)
+
+
+GEN_MUTANTS = {
+    "er_no_dedup": ("    if (seen) continue;\n    set[h] = x + 1;", "    set[h] = x + 1;"),
+    "er_row_off_by_one": ("if ((uint64_t)(mid * n - mid * (mid + 1) / 2) <= t) lo = mid;",
+                          "if ((uint64_t)(mid * n - mid * (mid + 1) / 2) < t) lo = mid;"),
+    "er_low_pairs_only": ("const uint64_t x = mul_hi(w, N);", "const uint64_t x = mul_hi(w, N) / 2;"),
+    "er_no_flip": ("src[got] = (int32_t)((w & 1u) ? j : i);", "src[got] = (int32_t)i;"),
+    "ba_sources_only": ("c = (r & 1u) ? dst[r >> 1] : src[r >> 1];", "c = src[r >> 1];"),
+    "ba_span_own_edges": ("2u * (uint64_t)ev);", "2u * (uint64_t)ev + 2u);"),
+    "ba_not_distinct": ("for (int32_t q = 0; q < j; ++q) dup |= dst[ev + q] == c;\n        if (!dup) break;",
+                        "if (!dup) break;"),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(GEN_MUTANTS))
+def test_planted_generator_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = GEN_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    er, ba = _lib_gens(str(lib))
+    if mutant.startswith("er"):
+        assert not _er_pins_pass(er), f"mutant {mutant} passed the pins"
+    else:
+        assert not _ba_pins_pass(ba), f"mutant {mutant} passed the pins"
