@@ -385,11 +385,24 @@ int tricc_graph_reorient(tricc_graph* g, const int32_t* d_key, void* stream);
  * from C = N+(u) ∩ N+(w) and the edges x -> z inside C.
  *   d_total   device uint64[1], the caller's (overwritten)
  * Asynchronous on `stream`. Errors: TRICC_EINVAL for a null handle or
- * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 4096 (the
+ * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 8192 (the
  * positions one node's bit rows can index in LDS, one block of them per
- * pass).
+ * pass). tricc_graph_reorient with the degeneracy order bounds d+ by the
+ * core numbers, which can bring a graph under the limit.
  */
 int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream);
+
+/*
+ * Number of 5-cliques (clique detection, as for tricc_graph_count_k4, one
+ * size up): a 5-clique u < w < x < y < z (by rank) is met once, at u, from
+ * the subgraph induced on N+(u) (bit rows in LDS): x in row w, y in the AND
+ * of rows w and x, z in that AND with row y.
+ *   d_total   device uint64[1], the caller's (overwritten)
+ * Asynchronous on `stream`. Errors: TRICC_EINVAL for a null handle or
+ * output; TRICC_EOVERFLOW when some out-degree d+(v) exceeds 1024 (one
+ * node's whole bit rows must fit in LDS).
+ */
+int tricc_graph_count_k5(const tricc_graph* g, uint64_t* d_total, void* stream);
 
 void tricc_graph_free(tricc_graph* g);
 

@@ -1,5 +1,5 @@
 """CPU oracle: exact triangle counts, clustering coefficients, edge tests,
-core numbers, 4-clique counts, R-MAT, G(n, m) and Barabasi-Albert edges.
+core numbers, 4- and 5-clique counts, R-MAT, G(n, m) and Barabasi-Albert edges.
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package. The product path never does, and it
@@ -43,6 +43,8 @@ def lib():
         L.oracle_core.restype = ctypes.c_int
         L.oracle_k4.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, P]
         L.oracle_k4.restype = ctypes.c_int
+        L.oracle_k5.argtypes = [i64, i64, P, P, ctypes.c_int, ctypes.c_int, P]
+        L.oracle_k5.restype = ctypes.c_int
         L.oracle_splitmix64.argtypes = [ctypes.c_uint64, i64, P]
         L.oracle_splitmix64.restype = ctypes.c_int
         d = ctypes.c_double
@@ -165,6 +167,16 @@ def k4(n, src, dst, order=0, threads=0):
     rc = lib().oracle_k4(n, src.size, _ptr(src), _ptr(dst), order, threads, ctypes.byref(total))
     if rc:
         raise OracleError(f"oracle_k4 failed ({rc})")
+    return int(total.value)
+
+
+def k5(n, src, dst, order=0, threads=0):
+    """Number of 5-cliques of the simple graph."""
+    src, dst = _i32(src), _i32(dst)
+    total = ctypes.c_uint64()
+    rc = lib().oracle_k5(n, src.size, _ptr(src), _ptr(dst), order, threads, ctypes.byref(total))
+    if rc:
+        raise OracleError(f"oracle_k5 failed ({rc})")
     return int(total.value)
 
 

@@ -636,6 +636,76 @@ int oracle_rmat(int scale, double a, double b, double c, double d, double noise,
   return 0;
 }
 
+/*
+ * Number of 5-cliques (clique detection, the paper's Section 4 table of
+ * graph-motif methods): every 5-clique has one vertex u of lowest rank, and
+ * its other four vertices w < x < y < z (by rank) satisfy w in N+(u),
+ * x in C1 = N+(u) ∩ N+(w), y in C2 = C1 ∩ N+(x), z in C2 ∩ N+(y), where N+(v)
+ * is the set of neighbours ranked above v. The count is the sum over u, w,
+ * x, y of |N+(y) ∩ C2|: three marker levels (N+(u), C1, C2) over a plain
+ * node iterator, with either rank order (order_mode as for oracle_k4).
+ * Returns 0, -1 on an id outside [0,n), -2 on allocation failure.
+ */
+int oracle_k5(int64_t n, int64_t m_raw, const int32_t* src, const int32_t* dst, int order_mode, int nthreads,
+              uint64_t* total) {
+  og_graph g;
+  int rc = og_build(n, m_raw, src, dst, &g);
+  if (rc) return rc;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  uint64_t count = 0;
+  int failed = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : count)
+  {
+    int64_t* m1 = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t)); /* in N+(u) */
+    int64_t* m2 = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t)); /* in C1 */
+    int64_t* m3 = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t)); /* in C2 */
+    if (!m1 || !m2 || !m3) {
+#pragma omp atomic write
+      failed = 1;
+    } else {
+      int64_t s2 = 0, s3 = 0;
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t u = 0; u < n; ++u) {
+        for (int64_t p = g.off[u]; p < g.off[u + 1]; ++p)
+          if (og_below(&g, order_mode, u, g.adj[p])) m1[g.adj[p]] = u + 1;
+        for (int64_t p = g.off[u]; p < g.off[u + 1]; ++p) {
+          const int64_t w = g.adj[p];
+          if (!og_below(&g, order_mode, u, w)) continue;
+          ++s2;
+          for (int64_t q = g.off[w]; q < g.off[w + 1]; ++q) {
+            const int64_t x = g.adj[q];
+            if (og_below(&g, order_mode, w, x) && m1[x] == u + 1) m2[x] = s2;
+          }
+          for (int64_t q = g.off[w]; q < g.off[w + 1]; ++q) {
+            const int64_t x = g.adj[q];
+            if (m2[x] != s2) continue;
+            ++s3;
+            for (int64_t r = g.off[x]; r < g.off[x + 1]; ++r) {
+              const int64_t y = g.adj[r];
+              if (og_below(&g, order_mode, x, y) && m2[y] == s2) m3[y] = s3;
+            }
+            for (int64_t r = g.off[x]; r < g.off[x + 1]; ++r) {
+              const int64_t y = g.adj[r];
+              if (m3[y] != s3) continue;
+              for (int64_t t = g.off[y]; t < g.off[y + 1]; ++t) {
+                const int64_t z = g.adj[t];
+                if (og_below(&g, order_mode, y, z) && m3[z] == s3) count += 1;
+              }
+            }
+          }
+        }
+      }
+    }
+    free(m1);
+    free(m2);
+    free(m3);
+  }
+  og_free(&g);
+  if (failed) return -2;
+  *total = count;
+  return 0;
+}
+
 /* floor(w * N / 2^64): the high word of the 128-bit product. */
 static uint64_t mul_hi(uint64_t w, uint64_t N) { return (uint64_t)(((unsigned __int128)w * N) >> 64); }
 

@@ -121,6 +121,7 @@ _SIGS = {
     "tricc_graph_has_edges": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P]),
     "tricc_core_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "tricc_graph_count_k4": (ctypes.c_int, [_P, _P, _P]),
+    "tricc_graph_count_k5": (ctypes.c_int, [_P, _P, _P]),
     "tricc_graph_degeneracy": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32), _P]),
     "tricc_graph_reorient": (ctypes.c_int, [_P, _P, _P]),
     "tricc_graph_core": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),

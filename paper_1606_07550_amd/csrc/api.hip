@@ -1038,6 +1038,18 @@ int tricc_graph_count_k4(const tricc_graph* g, uint64_t* d_total, void* stream) 
   return TRICC_OK;
 }
 
+int tricc_graph_count_k5(const tricc_graph* g, uint64_t* d_total, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (!d_total) return fail(TRICC_EINVAL, "null output");
+  if (g->info.max_outdeg > kK5Cap)
+    return fail(TRICC_EOVERFLOW, "5-clique counting takes out-degrees up to %d (this graph: %lld)", kK5Cap,
+                (long long)g->info.max_outdeg);
+  const Layout& L = g->L;
+  HIPCHK(launch_count_k5(g->n, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol),
+                         reinterpret_cast<unsigned long long*>(d_total), static_cast<hipStream_t>(stream)));
+  return TRICC_OK;
+}
+
 void tricc_graph_free(tricc_graph* g) { delete g; }
 
 }  // extern "C"

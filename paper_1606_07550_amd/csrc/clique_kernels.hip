@@ -1,7 +1,8 @@
-// 4-clique counts (clique detection, among the graph-motif methods of
-// Section 4): the triangle method one size up on the same degree-ordered
-// DAG. A 4-clique u < w < x < z (by rank) is met once, at u: w in N+(u),
-// x in C = N+(u) ∩ N+(w), z in N+(x) ∩ C.
+// 4- and 5-clique counts (clique detection, among the graph-motif methods of
+// Section 4): the triangle method one and two sizes up on the same
+// degree-ordered DAG. A 4-clique u < w < x < z (by rank) is met once, at u:
+// w in N+(u), x in C = N+(u) ∩ N+(w), z in N+(x) ∩ C; a 5-clique adds one
+// more level of the same intersection.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -13,8 +14,9 @@ constexpr int kK4NT = 256;
 // Out-degrees up to kK4BitsMid take the bit-row kernel with 256 threads and
 // 39 KB of LDS; up to kK4BitsMax the one with 1,024 threads and 136 KB (one
 // block per CU); up to 2,048 the pass kernel over quarters of the positions
-// (1,024 threads, 142 KB); up to kK4Cap the pass kernel over sixteenths
-// (150 KB).
+// (1,024 threads, 142 KB); up to 4,096 the pass kernel over sixteenths
+// (150 KB); up to kK4Cap = 8,192 the pass kernel over blocks of 64
+// positions (2 words per row, 102 KB).
 constexpr int kK4BitsMid = 512;
 constexpr int kK4BitsMax = 1024;
 
@@ -252,6 +254,100 @@ __global__ __launch_bounds__(kK4QNT) void k_count_k4_passes(int32_t n, int32_t c
   k4_block_total<kK4QWaves>(acc, red, total);
 }
 
+// 5-cliques, nodes with DMIN < d+(u) <= DMAX (and d+(u) >= 4): the bit rows
+// of the subgraph induced on N+(u) are built as for the 4-clique kernel; a
+// 5-clique u < w < x < y < z is then w's row bit x, y a bit of the AND of
+// rows w and x, and z a bit of that AND with row y. Each wavefront takes rows
+// w in turn and walks the x of row w one at a time: every lane forms one
+// word of the AND of rows w and x (lane & (RS - 1)), the y in it are listed
+// in LDS (per lane, in bit order, after a scan of the lanes' popcounts), and
+// groups of 64 / RS lanes add popcount(AND & row y), one word each.
+template <int DMIN, int DMAX, int NT>
+__global__ __launch_bounds__(NT) void k_count_k5_bits(int32_t n, int32_t chunk, const int64_t* __restrict__ doff,
+                                                      const int32_t* __restrict__ dcol,
+                                                      unsigned long long* __restrict__ total) {
+  constexpr int NW = NT / kWave;
+  static_assert(DMAX % 32 == 0 && DMAX <= 1024, "rows of at most 32 words");
+  __shared__ int32_t L[DMAX];
+  __shared__ uint32_t B[DMAX * (DMAX / 32)];
+  __shared__ uint16_t Y[NW][DMAX];
+  __shared__ unsigned long long red[NW];
+  __shared__ int32_t Q[NT];
+  __shared__ int32_t Qn;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  unsigned long long acc = 0;
+  for (int64_t base = (int64_t)blockIdx.x * chunk; base < n; base += (int64_t)gridDim.x * chunk) {
+    __syncthreads();  // the previous chunk's queue has been taken
+    if (threadIdx.x == 0) Qn = 0;
+    __syncthreads();
+    const int64_t v = base + threadIdx.x;
+    if ((int)threadIdx.x < chunk && v < n) {
+      const int32_t dv = (int32_t)(doff[v + 1] - doff[v]);
+      if (dv >= 4 && dv > DMIN && dv <= DMAX) Q[atomicAdd(&Qn, 1)] = (int32_t)v;
+    }
+    __syncthreads();
+    const int32_t nq = Qn;
+    for (int32_t qi = 0; qi < nq; ++qi) {  // block-uniform
+      const int32_t u = Q[qi];
+      const int64_t ub = doff[u];
+      const int32_t d = (int32_t)(doff[u + 1] - ub);
+      const int rs = d <= 32 ? 0 : 32 - __builtin_clz((uint32_t)((d + 31) / 32 - 1));
+      const int RS = 1 << rs;
+      const int32_t P = 1 << (32 - __builtin_clz((uint32_t)(d - 1)));  // power of two >= d, <= DMAX
+      __syncthreads();  // L and B of the previous node are no longer read
+      for (int32_t i = threadIdx.x; i < P; i += NT) L[i] = i < d ? dcol[ub + i] : kPad;
+      for (int32_t q = threadIdx.x; q < d * RS; q += NT) B[q] = 0u;
+      __syncthreads();
+      for (int32_t i = wv; i < d; i += NW) {
+        const int32_t w = L[i];
+        const int64_t wb = doff[w];
+        const int32_t dw = (int32_t)(doff[w + 1] - wb);
+        for (int32_t t = lane; t < dw; t += kWave) {
+          const int32_t y = dcol[wb + t];
+          const int32_t p = pow2_lower_pos(L, P, y);
+          if (L[p] == y) atomicOr(&B[i * RS + (p >> 5)], 1u << (p & 31));
+        }
+      }
+      __syncthreads();
+      const int32_t k = lane & (RS - 1);
+      const int32_t js = lane >> rs;
+      for (int32_t i = wv; i < d; i += NW) {
+        const uint32_t* Bi = B + i * RS;
+        const uint32_t bik = Bi[k];
+        for (int32_t kw = 0; kw < RS; ++kw) {
+          uint32_t word = Bi[kw];  // wave-uniform
+          while (word) {
+            const int32_t x = kw * 32 + __builtin_ctz(word);
+            word &= word - 1u;
+            const uint32_t wx = bik & B[x * RS + k];
+            // list the y of wx: lanes 0 .. RS-1 own one word each
+            const int32_t c = lane < RS ? __popc(wx) : 0;
+            const int32_t incl = wave_incl_scan(c);
+            const int32_t ny = __shfl(incl, kWave - 1, kWave);
+            if (ny < 2) continue;  // y and z both lie in wx (wave-uniform)
+            if (lane < RS) {
+              uint32_t bits = wx;
+              int32_t o = incl - c;
+              while (bits) {
+                Y[wv][o++] = (uint16_t)(lane * 32 + __builtin_ctz(bits));
+                bits &= bits - 1u;
+              }
+            }
+            wave_sync();
+            for (int32_t g = 0; g < ny; g += (kWave >> rs)) {
+              const int32_t jj = g + js;
+              if (jj < ny) acc += (unsigned long long)__popc(wx & B[(int32_t)Y[wv][jj] * RS + k]);
+            }
+            wave_sync();  // Y is rewritten for the next x
+          }
+        }
+      }
+    }
+  }
+  k4_block_total<NW>(acc, red, total);
+}
+
 __global__ void k_zero_one(unsigned long long* p) {
   if (threadIdx.x == 0) *p = 0ull;
 }
@@ -280,7 +376,20 @@ hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, 
     k_count_k4_bits<kK4BitsMid, kK4BitsMax, 1024, false><<<k4_grid(n, cb, 1024), 1024, 0, s>>>(n, cb, doff, dcol,
                                                                                                  total);
     k_count_k4_passes<kK4BitsMax, 2048, 512><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
-    k_count_k4_passes<2048, kK4Cap, 256><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
+    k_count_k4_passes<2048, 4096, 256><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
+    k_count_k4_passes<4096, kK4Cap, 64><<<k4_grid(n, cb, 1024), kK4QNT, 0, s>>>(n, cb, doff, dcol, total);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_count_k5(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* total,
+                           hipStream_t s) {
+  k_zero_one<<<1, 64, 0, s>>>(total);
+  if (n > 0) {
+    const int32_t cm = k4_chunk(n, 65536, kK4NT);
+    k_count_k5_bits<0, kK4BitsMid, kK4NT><<<k4_grid(n, cm, 65536), kK4NT, 0, s>>>(n, cm, doff, dcol, total);
+    const int32_t cb = k4_chunk(n, 2048, 512);
+    k_count_k5_bits<kK4BitsMid, kK5Cap, 512><<<k4_grid(n, cb, 2048), 512, 0, s>>>(n, cb, doff, dcol, total);
   }
   return hipGetLastError();
 }

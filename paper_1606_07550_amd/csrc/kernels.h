@@ -229,8 +229,13 @@ hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
 // *total = number of 4-cliques, over the DAG N+(v) = dcol[doff[v] ..
 // doff[v+1]) (ascending ids); every d+(v) must be <= kK4Cap (bit rows over
 // blocks of positions index at most this many).
-constexpr int32_t kK4Cap = 4096;
+constexpr int32_t kK4Cap = 8192;
 hipError_t launch_count_k4(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* total,
+                           hipStream_t s);
+// *total = number of 5-cliques over the same DAG; every d+(v) must be <=
+// kK5Cap (the bit rows of one node, whole, in LDS).
+constexpr int32_t kK5Cap = 1024;
+hipError_t launch_count_k5(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* total,
                            hipStream_t s);
 
 // R-MAT edges 0..m-1 with 2^scale nodes (a, b, c, d quadrant weights, noise

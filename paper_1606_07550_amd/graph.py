@@ -223,6 +223,15 @@ class Graph:
         self.reorient(order, stream)
         return dg
 
+    def count_k5(self, out=None, stream=None):
+        """Number of 5-cliques: uint64[1] (as an int64 tensor) on the device."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            rc = N.lib().tricc_graph_count_k5(self._h, _ptr(out), _stream_ptr(stream))
+        N.check(rc, "tricc_graph_count_k5")
+        return out
+
     def count_k4(self, out=None, stream=None):
         """Number of 4-cliques: uint64[1] (as an int64 tensor) on the device.
         Asynchronous. Raises TriccError (TRICC_EOVERFLOW) when some out-degree

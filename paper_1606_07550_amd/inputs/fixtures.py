@@ -147,5 +147,9 @@ def k4_core(core, centres, avg_deg, seed):
 
 
 # (core, centres, avg_deg, seed): the centres' out-degrees fall just above
-# 1,024, inside (1,024, 2,048] and inside (2,048, 4,096]
-K4_CORE_CASES = [(1030, 3, 240, 71), (1500, 4, 90, 72), (2100, 2, 60, 73), (3500, 3, 40, 74)]
+# 1,024, inside (1,024, 2,048], (2,048, 4,096] and (4,096, 8,192]
+K4_CORE_CASES = [(1030, 3, 240, 71), (1500, 4, 90, 72), (2100, 2, 60, 73), (3500, 3, 40, 74), (5000, 2, 40, 75)]
+
+# the same construction for 5-cliques: centres' out-degrees in (512, 1,024]
+# (the larger 5-clique kernel) with denser cores
+K5_CORE_CASES = [(600, 4, 120, 81), (1000, 3, 200, 82)]

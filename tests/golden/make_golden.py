@@ -15,7 +15,8 @@ in seconds, so it runs once here and the results are committed:
   node count, edge count, triangle total, average clustering coefficient and
   fingerprints of T and d.
 * ``k4_pass.json``: 4-clique counts of the graphs whose largest out-degree
-  falls in each range of the 4-clique pass kernels.
+  falls in each range of the 4-clique pass kernels, and 5-clique counts of
+  hub-and-core graphs whose centres reach the larger 5-clique kernel.
 
 A fingerprint of an integer array a[0..n) is the pair
 (sum_v a[v] * (v + 1), sum_v a[v]^2 * (2v + 1)) modulo 2^64: a test compares
@@ -122,6 +123,14 @@ def k4():
         print(f"k4 core={core} centres={centres}: {c} in {time.time() - t0:.1f}s", flush=True)
         out["graphs"].append({"core": core, "centres": centres, "avg_deg": avg_deg, "seed": seed, "n": int(n),
                               "k4": c})
+    out["k5_graphs"] = []
+    for core, centres, avg_deg, seed in F.K5_CORE_CASES:
+        n, s, d = F.k4_core(core, centres, avg_deg, seed)
+        t0 = time.time()
+        c = oracle.k5(n, s, d, order=1)
+        print(f"k5 core={core} centres={centres}: {c} in {time.time() - t0:.1f}s", flush=True)
+        out["k5_graphs"].append({"core": core, "centres": centres, "avg_deg": avg_deg, "seed": seed, "n": int(n),
+                                 "k5": c})
     with open(os.path.join(HERE, "k4_pass.json"), "w") as f:
         json.dump(out, f, indent=1)
 

@@ -94,9 +94,9 @@ def test_rmat17_and_from_csr():
 
 
 def test_out_degree_limit_is_enforced():
-    n, s, d = F.complete(4200)
+    n, s, d = F.complete(8194)
     g = P.Graph(n, dev(s), dev(d))
-    assert g.info["max_outdeg"] > 4096
+    assert g.info["max_outdeg"] > 8192
     with pytest.raises(N.TriccError) as ei:
         g.count_k4()
     assert ei.value.status == N.TRICC_EOVERFLOW
@@ -116,6 +116,78 @@ def test_pass_kernels_on_sparse_rows(case):
     print(f"[k4] core={case['core']} centres={case['centres']} n={n}", flush=True)
     g = P.Graph(n, dev(s), dev(d))
     mo = g.info["max_outdeg"]
-    assert case["core"] <= mo <= case["core"] + case["centres"] - 1 and 1024 < mo <= 4096
+    assert case["core"] <= mo <= case["core"] + case["centres"] - 1 and 1024 < mo <= 8192
     assert gpu_k4(g) == case["k4"]
     assert gpu_k4(g) == case["k4"]
+
+
+def gpu_k5(g):
+    out = g.count_k5()
+    torch.cuda.synchronize()
+    return int(out.cpu().numpy().view(np.uint64)[0])
+
+
+K5_CASES = [
+    ("messy_K10", lambda: F.messy(*F.complete(10), seed=25)),
+    ("families", lambda: F.disjoint_union(F.complete(7), F.wheel(4), F.ring_lattice(40, 8), F.windmill(4),
+                                          F.grid(5, 5), F.complete_bipartite(4, 5))),
+    ("rmat12", lambda: I.rmat(12, 16, seed=61)),
+    ("rmat13", lambda: I.rmat(13, 16, seed=62)),
+    ("er", lambda: (20000, *I.er(20000, 300000, 63))),
+    ("ba", lambda: (20000, *I.ba(20000, 10, 64))),
+    ("dense", lambda: (400, *I.er(400, 40000, 65))),
+    ("no_edges", lambda: (9, np.zeros(0, np.int32), np.zeros(0, np.int32))),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in K5_CASES])
+def test_k5_against_oracle(name):
+    n, s, d = dict(K5_CASES)[name]()
+    print(f"[k5] {name} n={n} m_raw={len(s)}", flush=True)
+    g = P.Graph(n, dev(s), dev(d))
+    ref = oracle.k5(n, s, d, order=1)
+    assert gpu_k5(g) == ref
+    assert gpu_k5(g) == ref  # repeat calls
+
+
+@pytest.mark.parametrize("k", [5, 6, 33, 64, 65, 300, 513, 514, 700, 1025])
+def test_k5_complete_graphs(k):
+    n, s, d = F.complete(k)
+    assert gpu_k5(P.Graph(n, dev(s), dev(d))) == comb(k, 5)
+
+
+def test_k5_out_degree_limit_and_degeneracy():
+    n, s, d = F.complete(1026)
+    g = P.Graph(n, dev(s), dev(d))
+    with pytest.raises(N.TriccError) as ei:
+        g.count_k5()
+    assert ei.value.status == N.TRICC_EOVERFLOW
+    # the same count under the degeneracy order, whose out-degrees stay
+    # within the core numbers
+    n, s, d = I.rmat(12, 16, seed=66)
+    g = P.Graph(n, dev(s), dev(d))
+    ref = oracle.k5(n, s, d, order=1)
+    assert gpu_k5(g) == ref
+    g.orient_degeneracy()
+    assert gpu_k5(g) == ref
+
+
+def _k5_core_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "k4_pass.json")) as f:
+        return json.load(f).get("k5_graphs", [])
+
+
+@pytest.mark.parametrize("case", _k5_core_cases(), ids=lambda c: f"core{c['core']}")
+def test_k5_larger_kernel_on_sparse_rows(case):
+    n, s, d = F.k4_core(case["core"], case["centres"], case["avg_deg"], case["seed"])
+    assert n == case["n"]
+    g = P.Graph(n, dev(s), dev(d))
+    assert 512 < g.info["max_outdeg"] <= 1024
+    assert gpu_k5(g) == case["k5"]
+
+
+def test_k4_complete_graph_above_4096():
+    n, s, d = F.complete(4100)
+    g = P.Graph(n, dev(s), dev(d))
+    assert g.info["max_outdeg"] == 4099
+    assert gpu_k4(g) == comb(4100, 4)

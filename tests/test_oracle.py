@@ -1013,3 +1013,120 @@ def test_planted_generator_mistake_is_caught(mutant, tmp_path):
         assert not _er_pins_pass(er), f"mutant {mutant} passed the pins"
     else:
         assert not _ba_pins_pass(ba), f"mutant {mutant} passed the pins"
+
+
+# ---------------------------------------------------------------------------
+# 5-clique counts: pinned to brute force over all 5-subsets, to networkx's
+# clique enumeration, to closed forms (C(n, 5) for K_n; n for the ring
+# lattice with 4 neighbours on each side, whose 5-cliques are its windows of
+# 5 consecutive nodes; 0 where no 5 nodes are pairwise adjacent), invariances
+# and planted mistakes
+
+def brute_k5(n, s, d):
+    A = adjacency(n, s, d).astype(bool)
+    nb = [set(np.flatnonzero(A[v]).tolist()) for v in range(n)]
+    cnt = 0
+    for q in itertools.combinations(range(n), 3):  # extend triangles: fewer subsets to visit
+        a, b, c = q
+        if b in nb[a] and c in nb[a] and c in nb[b]:
+            common = [z for z in nb[a] & nb[b] & nb[c] if z > c]
+            cnt += sum(1 for i, y in enumerate(common) for z in common[i + 1:] if z in nb[y])
+    return cnt
+
+
+K5_CASES = [
+    ("messy_K10", lambda: F.messy(*F.complete(10), seed=25)),
+    ("rmat6", lambda: I.rmat(6, 12, seed=26)),
+    ("er", lambda: (26, *I.er(26, 220, 27))),
+    ("ba", lambda: (30, *I.ba(30, 7, 28))),
+    ("union", lambda: F.disjoint_union(F.complete(7), F.wheel(4), F.ring_lattice(14, 8), F.windmill(3))),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in K5_CASES])
+def test_k5_against_brute_force(name):
+    n, s, d = dict(K5_CASES)[name]()
+    ref = brute_k5(n, s, d)
+    assert ref > 0 or name == "ba"
+    assert oracle.k5(n, s, d, order=0) == ref
+    assert oracle.k5(n, s, d, order=1) == ref
+
+
+def test_brute_k5_itself_on_closed_forms():
+    from math import comb
+    for k in (5, 6, 9):
+        assert brute_k5(*F.complete(k)) == comb(k, 5)
+    assert brute_k5(*F.ring_lattice(14, 8)) == 14 and brute_k5(*F.wheel(6)) == 0
+
+
+def test_k5_against_networkx():
+    for n, s, d in (I.rmat(9, 10, seed=33), (2000, *I.ba(2000, 6, 34))):
+        G = nx.Graph()
+        G.add_edges_from(zip(s.tolist(), d.tolist()))
+        G.remove_edges_from(nx.selfloop_edges(G))
+        ref = sum(1 for c in nx.enumerate_all_cliques(G) if len(c) == 5)
+        assert oracle.k5(n, s, d) == ref
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("complete", lambda: (F.complete(13), 1287)),
+    ("k5", lambda: (F.complete(5), 1)),
+    ("wheel", lambda: (F.wheel(9), 0)),
+    ("bipartite", lambda: (F.complete_bipartite(6, 6), 0)),
+    ("lattice6", lambda: (F.ring_lattice(40, 6), 0)),
+    ("lattice8", lambda: (F.ring_lattice(40, 8), 40)),
+])
+def test_k5_closed_forms(case, expect):
+    (n, s, d), k = expect()
+    assert oracle.k5(n, s, d) == k
+
+
+def test_k5_invariant_under_noise_and_relabelling():
+    n, s, d = I.rmat(9, 12, seed=35)
+    base = oracle.k5(n, s, d)
+    assert base > 0
+    assert oracle.k5(*F.messy(n, s, d, seed=36)) == base
+    n3, s3, d3, _ = F.relabel(n, s, d, seed=37)
+    assert oracle.k5(n3, s3, d3) == base
+
+
+K5_MUTANTS = {
+    "k5_no_rank_on_y": ("if (og_below(&g, order_mode, x, y) && m2[y] == s2) m3[y] = s3;",
+                        "if (m2[y] == s2) m3[y] = s3;"),
+    "k5_last_mark_wrong": ("if (og_below(&g, order_mode, y, z) && m3[z] == s3) count += 1;",
+                           "if (og_below(&g, order_mode, y, z) && m2[z] == s2) count += 1;"),
+    "k5_inner_stamp_not_advanced": ("            ++s3;\n", "\n"),
+}
+
+
+def _k5_pins_pass(lib_path):
+    import ctypes
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.c_void_p
+    L.oracle_k5.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_int, P]
+    for name, make in K5_CASES:
+        n, s, d = make()
+        s = np.ascontiguousarray(s, np.int32)
+        d = np.ascontiguousarray(d, np.int32)
+        ref = brute_k5(n, s, d)
+        for order in (0, 1):
+            tot = ctypes.c_uint64()
+            if L.oracle_k5(n, s.size, s.ctypes.data, d.ctypes.data, order, 1, ctypes.byref(tot)):
+                return False
+            if tot.value != ref:
+                return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", sorted(K5_MUTANTS))
+def test_planted_k5_mistake_is_caught(mutant, tmp_path):
+    src = os.path.join(os.path.dirname(HERE), "oracle", "tricc_oracle.c")
+    text = open(src).read()
+    old, new = K5_MUTANTS[mutant]
+    assert old in text, f"mutation anchor for {mutant} not found"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(text.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11", str(mpath), "-o", str(lib)],
+                   check=True)
+    assert not _k5_pins_pass(str(lib)), f"mutant {mutant} passed the pins"
