@@ -1142,6 +1142,9 @@ struct tricc_batch {
   unsigned long long* graph_tri = nullptr;
   double* graph_avg = nullptr;
   unsigned long long* batch_tri = nullptr;
+  int32_t* d_seg = nullptr;   // phase-2 segment bounds of the persistent kernel
+  int64_t* d_thr = nullptr;   // first node of each segment
+  std::vector<int64_t> h_node_off, h_edge_off;
   bool bound = false;
 };
 
@@ -1151,11 +1154,16 @@ struct BatchLayout {
   size_t hdr, node_off, edge_off, gsrc, gdst, graph_ws, total;
 };
 
+// Header: queue counters at byte 0 (2 + kPersistSegs int32), the error flag
+// at 64, the segment bounds at 128 (2 (kPersistSegs + 1) int32), the segment
+// thresholds at 256 (kPersistSegs + 1 int64).
+constexpr size_t kBatchHdr = 512;
+
 BatchLayout make_batch_layout(int64_t G, int64_t n_total, int64_t m_total) {
   BatchLayout L{};
   size_t p = 0;
   auto take = [&](size_t bytes) { size_t at = p; p = align_up(p + std::max<size_t>(bytes, 1)); return at; };
-  L.hdr = take(256);
+  L.hdr = take(kBatchHdr);
   L.node_off = take(sizeof(int64_t) * (G + 1));
   L.edge_off = take(sizeof(int64_t) * (G + 1));
   L.gsrc = take(sizeof(int32_t) * m_total);
@@ -1208,6 +1216,27 @@ int batch_bin(tricc_batch* b) {
   batch_graph_tuning(b->tuning, &b->g.tuning);
   int rc = bin_nodes(&b->g);
   if (rc) return rc;
+  // phase-2 segments: consecutive graphs with equal shares of the input pairs
+  {
+    const int32_t G = b->G;
+    int64_t thr[kPersistSegs + 1];
+    const int64_t E = G > 0 ? b->h_edge_off[G] : 0;
+    int32_t gi = 0;
+    thr[0] = 0;
+    for (int x = 1; x < kPersistSegs; ++x) {
+      const int64_t target = E * x / kPersistSegs;
+      while (gi < G && b->h_edge_off[gi] < target) ++gi;
+      thr[x] = G > 0 ? b->h_node_off[gi] : 0;
+    }
+    thr[kPersistSegs] = b->n_total;
+    if ((rc = upload(b->d_thr, thr, sizeof(thr), b->g.stream))) return rc;
+    const tricc_graph* g = &b->g;
+    const int32_t* binlist = g->at<int32_t>(g->L.binlist);
+    HIPCHK(launch_persist_segments(binlist + g->bin_off[1], (int32_t)(g->bin_off[2] - g->bin_off[1]),
+                                   binlist + g->bin_off[0], (int32_t)(g->bin_off[1] - g->bin_off[0]), b->d_thr,
+                                   b->d_seg, b->g.stream));
+    HIPCHK(hipStreamSynchronize(b->g.stream));
+  }
   int dev = 0, cus = 0, occ = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1229,13 +1258,11 @@ int batch_launch(tricc_batch* b, hipStream_t s) {
     BinLaunch bl{g->tuning.bin_variant[bin], binlist + g->bin_off[bin], (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin])};
     HIPCHK(launch_count_bin(bl, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, tot, s));
   }
-  const int32_t nm = (int32_t)(g->bin_off[1] - g->bin_off[0]);
-  const int32_t nw = (int32_t)(g->bin_off[2] - g->bin_off[1]);
   const int32_t nbk = (int32_t)(g->bin_off[3] - g->bin_off[2]);
   const int32_t ng = (int32_t)(g->bin_off[kNumBins] - g->bin_off[kNumBins - 1]);
   HIPCHK(launch_count_persist(b->tuning.persist_variant, b->grid, binlist + g->bin_off[kNumBins - 1], ng,
-                              binlist + g->bin_off[2], nbk, binlist + g->bin_off[1], nw, binlist + g->bin_off[0], nm,
-                              b->d_queue, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, tot, s));
+                              binlist + g->bin_off[2], nbk, binlist + g->bin_off[1], binlist + g->bin_off[0],
+                              b->d_seg, b->d_queue, g->at<int64_t>(L.doff), g->at<int32_t>(L.dcol), b->T, tot, s));
   HIPCHK(launch_graph_epilogue(b->G, b->d_node_off, b->T, g->at<int32_t>(L.deg), b->cc, b->graph_tri, b->graph_avg,
                                tot, b->batch_tri, s));
   return TRICC_OK;
@@ -1309,6 +1336,8 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
   b->ws_bytes = ws_bytes;
   b->d_queue = reinterpret_cast<int32_t*>(ws + BL.hdr);
   b->d_err = reinterpret_cast<int32_t*>(ws + BL.hdr + 64);
+  b->d_seg = reinterpret_cast<int32_t*>(ws + BL.hdr + 128);
+  b->d_thr = reinterpret_cast<int64_t*>(ws + BL.hdr + 256);
   b->d_node_off = reinterpret_cast<int64_t*>(ws + BL.node_off);
   b->d_edge_off = reinterpret_cast<int64_t*>(ws + BL.edge_off);
   b->gsrc = reinterpret_cast<int32_t*>(ws + BL.gsrc);
@@ -1323,9 +1352,11 @@ int tricc_batch_build(int32_t num_graphs, const int64_t* h_node_off, const int64
   std::memset(&g->info, 0, sizeof(g->info));
   batch_graph_tuning(bt, &g->tuning);
   auto bail = [&](int code) { delete b; return code; };
-  if (hipMemsetAsync(ws + BL.hdr, 0, 256, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
+  if (hipMemsetAsync(ws + BL.hdr, 0, kBatchHdr, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
   if ((rc = upload(b->d_node_off, h_node_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
   if ((rc = upload(b->d_edge_off, h_edge_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
+  b->h_node_off.assign(h_node_off, h_node_off + num_graphs + 1);
+  b->h_edge_off.assign(h_edge_off, h_edge_off + num_graphs + 1);
   if (launch_batch_relabel(num_graphs, b->d_node_off, b->d_edge_off, d_src, d_dst, m_total, b->gsrc, b->gdst,
                            b->d_err, s) != hipSuccess)
     return bail(fail(TRICC_EHIP, "relabel launch failed"));
@@ -1373,6 +1404,8 @@ int tricc_batch_build_csr(int32_t num_graphs, const int64_t* h_node_off, int64_t
   b->ws_bytes = ws_bytes;
   b->d_queue = reinterpret_cast<int32_t*>(ws + BL.hdr);
   b->d_err = reinterpret_cast<int32_t*>(ws + BL.hdr + 64);
+  b->d_seg = reinterpret_cast<int32_t*>(ws + BL.hdr + 128);
+  b->d_thr = reinterpret_cast<int64_t*>(ws + BL.hdr + 256);
   b->d_node_off = reinterpret_cast<int64_t*>(ws + BL.node_off);
   b->d_edge_off = reinterpret_cast<int64_t*>(ws + BL.edge_off);
   b->gsrc = reinterpret_cast<int32_t*>(ws + BL.gsrc);
@@ -1387,7 +1420,7 @@ int tricc_batch_build_csr(int32_t num_graphs, const int64_t* h_node_off, int64_t
   std::memset(&g->info, 0, sizeof(g->info));
   batch_graph_tuning(bt, &g->tuning);
   auto bail = [&](int code) { delete b; return code; };
-  if (hipMemsetAsync(ws + BL.hdr, 0, 256, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
+  if (hipMemsetAsync(ws + BL.hdr, 0, kBatchHdr, s) != hipSuccess) return bail(fail(TRICC_EHIP, "memset failed"));
   if ((rc = upload(b->d_node_off, h_node_off, sizeof(int64_t) * (num_graphs + 1), s))) return bail(rc);
   // the graphs' entry ranges, rowptr at the node boundaries; the row offsets
   // themselves are checked by the CSR build
@@ -1399,6 +1432,10 @@ int tricc_batch_build_csr(int32_t num_graphs, const int64_t* h_node_off, int64_t
     if (last != nnz) return bail(fail(TRICC_EINVAL, "rowptr[total nodes] = %lld, expected nnz = %lld",
                                       (long long)last, (long long)nnz));
   }
+  b->h_node_off.assign(h_node_off, h_node_off + num_graphs + 1);
+  b->h_edge_off.assign(num_graphs + 1, 0);
+  if (num_graphs > 0 && (rc = sync_copy(b->h_edge_off.data(), b->d_edge_off, sizeof(int64_t) * (num_graphs + 1), s)))
+    return bail(rc);
   if (launch_batch_relabel(num_graphs, b->d_node_off, b->d_edge_off, nullptr, d_col, nnz, nullptr, b->gdst, b->d_err,
                            s) != hipSuccess)
     return bail(fail(TRICC_EHIP, "relabel launch failed"));

@@ -163,22 +163,21 @@ __device__ __forceinline__ int cuckoo_find(const int32_t* K, int32_t x) {
 }
 
 // Probes of the streaming loops: true when the lane is valid and x is in the
-// table, with *off the byte offset of x's counter in C (4 x slot); *hits
-// grows by the wave's number of such lanes.
+// table, with *off the byte offset of x's counter in C (4 x slot). The
+// callers count the hits (per lane in a register on the long-list path, so
+// that no scalar instruction is spent per 64 ids).
 template <int NB>
 struct BucketProbe {
   const int4* Kb;
-  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off, uint32_t* hits) const {
-    const bool hit = bucket_credit<NB>(Kb, x, valid, off);
-    *hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
-    return hit;
+  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off) const {
+    return bucket_credit<NB>(Kb, x, valid, off);
   }
 };
 
 template <int SLOTS>
 struct CuckooProbe {
   const int32_t* K;
-  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off, uint32_t* hits) const {
+  __device__ __forceinline__ bool operator()(int32_t x, bool valid, int* off) const {
     x = valid ? x : -2;  // in no table
     uint32_t a, b;
     cuckoo_off<SLOTS>(x, &a, &b);
@@ -186,11 +185,21 @@ struct CuckooProbe {
     const bool ea = *reinterpret_cast<const int32_t*>(Kc + a) == x;
     const bool eb = *reinterpret_cast<const int32_t*>(Kc + b) == x;
     *off = (int)(ea ? a : b);
-    // the compare masks are counted as they are (a == b makes them equal)
-    *hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ea) | __builtin_amdgcn_ballot_w64(eb));
     return ea | eb;
   }
 };
+
+// Sum over the 64 lanes of a wavefront (all active): 16-lane row sums by
+// DPP lane permutations (pairs, quads, half-row and row mirrors), then the
+// four row sums read on the scalar unit.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xf, 0xf, false);  // row_mirror
+  return (uint32_t)(__builtin_amdgcn_readlane((int)x, 0) + __builtin_amdgcn_readlane((int)x, 16) +
+                    __builtin_amdgcn_readlane((int)x, 32) + __builtin_amdgcn_readlane((int)x, 48));
+}
 
 // LDS of one node group of the wave-stream kernel.
 template <int SLOTS, int CAP>
@@ -259,7 +268,8 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
       for (int r = 0; r < kPackUnroll; ++r) {
         if (t0 + r * kWave >= total) break;
         int off;
-        const bool hit = probe(x[r], t0 + r * kWave + lane < total, &off, &hits);
+        const bool hit = probe(x[r], t0 + r * kWave + lane < total, &off);
+        hits += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
         if (hit) {
           credit(C, off);
           atomicAdd(&Wc[base + kk[r]], 1u);
@@ -285,11 +295,14 @@ __device__ __forceinline__ void load_chunk(int32_t (&x)[U], const int32_t* L, in
 }
 
 // One wavefront streams the long lists Wl[j] (j = j0, j0 + step, ... < nl)
-// against the bucket table, U loads of 64 ids per step: the next step's
-// loads (same list, or the first chunk of the next one) are in flight while
-// the current chunk is probed. Base and length of a list are wave-uniform
-// (scalar registers). Each hit credits its table slot; done(i, hits)
-// receives list i's hit count (wave-uniform). Returns the wave's hits.
+// against the table, U loads of 64 ids per step: the next step's loads
+// (same list, or the first chunk of the next one) are in flight while the
+// current chunk is probed. Base and length of a list are wave-uniform
+// (scalar registers). Each hit credits its table slot and the lane's hit
+// count; at the end of a list the lanes' counts are summed (DPP) and
+// done(i, hits) receives list i's hit count (wave-uniform). Per chunk of 64
+// ids only the exit test and the credit's exec mask use the scalar unit.
+// Returns the wave's hits.
 template <int U, typename Probe, typename Done>
 __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_t nl, const int32_t* Wl,
                                                 const int32_t* Wb, const int32_t* Wn,
@@ -303,7 +316,7 @@ __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_
   int32_t b = __builtin_amdgcn_readfirstlane(Wb[i]);
   int32_t n = __builtin_amdgcn_readfirstlane(Wn[i]);
   int32_t p = 0;
-  uint32_t total = 0, cw = 0;
+  uint32_t total = 0, hv = 0;  // hv: this lane's hits in list i
   // one pipeline step: load the chunk after (i, p) into nxt, probe cur;
   // false once the last list is done. Two register sets alternate, so no
   // copy has to wait for the loads in flight.
@@ -320,17 +333,20 @@ __device__ __forceinline__ uint32_t stream_long(int32_t j0, int32_t step, int32_
       }
     }
     load_chunk<U>(nxt, dcol + nb, np, nn, lane);
+    const int32_t rem = n - p;  // ids of list i from p on
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      if (p + k * kWave >= n) break;
+      if (k * kWave >= rem) break;
       int off;
-      const bool hit = probe(cur[k], lane < n - p - k * kWave, &off, &cw);
+      const bool hit = probe(cur[k], lane + k * kWave < rem, &off);
       if (hit) credit(C, off);
+      hv += (uint32_t)hit;
     }
     if (np == 0) {
+      const uint32_t cw = wave_sum_u32(hv);
+      hv = 0;
       done(i, cw);
       total += cw;
-      cw = 0;
       if (nj >= nl) return false;
     }
     j = nj;
@@ -801,11 +817,10 @@ __device__ __forceinline__ void small_stream(SmallLds<GS>& S, int32_t incl, int3
     for (int r = 0; r < kPackUnroll; ++r) {
       if (t0 + r * kWave >= total) break;
       int off;
-      uint32_t unused = 0;
       bool hit;
       if constexpr (CK) {
         hit = CuckooProbe<4 * GS>{reinterpret_cast<const int32_t*>(S.K[kk[r] / GS])}(
-            x[r], t0 + r * kWave + lane < total, &off, &unused);
+            x[r], t0 + r * kWave + lane < total, &off);
       } else {
         hit = bucket_credit<GS>(S.K[kk[r] / GS], x[r], t0 + r * kWave + lane < total, &off);
       }
@@ -893,16 +908,22 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
 // nodes (d+ <= CW), then groups of short-list nodes: 8 at a time for the
 // 8-lane merge (SMALL == 0) or 64 / SMALL at a time on the packed
 // small-node path with SMALL lanes per node (d+ <= SMALL). A wave takes
-// kPersistGrab items per atomic on queue[1] and issues its next grab before
-// running the current items, so the atomic's latency hides behind their
-// loads. Each wave owns a private LDS region in phase 2.
+// kPersistGrab items per atomic and issues its next grab before running the
+// current items, so the atomic's latency hides behind their loads. Each wave
+// owns a private LDS region in phase 2.
+// Phase 2 is split into kPersistSegs segments of consecutive graphs (equal
+// shares of the edges), one per XCD: the chip hands out blocks to its XCDs
+// in turn, so block b starts on segment b mod kPersistSegs and the graphs a
+// segment holds stay in one XCD's L2 while they are counted; a wave whose
+// segment is empty takes items of the next ones.
 constexpr int kPersistGrab = 8;
 
 template <int SW, int CW, int SB, int CB, int SMALL = 0, bool CK = false>
 __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict__ glist, int32_t ng,
                                                        const int32_t* __restrict__ blist, int32_t nbk,
-                                                       const int32_t* __restrict__ wlist, int32_t nw,
-                                                       const int32_t* __restrict__ mlist, int32_t nm,
+                                                       const int32_t* __restrict__ wlist,
+                                                       const int32_t* __restrict__ mlist,
+                                                       const int32_t* __restrict__ seg,
                                                        int32_t* __restrict__ queue,
                                                        const int64_t* __restrict__ doff,
                                                        const int32_t* __restrict__ dcol,
@@ -932,27 +953,73 @@ __global__ __launch_bounds__(256) void k_count_persist(const int32_t* __restrict
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   unsigned char* mine = smem + wv * kWaveBytes;
-  const int32_t n2 = nw + (int32_t)(((int64_t)nm + NPW - 1) / NPW);
-  int32_t got = 0;
-  if (lane == 0) got = atomicAdd(queue + 1, kPersistGrab);
-  int32_t cur = __builtin_amdgcn_readfirstlane(got);
-  while (cur < n2) {
-    int32_t nxt = 0;
-    if (lane == 0) nxt = atomicAdd(queue + 1, kPersistGrab);
-    const int32_t end = min(cur + kPersistGrab, n2);
-    for (int32_t it = cur; it < end; ++it) {
-      if (it < nw) {
-        node_count_wave<kWave, SW, CW, 4, CK>(wlist[it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T, tot);
-      } else if constexpr (SMALL != 0) {
-        nodes_count_small<kGS, CK>(mlist, (int64_t)(it - nw) * NPW, nm, *reinterpret_cast<SL*>(mine), doff, dcol,
-                                   T, tot);
-      } else {
-        const int64_t k = (int64_t)(it - nw) * NPW + lane / 8;
-        node_count_merge<8>(k < nm ? mlist[k] : -1, doff, dcol, T, tot);
+  // Phase 2 takes the items of segment x = (this block's XCD) first, then
+  // moves on to the other segments once it is empty: seg[x .. x+1] bound the
+  // segment's single-wave nodes in wlist, seg[kPersistSegs + 1 + x ..] its
+  // short-list nodes in mlist; queue[2 + x] counts the items taken.
+  const int x0 = (int)(blockIdx.x % kPersistSegs);
+  for (int t = 0; t < kPersistSegs; ++t) {
+    const int x = (x0 + t) % kPersistSegs;
+    const int32_t wb = seg[x], nwx = seg[x + 1] - wb;
+    const int32_t mb = seg[kPersistSegs + 1 + x], me = seg[kPersistSegs + 2 + x];
+    const int32_t n2 = nwx + (int32_t)(((int64_t)(me - mb) + NPW - 1) / NPW);
+    int32_t got = 0;
+    if (lane == 0) got = atomicAdd(queue + 2 + x, kPersistGrab);
+    int32_t cur = __builtin_amdgcn_readfirstlane(got);
+    while (cur < n2) {
+      int32_t nxt = 0;
+      if (lane == 0) nxt = atomicAdd(queue + 2 + x, kPersistGrab);
+      const int32_t end = min(cur + kPersistGrab, n2);
+      for (int32_t it = cur; it < end; ++it) {
+        if (it < nwx) {
+          node_count_wave<kWave, SW, CW, 4, CK>(wlist[wb + it], *reinterpret_cast<WL*>(mine), red, doff, dcol, T,
+                                                tot);
+        } else if constexpr (SMALL != 0) {
+          nodes_count_small<kGS, CK>(mlist, mb + (int64_t)(it - nwx) * NPW, me, *reinterpret_cast<SL*>(mine), doff,
+                                     dcol, T, tot);
+        } else {
+          const int64_t k = mb + (int64_t)(it - nwx) * NPW + lane / 8;
+          node_count_merge<8>(k < me ? mlist[k] : -1, doff, dcol, T, tot);
+        }
       }
+      cur = __builtin_amdgcn_readlane(nxt, 0);
     }
-    cur = __builtin_amdgcn_readlane(nxt, 0);
   }
+}
+
+// Segment bounds of the persistent kernel's phase 2 (see k_count_persist):
+// for x = 0 .. kPersistSegs, out[x] = first index of wlist whose node is at
+// least thr[x], out[kPersistSegs + 1 + x] the same in mlist. The lists are in
+// ascending node order up to the classification's blocks of ids, so a
+// boundary may land inside one such block: locality only, every item is
+// still taken exactly once.
+__global__ void k_persist_segments(const int32_t* __restrict__ wlist, int32_t nw, const int32_t* __restrict__ mlist,
+                                   int32_t nm, const int64_t* __restrict__ thr, int32_t* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= 2 * (kPersistSegs + 1)) return;
+  const bool m = i > kPersistSegs;
+  const int x = m ? i - kPersistSegs - 1 : i;
+  const int32_t* L = m ? mlist : wlist;
+  const int32_t n = m ? nm : nw;
+  int32_t r;
+  if (x == 0) r = 0;
+  else if (x == kPersistSegs) r = n;
+  else {
+    const int64_t t = thr[x];
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if ((int64_t)L[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    r = lo;
+  }
+  out[i] = r;
+}
+
+hipError_t launch_persist_segments(const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                   const int64_t* thr, int32_t* out, hipStream_t s) {
+  k_persist_segments<<<1, 64, 0, s>>>(wlist, nw, mlist, nm, thr, out);
+  return hipGetLastError();
 }
 
 struct PersistShape { int sw, cw, sb, cb, small, ck = 0; };
@@ -987,18 +1054,18 @@ const void* persist_kernel(int v) {
 
 template <int SW, int CW, int SB, int CB, int SMALL = 0, bool CK = false>
 static void launch_persist(unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist, int32_t nbk,
-                           const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm, int32_t* queue,
+                           const int32_t* wlist, const int32_t* mlist, const int32_t* seg, int32_t* queue,
                            const int64_t* doff, const int32_t* dcol, unsigned long long* T, unsigned long long* tot,
                            hipStream_t s) {
-  k_count_persist<SW, CW, SB, CB, SMALL, CK><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, nw, mlist, nm, queue,
+  k_count_persist<SW, CW, SB, CB, SMALL, CK><<<grid, 256, 0, s>>>(glist, ng, blist, nbk, wlist, mlist, seg, queue,
                                                                    doff, dcol, T, tot);
 }
 
 hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
-                                int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                int32_t nbk, const int32_t* wlist, const int32_t* mlist, const int32_t* seg,
                                 int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
                                 unsigned long long* tot, hipStream_t s) {
-#define TRICC_PERSIST_ARGS grid, glist, ng, blist, nbk, wlist, nw, mlist, nm, queue, doff, dcol, T, tot, s
+#define TRICC_PERSIST_ARGS grid, glist, ng, blist, nbk, wlist, mlist, seg, queue, doff, dcol, T, tot, s
   switch (v) {
     case 0: launch_persist<256, 64, 1024, 256>(TRICC_PERSIST_ARGS); break;
     case 1: launch_persist<256, 64, 4096, 1024>(TRICC_PERSIST_ARGS); break;
@@ -1014,17 +1081,15 @@ hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int3
   return hipGetLastError();
 }
 
-// Clears T[n], the kTotSlots total counters and the two work-queue counters
-// (a kernel, so that it can sit in a captured graph).
+// Clears T[n], the kTotSlots total counters and the work-queue counters
+// (phase 1 and one per phase-2 segment; a kernel, so that it can sit in a
+// captured graph).
 __global__ __launch_bounds__(256) void k_batch_zero(unsigned long long* __restrict__ T, int64_t n,
                                                     unsigned long long* __restrict__ tot,
                                                     int32_t* __restrict__ queue) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 == 0) {
-    queue[0] = 0;
-    queue[1] = 0;
-  }
+  if (i0 < 2 + kPersistSegs) queue[i0] = 0;
   if (i0 < kTotSlots) tot[i0] = 0ull;
   for (int64_t i = i0; i < n; i += stride) T[i] = 0ull;
 }

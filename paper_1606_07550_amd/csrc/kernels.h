@@ -175,16 +175,24 @@ hipError_t launch_finish(int64_t nb, int32_t n, const double* part_cc, const uns
 // ---- Batched graphs ---------------------------------------------------------
 // Persistent intersection kernel over four node lists (hubs -> global
 // fallback, block nodes, single-wave nodes, short-list nodes); queue[0] and
-// queue[1] must be 0 at launch (launch_batch_zero clears both).
+// the queue counters must be 0 at launch (launch_batch_zero clears them).
 int persist_variant_count();
 int persist_wave_cap(int v);   // largest d+ of a single-wave node
 int persist_block_cap(int v);  // largest d+ of a block node
 int persist_merge_cap(int v);  // largest merge_limit the variant accepts
 const void* persist_kernel(int v);
+// Phase 2 of the persistent kernel runs in kPersistSegs segments (one per
+// XCD of the chip: 256 CUs in 8 XCDs); seg holds 2 (kPersistSegs + 1) bounds
+// (launch_persist_segments); queue needs 2 + kPersistSegs counters.
+constexpr int kPersistSegs = 8;
 hipError_t launch_count_persist(int v, unsigned grid, const int32_t* glist, int32_t ng, const int32_t* blist,
-                                int32_t nbk, const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                int32_t nbk, const int32_t* wlist, const int32_t* mlist, const int32_t* seg,
                                 int32_t* queue, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
                                 unsigned long long* tot, hipStream_t s);
+// Bounds of the segments in wlist[0, nw) and mlist[0, nm): thr[x] (x = 0 ..
+// kPersistSegs) is the first node id of segment x.
+hipError_t launch_persist_segments(const int32_t* wlist, int32_t nw, const int32_t* mlist, int32_t nm,
+                                   const int64_t* thr, int32_t* out, hipStream_t s);
 hipError_t launch_batch_zero(unsigned long long* T, int64_t n, unsigned long long* tot, int32_t* queue,
                              hipStream_t s);
 // batch_tri (may be null): the batch's total from tot.
