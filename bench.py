@@ -47,9 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS) + ["er"])
-    ap.add_argument("--cpu-sample-stride", type=int, default=64,
+    ap.add_argument("--cpu-sample-stride", type=int, default=256,
                     help="CPU oracle: count from the root nodes with id % stride == 0 on all host threads")
-    ap.add_argument("--cpu-sample-stride1", type=int, default=2048,
+    ap.add_argument("--cpu-sample-stride1", type=int, default=8192,
                     help="CPU oracle: the same on one thread from id % stride1 == 0 (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="JSON file with bin_limit / bin_variant")

@@ -14,13 +14,6 @@ namespace tricc {
 
 namespace {
 
-inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
-  int64_t g = (work + per_block - 1) / per_block;
-  if (g < 1) g = 1;
-  if (g > (int64_t)cap) g = cap;
-  return (unsigned)g;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,15 @@ constexpr int32_t kPad = 0x7fffffff;  // sort padding; node ids are < 2^31 - 1
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Blocks for `work` items at per_block items each, at least 1, at most cap
+// (grid-stride kernels cover the rest).
+inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (int64_t)cap) g = cap;
+  return (unsigned)g;
+}
+
 // Orders the LDS traffic of one wavefront: all lanes of a wave run in lockstep,
 // so a fence plus a scheduling barrier is enough between a write by one lane
 // and a read by another lane of the same wave.

@@ -22,13 +22,6 @@ constexpr int32_t kServeChunk = 2048;
 
 namespace {
 
-inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
-  int64_t g = (work + per_block - 1) / per_block;
-  if (g < 1) g = 1;
-  if (g > (int64_t)cap) g = cap;
-  return (unsigned)g;
-}
-
 // query of flat item i: last q with qoff[q] <= i
 __device__ __forceinline__ int32_t find_query(const int64_t* qoff, int32_t Q, int64_t i) {
   int32_t lo = 0, hi = Q - 1;
