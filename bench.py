@@ -119,6 +119,17 @@ def probe_bandwidth(torch, N, nbytes=2 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
+def build_line(ms, n, m_raw, m):
+    """The build's compulsory bytes: the input pairs read once (8 per pair);
+    the symmetric rows (4 per entry, 2m entries), the DAG's out- and
+    in-lists (4 per entry each) written once; three offset arrays (8 per
+    node) and three degree arrays (4 per node). Everything the sorts and
+    the orientation move beyond that is above this floor."""
+    b = 8 * m_raw + 4 * 2 * m + 4 * m + 4 * m + 3 * 8 * (n + 1) + 3 * 4 * n
+    gbps = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"ms": ms, "compulsory_bytes": b, "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS}
+
+
 def measured_counters(workload, variant, bin):
     """rocprofv3 counters of the dominant kernel from the committed summary
     (profiles/counters_<workload>.md): DRAM-side bytes, L2 hit rate and the
@@ -802,6 +813,7 @@ def main():
                                          if avg_bin_ms[b] > 0 else 0.0 for b in range(nb)]},
         "count_only": {"ms": count_ms, "edges_per_s": m / (count_ms * 1e-3)},
         "build_ms": 1e3 * build_s / args.steps,
+        "build": build_line(1e3 * build_s / args.steps, n, int(src.numel()), m),
         "probe_copy_GBps": bw,
     }
     if not args.no_core:
