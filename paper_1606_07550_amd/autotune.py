@@ -30,6 +30,11 @@ LIMIT_SETS = [
     [32, 128, 512, 1024, 4096],
     [64, 128, 512, 1024, 4096],
     [32, 128, 256, 1024, 4096],
+    [64, 256, 512, 768, 4096],
+    [64, 256, 640, 1024, 4096],
+    [64, 256, 512, 1024, 2048],
+    [96, 256, 512, 1024, 4096],
+    [64, 192, 512, 1024, 4096],
 ]
 
 
