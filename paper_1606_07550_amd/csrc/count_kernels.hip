@@ -219,7 +219,7 @@ struct WaveGroupLds {
 // short lists per step instead of one list per step.
 constexpr int32_t kPackShort = 64;
 // Steps of 64 ids whose gathers are issued together in the packed streams.
-constexpr int kPackUnroll = 4;
+constexpr int kPackUnroll = 3;
 
 // Lanes per node on the packed small-node path by default (d+ <= kSmallGS).
 constexpr int kSmallGS = 16;
