@@ -109,7 +109,9 @@ int tricc_variant_capacity(int variant);
  *   9       N+(u) as a bitmap over all ids in HBM (any d+; the default for
  *           nodes above every LDS table)
  *   10..17  as 0..7 with two-choice cuckoo tables
- *   18, 19  cuckoo tables for d+ <= 128 and <= 256, two wavefronts per node */
+ *   18, 19  cuckoo tables for d+ <= 128 and <= 256, two wavefronts per node
+ *   20      cuckoo table of 4,096 slots for d+ <= 2048, sixteen wavefronts
+ *           per node (two blocks fill a CU's wave slots) */
 int tricc_variant_count(void);
 /* 1 if the variant implements both sides of the min-side split (every
  * variant but 8 and 9). */

@@ -1185,6 +1185,8 @@ static constexpr VariantInfo kVariants[] = {
     {256, 256, 512, 256},     // 17: d+ <= 256, denser table
     {128, 128, 512, 128},     // 18: d+ <= 128, two wavefronts per node
     {128, 128, 1024, 256},    // 19: d+ <= 256, two wavefronts per node
+    {1024, 1024, 4096, 2048}, // 20: d+ <= 2048, sixteen wavefronts per node (two blocks per CU
+                              //     fill its wave slots, against 16 waves for variant 16)
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = 8;
@@ -1236,6 +1238,7 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 17: launch_ms<256, 256, 512, 256, true>(b, doff, dcol, T, tot, s); break;
     case 18: launch_ms<128, 128, 512, 128, true>(b, doff, dcol, T, tot, s); break;
     case 19: launch_ms<128, 128, 1024, 256, true>(b, doff, dcol, T, tot, s); break;
+    case 20: launch_ms<1024, 1024, 4096, 2048, true>(b, doff, dcol, T, tot, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T, tot);
       break;
