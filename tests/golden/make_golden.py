@@ -17,13 +17,17 @@ in seconds, so it runs once here and the results are committed:
 * ``k4_pass.json``: 4-clique counts of the graphs whose largest out-degree
   falls in each range of the 4-clique pass kernels, and 5-clique counts of
   hub-and-core graphs whose centres reach the larger 5-clique kernel.
+* ``serving_rmat22.json``: for 408 of the 20,000 BFS-ball queries on R-MAT
+  22 (seed 22, query seed 2022): the 8 largest and 400 drawn uniformly
+  (seed 4222), the induced subgraph's edge count, triangle total and
+  average clustering coefficient.
 
 A fingerprint of an integer array a[0..n) is the pair
 (sum_v a[v] * (v + 1), sum_v a[v]^2 * (2v + 1)) modulo 2^64: a test compares
 the GPU's per-node counts against the oracle's through it without storing
 them (314 MB for the batch).
 
-Usage: python tests/golden/make_golden.py [rmat24|batch|k4|all]
+Usage: python tests/golden/make_golden.py [rmat24|batch|k4|serving|all]
 """
 import json
 import os
@@ -135,6 +139,44 @@ def k4():
         json.dump(out, f, indent=1)
 
 
+def serving_picks(sizes):
+    """The queries the stored serving results cover: the 8 largest and 400
+    drawn uniformly (seed 4222), ascending."""
+    rng = np.random.default_rng(4222)
+    return np.unique(np.concatenate([np.argsort(sizes, kind="stable")[-8:],
+                                     rng.choice(sizes.size, size=400, replace=False)]))
+
+
+def serving():
+    import oracle
+    from paper_1606_07550_amd import inputs as I
+    n, s, d = I.rmat(22, 16, seed=22)
+    Q = 20000
+    off, nodes, _ = I.bfs_queries(n, s, d, Q, seed=2022)
+    picks = serving_picks(np.diff(off))
+
+    def one(q):
+        S = nodes[off[q]:off[q + 1]]
+        r = oracle.induced(n, s, d, S, threads=1)
+        return {"q": int(q), "k": int(S.size), "m": r["m"], "total": r["total"], "avg_hex": float(r["avg"]).hex()}
+
+    t0 = time.time()
+    order = sorted(picks.tolist(), key=lambda q: -(off[q + 1] - off[q]))  # largest first
+    res = {}
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 1) as ex:
+        for q, r in zip(order, ex.map(one, order)):
+            res[q] = r
+    print(f"serving oracle {time.time() - t0:.1f}s for {len(order)} queries", flush=True)
+    out = {
+        "_source": "CPU oracle (oracle_induced) on R-MAT scale 22 (edge factor 16, seed 22, permuted) for the "
+                   "BFS-ball queries of paper_1606_07550_amd.inputs.bfs_queries (20,000 queries, seed 2022) "
+                   "listed by tests/golden/make_golden.py serving_picks; written by tests/golden/make_golden.py",
+        "queries": [res[q] for q in sorted(res)],
+    }
+    with open(os.path.join(HERE, "serving_rmat22.json"), "w") as f:
+        json.dump(out, f, separators=(",", ":"))
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("k4", "all"):
@@ -143,3 +185,5 @@ if __name__ == "__main__":
         batch()
     if what in ("rmat24", "all"):
         rmat24()
+    if what in ("serving", "all"):
+        serving()
