@@ -111,7 +111,10 @@ int tricc_variant_capacity(int variant);
  *   10..17  as 0..7 with two-choice cuckoo tables
  *   18, 19  cuckoo tables for d+ <= 128 and <= 256, two wavefronts per node
  *   20      cuckoo table of 4,096 slots for d+ <= 2048, sixteen wavefronts
- *           per node (two blocks fill a CU's wave slots) */
+ *           per node (two blocks fill a CU's wave slots)
+ *   21, 22  d+ <= 64: four nodes with d+ <= 16 per wavefront (one 64-slot
+ *           table each), the bin's other nodes one per wavefront as 1 / 11;
+ *           21 bucket tables, 22 cuckoo tables */
 int tricc_variant_count(void);
 /* 1 if the variant implements both sides of the min-side split (every
  * variant but 8 and 9). */

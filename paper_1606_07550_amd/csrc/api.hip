@@ -302,6 +302,9 @@ int bin_nodes(tricc_graph* g) {
     HIPCHK(launch_in_chunks(inlist, nin, g->at<int32_t>(L.din), hdr + kHdrInCap, d_in_off, g->at<int32_t>(L.inch), s));
     int64_t* incoff = g->at<int64_t>(L.incoff);
     HIPCHK(launch_scan_i32(g->at<int32_t>(L.inch), nin, incoff, g->at<int64_t>(L.scan_tmp), s));
+    // chunk -> owner map in tmp (free after the orientation): at most one
+    // chunk per owner plus d-(w) / 16 per owner, below the 2 m_raw entries
+    HIPCHK(launch_in_owners(nin, incoff, g->at<int32_t>(L.tmp), s));
     int64_t* d_items = reinterpret_cast<int64_t*>(g->ws + L.hdr + kHdrInItems * 4);
     HIPCHK(launch_gather_offsets(incoff, d_in_off, kNumBins + 1, d_items, s));
     if ((rc = sync_copy(g->in_items, d_items, sizeof(g->in_items), s))) return rc;
@@ -687,6 +690,8 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
   if (g->tuning.min_side && count_variant_min_side(bl.variant)) {
     bl.in_list = g->at<int32_t>(L.inlist) + g->in_off[bin];
     bl.in_coff = g->at<int64_t>(L.incoff) + g->in_off[bin];
+    bl.in_owner = g->at<int32_t>(L.tmp) + g->in_items[bin];
+    bl.in_base = (int32_t)g->in_off[bin];
     bl.in_nodes = (int32_t)(g->in_off[bin + 1] - g->in_off[bin]);
     bl.in_items = g->in_items[bin + 1] - g->in_items[bin];
     bl.w_max = g->tuning.bin_limit[kNumBins - 2];

@@ -1463,6 +1463,21 @@ hipError_t launch_in_chunks(const int32_t* list, int64_t nlist, const int32_t* d
   return hipGetLastError();
 }
 
+// Chunk -> owner map of the in-list items, so that a work item finds its
+// owner with one load instead of a search over the chunk prefix.
+__global__ __launch_bounds__(256) void k_in_owners(int64_t nlist, const int64_t* __restrict__ coff,
+                                                   int32_t* __restrict__ owner) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nlist; i += stride)
+    for (int64_t c = coff[i]; c < coff[i + 1]; ++c) owner[c] = (int32_t)i;
+}
+
+hipError_t launch_in_owners(int64_t nlist, const int64_t* coff, int32_t* owner, hipStream_t s) {
+  if (nlist == 0) return hipSuccess;
+  k_in_owners<<<grid_for(nlist, 256, 1u << 14), 256, 0, s>>>(nlist, coff, owner);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // sum over DAG edges u->w of d+(u) + d+(w): the list elements a merge-based
 // intersection reads (the algorithmic-bytes measure of the hot loop).

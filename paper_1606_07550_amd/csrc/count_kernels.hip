@@ -558,12 +558,26 @@ __device__ __forceinline__ void node_count_inw(int32_t w, int64_t chunk, WaveGro
 // nodes from their out-lists (skipping edges owned by in-lists), the rest run
 // the bin's in-list chunks. In-list items: the nodes inl[0..nin) with chunk
 // prefix inc[0..nin] (inc[0] need not be 0).
+// owner[j] - base = p, the index of item j's node in list: the chunk -> owner
+// map built with the chunk prefix.
 struct InItems {
   const int32_t* list;
   const int64_t* coff;
+  const int32_t* owner;
+  int32_t base;
   int32_t nodes;
   int64_t items;
 };
+
+// In-list item j of a bin: its owner w and chunk (w = -1 past the items).
+__device__ __forceinline__ void in_item(const InItems& in, int64_t j, int32_t* w, int64_t* chunk) {
+  *w = -1;
+  *chunk = 0;
+  if (j >= in.items) return;
+  const int32_t p = in.owner[j] - in.base;
+  *w = in.list[p];
+  *chunk = in.coff[0] + j - in.coff[p];
+}
 
 template <int NT, int G, int SLOTS, int CAP, int U, bool CK>
 __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ list, int32_t nlist, InItems in,
@@ -584,19 +598,9 @@ __global__ __launch_bounds__(NT) void k_count_ms(const int32_t* __restrict__ lis
     node_count_wave<G, SLOTS, CAP, U, CK>(idx < nlist ? list[idx] : -1, lds[gi], red, doff, dcol, T, tot, w_max);
     return;
   }
-  const int64_t j = ((int64_t)blockIdx.x - nbu) * GPB + gi;
-  int32_t w = -1;
-  int64_t chunk = 0;
-  if (j < in.items) {
-    const int64_t gc = in.coff[0] + j;
-    int32_t lo = 0, hi = in.nodes - 1;  // last p with coff[p] <= gc
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (in.coff[mid] <= gc) lo = mid; else hi = mid - 1;
-    }
-    w = in.list[lo];
-    chunk = gc - in.coff[lo];
-  }
+  int32_t w;
+  int64_t chunk;
+  in_item(in, ((int64_t)blockIdx.x - nbu) * GPB + gi, &w, &chunk);
   node_count_inw<G, SLOTS, CAP, U, CK>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T, tot);
 }
 
@@ -834,12 +838,17 @@ __device__ __forceinline__ void small_stream(SmallLds<GS>& S, int32_t incl, int3
 
 // CK: the node tables are cuckoo tables (all of the wave's tables are
 // rebuilt in the bucket layout if one insert gives up).
+// Nodes with d+(u) > GS are left out; the returned lane mask has bit k * GS
+// set for each such node list[first + k] (wave-uniform). w_max > 0
+// (min-side mode): edges u->w with d+(u) < d+(w) <= w_max are left to w's
+// in-list pass, as in node_count_wave.
 template <int GS, bool CK = false>
-__device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ list, int64_t first, int64_t nlist,
-                                                  SmallLds<GS>& S, const int64_t* __restrict__ doff,
-                                                  const int32_t* __restrict__ dcol,
-                                                  unsigned long long* __restrict__ T,
-                                                  unsigned long long* __restrict__ tot) {
+__device__ __forceinline__ uint64_t nodes_count_small(const int32_t* __restrict__ list, int64_t first,
+                                                      int64_t nlist, SmallLds<GS>& S,
+                                                      const int64_t* __restrict__ doff,
+                                                      const int32_t* __restrict__ dcol,
+                                                      unsigned long long* __restrict__ T,
+                                                      unsigned long long* __restrict__ tot, int32_t w_max = 0) {
   static_assert(kWave % GS == 0 && GS >= 4, "GS divides the wave");
   constexpr int NB = GS;
   const int lane = lane_id();
@@ -859,6 +868,11 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
     ub = doff[u];
     nu = (int32_t)(doff[u + 1] - ub);
   }
+  const uint64_t big = __builtin_amdgcn_ballot_w64(j == 0 && nu > GS);
+  if (nu > GS) {  // left to the caller
+    u = -1;
+    nu = 0;
+  }
   wave_sync();
   bool gave_up = false;
   if (j < nu) {
@@ -868,6 +882,8 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
     const int64_t b = doff[w];
     wb = (int32_t)b;
     wn = (int32_t)(doff[w + 1] - b);
+    // edges u->w with d+(u) < d+(w) <= w_max are counted from w's in-list
+    if (nu < wn && wn <= w_max) wn = 0;
   }
   wave_sync();
   bool ck = false;
@@ -897,6 +913,46 @@ __device__ __forceinline__ void nodes_count_small(const int32_t* __restrict__ li
     const uint32_t cs = C[s];
     if (key >= 0 && cs) atomicAdd(&T[key], (unsigned long long)cs);
   }
+  return big;
+}
+
+// Bin kernel for short out-lists (d+ <= CAP <= 64), one wavefront per group:
+// each wavefront takes 64 / GS consecutive nodes of the bin, counts those
+// with d+ <= GS together on the packed small-node path, then the others one
+// by one as node_count_wave does. The in-list side (blocks after the first
+// ceil(nlist / (GPB * 64 / GS))) is k_count_ms's.
+template <int NT, int SLOTS, int CAP, int U, bool CK, int GS>
+__global__ __launch_bounds__(NT) void k_count_mss(const int32_t* __restrict__ list, int32_t nlist, InItems in,
+                                                  int32_t w_max, const int64_t* __restrict__ doff,
+                                                  const int32_t* __restrict__ dcol,
+                                                  const int64_t* __restrict__ dinoff,
+                                                  const int32_t* __restrict__ dincol,
+                                                  unsigned long long* __restrict__ T,
+                                                  unsigned long long* __restrict__ tot) {
+  constexpr int GPB = NT / kWave;
+  constexpr int NPW = kWave / GS;
+  using WL = WaveGroupLds<SLOTS, CAP>;
+  static_assert(CAP <= kWave && sizeof(SmallLds<GS>) <= sizeof(WL), "one wave's LDS holds either path");
+  __shared__ WL lds[GPB];
+  __shared__ unsigned long long red[GPB];
+  const int gi = threadIdx.x / kWave;
+  const int64_t nbu = ((int64_t)nlist + GPB * NPW - 1) / (GPB * NPW);
+  if ((int64_t)blockIdx.x < nbu) {
+    const int64_t first = ((int64_t)blockIdx.x * GPB + gi) * NPW;
+    uint64_t big = nodes_count_small<GS, CK>(list, first, nlist, *reinterpret_cast<SmallLds<GS>*>(&lds[gi]), doff,
+                                             dcol, T, tot, w_max);
+    wave_sync();  // the small path's LDS is reused below
+    while (big) {
+      const int k = __builtin_ctzll(big) / GS;
+      big &= big - 1;
+      node_count_wave<kWave, SLOTS, CAP, U, CK>(list[first + k], lds[gi], red, doff, dcol, T, tot, w_max);
+    }
+    return;
+  }
+  int32_t w;
+  int64_t chunk;
+  in_item(in, ((int64_t)blockIdx.x - nbu) * GPB + gi, &w, &chunk);
+  node_count_inw<kWave, SLOTS, CAP, U, CK>(w, chunk, lds[gi], red, doff, dcol, dinoff, dincol, T, tot);
 }
 
 // Persistent form (batched graphs): one launch covers every node of the
@@ -1187,6 +1243,9 @@ static constexpr VariantInfo kVariants[] = {
     {128, 128, 1024, 256},    // 19: d+ <= 256, two wavefronts per node
     {1024, 1024, 4096, 2048}, // 20: d+ <= 2048, sixteen wavefronts per node (two blocks per CU
                               //     fill its wave slots, against 16 waves for variant 16)
+    // short out-lists: four nodes with d+ <= 16 per wavefront, the rest as variant 1 / 11
+    {256, 64, 256, 64},       // 21: d+ <= 64, bucket tables
+    {256, 64, 256, 64},       // 22: d+ <= 64, cuckoo tables
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = 8;
@@ -1203,9 +1262,21 @@ static void launch_ms(const BinLaunch& b, const int64_t* doff, const int32_t* dc
   const int64_t nbu = ((int64_t)b.count + GPB - 1) / GPB;
   const int64_t nbw = (b.in_items + GPB - 1) / GPB;
   if (nbu + nbw == 0) return;
-  InItems in{b.in_list, b.in_coff, b.in_nodes, b.in_items};
+  InItems in{b.in_list, b.in_coff, b.in_owner, b.in_base, b.in_nodes, b.in_items};
   k_count_ms<NT, G, SLOTS, CAP, U, CK><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
                                                                         b.dinoff, b.dincol, T, tot);
+}
+
+template <bool CK, int U = 8>
+static void launch_mss(const BinLaunch& b, const int64_t* doff, const int32_t* dcol, unsigned long long* T,
+                       unsigned long long* tot, hipStream_t s) {
+  constexpr int NT = 256, GS = kSmallGS, GPB = NT / kWave;
+  const int64_t nbu = ((int64_t)b.count + GPB * (kWave / GS) - 1) / (GPB * (kWave / GS));
+  const int64_t nbw = (b.in_items + GPB - 1) / GPB;
+  if (nbu + nbw == 0) return;
+  InItems in{b.in_list, b.in_coff, b.in_owner, b.in_base, b.in_nodes, b.in_items};
+  k_count_mss<NT, 256, 64, U, CK, GS><<<(unsigned)(nbu + nbw), NT, 0, s>>>(b.list, b.count, in, b.w_max, doff, dcol,
+                                                                       b.dinoff, b.dincol, T, tot);
 }
 
 // Hub bitmaps: one bit per node id, as many bitmaps as fit 256 MB (8 to 256,
@@ -1239,6 +1310,8 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 18: launch_ms<128, 128, 512, 128, true>(b, doff, dcol, T, tot, s); break;
     case 19: launch_ms<128, 128, 1024, 256, true>(b, doff, dcol, T, tot, s); break;
     case 20: launch_ms<1024, 1024, 4096, 2048, true>(b, doff, dcol, T, tot, s); break;
+    case 21: launch_mss<false>(b, doff, dcol, T, tot, s); break;
+    case 22: launch_mss<true>(b, doff, dcol, T, tot, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T, tot);
       break;

@@ -110,6 +110,8 @@ hipError_t launch_classify_inbins(int pass, int32_t n, const int32_t* dplus, con
 // nch[i] = ceil(d-(list[i]) / cap_of[bin of i])
 hipError_t launch_in_chunks(const int32_t* list, int64_t nlist, const int32_t* din, const int32_t* cap_of,
                             const int64_t* bin_off, int32_t* nch, hipStream_t s);
+// owner[c] = i for each in-list chunk c in [coff[i], coff[i+1]), i < nlist
+hipError_t launch_in_owners(int64_t nlist, const int64_t* coff, int32_t* owner, hipStream_t s);
 
 hipError_t launch_list_elems(int32_t n, const int64_t* doff, const int32_t* dcol, unsigned long long* out,
                              hipStream_t s);
@@ -139,6 +141,8 @@ struct BinLaunch {
   // min-side variants only: the bin's in-list items and the ownership bound
   const int32_t* in_list = nullptr;
   const int64_t* in_coff = nullptr;
+  const int32_t* in_owner = nullptr;  // owner index (+ in_base) of each of the bin's chunks
+  int32_t in_base = 0;
   int32_t in_nodes = 0;
   int64_t in_items = 0;
   int32_t w_max = 0;

@@ -209,6 +209,10 @@ MIN_SIDE_TUNINGS = [
     {"bin_limit": [16, 64, 256, 1024, 4096], "bin_variant": [10, 11, 12, 13, 14, 9], "min_side": 1},
     {"bin_limit": [64, 256, 512, 1024, 2048], "bin_variant": [11, 17, 15, 13, 16, 8], "min_side": 1},
     {"bin_limit": [4, 8, 32, 128, 512], "bin_variant": [10, 10, 11, 12, 13, 8], "min_side": 1},
+    # four short-list nodes per wavefront, the longer ones of the bin one by one
+    {"bin_limit": [64, 256, 640, 1024, 4096], "bin_variant": [21, 19, 15, 20, 20, 9], "min_side": 1},
+    {"bin_limit": [64, 256, 640, 1024, 4096], "bin_variant": [22, 19, 15, 20, 20, 9], "min_side": 1},
+    {"bin_limit": [8, 24, 64, 256, 1024], "bin_variant": [21, 22, 21, 12, 13, 8], "min_side": 1},
 ]
 
 
