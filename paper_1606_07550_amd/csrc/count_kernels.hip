@@ -245,7 +245,7 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
     }
     const int32_t incl = wave_incl_scan(nb);
     const int32_t total = __shfl(incl, kWave - 1, kWave);
-    const int32_t excl = incl - nb;
+    const int32_t dlt = bb - (incl - nb);  // list k's id at t: dcol[dlt_k + t]
     for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
       // kPackUnroll independent gathers in flight before the probes
       int32_t x[kPackUnroll];
@@ -259,9 +259,8 @@ __device__ __forceinline__ uint32_t stream_packed(int32_t i0, int32_t i1, const 
           const int32_t v = __shfl(incl, k + step - 1, kWave);
           if (v <= t) k += step;
         }
-        const int32_t kb = __shfl(bb, k, kWave);
-        const int32_t ke = __shfl(excl, k, kWave);
-        x[r] = t < total ? dcol[kb + (t - ke)] : -1;
+        const int32_t at = __shfl(dlt, k, kWave) + t;
+        x[r] = t < total ? dcol[at] : -1;
         kk[r] = k;
       }
 #pragma unroll
@@ -799,6 +798,7 @@ struct SmallLds {
 template <int GS, bool CK>
 __device__ __forceinline__ void small_stream(SmallLds<GS>& S, int32_t incl, int32_t total, int32_t excl, int32_t wb,
                                              const int32_t* __restrict__ dcol, int lane) {
+  const int32_t dlt = wb - excl;  // list k's id at t: dcol[dlt_k + t]
   for (int32_t t0 = 0; t0 < total; t0 += kPackUnroll * kWave) {
     // kPackUnroll independent gathers in flight before the probes
     int32_t x[kPackUnroll];
@@ -812,9 +812,8 @@ __device__ __forceinline__ void small_stream(SmallLds<GS>& S, int32_t incl, int3
         const int32_t v = __shfl(incl, k + step - 1, kWave);
         if (v <= t) k += step;
       }
-      const int32_t kb = __shfl(wb, k, kWave);
-      const int32_t ke = __shfl(excl, k, kWave);
-      x[r] = t < total ? dcol[kb + (t - ke)] : -1;
+      const int32_t at = __shfl(dlt, k, kWave) + t;
+      x[r] = t < total ? dcol[at] : -1;
       kk[r] = k;
     }
 #pragma unroll
