@@ -924,13 +924,17 @@ int tricc_graph_has_edges(const tricc_graph* g, int64_t q, const int32_t* d_u, c
 
 int tricc_core_workspace_size(int32_t n, size_t* bytes) {
   if (n < 0 || !bytes) return fail(TRICC_EINVAL, "bad core workspace query");
-  *bytes = 5 * align_up(sizeof(int32_t) * (size_t)std::max(n, 1)) + 256;
+  *bytes = 7 * align_up(sizeof(int32_t) * (size_t)std::max(n, 1)) + 256;
   return TRICC_OK;
 }
 
 }  // extern "C"
 
 namespace {
+
+// Levels per window of the core peeling: a scan of every node left opens a
+// window [k, k + kCoreWindow], whose levels then scan the near list only.
+constexpr int32_t kCoreWindow = 32;
 
 // Peeling loop of the core decomposition; with d_order, every node's removal
 // round as well (frontiers counted across levels).
@@ -950,9 +954,10 @@ int core_impl(const tricc_graph* g, int32_t k_stop, int32_t* d_core, int32_t* d_
     int32_t* cur = reinterpret_cast<int32_t*>(w);
     int32_t* F = reinterpret_cast<int32_t*>(w + slice);
     int32_t* G = reinterpret_cast<int32_t*>(w + 2 * slice);
-    int32_t* A = reinterpret_cast<int32_t*>(w + 3 * slice);  // nodes left, listed by the last scan
+    int32_t* A = reinterpret_cast<int32_t*>(w + 3 * slice);  // nodes left, listed by the last full scan
     int32_t* S = reinterpret_cast<int32_t*>(w + 4 * slice);
-    int32_t* cnt = reinterpret_cast<int32_t*>(w + 5 * slice);
+    int32_t* near[2] = {reinterpret_cast<int32_t*>(w + 5 * slice), reinterpret_cast<int32_t*>(w + 6 * slice)};
+    int32_t* cnt = reinterpret_cast<int32_t*>(w + 7 * slice);
     const Layout& L = g->L;
     const int64_t* off = g->at<int64_t>(L.raw_off);
     const int32_t* deg = g->at<int32_t>(L.deg);
@@ -961,36 +966,59 @@ int core_impl(const tricc_graph* g, int32_t k_stop, int32_t* d_core, int32_t* d_
     int64_t left = n;
     int32_t k = 0;
     int rc;
-    // scan candidates: all ids, until at most a quarter of the nodes are
-    // left; from then on each scan lists the survivors for the next one
+    // full-scan candidates: all ids, until at most a quarter of the nodes
+    // are left; from then on each full scan lists the survivors for the next
     const int32_t* cand = nullptr;
     int32_t ncand = n;
+    // the window of levels [.., U] and its near list near[x] (length nx):
+    // every node left with current degree <= U is on it
+    int32_t U = -1, nx = 0, x = 0;
     while (left > 0 && (k_stop < 0 || k < k_stop)) {
-      const bool listing = cand != nullptr || left <= n / 4;
-      HIPCHK(launch_core_reset(cnt, 0, s));
-      HIPCHK(launch_core_scan(ncand, cand, k, cur, d_core, F, listing ? S : nullptr, cnt, d_order, round, s));
-      int32_t c[4];
-      if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
-      if (listing) {
-        std::swap(A, S);
-        cand = A;
-        ncand = c[3];
+      const bool full = k > U || nx == 0;
+      const int y = x ^ 1;  // the scan lists this level's near nodes in near[y]
+      int32_t c[8];
+      if (full) {
+        U = k + kCoreWindow;
+        if (k_stop >= 0) U = std::min(U, k_stop - 1);  // no level at or above k_stop is peeled
+        const bool listing = cand != nullptr || left <= n / 4;
+        HIPCHK(launch_core_reset(cnt, 0, 6 + y, s));
+        HIPCHK(launch_core_scan(ncand, cand, k, cur, d_core, F, listing ? S : nullptr, cnt, d_order, round, U, near[y],
+                                cnt + 6 + y, s));
+        if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
+        if (listing) {
+          std::swap(A, S);
+          cand = A;
+          ncand = c[3];
+        }
+      } else {
+        HIPCHK(launch_core_reset(cnt, 0, 6 + y, s));
+        HIPCHK(launch_core_scan(nx, near[x], k, cur, d_core, F, nullptr, cnt, d_order, round, U, near[y], cnt + 6 + y,
+                                s));
+        if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
       }
-      if (c[0] == 0) {  // no node at this level: jump to the smallest current degree left
-        if (c[2] == 0x7fffffff) break;
-        k = c[2];
+      x = y;
+      nx = c[6 + x];
+      if (c[0] == 0) {  // no node at this level: jump to the smallest current degree seen
+        if (c[2] == 0x7fffffff) {
+          if (full) break;  // no node left at all
+          k = U + 1;        // none left in the window: every node left is above U
+        } else {
+          k = c[2];
+        }
         continue;
       }
       int32_t nf = c[0];
       while (nf > 0) {
         left -= nf;
-        HIPCHK(launch_core_reset(cnt, 1, s));
-        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, d_order, round, s));
+        HIPCHK(launch_core_reset(cnt, 1, -1, s));
+        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, d_order, round, U, near[x], cnt + 6 + x,
+                                s));
         ++round;
         if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
         std::swap(F, G);
         nf = c[1];
       }
+      nx = c[6 + x];
       maxc = k;
       ++k;
     }

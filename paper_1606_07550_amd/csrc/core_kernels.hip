@@ -8,6 +8,12 @@
 // skipped: a scan that finds no frontier reports the smallest current
 // degree left.
 //
+// Scans of every node left are made once per window of levels [k, U]: the
+// scan at k also lists the nodes left with current degree <= U (the near
+// list), and the peels append every node whose current degree falls from
+// U + 1 to U. Every node left with current degree <= U is thus on the near
+// list, so the levels up to U scan that list alone.
+//
 // With `order` given, each node also records the round in which it was
 // removed (rounds count every frontier, across levels). A node removed in
 // round r had current degree <= k then, counting exactly its neighbours
@@ -46,8 +52,9 @@ __global__ __launch_bounds__(kCoreNT) void k_core_init(int32_t n, const int32_t*
 }
 
 // cnt[0] = frontier size, cnt[1] = next frontier size, cnt[2] = smallest
-// current degree above k among the nodes left, cnt[3] = survivors listed.
-__global__ void k_core_reset(int32_t* __restrict__ cnt, int which) {
+// current degree above k among the nodes scanned, cnt[3] = survivors
+// listed, cnt[6] and cnt[7] = lengths of the two near-list buffers.
+__global__ void k_core_reset(int32_t* __restrict__ cnt, int which, int near) {
   if (threadIdx.x == 0) {
     if (which == 0) {
       cnt[0] = 0;
@@ -56,6 +63,7 @@ __global__ void k_core_reset(int32_t* __restrict__ cnt, int which) {
     } else {
       cnt[1] = 0;
     }
+    if (near >= 0) cnt[near] = 0;
   }
 }
 
@@ -67,12 +75,13 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
                                                        const int32_t* __restrict__ cur, int32_t* __restrict__ core,
                                                        int32_t* __restrict__ F, int32_t* __restrict__ S,
                                                        int32_t* __restrict__ cnt, int32_t* __restrict__ order,
-                                                       int32_t round) {
+                                                       int32_t round, int32_t U, int32_t* __restrict__ Nr,
+                                                       int32_t* __restrict__ ncnt) {
   const int64_t stride = (int64_t)gridDim.x * kCoreNT;
   int32_t mn = 0x7fffffff;
   for (int64_t b = (int64_t)blockIdx.x * kCoreNT; b < na; b += stride) {  // uniform trip count
     const int64_t i = b + threadIdx.x;
-    bool take = false, keep = false;
+    bool take = false, keep = false, near = false;
     int32_t v = 0;
     if (i < na) {
       v = A ? A[i] : (int32_t)i;
@@ -85,11 +94,13 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
         } else {
           mn = min(mn, c);
           keep = true;
+          near = c <= U;
         }
       }
     }
     wave_push(take, v, F, cnt);
     if (S) wave_push(keep, v, S, cnt + 3);
+    if (Nr) wave_push(near, v, Nr, ncnt);
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, kWave));
@@ -98,10 +109,15 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
 
 // Lowers the current degree of w (if still left) at level k; true for the
 // one decrement that takes it from k + 1 to k (w then has core number k).
-__device__ __forceinline__ bool core_drop(int32_t w, int32_t k, int32_t* __restrict__ cur,
+// *enter: this decrement took it from U + 1 to U (w joins the near list).
+__device__ __forceinline__ bool core_drop(int32_t w, int32_t k, int32_t U, int32_t* __restrict__ cur,
                                           int32_t* __restrict__ core, int32_t* __restrict__ order,
-                                          int32_t next_round) {
-  if (core[w] < 0 && atomicSub(&cur[w], 1) == k + 1) {
+                                          int32_t next_round, bool* enter) {
+  *enter = false;
+  if (core[w] >= 0) return false;
+  const int32_t old = atomicSub(&cur[w], 1);
+  *enter = old == U + 1;
+  if (old == k + 1) {
     core[w] = k;
     if (order) order[w] = next_round;
     return true;
@@ -122,7 +138,8 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
                                                        const int32_t* __restrict__ adj, int32_t* __restrict__ cur,
                                                        int32_t* __restrict__ core, int32_t* __restrict__ G,
                                                        int32_t* __restrict__ cnt, int32_t* __restrict__ order,
-                                                       int32_t round) {
+                                                       int32_t round, int32_t U, int32_t* __restrict__ Nr,
+                                                       int32_t* __restrict__ ncnt) {
   constexpr int GPB = kCoreNT / kPeelG;
   const int lane = lane_id();
   const int g = threadIdx.x % kPeelG;
@@ -143,13 +160,14 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
     for (int o = kWave / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
     for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG) {
       const int32_t j = j0 + g;
-      bool take = false;
+      bool take = false, enter = false;
       int32_t w = 0;
       if (j < ds) {
         w = adj[rb + j];
-        take = core_drop(w, k, cur, core, order, round + 1);
+        take = core_drop(w, k, U, cur, core, order, round + 1, &enter);
       }
       wave_push(take, w, G, cnt + 1);
+      if (Nr) wave_push(enter, w, Nr, ncnt);
     }
     // long rows: the whole wavefront on each in turn (group leaders' bits)
     uint64_t longs = __ballot(g == 0 && dv > kPeelShort);
@@ -161,13 +179,14 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
                         (uint32_t)__shfl((int32_t)rb, src, kWave);
       for (int32_t j0 = 0; j0 < d; j0 += kWave) {
         const int32_t j = j0 + lane;
-        bool take = false;
+        bool take = false, enter = false;
         int32_t w = 0;
         if (j < d) {
           w = adj[r + j];
-          take = core_drop(w, k, cur, core, order, round + 1);
+          take = core_drop(w, k, U, cur, core, order, round + 1, &enter);
         }
         wave_push(take, w, G, cnt + 1);
+        if (Nr) wave_push(enter, w, Nr, ncnt);
       }
     }
   }
@@ -191,24 +210,25 @@ hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s) {
-  k_core_reset<<<1, 64, 0, s>>>(cnt, which);
+hipError_t launch_core_reset(int32_t* cnt, int which, int near, hipStream_t s) {
+  k_core_reset<<<1, 64, 0, s>>>(cnt, which, near);
   return hipGetLastError();
 }
 
 hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
-                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, hipStream_t s) {
+                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, int32_t U, int32_t* Nr,
+                            int32_t* ncnt, hipStream_t s) {
   if (na <= 0) return hipSuccess;
-  k_core_scan<<<core_grid(na), kCoreNT, 0, s>>>(na, A, k, cur, core, F, S, cnt, order, round);
+  k_core_scan<<<core_grid(na), kCoreNT, 0, s>>>(na, A, k, cur, core, F, S, cnt, order, round, U, Nr, ncnt);
   return hipGetLastError();
 }
 
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
                             const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
-                            int32_t round, hipStream_t s) {
+                            int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, k, off, deg, adj, cur, core, G, cnt, order,
-                                                                  round);
+                                                                  round, U, Nr, ncnt);
   return hipGetLastError();
 }
 

@@ -222,19 +222,26 @@ hipError_t launch_has_edges(int64_t q, const int32_t* qu, const int32_t* qv, int
 
 // ---- Core numbers ------------------------------------------------------------
 // Level-synchronous peeling over the simple graph's rows (row v =
-// adj[off[v] .. off[v] + deg[v])). cur, F, G, A, S: int32[n] scratch; core:
-// int32[n] (-1 while a node is left); cnt: int32[4] counters (see
-// core_kernels.hip). The scan visits the listed candidates A[0, na) (A ==
-// NULL: all ids) and lists the other nodes left in S (if not NULL).
+// adj[off[v] .. off[v] + deg[v])). cur, F, G, A, S, and the two near lists:
+// int32[n] scratch; core: int32[n] (-1 while a node is left); cnt: int32[8]
+// counters (see core_kernels.hip). The scan visits the listed candidates
+// A[0, na) (A == NULL: all ids), lists the other nodes left in S (if not
+// NULL) and those of them with current degree <= U in the near list Nr (if
+// not NULL; its length in *ncnt).
 hipError_t launch_core_init(int32_t n, const int32_t* deg, int32_t* cur, int32_t* core, hipStream_t s);
-hipError_t launch_core_reset(int32_t* cnt, int which, hipStream_t s);
+// which 0: frontier, minimum and survivor counters; 1: next-frontier
+// counter; near >= 0: also clears cnt[near]
+hipError_t launch_core_reset(int32_t* cnt, int which, int near, hipStream_t s);
 // order (may be null): removal round of each node taken, `round` for the
 // scan's frontier and round + 1 for the peel's next frontier.
 hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32_t* cur, int32_t* core, int32_t* F,
-                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, hipStream_t s);
+                            int32_t* S, int32_t* cnt, int32_t* order, int32_t round, int32_t U, int32_t* Nr,
+                            int32_t* ncnt, hipStream_t s);
+// Nr (may be null): a node whose current degree falls from U + 1 to U is
+// appended to it (*ncnt its length).
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
                             const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
-                            int32_t round, hipStream_t s);
+                            int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt, hipStream_t s);
 hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
 
 // ---- 4-clique counts ---------------------------------------------------------
