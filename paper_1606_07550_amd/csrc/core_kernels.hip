@@ -107,27 +107,48 @@ __global__ __launch_bounds__(kCoreNT) void k_core_scan(int32_t na, const int32_t
   if (lane_id() == 0 && mn != 0x7fffffff) atomicMin(cnt + 2, mn);
 }
 
-// Lowers the current degree of w (if still left) at level k; true for the
-// one decrement that takes it from k + 1 to k (w then has core number k).
-// *enter: this decrement took it from U + 1 to U (w joins the near list).
-__device__ __forceinline__ bool core_drop(int32_t w, int32_t k, int32_t U, int32_t* __restrict__ cur,
-                                          int32_t* __restrict__ core, int32_t* __restrict__ order,
-                                          int32_t next_round, bool* enter) {
-  *enter = false;
-  if (core[w] >= 0) return false;
-  const int32_t old = atomicSub(&cur[w], 1);
-  *enter = old == U + 1;
-  if (old == k + 1) {
-    core[w] = k;
-    if (order) order[w] = next_round;
-    return true;
-  }
-  return false;
-}
-
 // Rows up to this length are walked by their node's 8-lane group; longer
 // ones by the whole wavefront, one node after the other.
 constexpr int32_t kPeelShort = 64;
+// Steps of a walk issued together: their loads and atomic subtractions are
+// in flight at once, since each waits on a round trip to memory.
+constexpr int kPeelU = 8;
+
+// kPeelU steps of a walk over row[0, d): the entries j0 + q * W + t, q <
+// kPeelU (t = the lane's place among the W walkers). Every lane of the
+// wavefront calls it (the pushes are wave-wide).
+__device__ __forceinline__ void peel_steps(const int32_t* __restrict__ row, int32_t d, int32_t j0, int32_t W,
+                                           int32_t t, int32_t k, int32_t U, int32_t* __restrict__ cur,
+                                           int32_t* __restrict__ core, int32_t* __restrict__ order,
+                                           int32_t next_round, int32_t* __restrict__ G, int32_t* __restrict__ gcnt,
+                                           int32_t* __restrict__ Nr, int32_t* __restrict__ ncnt) {
+  int32_t w[kPeelU];
+  bool live[kPeelU];
+#pragma unroll
+  for (int q = 0; q < kPeelU; ++q) {
+    const int32_t j = j0 + q * W + t;
+    live[q] = j < d;
+    w[q] = live[q] ? row[j] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kPeelU; ++q) live[q] = live[q] && core[w[q]] < 0;
+  int32_t old[kPeelU];
+#pragma unroll
+  for (int q = 0; q < kPeelU; ++q) old[q] = live[q] ? atomicSub(&cur[w[q]], 1) : 0;
+#pragma unroll
+  for (int q = 0; q < kPeelU; ++q) {
+    // the one decrement from k + 1 to k gives w core number k; the one from
+    // U + 1 to U puts it on the near list
+    const bool take = live[q] && old[q] == k + 1;
+    const bool enter = live[q] && old[q] == U + 1;
+    if (take) {
+      core[w[q]] = k;
+      if (order) order[w[q]] = next_round;
+    }
+    wave_push(take, w[q], G, gcnt);
+    if (Nr) wave_push(enter, w[q], Nr, ncnt);
+  }
+}
 
 // Removes the frontier F[0, nf) of level k: every neighbour w still left
 // loses one from its current degree; the one decrement that takes it from
@@ -158,17 +179,8 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
     int32_t dmax = ds;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
-    for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG) {
-      const int32_t j = j0 + g;
-      bool take = false, enter = false;
-      int32_t w = 0;
-      if (j < ds) {
-        w = adj[rb + j];
-        take = core_drop(w, k, U, cur, core, order, round + 1, &enter);
-      }
-      wave_push(take, w, G, cnt + 1);
-      if (Nr) wave_push(enter, w, Nr, ncnt);
-    }
+    for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG * kPeelU)
+      peel_steps(adj + rb, ds, j0, kPeelG, g, k, U, cur, core, order, round + 1, G, cnt + 1, Nr, ncnt);
     // long rows: the whole wavefront on each in turn (group leaders' bits)
     uint64_t longs = __ballot(g == 0 && dv > kPeelShort);
     while (longs) {
@@ -177,17 +189,8 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
       const int32_t d = __shfl(dv, src, kWave);
       const int64_t r = ((int64_t)__shfl((int32_t)(rb >> 32), src, kWave) << 32) |
                         (uint32_t)__shfl((int32_t)rb, src, kWave);
-      for (int32_t j0 = 0; j0 < d; j0 += kWave) {
-        const int32_t j = j0 + lane;
-        bool take = false, enter = false;
-        int32_t w = 0;
-        if (j < d) {
-          w = adj[r + j];
-          take = core_drop(w, k, U, cur, core, order, round + 1, &enter);
-        }
-        wave_push(take, w, G, cnt + 1);
-        if (Nr) wave_push(enter, w, Nr, ncnt);
-      }
+      for (int32_t j0 = 0; j0 < d; j0 += kWave * kPeelU)
+        peel_steps(adj + r, d, j0, kWave, lane, k, U, cur, core, order, round + 1, G, cnt + 1, Nr, ncnt);
     }
   }
 }
