@@ -114,7 +114,10 @@ int tricc_variant_capacity(int variant);
  *           per node (two blocks fill a CU's wave slots)
  *   21, 22  d+ <= 64: four nodes with d+ <= 16 per wavefront (one 64-slot
  *           table each), the bin's other nodes one per wavefront as 1 / 11;
- *           21 bucket tables, 22 cuckoo tables */
+ *           21 bucket tables, 22 cuckoo tables
+ *   23..26  cuckoo tables up to half full: 512 slots for d+ <= 256 (two
+ *           wavefronts per node), 1,024 slots for d+ <= 512 (four or eight
+ *           wavefronts), 2,048 slots for d+ <= 1024 (sixteen wavefronts) */
 int tricc_variant_count(void);
 /* 1 if the variant implements both sides of the min-side split (every
  * variant but 8 and 9). */

@@ -524,8 +524,8 @@ int csr_build(tricc_graph* g, int64_t nnz, const int64_t* d_rowptr, const int32_
 
 namespace {
 void tricc_default_tuning_impl(tricc_tuning* out) {
-  static const int32_t lim[kNumBins - 1] = {64, 256, 640, 1024, 4096};
-  static const int32_t var[kNumBins] = {1, 19, 15, 20, 14, 9};
+  static const int32_t lim[kNumBins - 1] = {64, 192, 512, 1024, 4096};
+  static const int32_t var[kNumBins] = {21, 23, 24, 20, 14, 9};
   std::memcpy(out->bin_limit, lim, sizeof(lim));
   std::memcpy(out->bin_variant, var, sizeof(var));
   out->min_side = 1;

@@ -1245,6 +1245,10 @@ static constexpr VariantInfo kVariants[] = {
     // short out-lists: four nodes with d+ <= 16 per wavefront, the rest as variant 1 / 11
     {256, 64, 256, 64},       // 21: d+ <= 64, bucket tables
     {256, 64, 256, 64},       // 22: d+ <= 64, cuckoo tables
+    {128, 128, 512, 256},     // 23: d+ <= 256, two wavefronts per node, half-full cuckoo table
+    {256, 256, 1024, 512},    // 24: d+ <= 512, four wavefronts per node, half-full cuckoo table
+    {512, 512, 1024, 512},    // 25: d+ <= 512, eight wavefronts per node, half-full cuckoo table
+    {1024, 1024, 2048, 1024}, // 26: d+ <= 1024, sixteen wavefronts per node, half-full cuckoo table
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kVariantGlobal = 8;
@@ -1311,6 +1315,10 @@ hipError_t launch_count_bin(const BinLaunch& b, const int64_t* doff, const int32
     case 20: launch_ms<1024, 1024, 4096, 2048, true>(b, doff, dcol, T, tot, s); break;
     case 21: launch_mss<false>(b, doff, dcol, T, tot, s); break;
     case 22: launch_mss<true>(b, doff, dcol, T, tot, s); break;
+    case 23: launch_ms<128, 128, 512, 256, true>(b, doff, dcol, T, tot, s); break;
+    case 24: launch_ms<256, 256, 1024, 512, true>(b, doff, dcol, T, tot, s); break;
+    case 25: launch_ms<512, 512, 1024, 512, true>(b, doff, dcol, T, tot, s); break;
+    case 26: launch_ms<1024, 1024, 2048, 1024, true>(b, doff, dcol, T, tot, s); break;
     case kVariantGlobal:
       k_count_global<<<(unsigned)b.count, 256, 0, s>>>(b.list, b.count, doff, dcol, T, tot);
       break;

@@ -113,7 +113,7 @@ def test_min_side_variants_and_tuning_check():
     from paper_1606_07550_amd import default_tuning, variant_count
     L = N.lib()
     ms = [v for v in range(variant_count()) if L.tricc_variant_min_side(v)]
-    assert ms == list(range(0, 8)) + list(range(10, 23))
+    assert ms == list(range(0, 8)) + list(range(10, 27))
     t = default_tuning()
     assert t.min_side == 1 and all(L.tricc_variant_min_side(t.bin_variant[b]) for b in range(N.NUM_BINS - 1))
     bad = default_tuning()

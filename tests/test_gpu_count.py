@@ -213,6 +213,9 @@ MIN_SIDE_TUNINGS = [
     {"bin_limit": [64, 256, 640, 1024, 4096], "bin_variant": [21, 19, 15, 20, 20, 9], "min_side": 1},
     {"bin_limit": [64, 256, 640, 1024, 4096], "bin_variant": [22, 19, 15, 20, 20, 9], "min_side": 1},
     {"bin_limit": [8, 24, 64, 256, 1024], "bin_variant": [21, 22, 21, 12, 13, 8], "min_side": 1},
+    # half-full tables
+    {"bin_limit": [64, 256, 512, 1024, 4096], "bin_variant": [21, 23, 24, 26, 20, 9], "min_side": 1},
+    {"bin_limit": [32, 128, 512, 1024, 2048], "bin_variant": [22, 23, 25, 26, 20, 8], "min_side": 1},
 ]
 
 
