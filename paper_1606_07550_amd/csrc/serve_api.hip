@@ -31,12 +31,13 @@
 namespace tricc {
 hipError_t launch_serve_clear(int2* tab, int64_t total, hipStream_t s);
 hipError_t launch_serve_insert(int32_t Q, const int64_t* qoff, const int32_t* nodes, int64_t N, const int64_t* toff,
-                               int2* tab, int32_t n, const int32_t* deg, int32_t* nchunks, int32_t* err,
+                               int2* tab, int32_t n, const int32_t* deg, int32_t* nchunks, int32_t* qidx, int32_t* err,
                                hipStream_t s);
+hipError_t launch_serve_items(int64_t N, const int64_t* coff, int32_t* item, hipStream_t s);
 hipError_t launch_serve_pairs(int pass, int32_t Q, const int64_t* qoff, const int32_t* nodes, const int64_t* coff,
-                              int64_t C, const int64_t* toff, const int2* tab, const int64_t* off, const int32_t* deg,
-                              const int32_t* adj, int32_t* cnt, const int64_t* pos, int32_t* psrc, int32_t* pdst,
-                              hipStream_t s);
+                              int64_t C, const int32_t* item, const int32_t* qidx, const int64_t* toff, const int2* tab,
+                              const int64_t* off, const int32_t* deg, const int32_t* adj, int32_t* cnt,
+                              const int64_t* pos, int32_t* psrc, int32_t* pdst, hipStream_t s);
 hipError_t launch_serve_query_pairs(int32_t Q, const int64_t* qoff, const int64_t* coff, const int64_t* pos,
                                     int64_t* qpairs, hipStream_t s);
 }  // namespace tricc
@@ -59,8 +60,8 @@ inline int64_t pow2_at_least(int64_t x) {
 // from an upper bound on its pairs. G queries, N nodes, D = sum of resident
 // degrees of the nodes, M = bound on emitted pairs, T = table slots.
 struct SlotLayout {
-  size_t nodes, qoff, toff, tab, nchunks, coff, scan, cnt, pos, psrc, pdst, qpairs, err, T, cc, gtri, gavg, batch,
-      total;
+  size_t nodes, qoff, toff, tab, nchunks, qidx, coff, item, scan, cnt, pos, psrc, pdst, qpairs, err, T, cc, gtri,
+      gavg, batch, total;
 };
 
 SlotLayout slot_layout(int64_t G, int64_t N, int64_t D, int64_t M, int64_t Tslots) {
@@ -73,7 +74,9 @@ SlotLayout slot_layout(int64_t G, int64_t N, int64_t D, int64_t M, int64_t Tslot
   L.toff = take(8 * (G + 1));
   L.tab = take(8 * Tslots);
   L.nchunks = take(4 * N);
+  L.qidx = take(4 * N);  // query of each item
   L.coff = take(8 * (N + 1));
+  L.item = take(4 * C);  // item of each chunk
   L.scan = take(8 * (std::max(N, C) / 4096 + 4));
   L.cnt = take(4 * C);
   L.pos = take(8 * (C + 1));
@@ -183,7 +186,9 @@ int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, 
   int64_t* d_toff = reinterpret_cast<int64_t*>(at(L.toff));
   int2* tab = reinterpret_cast<int2*>(at(L.tab));
   int32_t* nchunks = reinterpret_cast<int32_t*>(at(L.nchunks));
+  int32_t* qidx = reinterpret_cast<int32_t*>(at(L.qidx));
   int64_t* coff = reinterpret_cast<int64_t*>(at(L.coff));
+  int32_t* item = reinterpret_cast<int32_t*>(at(L.item));
   int64_t* scan = reinterpret_cast<int64_t*>(at(L.scan));
   int32_t* cnt = reinterpret_cast<int32_t*>(at(L.cnt));
   int64_t* pos = reinterpret_cast<int64_t*>(at(L.pos));
@@ -204,7 +209,7 @@ int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, 
   SCHK(hipMemcpyAsync(d_toff, toff.data(), 8 * (size_t)(G + 1), hipMemcpyHostToDevice, st));
   SCHK(hipMemsetAsync(err, 0, 64, st));
   SCHK(launch_serve_clear(tab, Tsl, st));
-  SCHK(launch_serve_insert(G, d_qoff, nodes, N, d_toff, tab, S->n, S->deg, nchunks, err, st));
+  SCHK(launch_serve_insert(G, d_qoff, nodes, N, d_toff, tab, S->n, S->deg, nchunks, qidx, err, st));
   SCHK(launch_scan_i32(nchunks, N, coff, scan, st));
   int64_t C = 0;
   int32_t herr = 0;
@@ -213,16 +218,17 @@ int run_batch(tricc_server* S, char* ws, hipStream_t st, std::vector<Query>& B, 
   SCHK(hipStreamSynchronize(st));
   if (herr) return sfail(TRICC_EINVAL, "query node ids invalid on the device (flag %d)", herr);
   if (C > N + D / kChunk + 1) return sfail(TRICC_EOVERFLOW, "chunk bound exceeded");
-  SCHK(launch_serve_pairs(0, G, d_qoff, nodes, coff, C, d_toff, tab, S->off, S->deg, S->adj, cnt, nullptr, nullptr,
-                          nullptr, st));
+  SCHK(launch_serve_items(N, coff, item, st));
+  SCHK(launch_serve_pairs(0, G, d_qoff, nodes, coff, C, item, qidx, d_toff, tab, S->off, S->deg, S->adj, cnt, nullptr,
+                          nullptr, nullptr, st));
   SCHK(launch_scan_i32(cnt, C, pos, scan, st));
   SCHK(launch_serve_query_pairs(G, d_qoff, coff, pos, qpairs, st));
   std::vector<int64_t> hq(G + 1);
   SCHK(hipMemcpyAsync(hq.data(), qpairs, 8 * (size_t)(G + 1), hipMemcpyDeviceToHost, st));
   SCHK(hipStreamSynchronize(st));
   if (hq[G] > M) return sfail(TRICC_EOVERFLOW, "pair bound exceeded");
-  SCHK(launch_serve_pairs(1, G, d_qoff, nodes, coff, C, d_toff, tab, S->off, S->deg, S->adj, cnt, pos, psrc, pdst,
-                          st));
+  SCHK(launch_serve_pairs(1, G, d_qoff, nodes, coff, C, item, qidx, d_toff, tab, S->off, S->deg, S->adj, cnt, pos,
+                          psrc, pdst, st));
   tricc_batch* b = nullptr;
   int rc = tricc_batch_build(G, qoff.data(), hq.data(), psrc, pdst, at(L.batch), S->slot_bytes - L.batch, &bt, st, &b);
   if (rc) return rc;

@@ -52,17 +52,20 @@ __global__ __launch_bounds__(256) void k_serve_clear(int2* __restrict__ tab, int
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) tab[i] = make_int2(-1, -1);
 }
 
-// Inserts every (node, position) and writes the number of row chunks of
-// each item; flags node ids outside [0, n) or repeated inside one query.
+// Inserts every (node, position) and writes the number of row chunks and
+// the query of each item; flags node ids outside [0, n) or repeated inside
+// one query.
 __global__ __launch_bounds__(256) void k_serve_insert(int32_t Q, const int64_t* __restrict__ qoff,
                                                       const int32_t* __restrict__ nodes,
                                                       const int64_t* __restrict__ toff, int2* __restrict__ tab,
                                                       int32_t n, const int32_t* __restrict__ deg,
-                                                      int32_t* __restrict__ nchunks, int32_t* __restrict__ err) {
+                                                      int32_t* __restrict__ nchunks, int32_t* __restrict__ qidx,
+                                                      int32_t* __restrict__ err) {
   const int64_t N = qoff[Q];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
     const int32_t q = find_query(qoff, Q, i);
+    qidx[i] = q;
     const int32_t v = nodes[i];
     if ((uint32_t)v >= (uint32_t)n) {
       atomicOr(err, 1);
@@ -82,11 +85,22 @@ __global__ __launch_bounds__(256) void k_serve_insert(int32_t Q, const int64_t* 
   }
 }
 
+// Item of every row chunk (the chunk prefix coff inverted), so that a
+// chunk finds its item with one load instead of a search.
+__global__ __launch_bounds__(256) void k_serve_items(int64_t N, const int64_t* __restrict__ coff,
+                                                     int32_t* __restrict__ item) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+    for (int64_t c = coff[i]; c < coff[i + 1]; ++c) item[c] = (int32_t)i;
+}
+
 // One wavefront per (item, chunk): pass 0 counts the emitted pairs of the
 // chunk into cnt[c]; pass 1 writes them, in row order, at pos[c].
 __global__ __launch_bounds__(256) void k_serve_pairs(int pass, int32_t Q, const int64_t* __restrict__ qoff,
                                                      const int32_t* __restrict__ nodes,
                                                      const int64_t* __restrict__ coff,  // chunk prefix per item
+                                                     const int32_t* __restrict__ item,  // item of each chunk
+                                                     const int32_t* __restrict__ qidx,  // query of each item
                                                      const int64_t* __restrict__ toff,
                                                      const int2* __restrict__ tab, const int64_t* __restrict__ off,
                                                      const int32_t* __restrict__ deg,
@@ -98,14 +112,8 @@ __global__ __launch_bounds__(256) void k_serve_pairs(int pass, int32_t Q, const 
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int l = lane_id();
   for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < C; c += nwaves) {
-    // item of chunk c: last i with coff[i] <= c
-    int64_t lo = 0, hi = N - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (coff[mid] <= c) lo = mid; else hi = mid - 1;
-    }
-    const int64_t i = lo;
-    const int32_t q = find_query(qoff, Q, i);
+    const int64_t i = item[c];
+    const int32_t q = qidx[i];
     const int32_t v = nodes[i];
     const int32_t pv = (int32_t)(i - qoff[q]);
     const int2* t = tab + toff[q];
@@ -148,20 +156,26 @@ hipError_t launch_serve_clear(int2* tab, int64_t total, hipStream_t s) {
 }
 
 hipError_t launch_serve_insert(int32_t Q, const int64_t* qoff, const int32_t* nodes, int64_t N, const int64_t* toff,
-                               int2* tab, int32_t n, const int32_t* deg, int32_t* nchunks, int32_t* err,
+                               int2* tab, int32_t n, const int32_t* deg, int32_t* nchunks, int32_t* qidx, int32_t* err,
                                hipStream_t s) {
   if (N == 0) return hipSuccess;
-  k_serve_insert<<<grid_for(N, 256, 1u << 14), 256, 0, s>>>(Q, qoff, nodes, toff, tab, n, deg, nchunks, err);
+  k_serve_insert<<<grid_for(N, 256, 1u << 14), 256, 0, s>>>(Q, qoff, nodes, toff, tab, n, deg, nchunks, qidx, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve_items(int64_t N, const int64_t* coff, int32_t* item, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  k_serve_items<<<grid_for(N, 256, 1u << 14), 256, 0, s>>>(N, coff, item);
   return hipGetLastError();
 }
 
 hipError_t launch_serve_pairs(int pass, int32_t Q, const int64_t* qoff, const int32_t* nodes, const int64_t* coff,
-                              int64_t C, const int64_t* toff, const int2* tab, const int64_t* off, const int32_t* deg,
-                              const int32_t* adj, int32_t* cnt, const int64_t* pos, int32_t* psrc, int32_t* pdst,
-                              hipStream_t s) {
+                              int64_t C, const int32_t* item, const int32_t* qidx, const int64_t* toff, const int2* tab,
+                              const int64_t* off, const int32_t* deg, const int32_t* adj, int32_t* cnt,
+                              const int64_t* pos, int32_t* psrc, int32_t* pdst, hipStream_t s) {
   if (C == 0) return hipSuccess;
-  k_serve_pairs<<<grid_for(C * kWave, 256, 1u << 14), 256, 0, s>>>(pass, Q, qoff, nodes, coff, toff, tab, off, deg,
-                                                                   adj, cnt, pos, psrc, pdst);
+  k_serve_pairs<<<grid_for(C * kWave, 256, 1u << 14), 256, 0, s>>>(pass, Q, qoff, nodes, coff, item, qidx, toff, tab,
+                                                                   off, deg, adj, cnt, pos, psrc, pdst);
   return hipGetLastError();
 }
 
