@@ -679,21 +679,26 @@ int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream) {
   return TRICC_OK;
 }
 
-int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream) {
-  if (!g) return fail(TRICC_EINVAL, "null graph");
-  if (bin < 0 || bin >= kNumBins) return fail(TRICC_EINVAL, "bin %d out of range", bin);
-  const int32_t count = (int32_t)(g->bin_off[bin + 1] - g->bin_off[bin]);
-  if (count == 0 && g->in_items[bin + 1] == g->in_items[bin]) return TRICC_OK;
+}  // extern "C"
+
+namespace {
+
+// Bins b0 .. b1 (one variant) in one launch: their node lists, in-list
+// owners and chunks are contiguous, so the launch covers the union, and the
+// last blocks of one bin overlap the next bin's instead of draining first.
+int count_bins(tricc_graph* g, int b0, int b1, uint64_t* d_node_tri, void* stream) {
+  const int32_t count = (int32_t)(g->bin_off[b1 + 1] - g->bin_off[b0]);
+  if (count == 0 && g->in_items[b1 + 1] == g->in_items[b0]) return TRICC_OK;
   if (!d_node_tri) return fail(TRICC_EINVAL, "null output");
   const Layout& L = g->L;
-  BinLaunch bl{g->tuning.bin_variant[bin], g->at<int32_t>(L.binlist) + g->bin_off[bin], count};
+  BinLaunch bl{g->tuning.bin_variant[b0], g->at<int32_t>(L.binlist) + g->bin_off[b0], count};
   if (g->tuning.min_side && count_variant_min_side(bl.variant)) {
-    bl.in_list = g->at<int32_t>(L.inlist) + g->in_off[bin];
-    bl.in_coff = g->at<int64_t>(L.incoff) + g->in_off[bin];
-    bl.in_owner = g->at<int32_t>(L.tmp) + g->in_items[bin];
-    bl.in_base = (int32_t)g->in_off[bin];
-    bl.in_nodes = (int32_t)(g->in_off[bin + 1] - g->in_off[bin]);
-    bl.in_items = g->in_items[bin + 1] - g->in_items[bin];
+    bl.in_list = g->at<int32_t>(L.inlist) + g->in_off[b0];
+    bl.in_coff = g->at<int64_t>(L.incoff) + g->in_off[b0];
+    bl.in_owner = g->at<int32_t>(L.tmp) + g->in_items[b0];
+    bl.in_base = (int32_t)g->in_off[b0];
+    bl.in_nodes = (int32_t)(g->in_off[b1 + 1] - g->in_off[b0]);
+    bl.in_items = g->in_items[b1 + 1] - g->in_items[b0];
     bl.w_max = g->tuning.bin_limit[kNumBins - 2];
     bl.dinoff = g->at<int64_t>(L.dinoff);
     bl.dincol = g->at<int32_t>(L.dincol);
@@ -705,6 +710,16 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
                           reinterpret_cast<unsigned long long*>(d_node_tri), g->at<unsigned long long>(L.tot),
                           static_cast<hipStream_t>(stream)));
   return TRICC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (bin < 0 || bin >= kNumBins) return fail(TRICC_EINVAL, "bin %d out of range", bin);
+  return count_bins(g, bin, bin, d_node_tri, stream);
 }
 
 int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
@@ -740,7 +755,13 @@ int tricc_count(tricc_graph* g, uint64_t* d_node_tri, float* d_node_cc, uint64_t
   if ((g->n > 0 && (!d_node_tri || !d_node_cc)) || !d_total || !d_avg_cc)
     return fail(TRICC_EINVAL, "null output");
   int rc = tricc_count_begin(g, d_node_tri, stream);
-  for (int b = 0; b < kNumBins && !rc; ++b) rc = tricc_count_bin(g, b, d_node_tri, stream);
+  for (int b0 = 0; b0 < kNumBins && !rc;) {
+    // adjacent bins with one variant run as one launch
+    int b1 = b0;
+    while (b1 + 1 < kNumBins && g->tuning.bin_variant[b1 + 1] == g->tuning.bin_variant[b0]) ++b1;
+    rc = count_bins(g, b0, b1, d_node_tri, stream);
+    b0 = b1 + 1;
+  }
   if (!rc) rc = tricc_count_finish(g, d_node_tri, d_node_cc, d_total, d_avg_cc, stream);
   return rc;
 }
