@@ -1029,15 +1029,19 @@ int core_impl(const tricc_graph* g, int32_t k_stop, int32_t* d_core, int32_t* d_
         continue;
       }
       int32_t nf = c[0];
+      const int R = core_peel_batch();  // even: the frontier left ends in F
       while (nf > 0) {
+        // R rounds per read-back; the ones after the level's last frontier
+        // find an empty frontier and do nothing
+        HIPCHK(launch_core_peel_batch(F, G, nf, k, off, deg, adj, cur, d_core, cnt, d_order, round, U, near[x],
+                                      cnt + 6 + x, s));
+        int32_t b[16 + 8];
+        if ((rc = sync_copy(b, cnt, sizeof(int32_t) * (16 + R), s))) return rc;
         left -= nf;
-        HIPCHK(launch_core_reset(cnt, 1, -1, s));
-        HIPCHK(launch_core_peel(F, nf, k, off, deg, adj, cur, d_core, G, cnt, d_order, round, U, near[x], cnt + 6 + x,
-                                s));
-        ++round;
-        if ((rc = sync_copy(c, cnt, sizeof(c), s))) return rc;
-        std::swap(F, G);
-        nf = c[1];
+        for (int i = 0; i + 1 < R; ++i) left -= b[16 + i];
+        round += R;
+        nf = b[16 + R - 1];
+        c[6 + x] = b[6 + x];
       }
       nx = c[6 + x];
       maxc = k;

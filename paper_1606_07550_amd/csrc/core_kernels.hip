@@ -20,6 +20,8 @@
 // removed in round r or later, so orienting every edge towards the later
 // (round, id) gives out-degrees at most the core number: the degeneracy
 // ordering.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -29,6 +31,12 @@ namespace {
 
 constexpr int kCoreNT = 256;
 constexpr int kPeelG = 8;  // lanes per frontier node in the peel
+
+// Rounds launched together by launch_core_peel_batch, the later ones reading
+// their frontier size on the device (a round whose frontier is empty does
+// nothing), so the host reads the counters back once per batch.
+constexpr int kPeelBatch = 4;
+constexpr int64_t kPeelBatchMinNodes = 1024;
 
 // Appends the items of the lanes with `take` to q[*cnt ..], one atomic per
 // wavefront. All lanes of the wavefront must call it.
@@ -55,6 +63,10 @@ __global__ __launch_bounds__(kCoreNT) void k_core_init(int32_t n, const int32_t*
 // current degree above k among the nodes scanned, cnt[3] = survivors
 // listed, cnt[6] and cnt[7] = lengths of the two near-list buffers.
 __global__ void k_core_reset(int32_t* __restrict__ cnt, int which, int near) {
+  if (which == 2) {  // the speculative rounds' next-frontier counters
+    if (threadIdx.x < kPeelBatch) cnt[16 + threadIdx.x] = 0;
+    return;
+  }
   if (threadIdx.x == 0) {
     if (which == 0) {
       cnt[0] = 0;
@@ -153,14 +165,19 @@ __device__ __forceinline__ void peel_steps(const int32_t* __restrict__ row, int3
 // Removes the frontier F[0, nf) of level k: every neighbour w still left
 // loses one from its current degree; the one decrement that takes it from
 // k + 1 to k gives it core number k and puts it on the next frontier G.
-__global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict__ F, int32_t nf, int32_t k,
+// nf_dev (may be null): the frontier size is read there (the previous
+// round's next-frontier count), not taken from nf; gcnt counts the next
+// frontier.
+__global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict__ F, int32_t nf,
+                                                       const int32_t* __restrict__ nf_dev, int32_t k,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ deg,
                                                        const int32_t* __restrict__ adj, int32_t* __restrict__ cur,
                                                        int32_t* __restrict__ core, int32_t* __restrict__ G,
-                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ order,
+                                                       int32_t* __restrict__ gcnt, int32_t* __restrict__ order,
                                                        int32_t round, int32_t U, int32_t* __restrict__ Nr,
                                                        int32_t* __restrict__ ncnt) {
+  if (nf_dev) nf = *nf_dev;
   constexpr int GPB = kCoreNT / kPeelG;
   const int lane = lane_id();
   const int g = threadIdx.x % kPeelG;
@@ -180,7 +197,7 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
     for (int32_t j0 = 0; j0 < dmax; j0 += kPeelG * kPeelU)
-      peel_steps(adj + rb, ds, j0, kPeelG, g, k, U, cur, core, order, round + 1, G, cnt + 1, Nr, ncnt);
+      peel_steps(adj + rb, ds, j0, kPeelG, g, k, U, cur, core, order, round + 1, G, gcnt, Nr, ncnt);
     // long rows: the whole wavefront on each in turn (group leaders' bits)
     uint64_t longs = __ballot(g == 0 && dv > kPeelShort);
     while (longs) {
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(kCoreNT) void k_core_peel(const int32_t* __restrict
       const int64_t r = ((int64_t)__shfl((int32_t)(rb >> 32), src, kWave) << 32) |
                         (uint32_t)__shfl((int32_t)rb, src, kWave);
       for (int32_t j0 = 0; j0 < d; j0 += kWave * kPeelU)
-        peel_steps(adj + r, d, j0, kWave, lane, k, U, cur, core, order, round + 1, G, cnt + 1, Nr, ncnt);
+        peel_steps(adj + r, d, j0, kWave, lane, k, U, cur, core, order, round + 1, G, gcnt, Nr, ncnt);
     }
   }
 }
@@ -230,8 +247,25 @@ hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64
                             const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
                             int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
-  k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, k, off, deg, adj, cur, core, G, cnt, order,
-                                                                  round, U, Nr, ncnt);
+  k_core_peel<<<core_grid((int64_t)nf * kPeelG), kCoreNT, 0, s>>>(F, nf, nullptr, k, off, deg, adj, cur, core, G,
+                                                                  cnt + 1, order, round, U, Nr, ncnt);
+  return hipGetLastError();
+}
+
+int core_peel_batch() { return kPeelBatch; }
+
+hipError_t launch_core_peel_batch(int32_t* B0, int32_t* B1, int32_t nf, int32_t k, const int64_t* off,
+                                  const int32_t* deg, const int32_t* adj, int32_t* cur, int32_t* core, int32_t* cnt,
+                                  int32_t* order, int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt,
+                                  hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  k_core_reset<<<1, 64, 0, s>>>(cnt, 2, -1);
+  // later rounds read their size on the device; their grid follows the
+  // first round's (grid-stride loops take larger frontiers)
+  const unsigned grid = core_grid(std::max<int64_t>((int64_t)nf, kPeelBatchMinNodes) * kPeelG);
+  for (int i = 0; i < kPeelBatch; ++i)
+    k_core_peel<<<grid, kCoreNT, 0, s>>>((i & 1) ? B1 : B0, nf, i ? cnt + 16 + i - 1 : nullptr, k, off, deg, adj,
+                                         cur, core, (i & 1) ? B0 : B1, cnt + 16 + i, order, round + i, U, Nr, ncnt);
   return hipGetLastError();
 }
 

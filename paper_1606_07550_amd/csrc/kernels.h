@@ -242,6 +242,16 @@ hipError_t launch_core_scan(int32_t na, const int32_t* A, int32_t k, const int32
 hipError_t launch_core_peel(const int32_t* F, int32_t nf, int32_t k, const int64_t* off, const int32_t* deg,
                             const int32_t* adj, int32_t* cur, int32_t* core, int32_t* G, int32_t* cnt, int32_t* order,
                             int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt, hipStream_t s);
+// core_peel_batch() rounds of one level: the frontier starts in B0 (nf
+// nodes) and alternates between B0 and B1; round i counts its next frontier
+// in cnt[16 + i] (cleared here) and takes the order value round + i + 1 for
+// it. Round i > 0 reads its size from cnt[16 + i - 1]; an empty round does
+// nothing. With an even batch the frontier left ends in B0.
+int core_peel_batch();
+hipError_t launch_core_peel_batch(int32_t* B0, int32_t* B1, int32_t nf, int32_t k, const int64_t* off,
+                                  const int32_t* deg, const int32_t* adj, int32_t* cur, int32_t* core, int32_t* cnt,
+                                  int32_t* order, int32_t round, int32_t U, int32_t* Nr, int32_t* ncnt,
+                                  hipStream_t s);
 hipError_t launch_core_fill(int32_t n, int32_t k, int32_t* core, hipStream_t s);
 
 // ---- 4-clique counts ---------------------------------------------------------
