@@ -185,16 +185,20 @@ int sort_large_rows(tricc_graph* g, int32_t nl, const int32_t* rows_dev) {
     }
   const int64_t nj_max = (int64_t)cbeg.size();
   if (nj_max > L.max_jobs) return fail(TRICC_EOVERFLOW, "too many large-row chunks");
-  // meta layout for the passes
-  size_t p = 0;
-  auto carve = [&](size_t bytes) { char* at = meta + p; p = align_up(p + bytes); return at; };
-  int64_t* m_a = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * nj_max));
-  int32_t* m_la = reinterpret_cast<int32_t*>(carve(sizeof(int32_t) * nj_max));
-  int32_t* m_lb = reinterpret_cast<int32_t*>(carve(sizeof(int32_t) * nj_max));
-  int64_t* m_o = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * nj_max));
-  int64_t* m_t = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (nj_max + 1)));
-  if ((rc = upload(m_a, cbeg.data(), sizeof(int64_t) * nj_max, s))) return rc;
-  if ((rc = upload(m_la, clen.data(), sizeof(int32_t) * nj_max, s))) return rc;
+  // The job arrays of a step (chunk sort, each merge pass, the dedup) sit in
+  // one block of meta, int64 arrays first, and go up in one copy: a pass has
+  // at most nj_max jobs (each covers 2 R >= 2 chunks of a row), and the
+  // block is rewritten only after the previous step's kernel (stream order).
+  int64_t* m_a = reinterpret_cast<int64_t*>(meta);
+  int64_t* m_o = m_a + nj_max;
+  int64_t* m_t = m_o + nj_max;
+  int32_t* m_la = reinterpret_cast<int32_t*>(m_t + nj_max + 1);
+  int32_t* m_lb = m_la + nj_max;
+  std::vector<int64_t> blk((size_t)(3 * nj_max + 1) + (size_t)(nj_max + 1));  // int64 view of the block
+  int32_t* blk32 = reinterpret_cast<int32_t*>(blk.data() + 3 * nj_max + 1);
+  std::copy(cbeg.begin(), cbeg.end(), blk.begin());
+  std::copy(clen.begin(), clen.end(), blk32);
+  if ((rc = upload(m_a, blk.data(), sizeof(int64_t) * blk.size(), s))) return rc;
   HIPCHK(launch_sort_chunks(m_a, m_la, (int32_t)nj_max, adj, s));
 
   bool in_adj = true;
@@ -219,13 +223,14 @@ int sort_large_rows(tricc_graph* g, int32_t nl, const int32_t* rows_dev) {
     }
     t.push_back(tiles);
     const int32_t nj = (int32_t)a.size();
-    if ((rc = upload(m_a, a.data(), sizeof(int64_t) * nj, s))) return rc;
-    if ((rc = upload(m_la, la.data(), sizeof(int32_t) * nj, s))) return rc;
-    if ((rc = upload(m_lb, lb.data(), sizeof(int32_t) * nj, s))) return rc;
-    if ((rc = upload(m_o, o.data(), sizeof(int64_t) * nj, s))) return rc;
-    if ((rc = upload(m_t, t.data(), sizeof(int64_t) * (nj + 1), s))) return rc;
+    if (nj > nj_max) return fail(TRICC_EOVERFLOW, "merge pass with more jobs than chunks");
+    std::copy(a.begin(), a.end(), blk.begin());
+    std::copy(o.begin(), o.end(), blk.begin() + nj_max);
+    std::copy(t.begin(), t.end(), blk.begin() + 2 * nj_max);
+    std::copy(la.begin(), la.end(), blk32);
+    std::copy(lb.begin(), lb.end(), blk32 + nj_max);
+    if ((rc = upload(m_a, blk.data(), sizeof(int64_t) * blk.size(), s))) return rc;
     HIPCHK(launch_merge_pass(m_a, m_la, m_lb, m_o, m_t, nj, tiles, in_adj ? adj : tmp, in_adj ? tmp : adj, s));
-    HIPCHK(hipStreamSynchronize(s));
     in_adj = !in_adj;
   }
   std::vector<int64_t> seg(nl);
@@ -233,7 +238,6 @@ int sort_large_rows(tricc_graph* g, int32_t nl, const int32_t* rows_dev) {
   if ((rc = upload(m_a, seg.data(), sizeof(int64_t) * nl, s))) return rc;
   HIPCHK(launch_dedup_rows(rows_dev, m_a, nl, g->at<int32_t>(L.len), in_adj ? adj : tmp,
                            g->at<int64_t>(L.raw_off), adj, g->at<int32_t>(L.deg), s));
-  HIPCHK(hipStreamSynchronize(s));
   g->info.large_rows = nl;
   return TRICC_OK;
 }
