@@ -680,14 +680,16 @@ __global__ __launch_bounds__(256) void k_sort_small(const int32_t* __restrict__ 
 
 // Rows of up to CAP entries: one block sorts one row (or one chunk) in LDS
 // with a bitonic network. DEDUP: compact the unique values in place and write
-// deg; otherwise write the sorted chunk back as is.
+// deg; otherwise write the sorted chunk back as is. Rows of at most lmin
+// entries are left to another kernel.
 template <int CAP, int NT, bool DEDUP>
 __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ rows,
                                                  const int64_t* __restrict__ seg_beg,
                                                  const int32_t* __restrict__ seg_len,
                                                  const int64_t* __restrict__ off,
                                                  const int32_t* __restrict__ len,
-                                                 int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+                                                 int32_t* __restrict__ adj, int32_t* __restrict__ deg,
+                                                 int32_t lmin) {
   __shared__ int32_t s[CAP];
   __shared__ int32_t lds_scan[NT / kWave + 1];
   int32_t v = -1;
@@ -701,6 +703,7 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ row
     beg = seg_beg[blockIdx.x];
     L = seg_len[blockIdx.x];
   }
+  if (L <= lmin) return;  // block-uniform
   int P = 2;
   while (P < L) P <<= 1;
   for (int i = threadIdx.x; i < P; i += NT) s[i] = i < L ? adj[beg + i] : kPad;
@@ -806,8 +809,11 @@ __global__ __launch_bounds__(256) void k_sort_wave(const int32_t* __restrict__ r
 // by shuffles, strides below 64 E swap registers inside a lane, and only the
 // strides of 64 E and up go through LDS (write, barrier, read of the partner,
 // barrier). The stages run in a loop over k with the strides unrolled, which
-// keeps the code small. DEDUP: the unique ids, compacted to the row start,
-// and deg[v]; otherwise the sorted chunk back in place.
+// keeps the code small. The network spans only the next power of two Q >= L
+// (the first Q ids, ascending; the pads beyond are left as they are), and
+// wavefronts wholly past Q skip the register and shuffle stages. DEDUP: the
+// unique ids, compacted to the row start, and deg[v]; otherwise the sorted
+// chunk back in place. Rows longer than the block holds are left alone.
 template <int E, int W, bool DEDUP>
 __global__ __launch_bounds__(kWave * W) void k_sort_block(const int32_t* __restrict__ rows,
                                                           const int64_t* __restrict__ seg_beg,
@@ -834,13 +840,17 @@ __global__ __launch_bounds__(kWave * W) void k_sort_block(const int32_t* __restr
     beg = seg_beg[blockIdx.x];
     L = seg_len[blockIdx.x];
   }
+  if (L > P) return;  // block-uniform: a longer row is another kernel's
+  int32_t Q = 2;
+  while (Q < L) Q <<= 1;
+  const bool idle = wv * PW >= Q;  // wavefront-uniform
   int32_t x[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int32_t i = i0 + e * kWave;
     x[e] = i < L ? adj[beg + i] : kPad;
   }
-  for (int k = 2; k <= P; k <<= 1) {
+  for (int k = 2; k <= Q; k <<= 1) {
 #pragma unroll
     for (int j = P / 2; j > 0; j >>= 1) {
       if (j >= k) continue;  // block-uniform: the strides of stage k are k / 2 .. 1
@@ -857,6 +867,8 @@ __global__ __launch_bounds__(kWave * W) void k_sort_block(const int32_t* __restr
           x[e] = (lo == up) ? min(x[e], y) : max(x[e], y);
         }
         __syncthreads();
+      } else if (idle) {
+        continue;
       } else if (j >= kWave) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -928,8 +940,12 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
     case kRow512: k_sort_wave<8><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRow1024: k_sort_wave<16><<<grid_for((int64_t)nrows * kWave, 256, 1u << 16), 256, 0, s>>>(rows, nrows, off, len, adj, deg); break;
     case kRowLds4k: k_sort_block<16, 4, true><<<nrows, 256, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
-    case kRowLds8k: k_sort_lds<8192, 512, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
-    case kRowLds32k: k_sort_lds<kLargeChunk, 1024, true><<<nrows, 1024, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds8k: k_sort_block<16, 8, true><<<nrows, 512, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg); break;
+    case kRowLds32k:  // up to 16,384 ids in registers (32 per lane would spill), longer rows by the LDS network
+      k_sort_block<16, 16, true><<<nrows, 1024, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg);
+      k_sort_lds<kLargeChunk, 1024, true><<<nrows, 1024, 0, s>>>(rows, nullptr, nullptr, off, len, adj, deg,
+                                                                 kWave * 16 * 16);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -938,7 +954,8 @@ hipError_t launch_sort_rows(int cls, const int32_t* rows, int32_t nrows, const i
 hipError_t launch_sort_chunks(const int64_t* chunk_beg, const int32_t* chunk_len, int32_t nchunks,
                               int32_t* buf, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
-  k_sort_lds<kLargeChunk, 1024, false><<<nchunks, 1024, 0, s>>>(nullptr, chunk_beg, chunk_len, nullptr, nullptr, buf, nullptr);
+  k_sort_lds<kLargeChunk, 1024, false><<<nchunks, 1024, 0, s>>>(nullptr, chunk_beg, chunk_len, nullptr, nullptr, buf,
+                                                                 nullptr, 0);
   return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@ enum RowClass : int {
   kRow8, kRow16, kRow32, kRow64,  // register bitonic sort by a lane group
   kRow128, kRow256, kRow512, kRow1024,  // register bitonic sort by a wavefront
   kRowLds4k,   // <= 4096, register bitonic sort by a block of 4 wavefronts
-  kRowLds8k,   // <= 8192, LDS bitonic sort, 512 threads
-  kRowLds32k,  // <= 32768, LDS bitonic sort, 1024 threads
+  kRowLds8k,   // <= 8192, register bitonic sort by a block of 8 wavefronts
+  kRowLds32k,  // <= 32768: <= 16384 by a block of 16 wavefronts, longer by an LDS bitonic sort
   kRowLarge,   // > 32768: chunk sort + merge passes
   kNumRowClasses
 };

@@ -372,6 +372,29 @@ def test_long_rows_take_every_sort_path():
     assert r["info"]["max_deg"] >= 100_000
 
 
+def test_sort_class_boundaries():
+    """Hub rows whose raw lengths sit on both sides of every sort-class limit
+    (1,024 / 4,096 / 8,192 / 16,384 / 32,768) and inside classes where the
+    network spans fewer ids than the block holds; leaves drawn with
+    replacement, so every long row also carries duplicates."""
+    rng = np.random.default_rng(31)
+    n = 60_000
+    lengths = [1024, 1025, 1500, 2048, 2049, 4096, 4097, 5000, 8192, 8193, 9000, 16384, 16385, 32768, 32769]
+    s = [np.full(L, h, np.int64) for h, L in enumerate(lengths)]
+    d = [rng.integers(100, n, L) for L in lengths]
+    hub_rows = [np.unique(x) for x in d]
+    s.append(rng.integers(100, n, 100_000))
+    d.append(rng.integers(100, n, 100_000))
+    s = np.concatenate(s).astype(np.int32)
+    d = np.concatenate(d).astype(np.int32)
+    perm = rng.permutation(s.size)
+    r, ref = parity(n, s[perm], d[perm])
+    A = {k: v.cpu().numpy() for k, v in r["graph"].arrays().items()}
+    for h, want in enumerate(hub_rows):
+        np.testing.assert_array_equal(A["adj"][A["off"][h]:A["off"][h] + A["deg"][h]], want)
+    assert r["info"]["large_rows"] >= 1
+
+
 def test_partition_spread_over_several_blocks():
     """The raw rows are built per id range (1024 ids here); a range with more
     entries than one block takes (2^18) is split over blocks that combine
