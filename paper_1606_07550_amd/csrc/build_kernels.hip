@@ -1293,13 +1293,29 @@ __device__ __forceinline__ void orient_copy_row(int32_t v, int g, const int64_t*
                                                 const int32_t* __restrict__ part, const int64_t* __restrict__ doff,
                                                 int32_t* __restrict__ dcol, const int64_t* __restrict__ dinoff,
                                                 int32_t* __restrict__ dincol) {
+  constexpr int U = 4;  // loads of each list issued together per step
   const int32_t dv = deg[v], dp = dplus[v];
+  const int32_t di = dincol ? dv - dp : 0;
   const int32_t* prow = part + off[v];
+  const int32_t* pend = prow + dv - 1;
   int32_t* out = dcol + doff[v];
-  for (int32_t k = g; k < dp; k += G) out[k] = prow[k];
-  if (!dincol) return;
-  int32_t* in = dincol + dinoff[v];
-  for (int32_t k = g; k < dv - dp; k += G) in[k] = prow[dv - 1 - k];
+  int32_t* in = dincol ? dincol + dinoff[v] : nullptr;
+  const int32_t dm = max(dp, di);
+  for (int32_t k0 = g; k0 < dm; k0 += G * U) {
+    int32_t a[U], b[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t k = k0 + q * G;
+      a[q] = k < dp ? prow[k] : 0;
+      b[q] = k < di ? pend[-k] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t k = k0 + q * G;
+      if (k < dp) out[k] = a[q];
+      if (k < di) in[k] = b[q];
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_orient_copy_short(int32_t n, const int64_t* __restrict__ off,
