@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--autotune-single", action="store_true",
                     help="search the single-graph bin tuning first (cached per arch/workload)")
     ap.add_argument("--no-edge-queries", action="store_true", help="skip the edge-existence leg")
+    ap.add_argument("--no-bin-split", action="store_true",
+                    help="skip the untimed per-bin launches that split merged launches by bin (for counter runs)")
     ap.add_argument("--no-core", action="store_true", help="skip the core-number leg")
     ap.add_argument("--no-degeneracy", action="store_true",
                     help="skip the degeneracy-order leg (triangles and 4-cliques under both orders)")
@@ -134,7 +136,7 @@ def measured_counters(workload, variant, bin):
     """rocprofv3 counters of the dominant kernel from the committed summary
     (profiles/counters_<workload>.md): DRAM-side bytes, L2 hit rate and the
     calibrated FETCH_SIZE + WRITE_SIZE traffic per launch, if they were taken
-    on this workload, variant and bin with the current intersection-kernel
+    on this workload, variant and bin (or bin range of one launch) with the current intersection-kernel
     source; else None."""
     from paper_1606_07550_amd import profiling
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"counters_{workload}.md")
@@ -143,7 +145,7 @@ def measured_counters(workload, variant, bin):
         return None
     if rec.get("count_kernels_sha256") != profiling.count_source_sha256() or int(rec.get("variant", -1)) != variant:
         return None
-    if "bin" in rec and int(rec["bin"]) != bin:
+    if "bin" in rec and str(rec["bin"]).strip() != str(bin):
         return None
     out = {"source": f"profiles/counters_{workload}.md"}
     for k in ("traffic_bytes_per_launch", "dram_bytes_per_launch", "l2_hit_rate"):
@@ -694,8 +696,20 @@ def main():
     sp = ctypes.c_void_p(stream.cuda_stream)
     ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     nb = N.NUM_BINS
-    bin_ms = [0.0] * nb
-    bin_launches = [0] * nb
+    tuning_used = (tuning or P.default_tuning()).as_dict()
+    variants = tuning_used["bin_variant"]
+    # the launches tricc_count issues: one per run of adjacent bins with one
+    # kernel variant
+    groups = []
+    b0 = 0
+    while b0 < nb:
+        b1 = b0
+        while b1 + 1 < nb and variants[b1 + 1] == variants[b0]:
+            b1 += 1
+        groups.append((b0, b1))
+        b0 = b1 + 1
+    launch_ms = [0.0] * len(groups)
+    launch_n = [0] * len(groups)
 
     def step(timed):
         tb0 = time.perf_counter()
@@ -704,21 +718,21 @@ def main():
         h = g._h
         N.check(L.tricc_count_begin(h, ptr(T), sp), "begin")
         evs = []
-        for b in range(nb):
-            if g.info["bin_count"][b] == 0:
+        for gi, (b0, b1) in enumerate(groups):
+            if sum(g.info["bin_count"][b0:b1 + 1]) == 0:
                 continue
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            N.check(L.tricc_count_bin(h, b, ptr(T), sp), "bin")
+            N.check(L.tricc_count_bins(h, b0, b1, ptr(T), sp), "bins")
             e1.record(stream)
-            evs.append((b, e0, e1))
+            evs.append((gi, e0, e1))
         N.check(L.tricc_count_finish(h, ptr(T), ptr(cc), ptr(total), ptr(avg), sp), "finish")
         if timed:
             torch.cuda.synchronize()
-            for b, e0, e1 in evs:
-                bin_ms[b] += e0.elapsed_time(e1)
-                bin_launches[b] += 1
+            for gi, e0, e1 in evs:
+                launch_ms[gi] += e0.elapsed_time(e1)
+                launch_n[gi] += 1
         return g, tb1 - tb0
 
     for i in range(args.warmup):
@@ -747,21 +761,44 @@ def main():
     torch.cuda.synchronize()
     count_ms = e0.elapsed_time(e1) / reps
 
+    # untimed: every bin in a launch of its own, to split merged launches by bin
+    bin_ms = None
+    if not args.no_bin_split:
+        bin_ms = [0.0] * nb
+        split_reps = 2
+        h = g._h
+        for _ in range(split_reps):
+            N.check(L.tricc_count_begin(h, ptr(T), sp), "begin")
+            evs = []
+            for b in range(nb):
+                if g.info["bin_count"][b] == 0:
+                    continue
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                N.check(L.tricc_count_bin(h, b, ptr(T), sp), "bin")
+                e1.record(stream)
+                evs.append((b, e0, e1))
+            N.check(L.tricc_count_finish(h, ptr(T), ptr(cc), ptr(total), ptr(avg), sp), "finish")
+            torch.cuda.synchronize()
+            for b, e0, e1 in evs:
+                bin_ms[b] += e0.elapsed_time(e1) / split_reps
+
     m = info["m"]
     tri = int(total.cpu().item())
-    # dominant intersection kernel
-    avg_bin_ms = [bin_ms[b] / bin_launches[b] if bin_launches[b] else 0.0 for b in range(nb)]
-    dom = max(range(nb), key=lambda b: avg_bin_ms[b])
-    dom_s = avg_bin_ms[dom] * 1e-3
-    dom_kbytes = info["bin_kernel_bytes"][dom]
-    dom_merge = 4 * info["bin_list_elems"][dom] + 4 * info["bin_edges"][dom]
+    # dominant intersection launch of the timed steps
+    avg_launch_ms = [launch_ms[i] / launch_n[i] if launch_n[i] else 0.0 for i in range(len(groups))]
+    dom_g = max(range(len(groups)), key=lambda i: avg_launch_ms[i])
+    d0, d1 = groups[dom_g]
+    dom_label = f"{d0}-{d1}" if d1 > d0 else f"{d0}"
+    dom_s = avg_launch_ms[dom_g] * 1e-3
+    dom_kbytes = sum(info["bin_kernel_bytes"][d0:d1 + 1])
+    dom_merge = sum(4 * info["bin_list_elems"][b] + 4 * info["bin_edges"][b] for b in range(d0, d1 + 1))
     achieved = dom_kbytes / dom_s / 1e9 if dom_s > 0 else 0.0
     stage_bytes = 4 * info["list_elems"] + 4 * m + 8 * (n + 1) + 12 * n
     stage_kbytes = sum(info["bin_kernel_bytes"]) + 8 * (n + 1) + 12 * n
-    a6_ms = sum(avg_bin_ms)
-    tuning_used = (tuning or P.default_tuning()).as_dict()
-    variant = tuning_used["bin_variant"][dom]
-    prof = measured_counters(cfg["workload"], variant, dom)
+    a6_ms = sum(avg_launch_ms)
+    variant = variants[d0]
+    prof = measured_counters(cfg["workload"], variant, dom_label)
     traffic = prof.get("traffic_bytes_per_launch") if prof else None
     bw, _ = probe_bandwidth(torch, N)
     line = {
@@ -786,8 +823,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": f"intersection bin {dom} (variant {variant})",
-            "kernel_ms": avg_bin_ms[dom],
+            "kernel": f"intersection {'bins' if d1 > d0 else 'bin'} {dom_label} (variant {variant}, one launch)",
+            "kernel_ms": avg_launch_ms[dom_g],
             # bytes the min-side kernel moves with no reuse between its work
             # items (exact count on this graph); the merge measure (both lists
             # read per edge) is a work measure, not a bandwidth
@@ -807,10 +844,16 @@ def main():
                      "kernel_frac": stage_kbytes / (a6_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if a6_ms else 0.0,
                      "merge_bytes": stage_bytes,
                      "compulsory_bytes": 4 * m + 8 * (n + 1) + 12 * n,
-                     "bin_ms": avg_bin_ms, "bin_count": info["bin_count"],
+                     "launches": [{"bins": [b0, b1], "variant": variants[b0], "ms": avg_launch_ms[i],
+                                   "kernel_bytes": sum(info["bin_kernel_bytes"][b0:b1 + 1]),
+                                   "kernel_GBps": sum(info["bin_kernel_bytes"][b0:b1 + 1])
+                                   / (avg_launch_ms[i] * 1e-3) / 1e9 if avg_launch_ms[i] > 0 else 0.0}
+                                  for i, (b0, b1) in enumerate(groups)],
+                     # untimed per-bin launches (one bin each)
+                     "bin_ms": bin_ms, "bin_count": info["bin_count"],
                      "bin_kernel_bytes": info["bin_kernel_bytes"],
-                     "bin_kernel_GBps": [info["bin_kernel_bytes"][b] / (avg_bin_ms[b] * 1e-3) / 1e9
-                                         if avg_bin_ms[b] > 0 else 0.0 for b in range(nb)]},
+                     "bin_kernel_GBps": [info["bin_kernel_bytes"][b] / (bin_ms[b] * 1e-3) / 1e9
+                                         if bin_ms and bin_ms[b] > 0 else 0.0 for b in range(nb)]},
         "count_only": {"ms": count_ms, "edges_per_s": m / (count_ms * 1e-3)},
         "build_ms": 1e3 * build_s / args.steps,
         "build": build_line(1e3 * build_s / args.steps, n, int(src.numel()), m),

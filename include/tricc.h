@@ -209,6 +209,14 @@ int tricc_count(tricc_graph* g, uint64_t* d_node_tri, float* d_node_cc, uint64_t
  */
 int tricc_count_begin(tricc_graph* g, uint64_t* d_node_tri, void* stream);
 int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream);
+/*
+ * Bins first..last (0 <= first <= last < TRICC_NUM_BINS), which must share
+ * one kernel variant in g's tuning, as ONE launch over their contiguous
+ * node lists and in-list chunks: what tricc_count issues for each run of
+ * adjacent bins with equal variants. TRICC_EINVAL for a bad range or mixed
+ * variants (nothing launched). Asynchronous; no-op if the bins are empty.
+ */
+int tricc_count_bins(tricc_graph* g, int first, int last, uint64_t* d_node_tri, void* stream);
 int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
                        double* d_avg_cc, void* stream);
 

@@ -128,6 +128,7 @@ _SIGS = {
                                         _P]),
     "tricc_count_begin": (ctypes.c_int, [_P, _P, _P]),
     "tricc_count_bin": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "tricc_count_bins": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "tricc_count_finish": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "tricc_count_check": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), _P]),
     "tricc_probe_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),

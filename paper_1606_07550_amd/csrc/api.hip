@@ -726,6 +726,16 @@ int tricc_count_bin(tricc_graph* g, int bin, uint64_t* d_node_tri, void* stream)
   return count_bins(g, bin, bin, d_node_tri, stream);
 }
 
+int tricc_count_bins(tricc_graph* g, int first, int last, uint64_t* d_node_tri, void* stream) {
+  if (!g) return fail(TRICC_EINVAL, "null graph");
+  if (first < 0 || last >= kNumBins || first > last)
+    return fail(TRICC_EINVAL, "bin range %d..%d out of range", first, last);
+  for (int b = first + 1; b <= last; ++b)
+    if (g->tuning.bin_variant[b] != g->tuning.bin_variant[first])
+      return fail(TRICC_EINVAL, "bins %d..%d do not share one kernel variant", first, last);
+  return count_bins(g, first, last, d_node_tri, stream);
+}
+
 int tricc_count_finish(tricc_graph* g, const uint64_t* d_node_tri, float* d_node_cc, uint64_t* d_total,
                        double* d_avg_cc, void* stream) {
   if (!g) return fail(TRICC_EINVAL, "null graph");

@@ -55,6 +55,16 @@ def _per_kernel(db, counter, every=1, offset=0):
     return out
 
 
+def _selection(bin, every, offset):
+    """The sentence naming which dispatches a summary averages."""
+    if every > 1:
+        return (f"Dispatches {offset}, {offset} + {every}, ... of this kernel (bin {bin}'s launches; "
+                f"{every} bins of one count run it).")
+    if bin is not None and "-" in str(bin):
+        return f"Every dispatch of this kernel in the command is one launch over bins {bin}."
+    return ""
+
+
 def traffic_summary(fetch_db, write_db, kernel, variant, workload, command, bin=None, every=1, offset=0):
     f = _per_kernel(fetch_db, "FETCH_SIZE", every, offset)
     w = _per_kernel(write_db, "WRITE_SIZE", every, offset)
@@ -67,8 +77,7 @@ def traffic_summary(fetch_db, write_db, kernel, variant, workload, command, bin=
     k = ks[0]
     fb = f[k][1] * 1024.0 * fscale
     wb = w[k][1] * 1024.0 * wscale
-    sel = (f"Dispatches {offset}, {offset} + {every}, ... of this kernel (bin {bin}'s launches; "
-           f"{every} bins of one count run it).") if every > 1 else ""
+    sel = _selection(bin, every, offset)
     lines = [
         f"# Memory traffic of {k.split('(')[0].replace('void ', '')} — {workload}",
         "",
@@ -118,8 +127,7 @@ def counters_summary(fetch_db, write_db, hitmiss_db, dram_db, kernel, variant, w
     dram_rd = r_k / r_p * PROBE_BYTES if r_p else 0.0
     dram_wr = wr_k / wr_p * PROBE_BYTES if wr_p else 0.0
     short = kname.split("(")[0].replace("void ", "")
-    sel = (f"Dispatches {offset}, {offset} + {every}, ... of this kernel (bin {bin}'s launches; "
-           f"{every} bins of one count run it).") if every > 1 else ""
+    sel = _selection(bin, every, offset)
     lines = [
         f"# rocprofv3 counters of {short} — {workload}",
         "",
@@ -218,7 +226,7 @@ def main():
     ap.add_argument("--variant", type=int)
     ap.add_argument("--workload")
     ap.add_argument("--command", default="")
-    ap.add_argument("--bin", type=int, default=None, help="the bin whose launches are summarised")
+    ap.add_argument("--bin", default=None, help="the bin (or bin range 'a-b' of one launch) summarised")
     ap.add_argument("--every", type=int, default=1, help="launches of the kernel per count")
     ap.add_argument("--offset", type=int, default=0, help="position of the bin's launch among them")
     a = ap.parse_args()

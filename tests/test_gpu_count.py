@@ -4,6 +4,7 @@ Counts are compared bit for bit; FP32 clustering coefficients within 1e-6
 relative of the FP64 oracle with exact zeros; the FP64 average within 1e-6
 relative (it is summed in FP64, so it is in fact much closer).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -336,6 +337,46 @@ def test_retune_matches():
         o = g.count()
         torch.cuda.synchronize()
         np.testing.assert_array_equal(o["T"].cpu().numpy().view(np.uint64), ref["T"])
+
+
+@pytest.mark.parametrize("tun", [
+    {"bin_limit": [16, 16, 16, 16, 64], "bin_variant": [0, 0, 0, 0, 1, 8], "min_side": 1},
+    {"bin_limit": [8, 24, 64, 256, 1024], "bin_variant": [21, 21, 21, 12, 13, 8], "min_side": 1},
+    {"bin_limit": [4, 8, 32, 128, 256], "bin_variant": [10, 10, 11, 12, 12, 8], "min_side": 0},
+])
+def test_count_bins_merged_launches(tun):
+    """Runs of adjacent bins with one variant launched as one grid
+    (tricc_count_bins, as tricc_count issues them) give the oracle's T and
+    total; ranges that mix variants or leave the bins are rejected."""
+    n, s, d = I.rmat(15, 16, seed=47)
+    ref = oracle.count(n, s, d, order=1)
+    g = P.Graph(n, to_dev(s), to_dev(d), tuning=tun)
+    L, h = N.lib(), g._h
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    T = torch.empty(n, dtype=torch.int64, device=DEV)
+    cc = torch.empty(n, dtype=torch.float32, device=DEV)
+    tot = torch.empty(1, dtype=torch.int64, device=DEV)
+    avg = torch.empty(1, dtype=torch.float64, device=DEV)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    var = tun["bin_variant"]
+    N.check(L.tricc_count_begin(h, ptr(T), sp), "begin")
+    b0, launches = 0, 0
+    while b0 < N.NUM_BINS:
+        b1 = b0
+        while b1 + 1 < N.NUM_BINS and var[b1 + 1] == var[b0]:
+            b1 += 1
+        N.check(L.tricc_count_bins(h, b0, b1, ptr(T), sp), "bins")
+        launches += 1
+        b0 = b1 + 1
+    assert launches < N.NUM_BINS
+    N.check(L.tricc_count_finish(h, ptr(T), ptr(cc), ptr(tot), ptr(avg), sp), "finish")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(T.cpu().numpy().view(np.uint64), ref["T"])
+    assert int(tot.cpu().numpy().view(np.uint64)[0]) == ref["total"]
+    mixed = next(b for b in range(N.NUM_BINS - 1) if var[b] != var[b + 1])
+    for first, last in ((mixed, mixed + 1), (-1, 0), (0, N.NUM_BINS), (2, 1)):
+        assert L.tricc_count_bins(h, first, last, ptr(T), sp) == N.TRICC_EINVAL
 
 
 def test_tuning_capacity_violation_is_rejected():
