@@ -136,8 +136,8 @@ def measured_counters(workload, variant, bin):
     """rocprofv3 counters of the dominant kernel from the committed summary
     (profiles/counters_<workload>.md): DRAM-side bytes, L2 hit rate and the
     calibrated FETCH_SIZE + WRITE_SIZE traffic per launch, if they were taken
-    on this workload, variant and bin (or bin range of one launch) with the current intersection-kernel
-    source; else None."""
+    on this workload, variant and bin (or bin range of one launch) with the
+    current intersection-kernel source; else None."""
     from paper_1606_07550_amd import profiling
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"counters_{workload}.md")
     rec = profiling.read_summary(path)
