@@ -678,10 +678,30 @@ __global__ __launch_bounds__(256) void k_sort_small(const int32_t* __restrict__ 
   if (active && g == 0) deg[v] = (int32_t)__popcll(gm);
 }
 
+// Bitonic compare-exchanges of one stride j of stage k on kSortRun ids held
+// by one thread in registers (x[r] is id base + r); run-local strides only.
+constexpr int kSortRun = 32;
+__device__ __forceinline__ void run_stage(int32_t (&x)[kSortRun], int base, int j, int k) {
+#pragma unroll
+  for (int r = 0; r < kSortRun; ++r) {
+    const int pr = r ^ j;
+    if (pr > r) {
+      const bool up = ((base + r) & k) == 0;
+      const int32_t a = x[r], b = x[pr];
+      x[r] = up ? min(a, b) : max(a, b);
+      x[pr] = up ? max(a, b) : min(a, b);
+    }
+  }
+}
+
 // Rows of up to CAP entries: one block sorts one row (or one chunk) in LDS
-// with a bitonic network. DEDUP: compact the unique values in place and write
-// deg; otherwise write the sorted chunk back as is. Rows of at most lmin
-// entries are left to another kernel.
+// with a bitonic network. Each thread owns a run of 32 consecutive ids: the
+// strides below 32 run in its registers (one LDS read and write for all of
+// them, the first five stages in one pass), the larger strides in LDS, one
+// barrier each. The LDS holds id i at i + i / 32, so a run's ids sit in
+// distinct banks for the 32 lanes that read them together. DEDUP: compact
+// the unique values in place and write deg; otherwise write the sorted chunk
+// back as is. Rows of at most lmin entries are left to another kernel.
 template <int CAP, int NT, bool DEDUP>
 __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ rows,
                                                  const int64_t* __restrict__ seg_beg,
@@ -690,8 +710,11 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ row
                                                  const int32_t* __restrict__ len,
                                                  int32_t* __restrict__ adj, int32_t* __restrict__ deg,
                                                  int32_t lmin) {
-  __shared__ int32_t s[CAP];
+  constexpr int R = kSortRun;
+  static_assert(CAP % R == 0 && CAP / R <= NT, "one run per thread");
+  __shared__ int32_t s[CAP + CAP / R];
   __shared__ int32_t lds_scan[NT / kWave + 1];
+  auto at = [](int i) { return i + (i >> 5); };
   int32_t v = -1;
   int64_t beg;
   int32_t L;
@@ -704,34 +727,58 @@ __global__ __launch_bounds__(NT) void k_sort_lds(const int32_t* __restrict__ row
     L = seg_len[blockIdx.x];
   }
   if (L <= lmin) return;  // block-uniform
-  int P = 2;
+  int P = R;
   while (P < L) P <<= 1;
-  for (int i = threadIdx.x; i < P; i += NT) s[i] = i < L ? adj[beg + i] : kPad;
+  for (int i = threadIdx.x; i < P; i += NT) s[at(i)] = i < L ? adj[beg + i] : kPad;
   __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
+  const int g = threadIdx.x;
+  const bool owner = g < P / R;  // thread g owns ids g R .. g R + R - 1, at g (R + 1) + r
+  int32_t x[R];
+  if (owner) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = s[g * (R + 1) + r];
+#pragma unroll
+    for (int k = 2; k <= R; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) run_stage(x, g * R, j, k);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[g * (R + 1) + r] = x[r];
+  }
+  __syncthreads();
+  for (int k = 2 * R; k <= P; k <<= 1) {
+    for (int j = k >> 1; j >= R; j >>= 1) {
       for (int i = threadIdx.x; i < (P >> 1); i += NT) {
         const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
         const int hi = lo + j;
         const bool up = (lo & k) == 0;
-        const int32_t a = s[lo], b = s[hi];
-        if ((a > b) == up) { s[lo] = b; s[hi] = a; }
+        const int32_t a = s[at(lo)], b = s[at(hi)];
+        if ((a > b) == up) { s[at(lo)] = b; s[at(hi)] = a; }
       }
       __syncthreads();
     }
+    if (owner) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = s[g * (R + 1) + r];
+#pragma unroll
+      for (int j = R >> 1; j > 0; j >>= 1) run_stage(x, g * R, j, k);
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[g * (R + 1) + r] = x[r];
+    }
+    __syncthreads();
   }
   if (!DEDUP) {
-    for (int i = threadIdx.x; i < L; i += NT) adj[beg + i] = s[i];
+    for (int i = threadIdx.x; i < L; i += NT) adj[beg + i] = s[at(i)];
     return;
   }
   int32_t carry = 0;
   for (int base = 0; base < L; base += NT) {
     const int i = base + threadIdx.x;
-    const int32_t x = i < L ? s[i] : kPad;
-    const bool u = i < L && (i == 0 || x != s[i - 1]);
+    const int32_t x0 = i < L ? s[at(i)] : kPad;
+    const bool u = i < L && (i == 0 || x0 != s[at(i - 1)]);
     int32_t tot;
     const int32_t ex = block_excl_scan<int32_t, NT>(u ? 1 : 0, lds_scan, &tot);
-    if (u) adj[beg + carry + ex] = x;
+    if (u) adj[beg + carry + ex] = x0;
     carry += tot;
   }
   if (threadIdx.x == 0) deg[v] = carry;
