@@ -132,6 +132,20 @@ def build_line(ms, n, m_raw, m):
     return {"ms": ms, "compulsory_bytes": b, "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS}
 
 
+def launch_groups(variants):
+    """The launches tricc_count issues for a tuning: one (first, last) bin
+    range per run of adjacent bins with one kernel variant."""
+    groups = []
+    b0 = 0
+    while b0 < len(variants):
+        b1 = b0
+        while b1 + 1 < len(variants) and variants[b1 + 1] == variants[b0]:
+            b1 += 1
+        groups.append((b0, b1))
+        b0 = b1 + 1
+    return groups
+
+
 def measured_counters(workload, variant, bin):
     """rocprofv3 counters of the dominant kernel from the committed summary
     (profiles/counters_<workload>.md): DRAM-side bytes, L2 hit rate and the
@@ -698,16 +712,7 @@ def main():
     nb = N.NUM_BINS
     tuning_used = (tuning or P.default_tuning()).as_dict()
     variants = tuning_used["bin_variant"]
-    # the launches tricc_count issues: one per run of adjacent bins with one
-    # kernel variant
-    groups = []
-    b0 = 0
-    while b0 < nb:
-        b1 = b0
-        while b1 + 1 < nb and variants[b1 + 1] == variants[b0]:
-            b1 += 1
-        groups.append((b0, b1))
-        b0 = b1 + 1
+    groups = launch_groups(variants)
     launch_ms = [0.0] * len(groups)
     launch_n = [0] * len(groups)
 

@@ -40,3 +40,28 @@ def test_counter_summaries_parse(name):
         assert key in rec, key
     assert 0.0 <= float(rec["l2_hit_rate"]) <= 1.0
     assert float(rec["dram_bytes_per_launch"]) > 0
+
+
+def test_launch_groups_follow_equal_adjacent_variants():
+    assert bench.launch_groups([21, 23, 24, 20, 20, 9]) == [(0, 0), (1, 1), (2, 2), (3, 4), (5, 5)]
+    assert bench.launch_groups([1, 1, 1, 1, 1, 1]) == [(0, 5)]
+    assert bench.launch_groups([0, 1, 0, 1, 0, 1]) == [(b, b) for b in range(6)]
+    assert bench.launch_groups([10, 10, 11, 12, 12, 8]) == [(0, 1), (2, 2), (3, 4), (5, 5)]
+
+
+def test_counters_are_used_only_for_their_launch(monkeypatch):
+    rec = {"count_kernels_sha256": profiling.count_source_sha256(), "variant": "20", "bin": "3-4",
+           "traffic_bytes_per_launch": "100", "dram_bytes_per_launch": "120", "l2_hit_rate": "0.05"}
+    monkeypatch.setattr(profiling, "read_summary", lambda path: dict(rec))
+    got = bench.measured_counters("rmat24", 20, "3-4")
+    assert got["traffic_bytes_per_launch"] == 100.0 and got["l2_hit_rate"] == 0.05
+    assert bench.measured_counters("rmat24", 20, "3") is None  # another launch
+    assert bench.measured_counters("rmat24", 21, "3-4") is None  # another variant
+    rec["count_kernels_sha256"] = "0" * 64  # taken on another kernel source
+    assert bench.measured_counters("rmat24", 20, "3-4") is None
+
+
+def test_summary_names_the_dispatches_it_averages():
+    assert "bins 3-4" in profiling._selection("3-4", 1, 0)
+    assert "bin 3's launches" in profiling._selection(3, 2, 0)
+    assert profiling._selection(None, 1, 0) == ""
